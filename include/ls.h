@@ -1,0 +1,168 @@
+/* ls.h -- C ABI of the MI355X (gfx950) Lippmann-Schwinger Nystrom operator library (libls.so).
+ *
+ * Problem (paper, Section 2, eqs. Lippmann-Schwinger_Omega and contrast_def): the total field u
+ * satisfies u + k^2 V[m u] = u_inc on the support Omega of the contrast m = 1 - n, with the
+ * Green's function G(x, y) = (i/4) H0^(1)(k |x - y|).
+ * Discretisation (Section 3, eqs. linear_system, nystrom_linear_system, linear_system_matrix):
+ * at the N quadrature nodes y_j of a curved triangular mesh with weights w_j,
+ *     L u = b,  L = I + k^2 V M,  V = G~ W + C,  M = diag(m(y_j)),  b_j = u_inc(y_j),
+ * where (G~)_jn = G(y_j, y_n) for j != n and 0 for j = n, W = diag(w), and C is the sparse
+ * near-singular correction of the density-interpolation (VDIM) scheme (eq. DIM_decomp): for each
+ * subdomain l and node j it has 10 entries on one element of l,
+ *     C_jn = E_l[L_n](y_j) - sum_{q in l, q != j} G(y_j, y_q) w_q L_n(y_q),
+ * with L_n the cubic Lagrange basis of that element and E_l[P](x) = int_{Omega_l} G(x,y) P(y) dy.
+ *
+ * Conventions
+ *   - Complex vectors are interleaved (re, im) doubles (the layout of torch.complex128).
+ *   - Right-hand-side blocks are RHS-major: column c of a block starts at ptr + 2*c*ld doubles.
+ *   - A handle may hold several independent scatterers; vectors are then the concatenation of
+ *     the scatterers' node sets in the order given to ls_setup, and every column has that layout.
+ *   - Vectors are always read and written in the caller's node order (the library reorders nodes
+ *     internally for locality).
+ *   - x, y, b, u, lam, a, grad arguments are DEVICE pointers owned by the caller; setup inputs
+ *     are HOST pointers copied by the call.  All device work is enqueued on the given stream.
+ *   - Every call validates its arguments before enqueuing anything and returns an ls_status;
+ *     ls_last_error(h) gives a message for the last failure on h.  A handle must not be used by
+ *     two host threads at once.
+ */
+#ifndef LS_H_
+#define LS_H_
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LS_OK = 0,
+  LS_NOT_CONVERGED = 1,     /* ls_solve_gmres: maxit reached; x holds the last iterate */
+  LS_ERR_ARG = -1,          /* invalid argument (nothing was enqueued) */
+  LS_ERR_HIP = -2,          /* a HIP runtime call failed */
+  LS_ERR_ALLOC = -3,        /* device or host allocation failed */
+  LS_ERR_BREAKDOWN = -4,    /* Krylov breakdown with a non-finite value */
+  LS_ERR_NONFINITE = -5,    /* non-finite right-hand side or initial guess */
+  LS_ERR_UNSUPPORTED = -6
+} ls_status;
+
+typedef enum {
+  LS_FP64 = 0,   /* every operation in FP64 */
+  LS_MIXED = 1   /* Green's tiles in FP32 (matrix cores), FP64 correction / small arguments */
+} ls_precision;
+
+enum { LS_CIRCLE = 0, LS_ELLIPSE = 1 };
+
+/* A closed analytic boundary curve of one subdomain, parametrised by t in [0, 2 pi):
+ * (cx + a cos t, cy + b sin t) (a = b for a circle).  orientation = +1 if the subdomain lies
+ * inside the curve, -1 if it lies outside it (e.g. the inner circle of an annulus). */
+typedef struct {
+  int32_t kind;
+  int32_t orientation;
+  int32_t subdomain;
+  int32_t pad_;
+  double cx, cy, a, b;
+} ls_curve;
+
+/* One scatterer.  Nodes come in groups of nq = 10 per element (element e owns nodes 10e..10e+9);
+ * elem_subdomain gives the subdomain (0..n_sub-1) of every element; the curves are the boundaries
+ * of every subdomain (Section 3, eq. vol_pot_decomp).  m is the complex contrast 1 - n at the nodes
+ * (interleaved, 2*n_nodes doubles).  All pointers are host pointers. */
+typedef struct {
+  int64_t n_nodes;
+  int32_t n_elems;
+  int32_t nq;
+  const double *x, *y, *w;
+  const int32_t *elem_subdomain;
+  const double *m;
+  double k;
+  int32_t n_curves;
+  int32_t pad_;
+  const ls_curve *curves;
+} ls_scatterer;
+
+typedef struct {
+  int32_t source_split;   /* far-sum source chunks per launch (0 = automatic) */
+  int32_t rhs_chunk;      /* RHS per pass of the batched FP64 kernel (0 = automatic; 1, 4, 8, 16) */
+  int32_t mixed_tile;     /* mixed-precision tile variant (0 = automatic / autotuned cache) */
+  int32_t n_threads_host; /* host threads for setup (0 = all) */
+} ls_options;
+
+typedef struct ls_ctx *ls_handle;
+
+/* Build the operator for n_scatterers scatterers: sorts nodes, assembles the correction C
+ * (exact polynomial potentials by Green's third identity on the boundary curves plus punctured
+ * Green's sums on the GPU) and C^H, and uploads everything to the current HIP device.
+ * Synchronous.  opt may be NULL. */
+ls_status ls_setup(const ls_scatterer *s, int32_t n_scatterers, const ls_options *opt,
+                   ls_handle *out);
+
+/* Same as ls_setup for one scatterer, but with C supplied by the caller as a CSR matrix in the
+ * caller's node order (rowptr[n_nodes+1], col[nnz], val[2*nnz] interleaved complex; host). */
+ls_status ls_setup_from_csr(const ls_scatterer *s, const int64_t *rowptr, const int32_t *col,
+                            const double *val, const ls_options *opt, ls_handle *out);
+
+/* y = L x for nrhs columns (x, y: device, complex, leading dimension ld >= total nodes).
+ * Asynchronous on stream.  May allocate workspace on first use of a larger nrhs. */
+ls_status ls_apply(ls_handle h, const double *x, double *y, int32_t nrhs, int64_t ld,
+                   ls_precision p, hipStream_t stream);
+
+/* y = L^H x = x + k^2 conj(m) (W conj(G~) x + C^H x)  (exact adjoint of ls_apply in FP64). */
+ls_status ls_apply_adjoint(ls_handle h, const double *x, double *y, int32_t nrhs, int64_t ld,
+                           ls_precision p, hipStream_t stream);
+
+typedef struct {
+  double tol;          /* relative residual ||b - L x||_2 / ||b||_2 per column */
+  int32_t maxit;       /* outer iterations (Arnoldi steps) */
+  int32_t restart;     /* 0 = no restart */
+  int32_t prec;        /* ls_precision: LS_MIXED = FP64 flexible GMRES around mixed inner GMRES */
+  int32_t adjoint;     /* solve L^H x = b instead */
+  int32_t x0_given;    /* use x as the initial guess */
+  int32_t inner_maxit; /* LS_MIXED: inner iterations per outer step (0 = automatic) */
+  double inner_tol;    /* LS_MIXED: inner relative tolerance (0 = automatic) */
+} ls_solve_opts;
+
+typedef struct {
+  int32_t *iters;       /* [nrhs] host, may be NULL: Arnoldi steps per column */
+  double *relres;       /* [nrhs] host, may be NULL: final true relative residual (FP64 apply) */
+  int64_t n_apply_fp64; /* FP64 operator applications (per column count summed) */
+  int64_t n_apply_mixed;
+  double seconds;
+} ls_solve_info;
+
+/* Solve L x = b (or L^H x = b) by GMRES without restart, x0 = 0 unless x0_given, each column
+ * independently.  Synchronous.  Returns LS_NOT_CONVERGED if any column missed tol. */
+ls_status ls_solve_gmres(ls_handle h, const double *b, double *x, int32_t nrhs, int64_t ld,
+                         const ls_solve_opts *o, ls_solve_info *info, hipStream_t stream);
+
+/* grad_j (real, device, total nodes) = sum_d Re[conj(a_jd - k^2 (V^H lam_d)_j) u_jd]:
+ * the gradient of a far-field misfit with respect to real nodal contrast values, given the
+ * forward fields u, the adjoint states lam (L^H lam = conj(m) a) and a = A^H r. */
+ls_status ls_grad_contrast(ls_handle h, const double *u, const double *lam, const double *a,
+                           int32_t nrhs, int64_t ld, double *grad, hipStream_t stream);
+
+/* Introspection. */
+int64_t ls_num_nodes(ls_handle h);                       /* total nodes */
+int32_t ls_num_scatterers(ls_handle h);
+int64_t ls_scatterer_offset(ls_handle h, int32_t s);     /* first node of scatterer s */
+int64_t ls_correction_nnz(ls_handle h, int32_t s);
+/* Copy scatterer s's correction back in the caller's node order (host buffers of sizes
+ * n_nodes+1, nnz, 2*nnz). */
+ls_status ls_export_correction(ls_handle h, int32_t s, int64_t *rowptr, int32_t *col, double *val);
+
+/* Diagnostic: G(z) = (i/4) H0^(1)(z) for n arguments given as z^2 (device in, device out,
+ * interleaved complex) with the kernels' own FP64 evaluation, or FP32 when single != 0. */
+ls_status ls_eval_green(const double *z2, double *g, int64_t n, int32_t single, hipStream_t stream);
+/* Same evaluation compiled for the host CPU (host pointers), for checks without a GPU. */
+ls_status ls_eval_green_host(const double *z2, double *g, int64_t n);
+
+void ls_destroy(ls_handle h);
+const char *ls_status_str(ls_status s);
+const char *ls_last_error(ls_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LS_H_ */

@@ -1,0 +1,267 @@
+"""MI355X (gfx950) Lippmann-Schwinger Nystrom operator: Python binding of libls.so.
+
+Argument marshalling only: every step of the operator, the solver and the gradient runs in
+the HIP library.  torch supplies device memory and the current stream.  The library must be
+built (``python -m paper_2608_17615_amd.build``); importing the compute entry points without
+it raises, there is no CPU fallback.
+
+The mathematics (paper, Sections 2-3): L u = u + k^2 (G~ W + C)(m u) at the quadrature nodes,
+with m = 1 - n the contrast, G~ the punctured Green's matrix, W the weights and C the sparse
+density-interpolation correction; see include/ls.h for the full statement of every call.
+"""
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libls.so")
+
+LS_OK, LS_NOT_CONVERGED = 0, 1
+FP64, MIXED = 0, 1
+_PREC = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}
+CIRCLE, ELLIPSE = 0, 1
+
+_lib = None
+
+
+class LSError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class _Curve(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("orientation", ctypes.c_int32), ("subdomain", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("cx", ctypes.c_double), ("cy", ctypes.c_double),
+                ("a", ctypes.c_double), ("b", ctypes.c_double)]
+
+
+class _Scatterer(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int64), ("n_elems", ctypes.c_int32), ("nq", ctypes.c_int32),
+                ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("elem_subdomain", ctypes.c_void_p), ("m", ctypes.c_void_p), ("k", ctypes.c_double),
+                ("n_curves", ctypes.c_int32), ("pad_", ctypes.c_int32), ("curves", ctypes.c_void_p)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("source_split", ctypes.c_int32), ("rhs_chunk", ctypes.c_int32),
+                ("mixed_tile", ctypes.c_int32), ("n_threads_host", ctypes.c_int32)]
+
+
+class _SolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("restart", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("adjoint", ctypes.c_int32), ("x0_given", ctypes.c_int32),
+                ("inner_maxit", ctypes.c_int32), ("inner_tol", ctypes.c_double)]
+
+
+class _SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_void_p), ("relres", ctypes.c_void_p), ("n_apply_fp64", ctypes.c_int64),
+                ("n_apply_mixed", ctypes.c_int64), ("seconds", ctypes.c_double)]
+
+
+def lib():
+    """The loaded libls.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_2608_17615_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.ls_setup.argtypes = [vp, i32, vp, vp]
+        L.ls_setup_from_csr.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.ls_apply.argtypes = [vp, vp, vp, i32, i64, i32, vp]
+        L.ls_apply_adjoint.argtypes = [vp, vp, vp, i32, i64, i32, vp]
+        L.ls_solve_gmres.argtypes = [vp, vp, vp, i32, i64, vp, vp, vp]
+        L.ls_grad_contrast.argtypes = [vp, vp, vp, vp, i32, i64, vp, vp]
+        L.ls_num_nodes.argtypes = [vp]
+        L.ls_num_nodes.restype = i64
+        L.ls_num_scatterers.argtypes = [vp]
+        L.ls_scatterer_offset.argtypes = [vp, i32]
+        L.ls_scatterer_offset.restype = i64
+        L.ls_correction_nnz.argtypes = [vp, i32]
+        L.ls_correction_nnz.restype = i64
+        L.ls_export_correction.argtypes = [vp, i32, vp, vp, vp]
+        L.ls_eval_green.argtypes = [vp, vp, i64, i32, vp]
+        L.ls_eval_green_host.argtypes = [vp, vp, i64]
+        L.ls_destroy.argtypes = [vp]
+        L.ls_destroy.restype = None
+        L.ls_status_str.argtypes = [i32]
+        L.ls_status_str.restype = ctypes.c_char_p
+        L.ls_last_error.argtypes = [vp]
+        L.ls_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status, handle=None):
+    if status < 0:
+        L = lib()
+        raise LSError(status, (L.ls_last_error(handle) or b"").decode() or L.ls_status_str(status).decode())
+    return status
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class Scatterer:
+    """Host description of one scatterer (all arrays in the caller's node order)."""
+    x: np.ndarray
+    y: np.ndarray
+    w: np.ndarray
+    elem_subdomain: np.ndarray
+    m: np.ndarray          # contrast 1 - n at the nodes (real or complex)
+    k: float
+    curves: list           # objects with kind ('circle'/'ellipse'), cx, cy, a, b, orientation, subdomain
+
+    @classmethod
+    def from_mesh(cls, mesh, m, k):
+        return cls(mesh.x, mesh.y, mesh.w, mesh.elem_subdomain, m, k, list(mesh.curves))
+
+    def _struct(self):
+        keep = []
+
+        def arr(a, dt):
+            a = np.ascontiguousarray(a, dtype=dt)
+            keep.append(a)
+            return a.ctypes.data
+
+        m = np.asarray(self.m)
+        mc = np.ascontiguousarray(m.astype(np.complex128)).view(np.float64)
+        n = int(np.asarray(self.x).size)
+        curves = (_Curve * max(1, len(self.curves)))()
+        for i, c in enumerate(self.curves):
+            kind = c.kind if isinstance(c.kind, int) else {"circle": CIRCLE, "ellipse": ELLIPSE}[c.kind]
+            curves[i] = _Curve(kind, int(c.orientation), int(c.subdomain), 0, float(c.cx), float(c.cy),
+                               float(c.a), float(c.b))
+        keep.append(curves)
+        s = _Scatterer(n, n // 10, 10, arr(self.x, np.float64), arr(self.y, np.float64), arr(self.w, np.float64),
+                       arr(self.elem_subdomain, np.int32), arr(mc, np.float64), float(self.k),
+                       len(self.curves), 0, ctypes.cast(curves, ctypes.c_void_p))
+        return s, keep
+
+
+def _options(source_split=0, rhs_chunk=0, mixed_tile=0, n_threads_host=0):
+    return _Options(source_split, rhs_chunk, mixed_tile, n_threads_host)
+
+
+class Operator:
+    """L = I + k^2 (G~ W + C) M for one or several scatterers, resident on the current GPU."""
+
+    def __init__(self, scatterers, correction=None, **options):
+        if isinstance(scatterers, Scatterer):
+            scatterers = [scatterers]
+        L = lib()
+        self._h = ctypes.c_void_p()
+        opts = _options(**options)
+        structs = [s._struct() for s in scatterers]
+        if correction is not None:
+            if len(structs) != 1:
+                raise ValueError("a supplied correction needs exactly one scatterer")
+            rowptr, col, val = correction
+            rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+            col = np.ascontiguousarray(col, dtype=np.int32)
+            val = np.ascontiguousarray(np.asarray(val, dtype=np.complex128)).view(np.float64)
+            _check(L.ls_setup_from_csr(ctypes.byref(structs[0][0]), rowptr.ctypes.data, col.ctypes.data,
+                                       val.ctypes.data, ctypes.byref(opts), ctypes.byref(self._h)))
+        else:
+            arr = (_Scatterer * len(structs))(*[s for s, _ in structs])
+            _check(L.ls_setup(arr, len(structs), ctypes.byref(opts), ctypes.byref(self._h)))
+        self.n = int(L.ls_num_nodes(self._h))
+        self.n_scatterers = int(L.ls_num_scatterers(self._h))
+        self.offsets = [int(L.ls_scatterer_offset(self._h, i)) for i in range(self.n_scatterers)]
+
+    def close(self):
+        if self._h:
+            lib().ls_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _cols(self, x):
+        import torch
+        if x.dtype != torch.complex128 or not x.is_cuda:
+            raise TypeError("vectors must be complex128 CUDA tensors")
+        x2 = x.reshape(1, -1) if x.dim() == 1 else x
+        if x2.shape[-1] != self.n or not x2.is_contiguous():
+            raise ValueError(f"expected a contiguous (B, {self.n}) tensor")
+        return x2
+
+    def apply(self, x, precision="fp64", adjoint=False, out=None):
+        import torch
+        x2 = self._cols(x)
+        y = torch.empty_like(x2) if out is None else out.reshape(x2.shape)
+        fn = lib().ls_apply_adjoint if adjoint else lib().ls_apply
+        _check(fn(self._h, x2.data_ptr(), y.data_ptr(), x2.shape[0], self.n, _PREC[precision], _stream()), self._h)
+        return y.reshape(x.shape)
+
+    def apply_adjoint(self, x, precision="fp64", out=None):
+        return self.apply(x, precision, adjoint=True, out=out)
+
+    def solve(self, b, tol=1e-8, maxit=1000, precision="fp64", adjoint=False, x0=None, inner_tol=0.0,
+              inner_maxit=0):
+        """Solve L x = b (or L^H x = b) by GMRES without restart; returns (x, info dict)."""
+        import torch
+        b2 = self._cols(b)
+        if x0 is not None:
+            x = self._cols(x0).clone()
+        else:
+            x = torch.zeros_like(b2)
+        B = b2.shape[0]
+        iters = np.zeros(B, dtype=np.int32)
+        relres = np.zeros(B, dtype=np.float64)
+        o = _SolveOpts(float(tol), int(maxit), 0, _PREC[precision], int(bool(adjoint)), int(x0 is not None),
+                       int(inner_maxit), float(inner_tol))
+        info = _SolveInfo(iters.ctypes.data, relres.ctypes.data, 0, 0, 0.0)
+        st = _check(lib().ls_solve_gmres(self._h, b2.data_ptr(), x.data_ptr(), B, self.n, ctypes.byref(o),
+                                         ctypes.byref(info), _stream()), self._h)
+        return x.reshape(b.shape), {"converged": st == LS_OK, "iters": iters, "relres": relres,
+                                    "n_apply_fp64": info.n_apply_fp64, "n_apply_mixed": info.n_apply_mixed,
+                                    "seconds": info.seconds}
+
+    def grad_contrast(self, u, lam, a):
+        import torch
+        u2, l2, a2 = self._cols(u), self._cols(lam), self._cols(a)
+        g = torch.empty(self.n, dtype=torch.float64, device=u2.device)
+        _check(lib().ls_grad_contrast(self._h, u2.data_ptr(), l2.data_ptr(), a2.data_ptr(), u2.shape[0], self.n,
+                                      g.data_ptr(), _stream()), self._h)
+        return g
+
+    def correction_nnz(self, s=0):
+        return int(lib().ls_correction_nnz(self._h, s))
+
+    def export_correction(self, s=0):
+        """Scatterer s's correction C as (rowptr, col, val) in the caller's node order."""
+        L = lib()
+        nnz = self.correction_nnz(s)
+        n = (self.offsets[s + 1] if s + 1 < self.n_scatterers else self.n) - self.offsets[s]
+        rowptr = np.zeros(n + 1, dtype=np.int64)
+        col = np.zeros(max(nnz, 1), dtype=np.int32)
+        val = np.zeros(max(nnz, 1), dtype=np.complex128)
+        _check(L.ls_export_correction(self._h, s, rowptr.ctypes.data, col.ctypes.data, val.ctypes.data), self._h)
+        return rowptr, col[:nnz], val[:nnz]
+
+
+def eval_green(z2, single=False):
+    """G(z) = (i/4) H0^(1)(z) at z^2 values (float64 CUDA tensor) with the kernels' evaluation."""
+    import torch
+    z2 = z2.contiguous()
+    g = torch.empty(z2.shape, dtype=torch.complex128, device=z2.device)
+    _check(lib().ls_eval_green(z2.data_ptr(), g.data_ptr(), z2.numel(), int(bool(single)), _stream()))
+    return g
+
+
+def eval_green_host(z2):
+    """Same evaluation compiled for the host CPU (numpy in, numpy complex128 out)."""
+    z2 = np.ascontiguousarray(z2, dtype=np.float64)
+    g = np.empty(z2.shape, dtype=np.complex128)
+    _check(lib().ls_eval_green_host(z2.ctypes.data, g.ctypes.data, z2.size))
+    return g

@@ -1,0 +1,367 @@
+// C ABI entry points: argument validation, internal node ordering, device uploads, dispatch.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using lsk::Scat;
+
+namespace {
+
+thread_local std::string g_err;   // errors raised before a handle exists
+
+ls_status fail(ls_ctx *h, ls_status st, const std::string &msg) {
+  if (h) h->err = msg;
+  g_err = msg;
+  return st;
+}
+
+#define HIPCHK(h, call)                                                                   \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail((h), LS_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+// Allocate max(count, 1) elements on the device and copy count elements from src.
+template <class T>
+ls_status upload(ls_ctx *h, T **dst, const T *src, size_t count) {
+  *dst = nullptr;
+  void *p = nullptr;
+  if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess)
+    return fail(h, LS_ERR_ALLOC, "hipMalloc failed");
+  h->owned.push_back(p);
+  *dst = (T *)p;
+  if (src && count) HIPCHK(h, hipMemcpy(p, src, count * sizeof(T), hipMemcpyHostToDevice));
+  return LS_OK;
+}
+
+// Hilbert-curve index of (x, y) on a 2^16 x 2^16 grid.
+uint64_t hilbert_index(uint32_t x, uint32_t y) {
+  const uint32_t n = 1u << 16;
+  uint64_t d = 0;
+  for (uint32_t s = n / 2; s > 0; s /= 2) {
+    const uint32_t rx = (x & s) ? 1u : 0u;
+    const uint32_t ry = (y & s) ? 1u : 0u;
+    d += (uint64_t)s * s * ((3u * rx) ^ ry);
+    if (ry == 0) {
+      if (rx == 1) {
+        x = n - 1 - x;
+        y = n - 1 - y;
+      }
+      std::swap(x, y);
+    }
+  }
+  return d;
+}
+
+ls_status validate_scatterer(const ls_scatterer &s) {
+  if (s.n_nodes <= 0 || s.nq != 10 || s.n_elems <= 0 || (int64_t)s.n_elems * 10 != s.n_nodes)
+    return fail(nullptr, LS_ERR_ARG, "scatterer: need nq = 10 and n_nodes = 10 * n_elems > 0");
+  if (s.n_nodes > (int64_t)INT32_MAX / 2) return fail(nullptr, LS_ERR_ARG, "scatterer: too many nodes");
+  if (!s.x || !s.y || !s.w || !s.m || !s.elem_subdomain)
+    return fail(nullptr, LS_ERR_ARG, "scatterer: null array");
+  if (!(s.k > 0) || !std::isfinite(s.k)) return fail(nullptr, LS_ERR_ARG, "scatterer: k must be > 0");
+  for (int64_t i = 0; i < s.n_nodes; ++i)
+    if (!std::isfinite(s.x[i]) || !std::isfinite(s.y[i]) || !std::isfinite(s.w[i]) ||
+        !std::isfinite(s.m[2 * i]) || !std::isfinite(s.m[2 * i + 1]))
+      return fail(nullptr, LS_ERR_NONFINITE, "scatterer: non-finite node data");
+  int32_t nsub = 0;
+  for (int32_t e = 0; e < s.n_elems; ++e) {
+    if (s.elem_subdomain[e] < 0) return fail(nullptr, LS_ERR_ARG, "scatterer: negative subdomain");
+    nsub = std::max(nsub, s.elem_subdomain[e] + 1);
+  }
+  if (s.n_curves < 0 || (s.n_curves > 0 && !s.curves))
+    return fail(nullptr, LS_ERR_ARG, "scatterer: bad curve list");
+  for (int32_t c = 0; c < s.n_curves; ++c) {
+    const ls_curve &cv = s.curves[c];
+    if ((cv.kind != LS_CIRCLE && cv.kind != LS_ELLIPSE) || (cv.orientation != 1 && cv.orientation != -1) ||
+        cv.subdomain < 0 || cv.subdomain >= nsub || !(cv.a > 0) || !(cv.b > 0))
+      return fail(nullptr, LS_ERR_ARG, "scatterer: bad curve");
+  }
+  return LS_OK;
+}
+
+}  // namespace
+
+namespace lsk {
+
+// Element order: by subdomain, then along a Hilbert curve through element centroids.
+std::vector<int32_t> element_order(const ls_scatterer &s) {
+  const int32_t ne = s.n_elems;
+  double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+  std::vector<double> cx(ne), cy(ne);
+  for (int32_t e = 0; e < ne; ++e) {
+    double ax = 0, ay = 0;
+    for (int q = 0; q < 10; ++q) {
+      ax += s.x[10 * (int64_t)e + q];
+      ay += s.y[10 * (int64_t)e + q];
+    }
+    cx[e] = ax / 10;
+    cy[e] = ay / 10;
+    x0 = std::min(x0, cx[e]);
+    x1 = std::max(x1, cx[e]);
+    y0 = std::min(y0, cy[e]);
+    y1 = std::max(y1, cy[e]);
+  }
+  const double span = std::max(std::max(x1 - x0, y1 - y0), 1e-300);
+  std::vector<uint64_t> key(ne);
+  for (int32_t e = 0; e < ne; ++e) {
+    const uint32_t gx = (uint32_t)std::min(65535.0, std::floor((cx[e] - x0) / span * 65535.0));
+    const uint32_t gy = (uint32_t)std::min(65535.0, std::floor((cy[e] - y0) / span * 65535.0));
+    key[e] = ((uint64_t)s.elem_subdomain[e] << 40) | hilbert_index(gx, gy);
+  }
+  std::vector<int32_t> ord(ne);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+  return ord;
+}
+
+// Upload one scatterer's node data in internal order; fills perm and the geometry arrays.
+ls_status upload_nodes(ls_ctx *h, Scat &sc, const ls_scatterer &s, const std::vector<int32_t> &eord) {
+  const int64_t n = s.n_nodes;
+  sc.n = n;
+  sc.k = s.k;
+  sc.perm_host.resize(n);
+  std::vector<double> px(n), py(n), w(n), m(2 * n), pos(2 * n);
+  int32_t nsub = 0;
+  for (int32_t e = 0; e < s.n_elems; ++e) nsub = std::max(nsub, s.elem_subdomain[e] + 1);
+  sc.n_sub = nsub;
+  for (size_t ie = 0; ie < eord.size(); ++ie)
+    for (int q = 0; q < 10; ++q) {
+      const int64_t i = 10 * (int64_t)ie + q;
+      const int64_t c = 10 * (int64_t)eord[ie] + q;
+      sc.perm_host[i] = (int32_t)c;
+      px[i] = s.x[c];
+      py[i] = s.y[c];
+      w[i] = s.w[c];
+      m[2 * i] = s.m[2 * c];
+      m[2 * i + 1] = s.m[2 * c + 1];
+      pos[2 * i] = px[i];
+      pos[2 * i + 1] = py[i];
+    }
+  ls_status st;
+  if ((st = upload(h, &sc.px, px.data(), n)) != LS_OK) return st;
+  if ((st = upload(h, &sc.py, py.data(), n)) != LS_OK) return st;
+  if ((st = upload(h, &sc.w, w.data(), n)) != LS_OK) return st;
+  if ((st = upload(h, (double **)&sc.m, m.data(), 2 * n)) != LS_OK) return st;
+  if ((st = upload(h, (double **)&sc.pos, pos.data(), 2 * n)) != LS_OK) return st;
+  if ((st = upload(h, &sc.perm, sc.perm_host.data(), n)) != LS_OK) return st;
+  return LS_OK;
+}
+
+// Upload C (internal order, CSR) and build/upload C^H.
+ls_status upload_correction(ls_ctx *h, Scat &sc, const std::vector<int64_t> &rp, const std::vector<int32_t> &ci,
+                            const std::vector<double> &cv) {
+  const int64_t n = sc.n, nnz = rp[n];
+  sc.nnz = nnz;
+  std::vector<int64_t> rpH(n + 1, 0);
+  for (int64_t q = 0; q < nnz; ++q) rpH[ci[q] + 1]++;
+  for (int64_t i = 0; i < n; ++i) rpH[i + 1] += rpH[i];
+  std::vector<int32_t> ciH(nnz);
+  std::vector<double> cvH(2 * nnz);
+  std::vector<int64_t> fill(rpH.begin(), rpH.end() - 1);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t q = rp[i]; q < rp[i + 1]; ++q) {
+      const int64_t d = fill[ci[q]]++;
+      ciH[d] = (int32_t)i;
+      cvH[2 * d] = cv[2 * q];
+      cvH[2 * d + 1] = -cv[2 * q + 1];
+    }
+  ls_status st;
+  if ((st = upload(h, &sc.rp, rp.data(), n + 1)) != LS_OK) return st;
+  if ((st = upload(h, &sc.ci, ci.data(), nnz)) != LS_OK) return st;
+  if ((st = upload(h, (double **)&sc.cv, cv.data(), 2 * nnz)) != LS_OK) return st;
+  if ((st = upload(h, &sc.rpH, rpH.data(), n + 1)) != LS_OK) return st;
+  if ((st = upload(h, &sc.ciH, ciH.data(), nnz)) != LS_OK) return st;
+  if ((st = upload(h, (double **)&sc.cvH, cvH.data(), 2 * nnz)) != LS_OK) return st;
+  return LS_OK;
+}
+
+}  // namespace lsk
+
+extern "C" {
+
+const char *ls_status_str(ls_status s) {
+  switch (s) {
+    case LS_OK: return "ok";
+    case LS_NOT_CONVERGED: return "not converged";
+    case LS_ERR_ARG: return "invalid argument";
+    case LS_ERR_HIP: return "HIP runtime error";
+    case LS_ERR_ALLOC: return "allocation failed";
+    case LS_ERR_BREAKDOWN: return "Krylov breakdown";
+    case LS_ERR_NONFINITE: return "non-finite input";
+    case LS_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char *ls_last_error(ls_handle h) { return h ? h->err.c_str() : g_err.c_str(); }
+
+void ls_destroy(ls_handle h) {
+  if (!h) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(h->device);
+  (void)hipDeviceSynchronize();
+  for (void *p : h->owned) (void)hipFree(p);
+  if (h->ws_apply.ptr) (void)hipFree(h->ws_apply.ptr);
+  if (h->ws_solve.ptr) (void)hipFree(h->ws_solve.ptr);
+  (void)hipSetDevice(cur);
+  delete h;
+}
+
+ls_status ls_setup_from_csr(const ls_scatterer *s, const int64_t *rowptr, const int32_t *col, const double *val,
+                            const ls_options *opt, ls_handle *out) {
+  if (!out) return fail(nullptr, LS_ERR_ARG, "out is null");
+  *out = nullptr;
+  if (!s || !rowptr || (!col && rowptr[s->n_nodes] > 0) || (!val && rowptr[s->n_nodes] > 0))
+    return fail(nullptr, LS_ERR_ARG, "null argument");
+  ls_status st = validate_scatterer(*s);
+  if (st != LS_OK) return st;
+  const int64_t n = s->n_nodes;
+  if (rowptr[0] != 0) return fail(nullptr, LS_ERR_ARG, "rowptr[0] must be 0");
+  for (int64_t i = 0; i < n; ++i)
+    if (rowptr[i + 1] < rowptr[i]) return fail(nullptr, LS_ERR_ARG, "rowptr not monotone");
+  const int64_t nnz = rowptr[n];
+  for (int64_t q = 0; q < nnz; ++q) {
+    if (col[q] < 0 || col[q] >= n) return fail(nullptr, LS_ERR_ARG, "column index out of range");
+    if (!std::isfinite(val[2 * q]) || !std::isfinite(val[2 * q + 1]))
+      return fail(nullptr, LS_ERR_NONFINITE, "non-finite correction value");
+  }
+  ls_ctx *h = new ls_ctx();
+  if (opt) h->opt = *opt;
+  HIPCHK(nullptr, hipGetDevice(&h->device));
+  h->sc.resize(1);
+  Scat &sc = h->sc[0];
+  sc.off = 0;
+  h->n_total = n;
+  const std::vector<int32_t> eord = lsk::element_order(*s);
+  if ((st = lsk::upload_nodes(h, sc, *s, eord)) != LS_OK) {
+    ls_destroy(h);
+    return st;
+  }
+  std::vector<int32_t> inv(n);
+  for (int64_t i = 0; i < n; ++i) inv[sc.perm_host[i]] = (int32_t)i;
+  std::vector<int64_t> rp(n + 1, 0);
+  std::vector<int32_t> ci(nnz);
+  std::vector<double> cv(2 * nnz);
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t r = sc.perm_host[i];
+    rp[i + 1] = rp[i] + (rowptr[r + 1] - rowptr[r]);
+    int64_t d = rp[i];
+    for (int64_t q = rowptr[r]; q < rowptr[r + 1]; ++q, ++d) {
+      ci[d] = inv[col[q]];
+      cv[2 * d] = val[2 * q];
+      cv[2 * d + 1] = val[2 * q + 1];
+    }
+  }
+  if ((st = lsk::upload_correction(h, sc, rp, ci, cv)) != LS_OK) {
+    ls_destroy(h);
+    return st;
+  }
+  *out = h;
+  return LS_OK;
+}
+
+static ls_status apply_common(ls_handle h, const double *x, double *y, int32_t nrhs, int64_t ld, ls_precision p,
+                              hipStream_t stream, lsk::Mode mode) {
+  if (!h) return fail(nullptr, LS_ERR_ARG, "null handle");
+  if (nrhs < 0) return fail(h, LS_ERR_ARG, "nrhs < 0");
+  if (nrhs == 0) return LS_OK;
+  if (!x || !y) return fail(h, LS_ERR_ARG, "null vector");
+  if (x == y) return fail(h, LS_ERR_ARG, "x and y must not alias");
+  if (ld < h->n_total) return fail(h, LS_ERR_ARG, "ld < number of nodes");
+  if (p != LS_FP64 && p != LS_MIXED) return fail(h, LS_ERR_ARG, "bad precision");
+  if (p == LS_MIXED) return fail(h, LS_ERR_UNSUPPORTED, "mixed precision apply not built");
+  size_t need = 0;
+  for (const Scat &sc : h->sc) {
+    const int nsplit = h->opt.source_split > 0 ? h->opt.source_split
+                                               : lsk::auto_source_split(sc.n, nrhs);
+    need = std::max(need, lsk::apply_workspace_bytes(sc.n, nrhs, nsplit));
+  }
+  if (need > h->ws_apply.bytes) {
+    if (h->ws_apply.ptr) {
+      HIPCHK(h, hipStreamSynchronize(stream));
+      HIPCHK(h, hipFree(h->ws_apply.ptr));
+      h->ws_apply.ptr = nullptr;
+      h->ws_apply.bytes = 0;
+    }
+    if (hipMalloc(&h->ws_apply.ptr, need) != hipSuccess) return fail(h, LS_ERR_ALLOC, "workspace allocation failed");
+    h->ws_apply.bytes = need;
+  }
+  for (const Scat &sc : h->sc) {
+    const int nsplit = h->opt.source_split > 0 ? h->opt.source_split : lsk::auto_source_split(sc.n, nrhs);
+    const int chunk = h->opt.rhs_chunk > 0 ? h->opt.rhs_chunk : 1;
+    HIPCHK(h, lsk::launch_apply_fp64(sc, x, y, nrhs, ld, mode, nsplit, chunk, h->ws_apply.ptr, stream));
+  }
+  return LS_OK;
+}
+
+ls_status ls_apply(ls_handle h, const double *x, double *y, int32_t nrhs, int64_t ld, ls_precision p,
+                   hipStream_t stream) {
+  return apply_common(h, x, y, nrhs, ld, p, stream, lsk::Mode::Forward);
+}
+
+ls_status ls_apply_adjoint(ls_handle h, const double *x, double *y, int32_t nrhs, int64_t ld, ls_precision p,
+                           hipStream_t stream) {
+  return apply_common(h, x, y, nrhs, ld, p, stream, lsk::Mode::Adjoint);
+}
+
+int64_t ls_num_nodes(ls_handle h) { return h ? h->n_total : -1; }
+int32_t ls_num_scatterers(ls_handle h) { return h ? (int32_t)h->sc.size() : -1; }
+int64_t ls_scatterer_offset(ls_handle h, int32_t s) {
+  return (h && s >= 0 && s < (int32_t)h->sc.size()) ? h->sc[s].off : -1;
+}
+int64_t ls_correction_nnz(ls_handle h, int32_t s) {
+  return (h && s >= 0 && s < (int32_t)h->sc.size()) ? h->sc[s].nnz : -1;
+}
+
+ls_status ls_export_correction(ls_handle h, int32_t s, int64_t *rowptr, int32_t *col, double *val) {
+  if (!h || s < 0 || s >= (int32_t)h->sc.size() || !rowptr || !col || !val)
+    return fail(h, LS_ERR_ARG, "bad argument");
+  const Scat &sc = h->sc[s];
+  const int64_t n = sc.n, nnz = sc.nnz;
+  std::vector<int64_t> rp(n + 1);
+  std::vector<int32_t> ci(std::max<int64_t>(nnz, 1));
+  std::vector<double> cv(2 * std::max<int64_t>(nnz, 1));
+  HIPCHK(h, hipMemcpy(rp.data(), sc.rp, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost));
+  if (nnz) {
+    HIPCHK(h, hipMemcpy(ci.data(), sc.ci, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+    HIPCHK(h, hipMemcpy(cv.data(), sc.cv, sizeof(double) * 2 * nnz, hipMemcpyDeviceToHost));
+  }
+  // back to caller order
+  std::vector<int32_t> inv(n);
+  for (int64_t i = 0; i < n; ++i) inv[sc.perm_host[i]] = (int32_t)i;
+  rowptr[0] = 0;
+  for (int64_t r = 0; r < n; ++r) {
+    const int64_t i = inv[r];
+    rowptr[r + 1] = rowptr[r] + (rp[i + 1] - rp[i]);
+    int64_t d = rowptr[r];
+    for (int64_t q = rp[i]; q < rp[i + 1]; ++q, ++d) {
+      col[d] = sc.perm_host[ci[q]];
+      val[2 * d] = cv[2 * q];
+      val[2 * d + 1] = cv[2 * q + 1];
+    }
+  }
+  return LS_OK;
+}
+
+ls_status ls_eval_green_host(const double *z2, double *g, int64_t n) {
+  if (n < 0 || (n > 0 && (!z2 || !g))) return fail(nullptr, LS_ERR_ARG, "bad argument");
+  lsk::eval_green_host(z2, g, n);
+  return LS_OK;
+}
+
+ls_status ls_eval_green(const double *z2, double *g, int64_t n, int32_t single, hipStream_t stream) {
+  if (n < 0 || (n > 0 && (!z2 || !g))) return fail(nullptr, LS_ERR_ARG, "bad argument");
+  HIPCHK(nullptr, lsk::launch_eval_green(z2, g, n, single, stream));
+  return LS_OK;
+}
+
+}  // extern "C"

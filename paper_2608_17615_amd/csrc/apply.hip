@@ -1,0 +1,251 @@
+// FP64 operator apply: y = L x = x + k^2 (G~ W + C)(m x)   (paper, Section 3,
+// eqs. linear_system and linear_system_matrix), and its adjoint
+// y = L^H x = x + k^2 conj(m) (W conj(G~) x + C^H x).
+//
+// Three kernels per apply, all stream-ordered:
+//   prologue : gather each column from the caller's order into the internal order and form
+//              the far-sum densities s = w m x (forward) or s = x (adjoint) in a [node][rhs]
+//              layout, plus f = m x (or x) in [rhs][node] layout for the sparse correction;
+//   far      : the punctured Green's sum t_j = sum_{n != j} G(y_j, y_n) s_n over a chunk of
+//              sources.  One target per lane; every lane of a wavefront walks the same source,
+//              whose position and densities are uniform across the wave and are read through the
+//              scalar data path into SGPRs (no LDS staging or barriers needed); G is evaluated in
+//              registers (hankel.h) once per pair and reused for the RHS of the chunk;
+//   epilogue : sum the source-chunk partials in a fixed order (deterministic), add the CSR
+//              correction, apply the diagonal factors and scatter to the caller's order.
+#include "hankel.h"
+#include "internal.h"
+
+namespace lsk {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__constant__ HankelTable d_hankel = kHankelTable;
+
+typedef __attribute__((address_space(4))) const HankelTable ConstTab;
+
+// The table's constant-address-space pointer, hidden from loop-invariant code motion: the
+// coefficient loads stay inside the source loop as scalar loads feeding SGPR operands,
+// instead of being hoisted into ~260 live vector registers.
+__device__ __forceinline__ ConstTab &hankel_table() {
+  ConstTab *t = (ConstTab *)&d_hankel;
+  asm volatile("" : "+s"(t));
+  return *t;
+}
+
+template <Mode M>
+__global__ __launch_bounds__(kBlock) void prologue_kernel(int64_t n, int nrhs, const int32_t *__restrict__ perm,
+                                                          const double *__restrict__ w,
+                                                          const double2 *__restrict__ m,
+                                                          const double2 *__restrict__ x, int64_t ld,
+                                                          int64_t off, double2 *__restrict__ sd,
+                                                          double2 *__restrict__ f) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n * nrhs) return;
+  const int64_t i = t / nrhs;
+  const int b = (int)(t - i * nrhs);
+  const double2 xv = x[(int64_t)b * ld + off + perm[i]];
+  if (M == Mode::Forward) {
+    const double2 mi = m[i];
+    const double2 fv = make_double2(mi.x * xv.x - mi.y * xv.y, mi.x * xv.y + mi.y * xv.x);
+    f[(int64_t)b * n + i] = fv;
+    sd[t] = make_double2(w[i] * fv.x, w[i] * fv.y);
+  } else {
+    f[(int64_t)b * n + i] = xv;
+    sd[t] = xv;
+  }
+}
+
+template <int BC, bool CONJ, bool MASKED>
+__device__ __forceinline__ void far_source(int j, int i, double xt, double yt, double k2,
+                                           const double2 *__restrict__ pos,
+                                           const double2 *__restrict__ d, double (&ar)[BC],
+                                           double (&ai)[BC]) {
+  const double2 p = pos[j];
+  const double dx = xt - p.x;
+  const double dy = yt - p.y;
+  const double A = k2 * std::fma(dx, dx, dy * dy);
+  double gr, gi;
+  green(A, gr, gi, hankel_table());
+  if (MASKED) {
+    const bool self = (j == i);
+    gr = self ? 0.0 : gr;
+    gi = self ? 0.0 : gi;
+  }
+  if (CONJ) gi = -gi;
+#pragma unroll
+  for (int b = 0; b < BC; ++b) {
+    const double2 s = d[b];
+    ar[b] = std::fma(gr, s.x, std::fma(-gi, s.y, ar[b]));
+    ai[b] = std::fma(gr, s.y, std::fma(gi, s.x, ai[b]));
+  }
+}
+
+// grid: (ceil(n / kBlock), source splits, nrhs / BC)
+template <int BC, bool CONJ>
+__global__ __launch_bounds__(kBlock) void far_fp64_kernel(int n, const double *__restrict__ px,
+                                                         const double *__restrict__ py,
+                                                         const double2 *__restrict__ pos,
+                                                         const double2 *__restrict__ sd, int nrhs,
+                                                         double k2, int split_len,
+                                                         double2 *__restrict__ part) {
+  const int c0 = blockIdx.z * BC;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int ii = i < n ? i : n - 1;
+  const double xt = px[ii], yt = py[ii];
+  const int w0 = __builtin_amdgcn_readfirstlane(blockIdx.x * kBlock + (threadIdx.x & ~63));
+  const int s0 = blockIdx.y * split_len;
+  const int s1 = min(n, s0 + split_len);
+  double ar[BC], ai[BC];
+#pragma unroll
+  for (int b = 0; b < BC; ++b) ar[b] = ai[b] = 0.0;
+  // sources before, inside and after this wavefront's own target range (only the middle
+  // range can contain the self pair j == i, which the punctured sum drops)
+  const int e0 = min(s1, max(s0, w0));
+  const int e1 = min(s1, max(s0, w0 + 64));
+  for (int j = s0; j < e0; ++j)
+    far_source<BC, CONJ, false>(j, i, xt, yt, k2, pos, sd + (int64_t)j * nrhs + c0, ar, ai);
+  for (int j = e0; j < e1; ++j)
+    far_source<BC, CONJ, true>(j, i, xt, yt, k2, pos, sd + (int64_t)j * nrhs + c0, ar, ai);
+  for (int j = e1; j < s1; ++j)
+    far_source<BC, CONJ, false>(j, i, xt, yt, k2, pos, sd + (int64_t)j * nrhs + c0, ar, ai);
+  if (i < n) {
+#pragma unroll
+    for (int b = 0; b < BC; ++b)
+      part[((int64_t)blockIdx.y * nrhs + c0 + b) * n + i] = make_double2(ar[b], ai[b]);
+  }
+}
+
+template <Mode M>
+__global__ __launch_bounds__(kBlock) void epilogue_kernel(
+    int64_t n, int nrhs, int nsplit, const double2 *__restrict__ part, const double2 *__restrict__ f,
+    const int64_t *__restrict__ rp, const int32_t *__restrict__ ci, const double2 *__restrict__ cv,
+    const double *__restrict__ w, const double2 *__restrict__ m, const int32_t *__restrict__ perm,
+    const double2 *__restrict__ x, double2 *__restrict__ y, int64_t ld, int64_t off, double k2) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int b = blockIdx.y;
+  if (i >= n) return;
+  double ar = 0.0, ai = 0.0;
+  for (int sp = 0; sp < nsplit; ++sp) {
+    const double2 p = part[((int64_t)sp * nrhs + b) * n + i];
+    ar += p.x;
+    ai += p.y;
+  }
+  if (M == Mode::Adjoint) {
+    ar *= w[i];
+    ai *= w[i];
+  }
+  const double2 *fb = f + (int64_t)b * n;
+  double cr = 0.0, cim = 0.0;
+  for (int64_t q = rp[i]; q < rp[i + 1]; ++q) {
+    const double2 c = cv[q];
+    const double2 v = fb[ci[q]];
+    cr = std::fma(c.x, v.x, std::fma(-c.y, v.y, cr));
+    cim = std::fma(c.x, v.y, std::fma(c.y, v.x, cim));
+  }
+  ar += cr;
+  ai += cim;
+  if (M == Mode::Adjoint) {
+    const double2 mi = m[i];   // conj(m) * acc
+    const double tr = mi.x * ar + mi.y * ai;
+    const double ti = mi.x * ai - mi.y * ar;
+    ar = tr;
+    ai = ti;
+  }
+  const int64_t c = (int64_t)b * ld + off + perm[i];
+  const double2 xv = x[c];
+  y[c] = make_double2(std::fma(k2, ar, xv.x), std::fma(k2, ai, xv.y));
+}
+
+__global__ void eval_green_kernel(const double *__restrict__ z2, double2 *__restrict__ g, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double gr, gi;
+  green(z2[i], gr, gi, d_hankel);
+  g[i] = make_double2(gr, gi);
+}
+
+template <int BC, bool CONJ>
+void launch_far(const Scat &s, const double2 *pos, const double2 *sd, int nrhs, int split_len, int nsplit,
+                double2 *part, hipStream_t st) {
+  dim3 grid((unsigned)((s.n + kBlock - 1) / kBlock), (unsigned)nsplit, (unsigned)(nrhs / BC));
+  far_fp64_kernel<BC, CONJ><<<grid, kBlock, 0, st>>>((int)s.n, s.px, s.py, pos, sd, nrhs, s.k * s.k,
+                                                     split_len, part);
+}
+
+}  // namespace
+
+int auto_source_split(int64_t n, int launches_per_split) {
+  // aim for about 8 waves per SIMD (256 CUs x 4 SIMDs) across the whole launch
+  const int64_t waves = ((n + 63) / 64) * (int64_t)launches_per_split;
+  int64_t s = (8192 + waves - 1) / waves;
+  if (s < 1) s = 1;
+  if (s > 64) s = 64;
+  if (s > n) s = n;
+  return (int)s;
+}
+
+size_t apply_workspace_bytes(int64_t n, int nrhs, int nsplit) {
+  // sd [n][nrhs], f [nrhs][n], part [nsplit][nrhs][n]  (double2 each)
+  return sizeof(double2) * (size_t)n * nrhs * (2 + (size_t)nsplit) + 256;
+}
+
+hipError_t launch_apply_fp64(const Scat &s, const double *x, double *y, int nrhs, int64_t ld, Mode mode,
+                             int nsplit, int rhs_chunk, void *ws, hipStream_t st) {
+  const int64_t n = s.n;
+  double2 *sd = (double2 *)ws;
+  double2 *f = sd + n * nrhs;
+  double2 *part = f + n * nrhs;
+  const double2 *pos = s.pos;
+  const double2 *xc = (const double2 *)x;
+  double2 *yc = (double2 *)y;
+  const unsigned gp = (unsigned)((n * nrhs + kBlock - 1) / kBlock);
+  if (mode == Mode::Forward)
+    prologue_kernel<Mode::Forward><<<gp, kBlock, 0, st>>>(n, nrhs, s.perm, s.w, s.m, xc, ld, s.off, sd, f);
+  else
+    prologue_kernel<Mode::Adjoint><<<gp, kBlock, 0, st>>>(n, nrhs, s.perm, s.w, s.m, xc, ld, s.off, sd, f);
+  const int split_len = (int)((n + nsplit - 1) / nsplit);
+  const bool conj = mode == Mode::Adjoint;
+  // RHS per pass: the largest of 16, 8, 4, 1 that is <= rhs_chunk and divides nrhs
+  int bc = 1;
+  for (int c : {16, 8, 4})
+    if (c <= rhs_chunk && nrhs % c == 0) {
+      bc = c;
+      break;
+    }
+  switch (bc * 2 + (conj ? 1 : 0)) {
+    case 2: launch_far<1, false>(s, pos, sd, nrhs, split_len, nsplit, part, st); break;
+    case 3: launch_far<1, true>(s, pos, sd, nrhs, split_len, nsplit, part, st); break;
+    case 8: launch_far<4, false>(s, pos, sd, nrhs, split_len, nsplit, part, st); break;
+    case 9: launch_far<4, true>(s, pos, sd, nrhs, split_len, nsplit, part, st); break;
+    case 16: launch_far<8, false>(s, pos, sd, nrhs, split_len, nsplit, part, st); break;
+    case 17: launch_far<8, true>(s, pos, sd, nrhs, split_len, nsplit, part, st); break;
+    case 32: launch_far<16, false>(s, pos, sd, nrhs, split_len, nsplit, part, st); break;
+    case 33: launch_far<16, true>(s, pos, sd, nrhs, split_len, nsplit, part, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  dim3 ge((unsigned)((n + kBlock - 1) / kBlock), (unsigned)nrhs);
+  const double k2 = s.k * s.k;
+  if (mode == Mode::Forward)
+    epilogue_kernel<Mode::Forward><<<ge, kBlock, 0, st>>>(n, nrhs, nsplit, part, f, s.rp, s.ci, s.cv, s.w, s.m,
+                                                         s.perm, xc, yc, ld, s.off, k2);
+  else
+    epilogue_kernel<Mode::Adjoint><<<ge, kBlock, 0, st>>>(n, nrhs, nsplit, part, f, s.rpH, s.ciH, s.cvH, s.w,
+                                                         s.m, s.perm, xc, yc, ld, s.off, k2);
+  return hipGetLastError();
+}
+
+void eval_green_host(const double *z2, double *g, int64_t n) {
+  for (int64_t i = 0; i < n; ++i) green(z2[i], g[2 * i], g[2 * i + 1], kHankelTable);
+}
+
+hipError_t launch_eval_green(const double *z2, double *g, int64_t n, int single, hipStream_t st) {
+  (void)single;
+  if (n == 0) return hipSuccess;
+  eval_green_kernel<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(z2, (double2 *)g, n);
+  return hipGetLastError();
+}
+
+}  // namespace lsk

@@ -1,0 +1,190 @@
+// In-register evaluation of the 2-D Helmholtz Green's function G = (i/4) H0^(1)(z).
+//
+// The Green's function is the one of the paper's Section 2 (after eq. Lippmann-Schwinger).
+// Inputs are z^2 = k^2 |x - y|^2 (never z itself: the small-argument branch needs no square
+// root and the others get z, 1/z and z^(-1/2) from one inverse fourth root).  Branches:
+//   z <  ZS : power series of J0 and of Y0 - (2/pi) ln(z/2) J0 in u = z^2/4, own ln;
+//   ZS <= z < ZF : modulus-phase form H0 = M e^{i theta} with two fitted intervals in 1/z;
+//   z >= ZF : modulus-phase form from the even/odd Hankel asymptotic structure in 1/z.
+// e^{i theta} uses a reduction modulo pi (two-constant Cody-Waite with FMA) and minimax
+// sine/cosine on [-pi/2, pi/2]; the parity of the multiple of pi flips the sign.
+// All coefficients are produced by gen_hankel_tables.py and passed in as one HankelTable, so a
+// kernel can keep them in memory read through the scalar data path instead of pinning ~130
+// doubles in vector registers.  Functions are host+device so the same arithmetic can be
+// checked on a CPU; on the device the initial inverse fourth root comes from the
+// single-precision hardware approximations and one Halley step.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "hankel_tables.h"
+
+namespace lsk {
+
+// r * x + c with c a wave-uniform coefficient.  On the device the coefficient stays in its
+// SGPR pair as the third operand of a VOP3 FMA; left to itself the compiler prefers the
+// two-address FMAC form, which first copies every coefficient into a vector register.
+__host__ __device__ __forceinline__ double fma_uniform(double r, double x, double c) {
+#ifdef __HIP_DEVICE_COMPILE__
+  double out;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(out) : "v"(r), "v"(x), "s"(c));
+  return out;
+#else
+  return std::fma(r, x, c);
+#endif
+}
+
+// Horner evaluation, constant term first.  Arr is a double[N] member of a table that may live
+// in any address space (the kernels read it from the constant address space).
+template <class Arr>
+__host__ __device__ __forceinline__ double horner(const Arr &c, double x) {
+  constexpr int N = (int)(sizeof(Arr) / sizeof(double));
+  double r = c[N - 1];
+#pragma unroll
+  for (int i = N - 2; i >= 0; --i) r = fma_uniform(r, x, c[i]);
+  return r;
+}
+
+// s = A^(-1/4), accurate to about one rounding.
+template <class Tab>
+__host__ __device__ __forceinline__ double inv_fourth_root(double A, const Tab &T) {
+#ifdef __HIP_DEVICE_COMPILE__
+  const float af = (float)A;
+  double s = (double)__builtin_amdgcn_rsqf(__builtin_amdgcn_sqrtf(af));
+#else
+  double s = 1.0 / std::sqrt(std::sqrt(A));
+#endif
+  // Halley-type step for (1 - e)^(-1/4) with e = 1 - A s^4: s (1 + e/4 + 5 e^2/32)
+  const double s2 = s * s;
+  const double e = std::fma(-A, s2 * s2, 1.0);
+  const double p = std::fma(e, T.consts[6], 0.25);
+  return std::fma(s * e, p, s);
+}
+
+__host__ __device__ __forceinline__ double rint_d(double x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  return __builtin_rint(x);
+#else
+  return std::nearbyint(x);
+#endif
+}
+
+__host__ __device__ __forceinline__ double fract_d(double x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  return __builtin_amdgcn_fract(x);
+#else
+  return x - std::floor(x);
+#endif
+}
+
+__host__ __device__ __forceinline__ double rcp_d(double x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  double y = __builtin_amdgcn_rcp(x);
+  double e = std::fma(-x, y, 1.0);
+  y = std::fma(y, e, y);
+  e = std::fma(-x, y, 1.0);
+  return std::fma(y, e, y);
+#else
+  return 1.0 / x;
+#endif
+}
+
+// natural logarithm of a positive normal double
+template <class Tab>
+__host__ __device__ __forceinline__ double log_d(double u, const Tab &T) {
+#ifdef __HIP_DEVICE_COMPILE__
+  double m = __builtin_amdgcn_frexp_mant(u);   // [0.5, 1)
+  int e = __builtin_amdgcn_frexp_exp(u);
+#else
+  int e;
+  double m = std::frexp(u, &e);
+#endif
+  const bool lo = m < T.consts[4];
+  m = lo ? m + m : m;
+  e = lo ? e - 1 : e;
+  const double s = (m - 1.0) * rcp_d(m + 1.0);
+  const double s2 = s * s;
+  const double lm = 2.0 * s * horner(T.log_p, s2);
+  return std::fma((double)e, T.consts[3], lm);
+}
+
+// (gre, gim) = M4 e^{i theta} rotated by i, theta = z + ph, M4 = |H0|/4
+template <class Tab>
+__host__ __device__ __forceinline__ void phase_tail(double z, double ph, double M4, double &gre,
+                                                    double &gim, const Tab &T) {
+  const double jf = rint_d((z + ph) * T.consts[2]);
+  double r = std::fma(-jf, T.consts[0], z);
+  r = std::fma(-jf, T.consts[1], r);
+  r = r + ph;
+  // (-1)^j: fract(j/2) is 0 or 1/2
+  const double sg = std::fma(-4.0, fract_d(0.5 * jf), 1.0);
+  const double Ms = M4 * sg;
+  const double r2 = r * r;
+  const double sn = r * horner(T.sin_r, r2);
+  const double cs = horner(T.cos_r, r2);
+  // G = (i/4) H0 = i M4 (cos + i sin) = -M4 sin + i M4 cos
+  gre = -Ms * sn;
+  gim = Ms * cs;
+}
+
+// z >= ZF
+template <class Tab>
+__host__ __device__ __forceinline__ void green_far(double A, double &gre, double &gim,
+                                                   const Tab &T) {
+  const double s = inv_fourth_root(A, T);  // z^(-1/2)
+  const double t = s * s;                  // 1/z
+  const double z = A * t;
+  const double t2 = t * t;
+  const double mod = horner(T.far_mod, t2);
+  const double ph = std::fma(t, horner(T.far_ph, t2), T.consts[5]);
+  phase_tail(z, ph, mod * s, gre, gim, T);
+}
+
+// ZS <= z < ZF
+template <class Tab>
+__host__ __device__ __forceinline__ void green_mid(double A, double &gre, double &gim,
+                                                   const Tab &T) {
+  const double s = inv_fourth_root(A, T);
+  const double t = s * s;
+  const double z = A * t;
+  double mod, ph;
+  if (A < ZM2) {
+    const double x = (t - MID1_TA) * MID1_SCALE;
+    mod = horner(T.mid1_mod, x);
+    ph = horner(T.mid1_ph, x);
+  } else {
+    const double x = (t - MID2_TA) * MID2_SCALE;
+    mod = horner(T.mid2_mod, x);
+    ph = horner(T.mid2_ph, x);
+  }
+  phase_tail(z, ph, mod * s, gre, gim, T);
+}
+
+// 0 < z < ZS
+template <class Tab>
+__host__ __device__ __forceinline__ void green_small(double A, double &gre, double &gim,
+                                                     const Tab &T) {
+  const double u = 0.25 * A;
+  const double j4 = horner(T.small_j, u);  // J0/4
+  const double r4 = horner(T.small_r, u);  // (Y0 - ln(u) J0 / pi)/4
+  const double L = log_d(u, T);
+  // G = (i/4)(J0 + i Y0) = -Y0/4 + i J0/4
+  gre = -std::fma(T.consts[2] * L, j4, r4);
+  gim = j4;
+}
+
+// G = (i/4) H0^(1)(z) for z^2 = A > 0 (any branch)
+template <class Tab>
+__host__ __device__ __forceinline__ void green(double A, double &gre, double &gim,
+                                               const Tab &T) {
+  if (A >= ZF2) {
+    green_far(A, gre, gim, T);
+  } else if (A >= ZS2) {
+    green_mid(A, gre, gim, T);
+  } else {
+    green_small(A, gre, gim, T);
+  }
+}
+
+}  // namespace lsk

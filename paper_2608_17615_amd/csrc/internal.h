@@ -1,0 +1,63 @@
+// Internal definitions shared by the library's translation units (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ls.h"
+
+namespace lsk {
+
+// One source of the single-RHS FP64 far sum: position and weighted density.
+struct alignas(32) Src4 {
+  double x, y, sr, si;
+};
+
+// One scatterer, all device arrays in the internal (sorted) node order.
+struct Scat {
+  int64_t n = 0, off = 0;     // nodes, offset in the concatenated caller vectors
+  double k = 0;
+  int32_t n_sub = 1;
+  double *px = nullptr, *py = nullptr, *w = nullptr;
+  double2 *pos = nullptr;     // (px, py) interleaved, read per source by the far sum
+  double2 *m = nullptr;       // contrast
+  int32_t *perm = nullptr;    // internal index -> caller index (within the scatterer)
+  int64_t nnz = 0;
+  int64_t *rp = nullptr, *rpH = nullptr;
+  int32_t *ci = nullptr, *ciH = nullptr;
+  double2 *cv = nullptr, *cvH = nullptr;
+  std::vector<int32_t> perm_host;   // same as perm, on the host
+};
+
+struct Workspace {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace lsk
+
+struct ls_ctx {
+  std::vector<lsk::Scat> sc;
+  int64_t n_total = 0;
+  int device = 0;
+  ls_options opt{};
+  std::string err;
+  lsk::Workspace ws_apply, ws_solve;
+  std::vector<void *> owned;  // device allocations freed by ls_destroy
+};
+
+namespace lsk {
+
+enum class Mode { Forward, Adjoint };
+
+// apply.hip
+hipError_t launch_apply_fp64(const Scat &s, const double *x, double *y, int nrhs, int64_t ld,
+                             Mode mode, int source_split, int rhs_chunk, void *ws, hipStream_t st);
+size_t apply_workspace_bytes(int64_t n, int nrhs, int source_split);
+hipError_t launch_eval_green(const double *z2, double *g, int64_t n, int single, hipStream_t st);
+void eval_green_host(const double *z2, double *g, int64_t n);
+int auto_source_split(int64_t n, int nrhs_per_launch);
+
+}  // namespace lsk
