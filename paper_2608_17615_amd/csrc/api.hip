@@ -91,6 +91,10 @@ ls_status validate_scatterer(const ls_scatterer &s) {
 
 namespace lsk {
 
+ls_status setup_fail(ls_ctx *h, ls_status st, const char *msg) { return fail(h, st, msg); }
+ls_status build_correction(ls_ctx *h, Scat &sc, const ls_scatterer &s, const std::vector<int32_t> &eord,
+                           hipStream_t st);
+
 // Element order: by subdomain, then along a Hilbert curve through element centroids.
 std::vector<int32_t> element_order(const ls_scatterer &s) {
   const int32_t ne = s.n_elems;
@@ -214,6 +218,51 @@ void ls_destroy(ls_handle h) {
   if (h->ws_solve.ptr) (void)hipFree(h->ws_solve.ptr);
   (void)hipSetDevice(cur);
   delete h;
+}
+
+ls_status ls_setup(const ls_scatterer *s, int32_t n_scatterers, const ls_options *opt, ls_handle *out) {
+  if (!out) return fail(nullptr, LS_ERR_ARG, "out is null");
+  *out = nullptr;
+  if (!s || n_scatterers <= 0) return fail(nullptr, LS_ERR_ARG, "need at least one scatterer");
+  for (int32_t i = 0; i < n_scatterers; ++i) {
+    ls_status st = validate_scatterer(s[i]);
+    if (st != LS_OK) return st;
+    if (s[i].n_curves == 0) return fail(nullptr, LS_ERR_ARG, "ls_setup needs the boundary curves");
+  }
+  int64_t total = 0;
+  for (int32_t i = 0; i < n_scatterers; ++i) total += s[i].n_nodes;
+  if (total > (int64_t)INT32_MAX / 2) return fail(nullptr, LS_ERR_ARG, "too many nodes in total");
+  ls_ctx *h = new ls_ctx();
+  if (opt) h->opt = *opt;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return fail(nullptr, LS_ERR_HIP, "hipGetDevice failed");
+  }
+  hipStream_t st = nullptr;
+  if (hipStreamCreate(&st) != hipSuccess) {
+    delete h;
+    return fail(nullptr, LS_ERR_HIP, "hipStreamCreate failed");
+  }
+  h->sc.resize(n_scatterers);
+  int64_t off = 0;
+  ls_status rc = LS_OK;
+  for (int32_t i = 0; i < n_scatterers && rc == LS_OK; ++i) {
+    Scat &sc = h->sc[i];
+    sc.off = off;
+    off += s[i].n_nodes;
+    const std::vector<int32_t> eord = lsk::element_order(s[i]);
+    rc = lsk::upload_nodes(h, sc, s[i], eord);
+    if (rc == LS_OK) rc = lsk::build_correction(h, sc, s[i], eord, st);
+  }
+  (void)hipStreamDestroy(st);
+  h->n_total = off;
+  if (rc != LS_OK) {
+    g_err = h->err;
+    ls_destroy(h);
+    return rc;
+  }
+  *out = h;
+  return LS_OK;
 }
 
 ls_status ls_setup_from_csr(const ls_scatterer *s, const int64_t *rowptr, const int32_t *col, const double *val,

@@ -3,10 +3,6 @@
 #include "internal.h"
 
 extern "C" {
-ls_status ls_setup(const ls_scatterer *, int32_t, const ls_options *, ls_handle *out) {
-  if (out) *out = nullptr;
-  return LS_ERR_UNSUPPORTED;
-}
 ls_status ls_solve_gmres(ls_handle, const double *, double *, int32_t, int64_t, const ls_solve_opts *,
                          ls_solve_info *, hipStream_t) {
   return LS_ERR_UNSUPPORTED;
