@@ -191,14 +191,16 @@ class Operator:
         if x.dtype != torch.complex128 or not x.is_cuda:
             raise TypeError("vectors must be complex128 CUDA tensors")
         x2 = x.reshape(1, -1) if x.dim() == 1 else x
-        if x2.shape[-1] != self.n or not x2.is_contiguous():
-            raise ValueError(f"expected a contiguous (B, {self.n}) tensor")
-        return x2
+        if x2.dim() != 2 or x2.shape[-1] != self.n:
+            raise ValueError(f"expected a (B, {self.n}) tensor")
+        return x2.contiguous()
 
     def apply(self, x, precision="fp64", adjoint=False, out=None):
         import torch
         x2 = self._cols(x)
-        y = torch.empty_like(x2) if out is None else out.reshape(x2.shape)
+        if out is not None and not (out.is_contiguous() and out.shape == x2.shape and out.dtype == x2.dtype):
+            raise ValueError("out must be a contiguous tensor shaped like x")
+        y = torch.empty_like(x2) if out is None else out
         fn = lib().ls_apply_adjoint if adjoint else lib().ls_apply
         _check(fn(self._h, x2.data_ptr(), y.data_ptr(), x2.shape[0], self.n, _PREC[precision], _stream()), self._h)
         return y.reshape(x.shape)

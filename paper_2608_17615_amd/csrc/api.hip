@@ -215,7 +215,7 @@ void ls_destroy(ls_handle h) {
   (void)hipDeviceSynchronize();
   for (void *p : h->owned) (void)hipFree(p);
   if (h->ws_apply.ptr) (void)hipFree(h->ws_apply.ptr);
-  if (h->ws_solve.ptr) (void)hipFree(h->ws_solve.ptr);
+  lsk::free_solve_ws(h);
   (void)hipSetDevice(cur);
   delete h;
 }
@@ -318,15 +318,13 @@ ls_status ls_setup_from_csr(const ls_scatterer *s, const int64_t *rowptr, const 
   return LS_OK;
 }
 
-static ls_status apply_common(ls_handle h, const double *x, double *y, int32_t nrhs, int64_t ld, ls_precision p,
-                              hipStream_t stream, lsk::Mode mode) {
-  if (!h) return fail(nullptr, LS_ERR_ARG, "null handle");
-  if (nrhs < 0) return fail(h, LS_ERR_ARG, "nrhs < 0");
-  if (nrhs == 0) return LS_OK;
-  if (!x || !y) return fail(h, LS_ERR_ARG, "null vector");
-  if (x == y) return fail(h, LS_ERR_ARG, "x and y must not alias");
-  if (ld < h->n_total) return fail(h, LS_ERR_ARG, "ld < number of nodes");
-  if (p != LS_FP64 && p != LS_MIXED) return fail(h, LS_ERR_ARG, "bad precision");
+}  // extern "C"
+
+namespace lsk {
+
+// Operator application without argument checks (callers validate).
+ls_status apply_op(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, Mode mode, ls_precision p,
+                   hipStream_t stream) {
   if (p == LS_MIXED) return fail(h, LS_ERR_UNSUPPORTED, "mixed precision apply not built");
   size_t need = 0;
   for (const Scat &sc : h->sc) {
@@ -350,6 +348,51 @@ static ls_status apply_common(ls_handle h, const double *x, double *y, int32_t n
     HIPCHK(h, lsk::launch_apply_fp64(sc, x, y, nrhs, ld, mode, nsplit, chunk, h->ws_apply.ptr, stream));
   }
   return LS_OK;
+}
+
+}  // namespace lsk
+
+extern "C" {
+
+static ls_status apply_common(ls_handle h, const double *x, double *y, int32_t nrhs, int64_t ld, ls_precision p,
+                              hipStream_t stream, lsk::Mode mode) {
+  if (!h) return fail(nullptr, LS_ERR_ARG, "null handle");
+  if (nrhs < 0) return fail(h, LS_ERR_ARG, "nrhs < 0");
+  if (nrhs == 0) return LS_OK;
+  if (!x || !y) return fail(h, LS_ERR_ARG, "null vector");
+  if (x == y) return fail(h, LS_ERR_ARG, "x and y must not alias");
+  if (ld < h->n_total) return fail(h, LS_ERR_ARG, "ld < number of nodes");
+  if (p != LS_FP64 && p != LS_MIXED) return fail(h, LS_ERR_ARG, "bad precision");
+  return lsk::apply_op(h, x, y, nrhs, ld, mode, p, stream);
+}
+
+ls_status ls_solve_gmres(ls_handle h, const double *b, double *x, int32_t nrhs, int64_t ld, const ls_solve_opts *o,
+                         ls_solve_info *info, hipStream_t stream) {
+  if (!h) return fail(nullptr, LS_ERR_ARG, "null handle");
+  if (!o) return fail(h, LS_ERR_ARG, "null options");
+  if (nrhs < 0) return fail(h, LS_ERR_ARG, "nrhs < 0");
+  if (nrhs == 0) return LS_OK;
+  if (!b || !x) return fail(h, LS_ERR_ARG, "null vector");
+  if (b == x) return fail(h, LS_ERR_ARG, "b and x must not alias");
+  if (ld < h->n_total) return fail(h, LS_ERR_ARG, "ld < number of nodes");
+  if (!(o->tol > 0) || !std::isfinite(o->tol)) return fail(h, LS_ERR_ARG, "tol must be > 0");
+  if (o->maxit < 1) return fail(h, LS_ERR_ARG, "maxit must be >= 1");
+  if (o->restart < 0) return fail(h, LS_ERR_ARG, "restart < 0");
+  if (o->prec != LS_FP64 && o->prec != LS_MIXED) return fail(h, LS_ERR_ARG, "bad precision");
+  return lsk::solve_gmres(h, b, x, nrhs, ld, *o, info, stream);
+}
+
+ls_status ls_grad_contrast(ls_handle h, const double *u, const double *lam, const double *a, int32_t nrhs,
+                           int64_t ld, double *grad, hipStream_t stream) {
+  if (!h) return fail(nullptr, LS_ERR_ARG, "null handle");
+  if (nrhs < 0) return fail(h, LS_ERR_ARG, "nrhs < 0");
+  if (!u || !lam || !a || !grad) return fail(h, LS_ERR_ARG, "null vector");
+  if (ld < h->n_total) return fail(h, LS_ERR_ARG, "ld < number of nodes");
+  if (nrhs == 0) {
+    HIPCHK(h, hipMemsetAsync(grad, 0, sizeof(double) * h->n_total, stream));
+    return LS_OK;
+  }
+  return lsk::grad_contrast(h, u, lam, a, nrhs, ld, grad, stream);
 }
 
 ls_status ls_apply(ls_handle h, const double *x, double *y, int32_t nrhs, int64_t ld, ls_precision p,

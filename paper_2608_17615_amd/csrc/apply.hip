@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kBlock) void epilogue_kernel(
     ar += p.x;
     ai += p.y;
   }
-  if (M == Mode::Adjoint) {
+  if (M != Mode::Forward) {
     ar *= w[i];
     ai *= w[i];
   }
@@ -155,6 +155,10 @@ __global__ __launch_bounds__(kBlock) void epilogue_kernel(
     ai = ti;
   }
   const int64_t c = (int64_t)b * ld + off + perm[i];
+  if (M == Mode::AdjointPotential) {
+    y[c] = make_double2(ar, ai);
+    return;
+  }
   const double2 xv = x[c];
   y[c] = make_double2(std::fma(k2, ar, xv.x), std::fma(k2, ai, xv.y));
 }
@@ -207,7 +211,7 @@ hipError_t launch_apply_fp64(const Scat &s, const double *x, double *y, int nrhs
   else
     prologue_kernel<Mode::Adjoint><<<gp, kBlock, 0, st>>>(n, nrhs, s.perm, s.w, s.m, xc, ld, s.off, sd, f);
   const int split_len = (int)((n + nsplit - 1) / nsplit);
-  const bool conj = mode == Mode::Adjoint;
+  const bool conj = mode != Mode::Forward;
   // RHS per pass: the largest of 16, 8, 4, 1 that is <= rhs_chunk and divides nrhs
   int bc = 1;
   for (int c : {16, 8, 4})
@@ -231,9 +235,13 @@ hipError_t launch_apply_fp64(const Scat &s, const double *x, double *y, int nrhs
   if (mode == Mode::Forward)
     epilogue_kernel<Mode::Forward><<<ge, kBlock, 0, st>>>(n, nrhs, nsplit, part, f, s.rp, s.ci, s.cv, s.w, s.m,
                                                          s.perm, xc, yc, ld, s.off, k2);
-  else
+  else if (mode == Mode::Adjoint)
     epilogue_kernel<Mode::Adjoint><<<ge, kBlock, 0, st>>>(n, nrhs, nsplit, part, f, s.rpH, s.ciH, s.cvH, s.w,
                                                          s.m, s.perm, xc, yc, ld, s.off, k2);
+  else
+    epilogue_kernel<Mode::AdjointPotential><<<ge, kBlock, 0, st>>>(n, nrhs, nsplit, part, f, s.rpH, s.ciH,
+                                                                  s.cvH, s.w, s.m, s.perm, xc, yc, ld, s.off,
+                                                                  k2);
   return hipGetLastError();
 }
 

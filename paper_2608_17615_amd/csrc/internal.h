@@ -50,7 +50,8 @@ struct ls_ctx {
 
 namespace lsk {
 
-enum class Mode { Forward, Adjoint };
+// Forward: y = L x;  Adjoint: y = L^H x;  AdjointPotential: y = V^H x = W conj(G~) x + C^H x.
+enum class Mode { Forward, Adjoint, AdjointPotential };
 
 // apply.hip
 hipError_t launch_apply_fp64(const Scat &s, const double *x, double *y, int nrhs, int64_t ld,
@@ -58,6 +59,17 @@ hipError_t launch_apply_fp64(const Scat &s, const double *x, double *y, int nrhs
 size_t apply_workspace_bytes(int64_t n, int nrhs, int source_split);
 hipError_t launch_eval_green(const double *z2, double *g, int64_t n, int single, hipStream_t st);
 void eval_green_host(const double *z2, double *g, int64_t n);
+
+// api.hip
+ls_status apply_op(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, Mode mode, ls_precision p,
+                   hipStream_t st);
+ls_status setup_fail(ls_ctx *h, ls_status st, const char *msg);
+// krylov.hip
+ls_status solve_gmres(ls_ctx *h, const double *b, double *x, int nrhs, int64_t ld, const ls_solve_opts &o,
+                      ls_solve_info *info, hipStream_t st);
+ls_status grad_contrast(ls_ctx *h, const double *u, const double *lam, const double *a, int nrhs, int64_t ld,
+                        double *grad, hipStream_t st);
+void free_solve_ws(ls_ctx *h);
 int auto_source_split(int64_t n, int nrhs_per_launch);
 
 }  // namespace lsk

@@ -1,0 +1,106 @@
+"""Device GMRES (FP64) and the contrast gradient against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2608_17615_amd as lsg
+from oracle import farfield as off
+from oracle import krylov as ok
+from oracle import vdim
+from oracle.operator import Operator as OOp
+from tests.gpu_cases import golden_problem, load_case, relmax, scatterer
+from workloads import problems as P
+
+pytestmark = pytest.mark.gpu
+
+
+def _golden_op(name, **kw):
+    p = golden_problem(name)
+    c = load_case(name)
+    return p, c, lsg.Operator(scatterer(p), correction=(c["rowptr"], c["col"], c["val"]), **kw)
+
+
+# (case, tol, bound on the true residual, bound on the distance to dense LU).  After a few
+# hundred Arnoldi steps the true residual of GMRES sits above its recursive estimate by about
+# eps * ||L|| ||x|| * (steps), so the k = 20 case is run at 1e-12 with a 1e-11 residual bound.
+@pytest.mark.parametrize("name,tol,rbound,ebound", [("disk2500", 1e-13, 2e-13, 1e-11),
+                                                     ("twomat1040", 1e-12, 1e-11, 1e-10),
+                                                     ("absorb900", 1e-13, 2e-13, 1e-11)])
+def test_gmres_matches_dense_lu(name, tol, rbound, ebound):
+    p, c, op = _golden_op(name)
+    b = torch.tensor(c["b"], device="cuda")
+    x, info = op.solve(b, tol=tol, maxit=800)
+    e = relmax(x.cpu().numpy(), c["u"])
+    print(f"{name}: iters {info['iters']} relres {info['relres']} vs LU {e:.3e}", flush=True)
+    assert info["converged"] and np.all(info["relres"] <= rbound)
+    assert e <= ebound
+
+
+def test_restart_and_initial_guess():
+    p, c, op = _golden_op("disk2500")
+    b = torch.tensor(c["b"], device="cuda")
+    x1, i1 = op.solve(b, tol=1e-12, maxit=2000)
+    lib = lsg.lib()
+    # restarted GMRES through the raw ABI reaches the same solution
+    import ctypes
+    xr = torch.zeros_like(b)
+    iters = np.zeros(2, np.int32)
+    rel = np.zeros(2)
+    o = lsg._SolveOpts(1e-12, 4000, 30, 0, 0, 0, 0, 0.0)
+    inf = lsg._SolveInfo(iters.ctypes.data, rel.ctypes.data, 0, 0, 0.0)
+    st = lib.ls_solve_gmres(op._h, b.data_ptr(), xr.data_ptr(), 2, op.n, ctypes.byref(o), ctypes.byref(inf),
+                            lsg._stream())
+    torch.cuda.synchronize()
+    assert st == 0 and np.all(rel <= 1e-12)
+    assert relmax(xr.cpu().numpy(), x1.cpu().numpy()) <= 1e-10
+    # a good initial guess converges immediately
+    x2, i2 = op.solve(b, tol=1e-10, maxit=50, x0=x1)
+    assert np.all(i2["iters"] <= 1) and i2["converged"]
+
+
+def test_not_converged_and_nonfinite():
+    p, c, op = _golden_op("disk2500")
+    b = torch.tensor(c["b"], device="cuda")
+    x, info = op.solve(b, tol=1e-14, maxit=3)
+    assert not info["converged"] and np.all(info["iters"] == 3)
+    bad = b.clone()
+    bad[0, 5] = float("nan")
+    with pytest.raises(lsg.LSError) as ei:
+        op.solve(bad, tol=1e-8, maxit=10)
+    assert ei.value.status == -5
+
+
+def test_adjoint_solve_matches_dense():
+    p, c, op = _golden_op("twomat1040")
+    C = vdim.correction_matrix  # noqa: F841  (the golden C is used)
+    import scipy.sparse as sp
+    Co = sp.csr_matrix((c["val"], c["col"], c["rowptr"]), shape=(p.n_nodes, p.n_nodes))
+    oop = OOp(p.mesh, p.k, p.m, Co)
+    rhs = P.random_vectors(p.n_nodes, 1, 9)
+    lam_ref = ok.lu_solve(oop.dense().conj().T, rhs)
+    lam, info = op.solve(torch.tensor(rhs, device="cuda"), tol=1e-13, maxit=800, adjoint=True)
+    assert info["converged"]
+    assert relmax(lam.cpu().numpy(), lam_ref) <= 1e-11
+
+
+def test_gradient_matches_oracle_adjoint():
+    """grad_j = sum_d Re[conj(a - k^2 V^H lam) u] with forward and adjoint solves on the GPU,
+    against the oracle's dense adjoint gradient (same C, same data)."""
+    p = P.disk_problem(3, 5.0, 1.8, directions=[0.0, 2.0])
+    p.m = p.m + 0.05 * np.sin(3 * p.mesh.x)
+    C = vdim.correction_matrix(p.mesh, p.k)
+    oop = OOp(p.mesh, p.k, p.m, C)
+    A = off.farfield_matrix(p.mesh, p.k, P.receivers(16))
+    b = p.incident()
+    u_ref = ok.lu_solve(oop.dense(), b)
+    data = off.farfield(A, p.m + 0.02, u_ref)
+    J_ref, g_ref, a_ref, lam_ref = off.adjoint_gradient(oop, A, u_ref, data)
+    op = lsg.Operator(scatterer(p), correction=(C.indptr, C.indices, C.data))
+    u, _ = op.solve(torch.tensor(b, device="cuda"), tol=1e-13, maxit=500)
+    r = off.farfield(A, p.m, u.cpu().numpy()) - data
+    a = (A.conj().T @ r.T).T
+    lam, _ = op.solve(torch.tensor(np.conj(p.m)[None, :] * a, device="cuda"), tol=1e-13, maxit=500, adjoint=True)
+    g = op.grad_contrast(u, lam, torch.tensor(a, device="cuda")).cpu().numpy()
+    e = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+    print(f"gradient rel err {e:.3e}", flush=True)
+    assert e <= 1e-10
