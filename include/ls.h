@@ -157,6 +157,18 @@ ls_status ls_eval_green(const double *z2, double *g, int64_t n, int32_t single, 
 /* Same evaluation compiled for the host CPU (host pointers), for checks without a GPU. */
 ls_status ls_eval_green_host(const double *z2, double *g, int64_t n);
 
+/* Kernel timing: when enabled, HIP events are recorded on the caller's stream around every
+ * far-sum kernel launch and around every operator application; ls_profile_query synchronises
+ * those events and returns the totals (milliseconds), optionally resetting them. */
+typedef struct {
+  int64_t far_launches;
+  double far_ms;
+  int64_t apply_calls;
+  double apply_ms;
+} ls_profile;
+ls_status ls_profile_enable(ls_handle h, int32_t on);
+ls_status ls_profile_query(ls_handle h, ls_profile *out, int32_t reset);
+
 void ls_destroy(ls_handle h);
 const char *ls_status_str(ls_status s);
 const char *ls_last_error(ls_handle h);

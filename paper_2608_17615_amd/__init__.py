@@ -45,6 +45,11 @@ class _Scatterer(ctypes.Structure):
                 ("n_curves", ctypes.c_int32), ("pad_", ctypes.c_int32), ("curves", ctypes.c_void_p)]
 
 
+class _Profile(ctypes.Structure):
+    _fields_ = [("far_launches", ctypes.c_int64), ("far_ms", ctypes.c_double), ("apply_calls", ctypes.c_int64),
+                ("apply_ms", ctypes.c_double)]
+
+
 class _Options(ctypes.Structure):
     _fields_ = [("source_split", ctypes.c_int32), ("rhs_chunk", ctypes.c_int32),
                 ("mixed_tile", ctypes.c_int32), ("n_threads_host", ctypes.c_int32)]
@@ -85,6 +90,8 @@ def lib():
         L.ls_export_correction.argtypes = [vp, i32, vp, vp, vp]
         L.ls_eval_green.argtypes = [vp, vp, i64, i32, vp]
         L.ls_eval_green_host.argtypes = [vp, vp, i64]
+        L.ls_profile_enable.argtypes = [vp, i32]
+        L.ls_profile_query.argtypes = [vp, vp, i32]
         L.ls_destroy.argtypes = [vp]
         L.ls_destroy.restype = None
         L.ls_status_str.argtypes = [i32]
@@ -236,6 +243,16 @@ class Operator:
         _check(lib().ls_grad_contrast(self._h, u2.data_ptr(), l2.data_ptr(), a2.data_ptr(), u2.shape[0], self.n,
                                       g.data_ptr(), _stream()), self._h)
         return g
+
+    def profile(self, enable=None, reset=False):
+        """Turn kernel timing on/off (enable=True/False) or read the totals (enable=None)."""
+        if enable is not None:
+            _check(lib().ls_profile_enable(self._h, int(bool(enable))), self._h)
+            return None
+        p = _Profile()
+        _check(lib().ls_profile_query(self._h, ctypes.byref(p), int(bool(reset))), self._h)
+        return {"far_launches": p.far_launches, "far_ms": p.far_ms, "apply_calls": p.apply_calls,
+                "apply_ms": p.apply_ms}
 
     def correction_nnz(self, s=0):
         return int(lib().ls_correction_nnz(self._h, s))

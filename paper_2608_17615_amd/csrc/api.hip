@@ -216,6 +216,8 @@ void ls_destroy(ls_handle h) {
   for (void *p : h->owned) (void)hipFree(p);
   if (h->ws_apply.ptr) (void)hipFree(h->ws_apply.ptr);
   lsk::free_solve_ws(h);
+  for (hipEvent_t e : h->ev_far) (void)hipEventDestroy(e);
+  for (hipEvent_t e : h->ev_apply) (void)hipEventDestroy(e);
   (void)hipSetDevice(cur);
   delete h;
 }
@@ -342,10 +344,28 @@ ls_status apply_op(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, 
     if (hipMalloc(&h->ws_apply.ptr, need) != hipSuccess) return fail(h, LS_ERR_ALLOC, "workspace allocation failed");
     h->ws_apply.bytes = need;
   }
+  hipEvent_t a0 = nullptr, a1 = nullptr;
+  if (h->prof) {
+    HIPCHK(h, hipEventCreate(&a0));
+    HIPCHK(h, hipEventCreate(&a1));
+    HIPCHK(h, hipEventRecord(a0, stream));
+  }
   for (const Scat &sc : h->sc) {
     const int nsplit = h->opt.source_split > 0 ? h->opt.source_split : lsk::auto_source_split(sc.n, nrhs);
     const int chunk = h->opt.rhs_chunk > 0 ? h->opt.rhs_chunk : 1;
-    HIPCHK(h, lsk::launch_apply_fp64(sc, x, y, nrhs, ld, mode, nsplit, chunk, h->ws_apply.ptr, stream));
+    hipEvent_t f0 = nullptr, f1 = nullptr;
+    if (h->prof) {
+      HIPCHK(h, hipEventCreate(&f0));
+      HIPCHK(h, hipEventCreate(&f1));
+      h->ev_far.push_back(f0);
+      h->ev_far.push_back(f1);
+    }
+    HIPCHK(h, lsk::launch_apply_fp64(sc, x, y, nrhs, ld, mode, nsplit, chunk, h->ws_apply.ptr, stream, f0, f1));
+  }
+  if (h->prof) {
+    HIPCHK(h, hipEventRecord(a1, stream));
+    h->ev_apply.push_back(a0);
+    h->ev_apply.push_back(a1);
   }
   return LS_OK;
 }
@@ -403,6 +423,38 @@ ls_status ls_apply(ls_handle h, const double *x, double *y, int32_t nrhs, int64_
 ls_status ls_apply_adjoint(ls_handle h, const double *x, double *y, int32_t nrhs, int64_t ld, ls_precision p,
                            hipStream_t stream) {
   return apply_common(h, x, y, nrhs, ld, p, stream, lsk::Mode::Adjoint);
+}
+
+ls_status ls_profile_enable(ls_handle h, int32_t on) {
+  if (!h) return fail(nullptr, LS_ERR_ARG, "null handle");
+  h->prof = on != 0;
+  return LS_OK;
+}
+
+ls_status ls_profile_query(ls_handle h, ls_profile *out, int32_t reset) {
+  if (!h || !out) return fail(h, LS_ERR_ARG, "null argument");
+  out->far_launches = (int64_t)h->ev_far.size() / 2;
+  out->apply_calls = (int64_t)h->ev_apply.size() / 2;
+  out->far_ms = out->apply_ms = 0.0;
+  for (size_t i = 0; i + 1 < h->ev_far.size(); i += 2) {
+    float ms = 0.f;
+    HIPCHK(h, hipEventSynchronize(h->ev_far[i + 1]));
+    HIPCHK(h, hipEventElapsedTime(&ms, h->ev_far[i], h->ev_far[i + 1]));
+    out->far_ms += ms;
+  }
+  for (size_t i = 0; i + 1 < h->ev_apply.size(); i += 2) {
+    float ms = 0.f;
+    HIPCHK(h, hipEventSynchronize(h->ev_apply[i + 1]));
+    HIPCHK(h, hipEventElapsedTime(&ms, h->ev_apply[i], h->ev_apply[i + 1]));
+    out->apply_ms += ms;
+  }
+  if (reset) {
+    for (hipEvent_t e : h->ev_far) (void)hipEventDestroy(e);
+    for (hipEvent_t e : h->ev_apply) (void)hipEventDestroy(e);
+    h->ev_far.clear();
+    h->ev_apply.clear();
+  }
+  return LS_OK;
 }
 
 int64_t ls_num_nodes(ls_handle h) { return h ? h->n_total : -1; }

@@ -197,7 +197,8 @@ size_t apply_workspace_bytes(int64_t n, int nrhs, int nsplit) {
 }
 
 hipError_t launch_apply_fp64(const Scat &s, const double *x, double *y, int nrhs, int64_t ld, Mode mode,
-                             int nsplit, int rhs_chunk, void *ws, hipStream_t st) {
+                             int nsplit, int rhs_chunk, void *ws, hipStream_t st, hipEvent_t far_start,
+                             hipEvent_t far_stop) {
   const int64_t n = s.n;
   double2 *sd = (double2 *)ws;
   double2 *f = sd + n * nrhs;
@@ -219,6 +220,7 @@ hipError_t launch_apply_fp64(const Scat &s, const double *x, double *y, int nrhs
       bc = c;
       break;
     }
+  if (far_start) (void)hipEventRecord(far_start, st);
   switch (bc * 2 + (conj ? 1 : 0)) {
     case 2: launch_far<1, false>(s, pos, sd, nrhs, split_len, nsplit, part, st); break;
     case 3: launch_far<1, true>(s, pos, sd, nrhs, split_len, nsplit, part, st); break;
@@ -230,6 +232,7 @@ hipError_t launch_apply_fp64(const Scat &s, const double *x, double *y, int nrhs
     case 33: launch_far<16, true>(s, pos, sd, nrhs, split_len, nsplit, part, st); break;
     default: return hipErrorInvalidValue;
   }
+  if (far_stop) (void)hipEventRecord(far_stop, st);
   dim3 ge((unsigned)((n + kBlock - 1) / kBlock), (unsigned)nrhs);
   const double k2 = s.k * s.k;
   if (mode == Mode::Forward)

@@ -40,6 +40,8 @@ struct Workspace {
 
 struct ls_ctx {
   std::vector<lsk::Scat> sc;
+  bool prof = false;
+  std::vector<hipEvent_t> ev_far, ev_apply;   // start/stop pairs, in launch order
   int64_t n_total = 0;
   int device = 0;
   ls_options opt{};
@@ -55,7 +57,8 @@ enum class Mode { Forward, Adjoint, AdjointPotential };
 
 // apply.hip
 hipError_t launch_apply_fp64(const Scat &s, const double *x, double *y, int nrhs, int64_t ld,
-                             Mode mode, int source_split, int rhs_chunk, void *ws, hipStream_t st);
+                             Mode mode, int source_split, int rhs_chunk, void *ws, hipStream_t st,
+                             hipEvent_t far_start = nullptr, hipEvent_t far_stop = nullptr);
 size_t apply_workspace_bytes(int64_t n, int nrhs, int source_split);
 hipError_t launch_eval_green(const double *z2, double *g, int64_t n, int single, hipStream_t st);
 void eval_green_host(const double *z2, double *g, int64_t n);
