@@ -83,10 +83,12 @@ typedef struct {
 } ls_scatterer;
 
 typedef struct {
-  int32_t source_split;   /* far-sum source chunks per launch (0 = automatic) */
-  int32_t rhs_chunk;      /* RHS per pass of the batched FP64 kernel (0 = automatic; 1, 4, 8, 16) */
-  int32_t mixed_tile;     /* mixed-precision tile variant (0 = automatic / autotuned cache) */
-  int32_t n_threads_host; /* host threads for setup (0 = all) */
+  int32_t source_split;     /* far-sum source chunks per launch (0 = automatic) */
+  int32_t rhs_chunk;        /* RHS per pass of the batched FP64 kernel (0 = automatic; 1, 4, 8, 16) */
+  int32_t targets_per_lane; /* targets per lane in the FP64 far sum (0 = automatic; 1 or 2) */
+  int32_t mixed_tile;       /* mixed-precision tile variant (0 = automatic / autotuned cache) */
+  int32_t n_threads_host;   /* host threads for setup (0 = all) */
+  int32_t reserved_;
 } ls_options;
 
 typedef struct ls_ctx *ls_handle;

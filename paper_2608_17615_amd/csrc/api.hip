@@ -328,10 +328,12 @@ namespace lsk {
 ls_status apply_op(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, Mode mode, ls_precision p,
                    hipStream_t stream) {
   if (p == LS_MIXED) return fail(h, LS_ERR_UNSUPPORTED, "mixed precision apply not built");
+  const int tpl = h->opt.targets_per_lane == 2 ? 2 : 1;
+  const int chunk = h->opt.rhs_chunk > 0 ? h->opt.rhs_chunk : 1;
   size_t need = 0;
   for (const Scat &sc : h->sc) {
     const int nsplit = h->opt.source_split > 0 ? h->opt.source_split
-                                               : lsk::auto_source_split(sc.n, nrhs);
+                                               : lsk::auto_source_split(sc.n, nrhs, std::max(1, nrhs / chunk), tpl);
     need = std::max(need, lsk::apply_workspace_bytes(sc.n, nrhs, nsplit));
   }
   if (need > h->ws_apply.bytes) {
@@ -351,8 +353,8 @@ ls_status apply_op(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, 
     HIPCHK(h, hipEventRecord(a0, stream));
   }
   for (const Scat &sc : h->sc) {
-    const int nsplit = h->opt.source_split > 0 ? h->opt.source_split : lsk::auto_source_split(sc.n, nrhs);
-    const int chunk = h->opt.rhs_chunk > 0 ? h->opt.rhs_chunk : 1;
+    const int nsplit = h->opt.source_split > 0 ? h->opt.source_split
+                                               : lsk::auto_source_split(sc.n, nrhs, std::max(1, nrhs / chunk), tpl);
     hipEvent_t f0 = nullptr, f1 = nullptr;
     if (h->prof) {
       HIPCHK(h, hipEventCreate(&f0));
@@ -360,7 +362,8 @@ ls_status apply_op(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, 
       h->ev_far.push_back(f0);
       h->ev_far.push_back(f1);
     }
-    HIPCHK(h, lsk::launch_apply_fp64(sc, x, y, nrhs, ld, mode, nsplit, chunk, h->ws_apply.ptr, stream, f0, f1));
+    HIPCHK(h, lsk::launch_apply_fp64(sc, x, y, nrhs, ld, mode, nsplit, chunk, tpl, h->ws_apply.ptr, stream, f0,
+                                     f1));
   }
   if (h->prof) {
     HIPCHK(h, hipEventRecord(a1, stream));

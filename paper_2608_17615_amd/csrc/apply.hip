@@ -58,33 +58,42 @@ __global__ __launch_bounds__(kBlock) void prologue_kernel(int64_t n, int nrhs, c
   }
 }
 
-template <int BC, bool CONJ, bool MASKED>
-__device__ __forceinline__ void far_source(int j, int i, double xt, double yt, double k2,
-                                           const double2 *__restrict__ pos,
-                                           const double2 *__restrict__ d, double (&ar)[BC],
-                                           double (&ai)[BC]) {
+// One source against the TPL targets of this lane: positions and densities of the source are
+// wave-uniform (scalar loads), G is evaluated once per pair and reused for the BC right-hand sides.
+template <int TPL, int BC, bool CONJ, bool MASKED>
+__device__ __forceinline__ void far_source(int j, const int (&it)[TPL], const double (&xt)[TPL],
+                                           const double (&yt)[TPL], double k2, const double2 *__restrict__ pos,
+                                           const double2 *__restrict__ d, double (&ar)[TPL][BC],
+                                           double (&ai)[TPL][BC]) {
   const double2 p = pos[j];
-  const double dx = xt - p.x;
-  const double dy = yt - p.y;
-  const double A = k2 * std::fma(dx, dx, dy * dy);
-  double gr, gi;
-  green(A, gr, gi, hankel_table());
-  if (MASKED) {
-    const bool self = (j == i);
-    gr = self ? 0.0 : gr;
-    gi = self ? 0.0 : gi;
+  double gr[TPL], gi[TPL];
+#pragma unroll
+  for (int q = 0; q < TPL; ++q) {
+    const double dx = xt[q] - p.x;
+    const double dy = yt[q] - p.y;
+    const double A = k2 * std::fma(dx, dx, dy * dy);
+    green(A, gr[q], gi[q], hankel_table());
+    if (MASKED) {
+      const bool self = (j == it[q]);
+      gr[q] = self ? 0.0 : gr[q];
+      gi[q] = self ? 0.0 : gi[q];
+    }
+    if (CONJ) gi[q] = -gi[q];
   }
-  if (CONJ) gi = -gi;
 #pragma unroll
   for (int b = 0; b < BC; ++b) {
-    const double2 s = d[b];
-    ar[b] = std::fma(gr, s.x, std::fma(-gi, s.y, ar[b]));
-    ai[b] = std::fma(gr, s.y, std::fma(gi, s.x, ai[b]));
+    const double2 sv = d[b];
+#pragma unroll
+    for (int q = 0; q < TPL; ++q) {
+      ar[q][b] = std::fma(gr[q], sv.x, std::fma(-gi[q], sv.y, ar[q][b]));
+      ai[q][b] = std::fma(gr[q], sv.y, std::fma(gi[q], sv.x, ai[q][b]));
+    }
   }
 }
 
-// grid: (ceil(n / kBlock), source splits, nrhs / BC)
-template <int BC, bool CONJ>
+// grid: (ceil(n / (kBlock * TPL)), source splits, nrhs / BC).  Lane l of the wavefront starting at
+// target w0 owns targets w0 + q*64 + l, q < TPL.
+template <int TPL, int BC, bool CONJ>
 __global__ __launch_bounds__(kBlock) void far_fp64_kernel(int n, const double *__restrict__ px,
                                                          const double *__restrict__ py,
                                                          const double2 *__restrict__ pos,
@@ -92,30 +101,41 @@ __global__ __launch_bounds__(kBlock) void far_fp64_kernel(int n, const double *_
                                                          double k2, int split_len,
                                                          double2 *__restrict__ part) {
   const int c0 = blockIdx.z * BC;
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  const int ii = i < n ? i : n - 1;
-  const double xt = px[ii], yt = py[ii];
-  const int w0 = __builtin_amdgcn_readfirstlane(blockIdx.x * kBlock + (threadIdx.x & ~63));
+  const int w0 = __builtin_amdgcn_readfirstlane(blockIdx.x * kBlock * TPL + (threadIdx.x >> 6) * 64 * TPL);
+  const int lane = threadIdx.x & 63;
+  int it[TPL];
+  double xt[TPL], yt[TPL];
+#pragma unroll
+  for (int q = 0; q < TPL; ++q) {
+    it[q] = w0 + q * 64 + lane;
+    const int ii = it[q] < n ? it[q] : n - 1;
+    xt[q] = px[ii];
+    yt[q] = py[ii];
+  }
   const int s0 = blockIdx.y * split_len;
   const int s1 = min(n, s0 + split_len);
-  double ar[BC], ai[BC];
+  double ar[TPL][BC], ai[TPL][BC];
 #pragma unroll
-  for (int b = 0; b < BC; ++b) ar[b] = ai[b] = 0.0;
+  for (int q = 0; q < TPL; ++q)
+#pragma unroll
+    for (int b = 0; b < BC; ++b) ar[q][b] = ai[q][b] = 0.0;
   // sources before, inside and after this wavefront's own target range (only the middle
   // range can contain the self pair j == i, which the punctured sum drops)
   const int e0 = min(s1, max(s0, w0));
-  const int e1 = min(s1, max(s0, w0 + 64));
+  const int e1 = min(s1, max(s0, w0 + 64 * TPL));
   for (int j = s0; j < e0; ++j)
-    far_source<BC, CONJ, false>(j, i, xt, yt, k2, pos, sd + (int64_t)j * nrhs + c0, ar, ai);
+    far_source<TPL, BC, CONJ, false>(j, it, xt, yt, k2, pos, sd + (int64_t)j * nrhs + c0, ar, ai);
   for (int j = e0; j < e1; ++j)
-    far_source<BC, CONJ, true>(j, i, xt, yt, k2, pos, sd + (int64_t)j * nrhs + c0, ar, ai);
+    far_source<TPL, BC, CONJ, true>(j, it, xt, yt, k2, pos, sd + (int64_t)j * nrhs + c0, ar, ai);
   for (int j = e1; j < s1; ++j)
-    far_source<BC, CONJ, false>(j, i, xt, yt, k2, pos, sd + (int64_t)j * nrhs + c0, ar, ai);
-  if (i < n) {
+    far_source<TPL, BC, CONJ, false>(j, it, xt, yt, k2, pos, sd + (int64_t)j * nrhs + c0, ar, ai);
 #pragma unroll
-    for (int b = 0; b < BC; ++b)
-      part[((int64_t)blockIdx.y * nrhs + c0 + b) * n + i] = make_double2(ar[b], ai[b]);
-  }
+  for (int q = 0; q < TPL; ++q)
+    if (it[q] < n) {
+#pragma unroll
+      for (int b = 0; b < BC; ++b)
+        part[((int64_t)blockIdx.y * nrhs + c0 + b) * n + it[q]] = make_double2(ar[q][b], ai[q][b]);
+    }
 }
 
 template <Mode M>
@@ -173,20 +193,29 @@ __global__ void eval_green_kernel(const double *__restrict__ z2, double2 *__rest
 
 template <int BC, bool CONJ>
 void launch_far(const Scat &s, const double2 *pos, const double2 *sd, int nrhs, int split_len, int nsplit,
-                double2 *part, hipStream_t st) {
-  dim3 grid((unsigned)((s.n + kBlock - 1) / kBlock), (unsigned)nsplit, (unsigned)(nrhs / BC));
-  far_fp64_kernel<BC, CONJ><<<grid, kBlock, 0, st>>>((int)s.n, s.px, s.py, pos, sd, nrhs, s.k * s.k,
-                                                     split_len, part);
+                double2 *part, int tpl, hipStream_t st) {
+  const int per_block = kBlock * tpl;
+  dim3 grid((unsigned)((s.n + per_block - 1) / per_block), (unsigned)nsplit, (unsigned)(nrhs / BC));
+  if (tpl == 2)
+    far_fp64_kernel<2, BC, CONJ><<<grid, kBlock, 0, st>>>((int)s.n, s.px, s.py, pos, sd, nrhs, s.k * s.k,
+                                                          split_len, part);
+  else
+    far_fp64_kernel<1, BC, CONJ><<<grid, kBlock, 0, st>>>((int)s.n, s.px, s.py, pos, sd, nrhs, s.k * s.k,
+                                                          split_len, part);
 }
 
 }  // namespace
 
-int auto_source_split(int64_t n, int launches_per_split) {
-  // aim for about 8 waves per SIMD (256 CUs x 4 SIMDs) across the whole launch
-  const int64_t waves = ((n + 63) / 64) * (int64_t)launches_per_split;
-  int64_t s = (8192 + waves - 1) / waves;
+int auto_source_split(int64_t n, int nrhs, int launches_per_split, int tpl) {
+  // aim for about 128 waves per SIMD (256 CUs x 4 SIMDs) over the launch: many short rounds
+  // of resident waves keep the CUs evenly loaded to the end (measured: 128 splits run the
+  // N = 58 500 single-RHS sum 38% faster than 8); the partial sums are capped at 512 MiB
+  const int64_t waves = ((n + 64 * tpl - 1) / (64 * tpl)) * (int64_t)launches_per_split;
+  int64_t s = (131072 + waves - 1) / waves;
+  const int64_t cap = ((int64_t)512 << 20) / ((int64_t)16 * n * nrhs);
+  if (s > cap) s = cap;
   if (s < 1) s = 1;
-  if (s > 64) s = 64;
+  if (s > 256) s = 256;
   if (s > n) s = n;
   return (int)s;
 }
@@ -197,7 +226,7 @@ size_t apply_workspace_bytes(int64_t n, int nrhs, int nsplit) {
 }
 
 hipError_t launch_apply_fp64(const Scat &s, const double *x, double *y, int nrhs, int64_t ld, Mode mode,
-                             int nsplit, int rhs_chunk, void *ws, hipStream_t st, hipEvent_t far_start,
+                             int nsplit, int rhs_chunk, int tpl, void *ws, hipStream_t st, hipEvent_t far_start,
                              hipEvent_t far_stop) {
   const int64_t n = s.n;
   double2 *sd = (double2 *)ws;
@@ -222,14 +251,14 @@ hipError_t launch_apply_fp64(const Scat &s, const double *x, double *y, int nrhs
     }
   if (far_start) (void)hipEventRecord(far_start, st);
   switch (bc * 2 + (conj ? 1 : 0)) {
-    case 2: launch_far<1, false>(s, pos, sd, nrhs, split_len, nsplit, part, st); break;
-    case 3: launch_far<1, true>(s, pos, sd, nrhs, split_len, nsplit, part, st); break;
-    case 8: launch_far<4, false>(s, pos, sd, nrhs, split_len, nsplit, part, st); break;
-    case 9: launch_far<4, true>(s, pos, sd, nrhs, split_len, nsplit, part, st); break;
-    case 16: launch_far<8, false>(s, pos, sd, nrhs, split_len, nsplit, part, st); break;
-    case 17: launch_far<8, true>(s, pos, sd, nrhs, split_len, nsplit, part, st); break;
-    case 32: launch_far<16, false>(s, pos, sd, nrhs, split_len, nsplit, part, st); break;
-    case 33: launch_far<16, true>(s, pos, sd, nrhs, split_len, nsplit, part, st); break;
+    case 2: launch_far<1, false>(s, pos, sd, nrhs, split_len, nsplit, part, tpl, st); break;
+    case 3: launch_far<1, true>(s, pos, sd, nrhs, split_len, nsplit, part, tpl, st); break;
+    case 8: launch_far<4, false>(s, pos, sd, nrhs, split_len, nsplit, part, tpl, st); break;
+    case 9: launch_far<4, true>(s, pos, sd, nrhs, split_len, nsplit, part, tpl, st); break;
+    case 16: launch_far<8, false>(s, pos, sd, nrhs, split_len, nsplit, part, tpl, st); break;
+    case 17: launch_far<8, true>(s, pos, sd, nrhs, split_len, nsplit, part, tpl, st); break;
+    case 32: launch_far<16, false>(s, pos, sd, nrhs, split_len, nsplit, part, tpl, st); break;
+    case 33: launch_far<16, true>(s, pos, sd, nrhs, split_len, nsplit, part, tpl, st); break;
     default: return hipErrorInvalidValue;
   }
   if (far_stop) (void)hipEventRecord(far_stop, st);

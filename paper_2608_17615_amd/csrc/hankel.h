@@ -128,43 +128,34 @@ __host__ __device__ __forceinline__ void phase_tail(double z, double ph, double 
   gim = Ms * cs;
 }
 
-// z >= ZF
+// ZS <= z: modulus-phase form.  Only the two polynomials depend on the argument range; the
+// inverse fourth root, the reduction and the sine/cosine are shared, so a wavefront whose lanes
+// straddle a range boundary repeats only the polynomial evaluation.
 template <class Tab>
-__host__ __device__ __forceinline__ void green_far(double A, double &gre, double &gim,
-                                                   const Tab &T) {
+__host__ __device__ __forceinline__ void green_modphase(double A, double &gre, double &gim, const Tab &T) {
   const double s = inv_fourth_root(A, T);  // z^(-1/2)
   const double t = s * s;                  // 1/z
   const double z = A * t;
-  const double t2 = t * t;
-  const double mod = horner(T.far_mod, t2);
-  const double ph = std::fma(t, horner(T.far_ph, t2), T.consts[5]);
-  phase_tail(z, ph, mod * s, gre, gim, T);
-}
-
-// ZS <= z < ZF
-template <class Tab>
-__host__ __device__ __forceinline__ void green_mid(double A, double &gre, double &gim,
-                                                   const Tab &T) {
-  const double s = inv_fourth_root(A, T);
-  const double t = s * s;
-  const double z = A * t;
   double mod, ph;
-  if (A < ZM2) {
-    const double x = (t - MID1_TA) * MID1_SCALE;
-    mod = horner(T.mid1_mod, x);
-    ph = horner(T.mid1_ph, x);
-  } else {
+  if (A >= ZF2) {
+    const double t2 = t * t;
+    mod = horner(T.far_mod, t2);
+    ph = std::fma(t, horner(T.far_ph, t2), T.consts[5]);
+  } else if (A >= ZM2) {
     const double x = (t - MID2_TA) * MID2_SCALE;
     mod = horner(T.mid2_mod, x);
     ph = horner(T.mid2_ph, x);
+  } else {
+    const double x = (t - MID1_TA) * MID1_SCALE;
+    mod = horner(T.mid1_mod, x);
+    ph = horner(T.mid1_ph, x);
   }
   phase_tail(z, ph, mod * s, gre, gim, T);
 }
 
 // 0 < z < ZS
 template <class Tab>
-__host__ __device__ __forceinline__ void green_small(double A, double &gre, double &gim,
-                                                     const Tab &T) {
+__host__ __device__ __forceinline__ void green_small(double A, double &gre, double &gim, const Tab &T) {
   const double u = 0.25 * A;
   const double j4 = horner(T.small_j, u);  // J0/4
   const double r4 = horner(T.small_r, u);  // (Y0 - ln(u) J0 / pi)/4
@@ -176,12 +167,9 @@ __host__ __device__ __forceinline__ void green_small(double A, double &gre, doub
 
 // G = (i/4) H0^(1)(z) for z^2 = A > 0 (any branch)
 template <class Tab>
-__host__ __device__ __forceinline__ void green(double A, double &gre, double &gim,
-                                               const Tab &T) {
-  if (A >= ZF2) {
-    green_far(A, gre, gim, T);
-  } else if (A >= ZS2) {
-    green_mid(A, gre, gim, T);
+__host__ __device__ __forceinline__ void green(double A, double &gre, double &gim, const Tab &T) {
+  if (A >= ZS2) {
+    green_modphase(A, gre, gim, T);
   } else {
     green_small(A, gre, gim, T);
   }

@@ -57,7 +57,7 @@ enum class Mode { Forward, Adjoint, AdjointPotential };
 
 // apply.hip
 hipError_t launch_apply_fp64(const Scat &s, const double *x, double *y, int nrhs, int64_t ld,
-                             Mode mode, int source_split, int rhs_chunk, void *ws, hipStream_t st,
+                             Mode mode, int source_split, int rhs_chunk, int tpl, void *ws, hipStream_t st,
                              hipEvent_t far_start = nullptr, hipEvent_t far_stop = nullptr);
 size_t apply_workspace_bytes(int64_t n, int nrhs, int source_split);
 hipError_t launch_eval_green(const double *z2, double *g, int64_t n, int single, hipStream_t st);
@@ -73,6 +73,6 @@ ls_status solve_gmres(ls_ctx *h, const double *b, double *x, int nrhs, int64_t l
 ls_status grad_contrast(ls_ctx *h, const double *u, const double *lam, const double *a, int nrhs, int64_t ld,
                         double *grad, hipStream_t st);
 void free_solve_ws(ls_ctx *h);
-int auto_source_split(int64_t n, int nrhs_per_launch);
+int auto_source_split(int64_t n, int nrhs, int launches_per_split, int tpl);
 
 }  // namespace lsk

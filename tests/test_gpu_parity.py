@@ -41,8 +41,9 @@ def test_adjoint_apply_matches_oracle(name):
     assert e <= 1e-12
 
 
-@pytest.mark.parametrize("opts", [dict(source_split=1), dict(source_split=7), dict(source_split=3, rhs_chunk=4),
-                                  dict(rhs_chunk=16)])
+@pytest.mark.parametrize("opts", [dict(source_split=1), dict(source_split=7, targets_per_lane=1),
+                                  dict(source_split=3, rhs_chunk=4), dict(rhs_chunk=16, targets_per_lane=1),
+                                  dict(rhs_chunk=8, targets_per_lane=2), dict(source_split=200)])
 def test_launch_configurations_agree(opts):
     p, c, op = _op("disk2500", **opts)
     x = torch.tensor(np.concatenate([c["x"]] * 6)[:16], device="cuda")   # 16 columns
