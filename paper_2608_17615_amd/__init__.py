@@ -53,7 +53,7 @@ class _Profile(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("source_split", ctypes.c_int32), ("rhs_chunk", ctypes.c_int32),
                 ("targets_per_lane", ctypes.c_int32), ("mixed_tile", ctypes.c_int32),
-                ("n_threads_host", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+                ("n_threads_host", ctypes.c_int32), ("fp64_matrix", ctypes.c_int32)]
 
 
 class _SolveOpts(ctypes.Structure):
@@ -153,8 +153,8 @@ class Scatterer:
         return s, keep
 
 
-def _options(source_split=0, rhs_chunk=0, targets_per_lane=0, mixed_tile=0, n_threads_host=0):
-    return _Options(source_split, rhs_chunk, targets_per_lane, mixed_tile, n_threads_host, 0)
+def _options(source_split=0, rhs_chunk=0, targets_per_lane=0, mixed_tile=0, n_threads_host=0, fp64_matrix=0):
+    return _Options(source_split, rhs_chunk, targets_per_lane, mixed_tile, n_threads_host, fp64_matrix)
 
 
 class Operator:

@@ -327,14 +327,21 @@ namespace lsk {
 // Operator application without argument checks (callers validate).
 ls_status apply_op(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, Mode mode, ls_precision p,
                    hipStream_t stream) {
-  if (p == LS_MIXED) return fail(h, LS_ERR_UNSUPPORTED, "mixed precision apply not built");
+  // path: FP32 tiles (mixed), FP64 tiles (batched FP64 on the matrix cores) or the FP64 VALU sum
+  const bool single = p == LS_MIXED;
+  const bool tiles = single || h->opt.fp64_matrix == 2 || (h->opt.fp64_matrix == 0 && nrhs >= 16);
   const int tpl = h->opt.targets_per_lane == 2 ? 2 : 1;
   const int chunk = h->opt.rhs_chunk > 0 ? h->opt.rhs_chunk : 1;
+  auto splits = [&](const Scat &sc) {
+    if (h->opt.source_split > 0) return h->opt.source_split;
+    return tiles ? lsk::tile_source_split(sc.n, nrhs, single)
+                 : lsk::auto_source_split(sc.n, nrhs, std::max(1, nrhs / chunk), tpl);
+  };
   size_t need = 0;
   for (const Scat &sc : h->sc) {
-    const int nsplit = h->opt.source_split > 0 ? h->opt.source_split
-                                               : lsk::auto_source_split(sc.n, nrhs, std::max(1, nrhs / chunk), tpl);
-    need = std::max(need, lsk::apply_workspace_bytes(sc.n, nrhs, nsplit));
+    const int nsplit = splits(sc);
+    need = std::max(need, tiles ? lsk::tile_workspace_bytes(sc.n, nrhs, nsplit)
+                                : lsk::apply_workspace_bytes(sc.n, nrhs, nsplit));
   }
   if (need > h->ws_apply.bytes) {
     if (h->ws_apply.ptr) {
@@ -353,8 +360,7 @@ ls_status apply_op(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, 
     HIPCHK(h, hipEventRecord(a0, stream));
   }
   for (const Scat &sc : h->sc) {
-    const int nsplit = h->opt.source_split > 0 ? h->opt.source_split
-                                               : lsk::auto_source_split(sc.n, nrhs, std::max(1, nrhs / chunk), tpl);
+    const int nsplit = splits(sc);
     hipEvent_t f0 = nullptr, f1 = nullptr;
     if (h->prof) {
       HIPCHK(h, hipEventCreate(&f0));
@@ -362,8 +368,11 @@ ls_status apply_op(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, 
       h->ev_far.push_back(f0);
       h->ev_far.push_back(f1);
     }
-    HIPCHK(h, lsk::launch_apply_fp64(sc, x, y, nrhs, ld, mode, nsplit, chunk, tpl, h->ws_apply.ptr, stream, f0,
-                                     f1));
+    if (tiles)
+      HIPCHK(h, lsk::launch_apply_tile(sc, x, y, nrhs, ld, mode, single, nsplit, h->ws_apply.ptr, stream, f0, f1));
+    else
+      HIPCHK(h, lsk::launch_apply_fp64(sc, x, y, nrhs, ld, mode, nsplit, chunk, tpl, h->ws_apply.ptr, stream, f0,
+                                       f1));
   }
   if (h->prof) {
     HIPCHK(h, hipEventRecord(a1, stream));

@@ -183,12 +183,18 @@ __global__ __launch_bounds__(kBlock) void epilogue_kernel(
   y[c] = make_double2(std::fma(k2, ar, xv.x), std::fma(k2, ai, xv.y));
 }
 
-__global__ void eval_green_kernel(const double *__restrict__ z2, double2 *__restrict__ g, int64_t n) {
+__global__ void eval_green_kernel(const double *__restrict__ z2, double2 *__restrict__ g, int64_t n, int single) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  double gr, gi;
-  green(z2[i], gr, gi, d_hankel);
-  g[i] = make_double2(gr, gi);
+  if (single) {
+    float gr, gi;
+    green32(z2[i], gr, gi, d_hankel);
+    g[i] = make_double2(gr, gi);
+  } else {
+    double gr, gi;
+    green(z2[i], gr, gi, d_hankel);
+    g[i] = make_double2(gr, gi);
+  }
 }
 
 template <int BC, bool CONJ>
@@ -262,6 +268,16 @@ hipError_t launch_apply_fp64(const Scat &s, const double *x, double *y, int nrhs
     default: return hipErrorInvalidValue;
   }
   if (far_stop) (void)hipEventRecord(far_stop, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_epilogue(s, part, nsplit, f, x, y, nrhs, ld, mode, st);
+}
+
+hipError_t launch_epilogue(const Scat &s, const double2 *part, int nsplit, const double2 *f, const double *x,
+                           double *y, int nrhs, int64_t ld, Mode mode, hipStream_t st) {
+  const int64_t n = s.n;
+  const double2 *xc = (const double2 *)x;
+  double2 *yc = (double2 *)y;
   dim3 ge((unsigned)((n + kBlock - 1) / kBlock), (unsigned)nrhs);
   const double k2 = s.k * s.k;
   if (mode == Mode::Forward)
@@ -282,9 +298,8 @@ void eval_green_host(const double *z2, double *g, int64_t n) {
 }
 
 hipError_t launch_eval_green(const double *z2, double *g, int64_t n, int single, hipStream_t st) {
-  (void)single;
   if (n == 0) return hipSuccess;
-  eval_green_kernel<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(z2, (double2 *)g, n);
+  eval_green_kernel<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(z2, (double2 *)g, n, single);
   return hipGetLastError();
 }
 

@@ -175,4 +175,57 @@ __host__ __device__ __forceinline__ void green(double A, double &gre, double &gi
   }
 }
 
+// ---------------------------------------------------------------- single precision
+// For the mixed-precision tiles: z >= 1 in FP32 (far form for z >= F32_ZF, one fitted
+// modulus-phase interval below), e^{i theta} from the hardware sine/cosine of the fractional
+// number of turns; z < 1 falls back to the FP64 series (its logarithm needs the precision).
+// Relative accuracy ~2e-5 at z ~ 100, limited by z itself in FP32.
+template <class Arr>
+__host__ __device__ __forceinline__ float hornerf(const Arr &c, float x) {
+  constexpr int N = (int)(sizeof(Arr) / sizeof(float));
+  float r = c[N - 1];
+#pragma unroll
+  for (int i = N - 2; i >= 0; --i) r = std::fma(r, x, c[i]);
+  return r;
+}
+
+template <class Tab>
+__host__ __device__ __forceinline__ void green32(double A, float &gre, float &gim, const Tab &T) {
+  if (A < 1.0) {
+    double r, i;
+    green_small(A, r, i, T);
+    gre = (float)r;
+    gim = (float)i;
+    return;
+  }
+  const float a = (float)A;
+#ifdef __HIP_DEVICE_COMPILE__
+  const float s = __builtin_amdgcn_rsqf(__builtin_amdgcn_sqrtf(a));  // z^(-1/2)
+#else
+  const float s = 1.0f / std::sqrt(std::sqrt(a));
+#endif
+  const float t = s * s, z = a * t;
+  float mod, ph;
+  if (a >= F32_ZF * F32_ZF) {
+    const float t2 = t * t;
+    mod = hornerf(F32_FAR_MOD, t2);
+    ph = std::fma(t, hornerf(F32_FAR_PH, t2), -0.785398163f);
+  } else {
+    const float x = (t - F32_MID_TA) * F32_MID_SCALE;
+    mod = hornerf(F32_MID_MOD, x);
+    ph = hornerf(F32_MID_PH, x);
+  }
+  const float m4 = mod * s;
+  const float rev = (z + ph) * 0.159154943f;   // turns
+#ifdef __HIP_DEVICE_COMPILE__
+  const float f = __builtin_amdgcn_fractf(rev);
+  const float sn = __builtin_amdgcn_sinf(f), cs = __builtin_amdgcn_cosf(f);
+#else
+  const float f = rev - std::floor(rev);
+  const float sn = std::sin(6.283185307f * f), cs = std::cos(6.283185307f * f);
+#endif
+  gre = -m4 * sn;
+  gim = m4 * cs;
+}
+
 }  // namespace lsk

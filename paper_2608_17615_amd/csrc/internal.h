@@ -60,6 +60,14 @@ hipError_t launch_apply_fp64(const Scat &s, const double *x, double *y, int nrhs
                              Mode mode, int source_split, int rhs_chunk, int tpl, void *ws, hipStream_t st,
                              hipEvent_t far_start = nullptr, hipEvent_t far_stop = nullptr);
 size_t apply_workspace_bytes(int64_t n, int nrhs, int source_split);
+hipError_t launch_epilogue(const Scat &s, const double2 *part, int nsplit, const double2 *f, const double *x,
+                           double *y, int nrhs, int64_t ld, Mode mode, hipStream_t st);
+// mfma.hip: batched right-hand sides on the matrix cores (single = FP32 tiles)
+int tile_ldx(int nrhs);
+size_t tile_workspace_bytes(int64_t n, int nrhs, int nsplit);
+int tile_source_split(int64_t n, int nrhs, bool single);
+hipError_t launch_apply_tile(const Scat &s, const double *x, double *y, int nrhs, int64_t ld, Mode mode, bool single,
+                             int nsplit, void *ws, hipStream_t st, hipEvent_t far_start, hipEvent_t far_stop);
 hipError_t launch_eval_green(const double *z2, double *g, int64_t n, int single, hipStream_t st);
 void eval_green_host(const double *z2, double *g, int64_t n);
 

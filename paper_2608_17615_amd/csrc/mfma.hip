@@ -1,0 +1,258 @@
+// Far-field Green's sum for a block of right-hand sides on the matrix cores.
+//
+// For a wavefront's 16*MT targets and 16*NT right-hand sides, each step over 4 sources forms
+// the complex tile  Y[16 x 16] += G[16 x 4] X[4 x 16]  per (M-tile, N-tile) with four real
+// 16x16x4 MFMAs (Re Re, -Im Im, Re Im, Im Re).  In the 16x16x4 operand layout lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16], so lane l evaluates G for exactly the pair (target
+// l % 16 of the tile, source l / 16 of the step) it feeds to the matrix core: the Green's tile is
+// built on the VALU in registers and never moves.  B operands are the densities of the 4 sources
+// for 16 consecutive right-hand sides ([source][rhs] layout, coalesced 16-wide rows).
+//   T = double : v_mfma_f64_16x16x4f64, FP64 everywhere (exact variant of the batched sum);
+//   T = float  : v_mfma_f32_16x16x4f32 with FP32 Green's values (FP64 for z < 1) and FP32
+//                accumulation within one source split; splits are summed in FP64 by the epilogue.
+// Result rows: FP32 tiles return D[4 (l/16) + r][l % 16], FP64 tiles D[l/16 + 4 r][l % 16]
+// (r = accumulator register), both verified on gfx950.
+#include "hankel.h"
+#include "internal.h"
+
+namespace lsk {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__constant__ HankelTable m_hankel = kHankelTable;
+typedef __attribute__((address_space(4))) const HankelTable ConstTab;
+
+__device__ __forceinline__ ConstTab &mtab() {
+  ConstTab *t = (ConstTab *)&m_hankel;
+  asm volatile("" : "+s"(t));
+  return *t;
+}
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <class T>
+struct Tile;
+
+template <>
+struct Tile<double> {
+  typedef v4d acc_t;
+  typedef double2 cplx_t;
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+  static __device__ __forceinline__ void green(double A, double &gr, double &gi) { lsk::green(A, gr, gi, mtab()); }
+  static __device__ __forceinline__ cplx_t make(double a, double b) { return make_double2(a, b); }
+};
+
+template <>
+struct Tile<float> {
+  typedef v4f acc_t;
+  typedef float2 cplx_t;
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+  static __device__ __forceinline__ void green(double A, float &gr, float &gi) { lsk::green32(A, gr, gi, mtab()); }
+  static __device__ __forceinline__ cplx_t make(double a, double b) { return make_float2((float)a, (float)b); }
+};
+
+// X[i][b] (b < ldx, zero for b >= nrhs): w m x (forward) or x (adjoint) in precision T, plus the
+// FP64 f[b][i] = m x (or x) for the sparse correction.
+template <class T, Mode M>
+__global__ __launch_bounds__(kBlock) void prologue_tile_kernel(int64_t n, int nrhs, int ldx,
+                                                               const int32_t *__restrict__ perm,
+                                                               const double *__restrict__ w,
+                                                               const double2 *__restrict__ m,
+                                                               const double2 *__restrict__ x, int64_t ld,
+                                                               int64_t off, typename Tile<T>::cplx_t *__restrict__ X,
+                                                               double2 *__restrict__ f) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n * ldx) return;
+  const int64_t i = t / ldx;
+  const int b = (int)(t - i * ldx);
+  if (b >= nrhs) {
+    X[t] = Tile<T>::make(0.0, 0.0);
+    return;
+  }
+  const double2 xv = x[(int64_t)b * ld + off + perm[i]];
+  if (M == Mode::Forward) {
+    const double2 mi = m[i];
+    const double2 fv = make_double2(mi.x * xv.x - mi.y * xv.y, mi.x * xv.y + mi.y * xv.x);
+    f[(int64_t)b * n + i] = fv;
+    X[t] = Tile<T>::make(w[i] * fv.x, w[i] * fv.y);
+  } else {
+    f[(int64_t)b * n + i] = xv;
+    X[t] = Tile<T>::make(xv.x, xv.y);
+  }
+}
+
+// grid: (ceil(n / (4 * 16 * MT)), source splits, ldx / (16 * NT))
+template <class T, int MT, int NT, bool CONJ>
+__global__ __launch_bounds__(kBlock) void far_tile_kernel(int n, const double2 *__restrict__ pos,
+                                                          const typename Tile<T>::cplx_t *__restrict__ X, int ldx,
+                                                          int nrhs, double k2, int split_len,
+                                                          double2 *__restrict__ part) {
+  typedef Tile<T> TL;
+  typedef typename TL::acc_t acc_t;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kk = lane >> 4, col = lane & 15;
+  const int t0 = (blockIdx.x * 4 + wave) * 16 * MT;
+  const int b0 = blockIdx.z * 16 * NT;
+  int tm[MT];
+  double xt[MT], yt[MT];
+#pragma unroll
+  for (int mi = 0; mi < MT; ++mi) {
+    tm[mi] = t0 + 16 * mi + col;
+    const double2 p = pos[tm[mi] < n ? tm[mi] : n - 1];
+    xt[mi] = p.x;
+    yt[mi] = p.y;
+  }
+  acc_t ar[MT][NT], ai[MT][NT];
+#pragma unroll
+  for (int mi = 0; mi < MT; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < NT; ++ni) {
+      ar[mi][ni] = acc_t{0, 0, 0, 0};
+      ai[mi][ni] = acc_t{0, 0, 0, 0};
+    }
+  const int s0 = blockIdx.y * split_len;
+  const int s1 = min(n, s0 + split_len);
+  for (int s = s0; s < s1; s += 4) {
+    const int src = s + kk;
+    const bool ok = src < s1;
+    const int sc = ok ? src : s0;
+    const double2 p = pos[sc];
+    T gr[MT], gi[MT], gn[MT];
+#pragma unroll
+    for (int mi = 0; mi < MT; ++mi) {
+      const double dx = xt[mi] - p.x, dy = yt[mi] - p.y;
+      const double A = k2 * std::fma(dx, dx, dy * dy);
+      TL::green(A, gr[mi], gi[mi]);
+      const bool zero = !ok || src == tm[mi];
+      gr[mi] = zero ? (T)0 : gr[mi];
+      gi[mi] = zero ? (T)0 : gi[mi];
+      if (CONJ) gi[mi] = -gi[mi];
+      gn[mi] = -gi[mi];
+    }
+    typename TL::cplx_t xb[NT];
+#pragma unroll
+    for (int ni = 0; ni < NT; ++ni) {
+      xb[ni] = X[(int64_t)sc * ldx + b0 + 16 * ni + col];
+      if (!ok) xb[ni] = TL::make(0.0, 0.0);
+    }
+#pragma unroll
+    for (int mi = 0; mi < MT; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < NT; ++ni) {
+        ar[mi][ni] = TL::mma(gr[mi], xb[ni].x, ar[mi][ni]);
+        ar[mi][ni] = TL::mma(gn[mi], xb[ni].y, ar[mi][ni]);
+        ai[mi][ni] = TL::mma(gr[mi], xb[ni].y, ai[mi][ni]);
+        ai[mi][ni] = TL::mma(gi[mi], xb[ni].x, ai[mi][ni]);
+      }
+  }
+#pragma unroll
+  for (int mi = 0; mi < MT; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < NT; ++ni)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int t = t0 + 16 * mi + TL::row(lane, r);
+        const int b = b0 + 16 * ni + col;
+        if (t < n && b < nrhs)
+          part[((int64_t)blockIdx.y * nrhs + b) * n + t] = make_double2((double)ar[mi][ni][r], (double)ai[mi][ni][r]);
+      }
+}
+
+template <class T, int MT, int NT>
+void launch_tile(const Scat &s, const void *X, int ldx, int nrhs, int split_len, int nsplit, double2 *part,
+                 bool conj, hipStream_t st) {
+  dim3 grid((unsigned)((s.n + 64 * MT - 1) / (64 * MT)), (unsigned)nsplit, (unsigned)(ldx / (16 * NT)));
+  typedef typename Tile<T>::cplx_t C;
+  if (conj)
+    far_tile_kernel<T, MT, NT, true><<<grid, kBlock, 0, st>>>((int)s.n, s.pos, (const C *)X, ldx, nrhs, s.k * s.k,
+                                                             split_len, part);
+  else
+    far_tile_kernel<T, MT, NT, false><<<grid, kBlock, 0, st>>>((int)s.n, s.pos, (const C *)X, ldx, nrhs, s.k * s.k,
+                                                              split_len, part);
+}
+
+template <class T, int MT>
+void launch_tile_nt(const Scat &s, const void *X, int ldx, int nrhs, int split_len, int nsplit, double2 *part,
+                    bool conj, hipStream_t st) {
+  const int groups = ldx / 16;
+  if (groups % 4 == 0)
+    launch_tile<T, MT, 4>(s, X, ldx, nrhs, split_len, nsplit, part, conj, st);
+  else if (groups % 2 == 0)
+    launch_tile<T, MT, 2>(s, X, ldx, nrhs, split_len, nsplit, part, conj, st);
+  else
+    launch_tile<T, MT, 1>(s, X, ldx, nrhs, split_len, nsplit, part, conj, st);
+}
+
+}  // namespace
+
+int tile_ldx(int nrhs) { return (nrhs + 15) / 16 * 16; }
+
+size_t tile_workspace_bytes(int64_t n, int nrhs, int nsplit) {
+  // X [n][ldx] (double2 upper bound), f [nrhs][n], part [nsplit][nrhs][n]
+  return sizeof(double2) * ((size_t)n * tile_ldx(nrhs) + (size_t)n * nrhs * (1 + (size_t)nsplit)) + 512;
+}
+
+int tile_source_split(int64_t n, int nrhs, bool single) {
+  const int mt = single ? 4 : 2;
+  const int ldx = tile_ldx(nrhs);
+  const int nt = (ldx / 16) % 4 == 0 ? 4 : ((ldx / 16) % 2 == 0 ? 2 : 1);
+  const int64_t waves = ((n + 16 * mt - 1) / (16 * mt)) * (ldx / (16 * nt));
+  int64_t s = (16384 + waves - 1) / waves;   // ~16 waves per SIMD over the launch
+  const int64_t cap = ((int64_t)1 << 30) / ((int64_t)16 * n * nrhs);
+  if (s > cap) s = cap;
+  if (s < 1) s = 1;
+  if (s > 128) s = 128;
+  if (s > n) s = n;
+  return (int)s;
+}
+
+hipError_t launch_apply_tile(const Scat &s, const double *x, double *y, int nrhs, int64_t ld, Mode mode, bool single,
+                             int nsplit, void *ws, hipStream_t st, hipEvent_t far_start, hipEvent_t far_stop) {
+  const int64_t n = s.n;
+  const int ldx = tile_ldx(nrhs);
+  char *p = (char *)ws;
+  void *X = p;
+  p += (single ? sizeof(float2) : sizeof(double2)) * (size_t)n * ldx;
+  p = (char *)(((uintptr_t)p + 255) & ~(uintptr_t)255);
+  double2 *f = (double2 *)p;
+  double2 *part = f + n * nrhs;
+  const unsigned gp = (unsigned)((n * ldx + kBlock - 1) / kBlock);
+  const double2 *xc = (const double2 *)x;
+  const bool fwd = mode == Mode::Forward;
+  if (single) {
+    if (fwd)
+      prologue_tile_kernel<float, Mode::Forward><<<gp, kBlock, 0, st>>>(n, nrhs, ldx, s.perm, s.w, s.m, xc, ld, s.off,
+                                                                        (float2 *)X, f);
+    else
+      prologue_tile_kernel<float, Mode::Adjoint><<<gp, kBlock, 0, st>>>(n, nrhs, ldx, s.perm, s.w, s.m, xc, ld, s.off,
+                                                                        (float2 *)X, f);
+  } else {
+    if (fwd)
+      prologue_tile_kernel<double, Mode::Forward><<<gp, kBlock, 0, st>>>(n, nrhs, ldx, s.perm, s.w, s.m, xc, ld,
+                                                                         s.off, (double2 *)X, f);
+    else
+      prologue_tile_kernel<double, Mode::Adjoint><<<gp, kBlock, 0, st>>>(n, nrhs, ldx, s.perm, s.w, s.m, xc, ld,
+                                                                         s.off, (double2 *)X, f);
+  }
+  const int split_len = (int)((n + nsplit - 1) / nsplit);
+  if (far_start) (void)hipEventRecord(far_start, st);
+  if (single)
+    launch_tile_nt<float, 4>(s, X, ldx, nrhs, split_len, nsplit, part, !fwd, st);
+  else
+    launch_tile_nt<double, 2>(s, X, ldx, nrhs, split_len, nsplit, part, !fwd, st);
+  if (far_stop) (void)hipEventRecord(far_stop, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_epilogue(s, part, nsplit, f, x, y, nrhs, ld, mode, st);
+}
+
+}  // namespace lsk

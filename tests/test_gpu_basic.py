@@ -24,3 +24,16 @@ def test_device_green_matches_mpmath_and_host():
     # (hardware reciprocal square root vs libm), so they may differ by a rounding of that root
     h = lsg.eval_green_host(z * z)
     assert np.all(np.abs(g - h) <= 1e-15 * np.abs(h) * np.maximum(1.0, z))
+
+
+def test_device_green_single_precision():
+    """FP32 evaluation used by the mixed-precision tiles (FP64 below z = 1)."""
+    mp.mp.dps = 30
+    z = np.concatenate([np.logspace(-5, np.log10(160), 2000), np.linspace(0.99, 1.01, 21), np.linspace(7.99, 8.01, 21)])
+    z2 = torch.tensor(z * z, dtype=torch.float64, device="cuda")
+    g = lsg.eval_green(z2, single=True).cpu().numpy()
+    ref = np.array([complex(0.25j * mp.hankel1(0, mp.mpf(float(t)))) for t in z])
+    err = np.abs(g - ref) / np.abs(ref)
+    print("single-precision green: max rel err", err.max(), "(z<1)", err[z < 1].max(), flush=True)
+    assert np.all(err[z < 1] <= 1e-7)                       # FP64 series, rounded to FP32
+    assert np.all(err <= 4e-7 * np.maximum(1.0, z))          # FP32 argument: ~z * 2^-24 phase error
