@@ -225,9 +225,9 @@ hipError_t ensure(void *&p, size_t &have, size_t need) {
   return e;
 }
 
-SolveWs *solve_ws(ls_ctx *h) {
-  if (!h->ws_solve.ptr) h->ws_solve.ptr = new SolveWs();
-  return (SolveWs *)h->ws_solve.ptr;
+SolveWs *solve_ws(ls_ctx *h, int level) {
+  if (!h->ws_solve.ptr) h->ws_solve.ptr = new SolveWs[3]();
+  return (SolveWs *)h->ws_solve.ptr + level;
 }
 
 unsigned tiles_of(int64_t n) { return (unsigned)((n + kTile - 1) / kTile); }
@@ -252,7 +252,7 @@ struct Gmres {
     const size_t ntile = tiles_of(n);
     const size_t need = sizeof(double2) * ntile * nrhs * (size_t)(maxvec + 1) +      // part
                         2 * sizeof(double2) * (size_t)nrhs * (maxvec + 1) +          // h, y
-                        sizeof(double) * nrhs + sizeof(double2 *) * (size_t)(2 * maxvec + 4) + 1024;
+                        sizeof(double) * nrhs + sizeof(double2 *) * (size_t)(2 * maxvec + 8) + 1024;
     hipError_t e = ensure(ws->small, ws->small_bytes, need);
     if (e != hipSuccess) return e;
     char *p = (char *)ws->small;
@@ -290,97 +290,93 @@ struct Gmres {
 
 }  // namespace
 
-ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, int64_t ld, const ls_solve_opts &o,
-                      ls_solve_info *info, hipStream_t st) {
-  const auto t_start = std::chrono::steady_clock::now();
+struct CoreOpts {
+  double tol;
+  int maxit, restart;
+  Mode mode;
+  ls_precision matvec;   // precision of the Arnoldi operator applications
+  bool flexible;         // FP64 flexible GMRES with an inner mixed-precision GMRES preconditioner
+  double inner_tol;
+  int inner_maxit;
+  bool x0_given;
+};
+
+struct CoreResult {
+  std::vector<int> iters;
+  std::vector<char> done;
+  int64_t n_fp64 = 0, n_mixed = 0;
+};
+
+// GMRES on contiguous (ld = n) device vectors b, x of nrhs columns.  x holds the initial guess
+// when o.x0_given, the approximate solution on return.  ws is this level's workspace; the
+// flexible variant runs its inner solves with a second workspace.
+ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b, double2 *x, int nrhs,
+                     const CoreOpts &o, CoreResult &res, hipStream_t st) {
   const int64_t n = h->n_total;
-  const Mode mode = o.adjoint ? Mode::Adjoint : Mode::Forward;
-  const bool flexible = o.prec == LS_MIXED;
   const int maxit = o.maxit;
   const int cyc = (o.restart > 0 && o.restart < maxit) ? o.restart : maxit;
-  SolveWs *ws = solve_ws(h);
-  Gmres G{h, st, n, nrhs, mode, ws};
+  Gmres G{h, st, n, nrhs, o.mode, ws};
 #define HIPTRY(call)                                                               \
   do {                                                                             \
     hipError_t e_ = (call);                                                        \
     if (e_ != hipSuccess) return setup_fail(h, LS_ERR_HIP, hipGetErrorString(e_)); \
   } while (0)
   HIPTRY(G.init(cyc + 1));
-  // vectors: r (residual / b copy), t (apply output), plus inner-solve space for flexible
   const size_t vb = sizeof(double2) * (size_t)n * nrhs;
-  HIPTRY(ensure(ws->vecs, ws->vec_bytes, 4 * vb));
+  HIPTRY(ensure(ws->vecs, ws->vec_bytes, 2 * vb));
   double2 *r = (double2 *)ws->vecs;
   double2 *t = r + (size_t)n * nrhs;
-  double2 *bb = t + (size_t)n * nrhs;
-  double2 *xs = bb + (size_t)n * nrhs;   // current iterate, contiguous (ld = n)
   HIPTRY(ensure_chunks(ws->V, cyc + 1, n, nrhs));
-  if (flexible) HIPTRY(ensure_chunks(ws->Z, cyc, n, nrhs));
-  // pointer table: [0, cyc] basis V, [cyc+2] scratch slot for norms
+  if (o.flexible) HIPTRY(ensure_chunks(ws->Z, cyc, n, nrhs));
   std::vector<double2 *> tbl(2 * (cyc + 1) + 4, nullptr);
   for (int i = 0; i <= cyc; ++i) tbl[i] = ws->V.vec(i, n, nrhs);
-  // contiguous copies of b and x (ld = n)
-  HIPTRY(hipMemcpy2DAsync(bb, n * sizeof(double2), b_in, ld * sizeof(double2), n * sizeof(double2), nrhs,
-                          hipMemcpyDeviceToDevice, st));
+  const int slot = G.max_vec + 2;
   std::vector<double> bnorm(nrhs);
-  {
-    tbl[G.max_vec + 2] = bb;
-    HIPTRY(hipMemcpyAsync(G.ptrs, tbl.data(), sizeof(double2 *) * tbl.size(), hipMemcpyHostToDevice, st));
-    HIPTRY(G.norms(bb, nullptr));
-    HIPTRY(hipMemcpyAsync(bnorm.data(), G.beta, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
-    HIPTRY(hipStreamSynchronize(st));
-  }
+  tbl[slot] = (double2 *)b;
+  HIPTRY(hipMemcpyAsync(G.ptrs, tbl.data(), sizeof(double2 *) * tbl.size(), hipMemcpyHostToDevice, st));
+  HIPTRY(G.norms(b, nullptr));
+  HIPTRY(hipMemcpyAsync(bnorm.data(), G.beta, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+  HIPTRY(hipStreamSynchronize(st));
   for (int c = 0; c < nrhs; ++c)
     if (!std::isfinite(bnorm[c])) return setup_fail(h, LS_ERR_NONFINITE, "non-finite right-hand side");
-  if (o.x0_given) {
-    HIPTRY(hipMemcpy2DAsync(xs, n * sizeof(double2), x_out, ld * sizeof(double2), n * sizeof(double2), nrhs,
-                            hipMemcpyDeviceToDevice, st));
-  } else {
-    HIPTRY(hipMemsetAsync(xs, 0, vb, st));
-  }
-  std::vector<int> iters(nrhs, 0);
-  std::vector<char> done(nrhs, 0);
+  if (!o.x0_given) HIPTRY(hipMemsetAsync(x, 0, vb, st));
+  res.iters.assign(nrhs, 0);
+  res.done.assign(nrhs, 0);
   std::vector<double> est(nrhs, 1.0);
-  int64_t n_fp64 = 0, n_mixed = 0;
   int total_it = 0;
-  ls_status status = LS_OK;
   bool first_cycle = true;
   std::vector<cplx> H, cs, sn, g;
-  std::vector<double2> hh((size_t)nrhs * (cyc + 1) * 2), hb(nrhs);
+  std::vector<double2> hh((size_t)nrhs * (cyc + 1) * 2);
   std::vector<double> betah(nrhs);
+  const dim3 gv(blocks_of(n), nrhs);
   while (total_it < maxit) {
-    // r = b - L x  (skip the apply when x = 0)
+    // r = b - L x (FP64), skipped while x = 0
     if (first_cycle && !o.x0_given) {
-      HIPTRY(hipMemcpyAsync(r, bb, vb, hipMemcpyDeviceToDevice, st));
+      HIPTRY(hipMemcpyAsync(r, b, vb, hipMemcpyDeviceToDevice, st));
     } else {
-      ls_status s2 = apply_op(h, (const double *)xs, (double *)t, nrhs, n, mode, LS_FP64, st);
+      ls_status s2 = apply_op(h, (const double *)x, (double *)t, nrhs, n, o.mode, o.flexible ? LS_FP64 : o.matvec, st);
       if (s2 != LS_OK) return s2;
-      ++n_fp64;
-      dim3 g2(blocks_of(n), nrhs);
-      axpy_kernel<<<g2, kBlock, 0, st>>>(n, bb, n, -1.0, t, n, r, n);
+      if (o.flexible || o.matvec == LS_FP64) ++res.n_fp64; else ++res.n_mixed;
+      axpy_kernel<<<gv, kBlock, 0, st>>>(n, b, n, -1.0, t, n, r, n);
       HIPTRY(hipGetLastError());
     }
     first_cycle = false;
-    tbl[G.max_vec + 2] = r;
+    tbl[slot] = r;
     HIPTRY(hipMemcpyAsync(G.ptrs, tbl.data(), sizeof(double2 *) * tbl.size(), hipMemcpyHostToDevice, st));
     HIPTRY(G.norms(r, nullptr));
     std::vector<double> rnorm(nrhs);
     HIPTRY(hipMemcpyAsync(rnorm.data(), G.beta, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
-    // V0 = r / ||r||
-    {
-      dim3 g2(blocks_of(n), nrhs);
-      scale_kernel<<<g2, kBlock, 0, st>>>(n, G.beta, r, n, tbl[0], n);
-      HIPTRY(hipGetLastError());
-    }
+    scale_kernel<<<gv, kBlock, 0, st>>>(n, G.beta, r, n, tbl[0], n);
+    HIPTRY(hipGetLastError());
     HIPTRY(hipStreamSynchronize(st));
     bool all = true;
     for (int c = 0; c < nrhs; ++c) {
       est[c] = bnorm[c] > 0 ? rnorm[c] / bnorm[c] : 0.0;
       if (!std::isfinite(est[c])) return setup_fail(h, LS_ERR_NONFINITE, "non-finite residual");
-      done[c] = est[c] <= o.tol;
-      all = all && done[c];
+      res.done[c] = est[c] <= o.tol;
+      all = all && res.done[c];
     }
     if (all) break;
-    // Hessenberg storage per column
     const int m = cyc;
     H.assign((size_t)nrhs * (m + 1) * m, cplx(0));
     cs.assign((size_t)nrhs * m, cplx(0));
@@ -390,45 +386,41 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
     std::vector<char> active(nrhs);
     for (int c = 0; c < nrhs; ++c) {
       g[(size_t)c * (m + 1)] = rnorm[c];
-      active[c] = !done[c];
+      active[c] = !res.done[c];
     }
     int j = 0;
     for (; j < m && total_it < maxit; ++j, ++total_it) {
       double2 *vj = tbl[j];
       double2 *w = tbl[j + 1];
-      if (flexible) {
-        // z_j = inner solve of L z = v_j with the mixed-precision operator, then w = L z_j (FP64)
+      if (o.flexible) {
+        // z_j ~ L^{-1} v_j by an inner GMRES with the mixed-precision operator, then w = L z_j
         double2 *zj = ws->Z.vec(j, n, nrhs);
-        ls_status s2 = LS_ERR_UNSUPPORTED;
-        (void)zj;
-        (void)n_mixed;
-        return setup_fail(h, s2, "mixed-precision solve not available");
-      } else {
-        ls_status s2 = apply_op(h, (const double *)vj, (double *)w, nrhs, n, mode, LS_FP64, st);
+        CoreOpts io{o.inner_tol, o.inner_maxit, 0, o.mode, LS_MIXED, false, 0.0, 0, false};
+        CoreResult ir;
+        ls_status s2 = gmres_core(h, ws_inner, nullptr, vj, zj, nrhs, io, ir, st);
+        if (s2 < 0) return s2;
+        res.n_mixed += ir.n_mixed;
+        res.n_fp64 += ir.n_fp64;
+        s2 = apply_op(h, (const double *)zj, (double *)w, nrhs, n, o.mode, LS_FP64, st);
         if (s2 != LS_OK) return s2;
-        ++n_fp64;
+        ++res.n_fp64;
+        tbl[slot] = r;   // the inner solve used its own pointer table; ours is intact
+      } else {
+        ls_status s2 = apply_op(h, (const double *)vj, (double *)w, nrhs, n, o.mode, o.matvec, st);
+        if (s2 != LS_OK) return s2;
+        if (o.matvec == LS_FP64) ++res.n_fp64; else ++res.n_mixed;
       }
       // CGS2 against V[0..j]
       const int nv = j + 1;
       double2 *h1 = G.hbuf, *h2 = G.ybuf;
       HIPTRY(G.dots(nv, w, h1, nv));
-      {
-        dim3 g2(blocks_of(n), nrhs);
-        update_kernel<<<g2, kBlock, 0, st>>>(n, nv, G.ptrs, n, h1, nv, -1.0, w, n);
-      }
+      update_kernel<<<gv, kBlock, 0, st>>>(n, nv, G.ptrs, n, h1, nv, -1.0, w, n);
       HIPTRY(G.dots(nv, w, h2, nv));
-      {
-        dim3 g2(blocks_of(n), nrhs);
-        update_kernel<<<g2, kBlock, 0, st>>>(n, nv, G.ptrs, n, h2, nv, -1.0, w, n);
-      }
-      tbl[G.max_vec + 2] = w;
-      HIPTRY(hipMemcpyAsync(G.ptrs + G.max_vec + 2, &tbl[G.max_vec + 2], sizeof(double2 *), hipMemcpyHostToDevice,
-                            st));
+      update_kernel<<<gv, kBlock, 0, st>>>(n, nv, G.ptrs, n, h2, nv, -1.0, w, n);
+      tbl[slot] = w;
+      HIPTRY(hipMemcpyAsync(G.ptrs + slot, &tbl[slot], sizeof(double2 *), hipMemcpyHostToDevice, st));
       HIPTRY(G.norms(w, nullptr));
-      {
-        dim3 g2(blocks_of(n), nrhs);
-        scale_kernel<<<g2, kBlock, 0, st>>>(n, G.beta, w, n, w, n);
-      }
+      scale_kernel<<<gv, kBlock, 0, st>>>(n, G.beta, w, n, w, n);
       HIPTRY(hipMemcpyAsync(hh.data(), h1, sizeof(double2) * nrhs * nv, hipMemcpyDeviceToHost, st));
       HIPTRY(hipMemcpyAsync(hh.data() + (size_t)nrhs * nv, h2, sizeof(double2) * nrhs * nv, hipMemcpyDeviceToHost,
                             st));
@@ -460,11 +452,11 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
         gc[j + 1] = -std::conj(snc[j]) * gc[j];
         gc[j] = csc[j] * gc[j];
         mc[c] = j + 1;
-        iters[c]++;
+        res.iters[c]++;
         est[c] = bnorm[c] > 0 ? std::abs(gc[j + 1]) / bnorm[c] : 0.0;
         if (est[c] <= o.tol || betah[c] == 0.0) {
           active[c] = 0;
-          done[c] = 1;
+          res.done[c] = 1;
         } else {
           any = true;
         }
@@ -475,7 +467,7 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
         break;
       }
     }
-    // x += V y per column (y from the triangular solves)
+    // x += V y (or Z y for the flexible variant) per column
     std::vector<double2> yv((size_t)nrhs * m, make_double2(0, 0));
     for (int c = 0; c < nrhs; ++c) {
       const int mm = mc[c];
@@ -490,42 +482,86 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
     }
     const int mmax = std::max(1, *std::max_element(mc.begin(), mc.end()));
     HIPTRY(hipMemcpyAsync(G.hbuf, yv.data(), sizeof(double2) * nrhs * m, hipMemcpyHostToDevice, st));
-    if (flexible) {
-      // x += Z y (not reached: flexible solves return above)
+    if (o.flexible) {
+      std::vector<double2 *> ztbl(mmax);
+      for (int i = 0; i < mmax; ++i) ztbl[i] = ws->Z.vec(i, n, nrhs);
+      HIPTRY(hipMemcpyAsync(G.ptrs + G.max_vec + 4, ztbl.data(), sizeof(double2 *) * mmax, hipMemcpyHostToDevice,
+                            st));
+      update_kernel<<<gv, kBlock, 0, st>>>(n, mmax, G.ptrs + G.max_vec + 4, n, G.hbuf, m, 1.0, x, n);
     } else {
-      dim3 g2(blocks_of(n), nrhs);
-      update_kernel<<<g2, kBlock, 0, st>>>(n, mmax, G.ptrs, n, G.hbuf, m, 1.0, xs, n);
-      HIPTRY(hipGetLastError());
+      update_kernel<<<gv, kBlock, 0, st>>>(n, mmax, G.ptrs, n, G.hbuf, m, 1.0, x, n);
     }
+    HIPTRY(hipGetLastError());
+    HIPTRY(hipStreamSynchronize(st));
     bool all_done = true;
-    for (int c = 0; c < nrhs; ++c) all_done = all_done && done[c];
+    for (int c = 0; c < nrhs; ++c) all_done = all_done && res.done[c];
     if (all_done || cyc >= maxit) break;
   }
+  return LS_OK;
+#undef HIPTRY
+}
+
+ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, int64_t ld, const ls_solve_opts &o,
+                      ls_solve_info *info, hipStream_t st) {
+  const auto t_start = std::chrono::steady_clock::now();
+  const int64_t n = h->n_total;
+  const Mode mode = o.adjoint ? Mode::Adjoint : Mode::Forward;
+  SolveWs *ws = solve_ws(h, 0), *wi = solve_ws(h, 1), *wt = solve_ws(h, 2);
+#define HIPTRY(call)                                                               \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess) return setup_fail(h, LS_ERR_HIP, hipGetErrorString(e_)); \
+  } while (0)
+  // contiguous copies of b and x plus the residual check buffers (top-level workspace)
+  const size_t vb = sizeof(double2) * (size_t)n * nrhs;
+  HIPTRY(ensure(wt->vecs, wt->vec_bytes, 4 * vb));
+  double2 *bb = (double2 *)wt->vecs, *xs = bb + (size_t)n * nrhs, *r = xs + (size_t)n * nrhs,
+          *t = r + (size_t)n * nrhs;
+  HIPTRY(hipMemcpy2DAsync(bb, n * sizeof(double2), b_in, ld * sizeof(double2), n * sizeof(double2), nrhs,
+                          hipMemcpyDeviceToDevice, st));
+  if (o.x0_given)
+    HIPTRY(hipMemcpy2DAsync(xs, n * sizeof(double2), x_out, ld * sizeof(double2), n * sizeof(double2), nrhs,
+                            hipMemcpyDeviceToDevice, st));
+  const bool flexible = o.prec == LS_MIXED;
+  CoreOpts co{o.tol, o.maxit, o.restart, mode, LS_FP64, flexible,
+              o.inner_tol > 0 ? o.inner_tol : 1e-3, o.inner_maxit > 0 ? o.inner_maxit : 400, o.x0_given != 0};
+  CoreResult res;
+  ls_status status = gmres_core(h, ws, wi, bb, xs, nrhs, co, res, st);
+  if (status < 0) return status;
   // true residuals with the FP64 apply
+  ls_status s2 = apply_op(h, (const double *)xs, (double *)t, nrhs, n, mode, LS_FP64, st);
+  if (s2 != LS_OK) return s2;
+  ++res.n_fp64;
   {
-    ls_status s2 = apply_op(h, (const double *)xs, (double *)t, nrhs, n, mode, LS_FP64, st);
-    if (s2 != LS_OK) return s2;
-    ++n_fp64;
-    dim3 g2(blocks_of(n), nrhs);
-    axpy_kernel<<<g2, kBlock, 0, st>>>(n, bb, n, -1.0, t, n, r, n);
+    Gmres G{h, st, n, nrhs, mode, ws};
+    HIPTRY(G.init(std::max(1, (o.restart > 0 && o.restart < o.maxit) ? o.restart : o.maxit) + 1));
+    const dim3 gv(blocks_of(n), nrhs);
+    axpy_kernel<<<gv, kBlock, 0, st>>>(n, bb, n, -1.0, t, n, r, n);
+    std::vector<double2 *> tbl(G.max_vec + 3, nullptr);
     tbl[G.max_vec + 2] = r;
-    HIPTRY(hipMemcpyAsync(G.ptrs + G.max_vec + 2, &tbl[G.max_vec + 2], sizeof(double2 *), hipMemcpyHostToDevice, st));
+    HIPTRY(hipMemcpyAsync(G.ptrs, tbl.data(), sizeof(double2 *) * tbl.size(), hipMemcpyHostToDevice, st));
     HIPTRY(G.norms(r, nullptr));
-    std::vector<double> rn(nrhs);
+    std::vector<double> rn(nrhs), bn(nrhs);
     HIPTRY(hipMemcpyAsync(rn.data(), G.beta, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    tbl[G.max_vec + 2] = bb;
+    HIPTRY(hipMemcpyAsync(G.ptrs, tbl.data(), sizeof(double2 *) * tbl.size(), hipMemcpyHostToDevice, st));
+    HIPTRY(G.norms(bb, nullptr));
+    HIPTRY(hipMemcpyAsync(bn.data(), G.beta, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
     HIPTRY(hipMemcpy2DAsync(x_out, ld * sizeof(double2), xs, n * sizeof(double2), n * sizeof(double2), nrhs,
                             hipMemcpyDeviceToDevice, st));
     HIPTRY(hipStreamSynchronize(st));
+    status = LS_OK;
     for (int c = 0; c < nrhs; ++c) {
-      const double rr = bnorm[c] > 0 ? rn[c] / bnorm[c] : 0.0;
+      const double rr = bn[c] > 0 ? rn[c] / bn[c] : 0.0;
       if (info && info->relres) info->relres[c] = rr;
-      if (info && info->iters) info->iters[c] = iters[c];
-      if (!done[c]) status = LS_NOT_CONVERGED;
+      if (info && info->iters) info->iters[c] = res.iters[c];
+      if (!res.done[c]) status = LS_NOT_CONVERGED;
     }
   }
   if (info) {
-    info->n_apply_fp64 = n_fp64 * nrhs;
-    info->n_apply_mixed = n_mixed * nrhs;
+    info->n_apply_fp64 = res.n_fp64 * nrhs;
+    info->n_apply_mixed = res.n_mixed * nrhs;
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   }
   return status;
@@ -535,7 +571,7 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
 ls_status grad_contrast(ls_ctx *h, const double *u, const double *lam, const double *a, int nrhs, int64_t ld,
                         double *grad, hipStream_t st) {
   const int64_t n = h->n_total;
-  SolveWs *ws = solve_ws(h);
+  SolveWs *ws = solve_ws(h, 2);
   // P = V^H lam, written with the caller's leading dimension
   const size_t pb = sizeof(double2) * (size_t)ld * nrhs;
   if (ensure(ws->vecs, ws->vec_bytes, std::max(pb, 4 * sizeof(double2) * (size_t)n * nrhs)) != hipSuccess)
@@ -552,13 +588,16 @@ ls_status grad_contrast(ls_ctx *h, const double *u, const double *lam, const dou
 }
 
 void free_solve_ws(ls_ctx *h) {
-  SolveWs *ws = (SolveWs *)h->ws_solve.ptr;
-  if (!ws) return;
-  for (void *p : ws->V.chunks) (void)hipFree(p);
-  for (void *p : ws->Z.chunks) (void)hipFree(p);
-  if (ws->small) (void)hipFree(ws->small);
-  if (ws->vecs) (void)hipFree(ws->vecs);
-  delete ws;
+  SolveWs *all = (SolveWs *)h->ws_solve.ptr;
+  if (!all) return;
+  for (int l = 0; l < 3; ++l) {
+    SolveWs *ws = all + l;
+    for (void *p : ws->V.chunks) (void)hipFree(p);
+    for (void *p : ws->Z.chunks) (void)hipFree(p);
+    if (ws->small) (void)hipFree(ws->small);
+    if (ws->vecs) (void)hipFree(ws->vecs);
+  }
+  delete[] all;
   h->ws_solve.ptr = nullptr;
 }
 
