@@ -118,11 +118,18 @@ typedef struct {
   double tol;          /* relative residual ||b - L x||_2 / ||b||_2 per column */
   int32_t maxit;       /* outer iterations (Arnoldi steps) */
   int32_t restart;     /* 0 = no restart */
-  int32_t prec;        /* ls_precision: LS_MIXED = FP64 flexible GMRES around mixed inner GMRES */
+  int32_t prec;        /* ls_precision, see below */
   int32_t adjoint;     /* solve L^H x = b instead */
   int32_t x0_given;    /* use x as the initial guess */
-  int32_t inner_maxit; /* LS_MIXED: inner iterations per outer step (0 = automatic) */
-  double inner_tol;    /* LS_MIXED: inner relative tolerance (0 = automatic) */
+  int32_t inner_maxit; /* LS_MIXED: > 0 selects flexible GMRES with this many inner steps */
+  double inner_tol;    /* LS_MIXED: inner tolerance (flexible) or granted operator accuracy (relaxed) */
+  /* LS_MIXED solves keep the Krylov basis, orthogonalisation and residuals in FP64.
+   *   inner_maxit > 0: flexible GMRES; each outer direction is preconditioned by up to
+   *                    inner_maxit steps of GMRES with the mixed operator (to inner_tol,
+   *                    default 1e-12, i.e. exactly inner_maxit steps).
+   *   inner_maxit = 0: relaxed GMRES; FP64 applications while the residual estimate exceeds
+   *                    0.3 tol / inner_tol (default inner_tol 1e-3), mixed ones after, then FP64
+   *                    refinement passes from the true residual if tol was missed. */
 } ls_solve_opts;
 
 typedef struct {

@@ -299,6 +299,7 @@ struct CoreOpts {
   double inner_tol;
   int inner_maxit;
   bool x0_given;
+  double relax_eps;      // > 0: FP64 applies while the residual estimate exceeds tol / relax_eps, mixed after
 };
 
 struct CoreResult {
@@ -354,9 +355,10 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
     if (first_cycle && !o.x0_given) {
       HIPTRY(hipMemcpyAsync(r, b, vb, hipMemcpyDeviceToDevice, st));
     } else {
-      ls_status s2 = apply_op(h, (const double *)x, (double *)t, nrhs, n, o.mode, o.flexible ? LS_FP64 : o.matvec, st);
+      const ls_precision pr = (o.flexible || o.relax_eps > 0) ? LS_FP64 : o.matvec;
+      ls_status s2 = apply_op(h, (const double *)x, (double *)t, nrhs, n, o.mode, pr, st);
       if (s2 != LS_OK) return s2;
-      if (o.flexible || o.matvec == LS_FP64) ++res.n_fp64; else ++res.n_mixed;
+      if (pr == LS_FP64) ++res.n_fp64; else ++res.n_mixed;
       axpy_kernel<<<gv, kBlock, 0, st>>>(n, b, n, -1.0, t, n, r, n);
       HIPTRY(hipGetLastError());
     }
@@ -395,7 +397,7 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
       if (o.flexible) {
         // z_j ~ L^{-1} v_j by an inner GMRES with the mixed-precision operator, then w = L z_j
         double2 *zj = ws->Z.vec(j, n, nrhs);
-        CoreOpts io{o.inner_tol, o.inner_maxit, 0, o.mode, LS_MIXED, false, 0.0, 0, false};
+        CoreOpts io{o.inner_tol, o.inner_maxit, 0, o.mode, LS_MIXED, false, 0.0, 0, false, 0.0};
         CoreResult ir;
         ls_status s2 = gmres_core(h, ws_inner, nullptr, vj, zj, nrhs, io, ir, st);
         if (s2 < 0) return s2;
@@ -406,9 +408,19 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
         ++res.n_fp64;
         tbl[slot] = r;   // the inner solve used its own pointer table; ours is intact
       } else {
-        ls_status s2 = apply_op(h, (const double *)vj, (double *)w, nrhs, n, o.mode, o.matvec, st);
+        // relaxed inexact Arnoldi: an application error of relative size eps perturbs the
+        // residual by about eps times the current residual, so once the largest active residual
+        // estimate is below tol / eps the cheaper mixed-precision operator is accurate enough
+        ls_precision pj = o.matvec;
+        if (o.relax_eps > 0) {
+          double worst = 0.0;
+          for (int c = 0; c < nrhs; ++c)
+            if (active[c]) worst = std::max(worst, est[c]);
+          pj = worst * o.relax_eps <= o.tol ? LS_MIXED : LS_FP64;
+        }
+        ls_status s2 = apply_op(h, (const double *)vj, (double *)w, nrhs, n, o.mode, pj, st);
         if (s2 != LS_OK) return s2;
-        if (o.matvec == LS_FP64) ++res.n_fp64; else ++res.n_mixed;
+        if (pj == LS_FP64) ++res.n_fp64; else ++res.n_mixed;
       }
       // CGS2 against V[0..j]
       const int nv = j + 1;
@@ -522,12 +534,42 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
   if (o.x0_given)
     HIPTRY(hipMemcpy2DAsync(xs, n * sizeof(double2), x_out, ld * sizeof(double2), n * sizeof(double2), nrhs,
                             hipMemcpyDeviceToDevice, st));
-  const bool flexible = o.prec == LS_MIXED;
-  CoreOpts co{o.tol, o.maxit, o.restart, mode, LS_FP64, flexible,
-              o.inner_tol > 0 ? o.inner_tol : 1e-3, o.inner_maxit > 0 ? o.inner_maxit : 400, o.x0_given != 0};
+  // LS_MIXED: with inner_maxit > 0, flexible GMRES whose preconditioner is inner_maxit steps of
+  // mixed-precision GMRES (to inner_tol); otherwise relaxed GMRES switching to the mixed operator
+  // once the residual is below tol / inner_tol (inner_tol = relative accuracy granted to it),
+  // followed by FP64 refinement passes from the true residual if that missed tol
+  const bool mixed = o.prec == LS_MIXED;
+  const bool flexible = mixed && o.inner_maxit > 0;
+  const double relax = (mixed && !flexible) ? (o.inner_tol > 0 ? o.inner_tol : 1e-3) : 0.0;
+  // the relaxed iteration aims its residual estimate below 0.3 tol so that its FP64 residual,
+  // perturbed by the mixed applications, still meets tol without a (Krylov-space-losing) restart
+  CoreOpts co{relax > 0 ? 0.3 * o.tol : o.tol, o.maxit, o.restart, mode, LS_FP64, flexible,
+              o.inner_tol > 0 ? o.inner_tol : 1e-12, o.inner_maxit, o.x0_given != 0, relax};
   CoreResult res;
   ls_status status = gmres_core(h, ws, wi, bb, xs, nrhs, co, res, st);
   if (status < 0) return status;
+  for (int pass = 0; pass < 3 && relax > 0; ++pass) {
+    // refinement from the FP64 residual for columns the relaxed iteration left above tol
+    int used = 0;
+    for (int c = 0; c < nrhs; ++c) used = std::max(used, res.iters[c]);
+    if (used >= o.maxit) break;
+    CoreOpts ro = co;
+    ro.x0_given = true;
+    ro.tol = o.tol;
+    ro.maxit = o.maxit - used;
+    CoreResult rr;
+    status = gmres_core(h, ws, wi, bb, xs, nrhs, ro, rr, st);
+    if (status < 0) return status;
+    int more = 0;
+    for (int c = 0; c < nrhs; ++c) {
+      res.iters[c] += rr.iters[c];
+      res.done[c] = rr.done[c];
+      more += rr.iters[c];
+    }
+    res.n_fp64 += rr.n_fp64;
+    res.n_mixed += rr.n_mixed;
+    if (more == 0) break;   // every column met tol on its FP64 residual
+  }
   // true residuals with the FP64 apply
   ls_status s2 = apply_op(h, (const double *)xs, (double *)t, nrhs, n, mode, LS_FP64, st);
   if (s2 != LS_OK) return s2;

@@ -112,12 +112,27 @@ def test_mixed_flexible_gmres_reaches_fp64_accuracy(name, tol):
     true FP64 residual meets tol and the solution matches dense LU accordingly."""
     p, c, op = _golden_op(name)
     b = torch.tensor(c["b"], device="cuda")
-    x, info = op.solve(b, tol=tol, maxit=100, precision="mixed", inner_tol=1e-3)
+    x, info = op.solve(b, tol=tol, maxit=100, precision="mixed", inner_tol=1e-3, inner_maxit=400)
     e = relmax(x.cpu().numpy(), c["u"])
     print(f"{name}: mixed outer iters {info['iters']} relres {info['relres']} applies fp64 {info['n_apply_fp64']} "
           f"mixed {info['n_apply_mixed']} vs LU {e:.2e}", flush=True)
     assert info["converged"] and np.all(info["relres"] <= 1.5 * tol)
     assert e <= 1e3 * tol
     # batched columns through the tile path converge column by column as well
-    xb, ib = op.solve(b.repeat(9, 1), tol=tol, maxit=100, precision="mixed", inner_tol=1e-3)
+    xb, ib = op.solve(b.repeat(9, 1), tol=tol, maxit=100, precision="mixed", inner_tol=1e-3, inner_maxit=400)
     assert ib["converged"] and np.all(ib["relres"] <= 1.5 * tol)
+
+
+@pytest.mark.parametrize("name,tol", [("disk2500", 1e-10), ("twomat1040", 1e-9)])
+@pytest.mark.parametrize("B", [1, 17])
+def test_mixed_relaxed_gmres(name, tol, B):
+    """Relaxed GMRES: FP64 applications until the residual is below tol / eps, FP32-tile ones
+    after, FP64 refinement from the true residual; must meet tol on the FP64 residual."""
+    p, c, op = _golden_op(name)
+    b = torch.tensor(c["b"], device="cuda").repeat(9, 1)[:B]
+    x, info = op.solve(b, tol=tol, maxit=2000, precision="mixed")
+    e = relmax(x.cpu().numpy(), np.concatenate([c["u"]] * 9)[:B])
+    print(f"{name} B={B}: relaxed iters {info['iters'][:2]} applies fp64 {info['n_apply_fp64'] // B} "
+          f"mixed {info['n_apply_mixed'] // B} relres {info['relres'].max():.2e} vs LU {e:.2e}", flush=True)
+    assert info["converged"] and np.all(info["relres"] <= 1.5 * tol) and info["n_apply_mixed"] > 0
+    assert e <= 1e3 * tol
