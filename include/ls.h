@@ -151,6 +151,28 @@ ls_status ls_solve_gmres(ls_handle h, const double *b, double *x, int32_t nrhs, 
 ls_status ls_grad_contrast(ls_handle h, const double *u, const double *lam, const double *a,
                            int32_t nrhs, int64_t ld, double *grad, hipStream_t stream);
 
+/* Far field of scatterer s at R receiver angles thetas (host array):
+ *   uinf[d*R + r] = -k^2 gamma sum_q w_q exp(-i k (cos t_r, sin t_r).y_q) m_q u_qd,
+ *   gamma = exp(i pi/4)/sqrt(8 pi k)
+ * (the far-field pattern of the scattered part of the representation formula, Section 2, in the
+ * normalisation of the energy balance of Section 5).  u: device, nrhs columns with leading
+ * dimension ld.  uinf: device, nrhs x R complex.  If data (device, nrhs x R) is given, res
+ * (device, may be NULL) receives uinf - data and *misfit (host, may be NULL) the value
+ * 1/2 sum |uinf - data|^2, in which case the call synchronises the stream. */
+ls_status ls_farfield(ls_handle h, int32_t s, const double *u, int32_t nrhs, int64_t ld, const double *thetas,
+                      int32_t R, const double *data, double *uinf, double *res, double *misfit,
+                      hipStream_t stream);
+
+/* Adjoint of the far-field map of scatterer s: a = A^H res and rhs = conj(m) a (the right-hand
+ * side of the adjoint solve L^H lam = conj(m) a), each written for scatterer s's nodes of nrhs
+ * columns with leading dimension ld (device; either may be NULL). */
+ls_status ls_farfield_adjoint(ls_handle h, int32_t s, const double *res, int32_t nrhs, int64_t ld,
+                              const double *thetas, int32_t R, double *a, double *rhs, hipStream_t stream);
+
+/* Replace the contrast m = 1 - n of every scatterer (device, caller order, interleaved complex,
+ * total nodes).  The correction C depends only on the geometry and k, so it is kept. */
+ls_status ls_set_contrast(ls_handle h, const double *m, hipStream_t stream);
+
 /* Introspection. */
 int64_t ls_num_nodes(ls_handle h);                       /* total nodes */
 int32_t ls_num_scatterers(ls_handle h);

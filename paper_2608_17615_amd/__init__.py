@@ -91,6 +91,9 @@ def lib():
         L.ls_export_correction.argtypes = [vp, i32, vp, vp, vp]
         L.ls_eval_green.argtypes = [vp, vp, i64, i32, vp]
         L.ls_eval_green_host.argtypes = [vp, vp, i64]
+        L.ls_farfield.argtypes = [vp, i32, vp, i32, i64, vp, i32, vp, vp, vp, vp, vp]
+        L.ls_farfield_adjoint.argtypes = [vp, i32, vp, i32, i64, vp, i32, vp, vp, vp]
+        L.ls_set_contrast.argtypes = [vp, vp, vp]
         L.ls_profile_enable.argtypes = [vp, i32]
         L.ls_profile_query.argtypes = [vp, vp, i32]
         L.ls_destroy.argtypes = [vp]
@@ -245,6 +248,49 @@ class Operator:
                                       g.data_ptr(), _stream()), self._h)
         return g
 
+    def set_contrast(self, m):
+        """Replace the contrast (CUDA tensor of all nodes, real or complex); C is kept."""
+        import torch
+        mc = m.to(torch.complex128).contiguous()
+        if mc.numel() != self.n or not mc.is_cuda:
+            raise ValueError(f"expected a CUDA tensor with {self.n} entries")
+        _check(lib().ls_set_contrast(self._h, mc.data_ptr(), _stream()), self._h)
+        self._m_keep = mc
+
+    def farfield(self, u, thetas, data=None, s=0):
+        """Far-field pattern of scatterer s at angles thetas; with data also the residual and
+        the misfit 1/2 sum |uinf - data|^2.  Returns (uinf, res or None, J or None)."""
+        import torch
+        u2 = self._cols(u)
+        th = np.ascontiguousarray(thetas, dtype=np.float64)
+        B, R = u2.shape[0], th.size
+        uinf = torch.empty((B, R), dtype=torch.complex128, device=u2.device)
+        res = J = None
+        dptr = None
+        if data is not None:
+            data = data.to(torch.complex128).reshape(B, R).contiguous()
+            res = torch.empty_like(uinf)
+            dptr = data.data_ptr()
+            Jh = ctypes.c_double()
+        _check(lib().ls_farfield(self._h, s, u2.data_ptr(), B, self.n, th.ctypes.data, R, dptr, uinf.data_ptr(),
+                                 res.data_ptr() if res is not None else None,
+                                 ctypes.byref(Jh) if data is not None else None, _stream()), self._h)
+        if data is not None:
+            J = Jh.value
+        return uinf, res, J
+
+    def farfield_adjoint(self, res, thetas, s=0):
+        """(a, rhs) with a = A^H res and rhs = conj(m) a on scatterer s (zero elsewhere)."""
+        import torch
+        th = np.ascontiguousarray(thetas, dtype=np.float64)
+        res = res.to(torch.complex128).contiguous()
+        B = res.shape[0]
+        a = torch.zeros((B, self.n), dtype=torch.complex128, device=res.device)
+        rhs = torch.zeros_like(a)
+        _check(lib().ls_farfield_adjoint(self._h, s, res.data_ptr(), B, self.n, th.ctypes.data, th.size,
+                                         a.data_ptr(), rhs.data_ptr(), _stream()), self._h)
+        return a, rhs
+
     def profile(self, enable=None, reset=False):
         """Turn kernel timing on/off (enable=True/False) or read the totals (enable=None)."""
         if enable is not None:
@@ -285,3 +331,42 @@ def eval_green_host(z2):
     g = np.empty(z2.shape, dtype=np.complex128)
     _check(lib().ls_eval_green_host(z2.ctypes.data, g.ctypes.data, z2.size))
     return g
+
+
+def _autograd():
+    import torch
+
+    class FarFieldMisfit(torch.autograd.Function):
+        """J(m) = 1/2 sum_{d,r} |u_inf,d(theta_r) - data_{d,r}|^2 with L(m) u_d = b_d.
+
+        forward: set the contrast, solve, far field and misfit; only the converged fields u and the
+        far-field residual are kept (no Krylov vectors).  backward: a = A^H res, adjoint solve
+        L^H lam = conj(m) a, grad_j = sum_d Re[conj(a_jd - k^2 (V^H lam_d)_j) u_jd].
+        """
+
+        @staticmethod
+        def forward(ctx, m, op, b, data, thetas, tol, maxit, precision):
+            op.set_contrast(m)
+            u, info = op.solve(b, tol=tol, maxit=maxit, precision=precision)
+            _, res, J = op.farfield(u, thetas, data)
+            ctx.op, ctx.thetas, ctx.tol, ctx.maxit, ctx.precision = op, thetas, tol, maxit, precision
+            ctx.solve_info = info
+            ctx.save_for_backward(m, u, res)
+            return torch.tensor(J, dtype=torch.float64, device=m.device)
+
+        @staticmethod
+        def backward(ctx, gJ):
+            m, u, res = ctx.saved_tensors
+            op = ctx.op
+            op.set_contrast(m)
+            a, rhs = op.farfield_adjoint(res, ctx.thetas)
+            lam, _ = op.solve(rhs, tol=ctx.tol, maxit=ctx.maxit, precision=ctx.precision, adjoint=True)
+            g = op.grad_contrast(u, lam, a)
+            return gJ * g, None, None, None, None, None, None, None
+
+    return FarFieldMisfit
+
+
+def farfield_misfit(m, op, b, data, thetas, tol=1e-10, maxit=2000, precision="fp64"):
+    """Differentiable far-field misfit J(m) (real contrast m as a float64 CUDA tensor)."""
+    return _autograd().apply(m, op, b, data, thetas, tol, maxit, precision)

@@ -215,6 +215,7 @@ void ls_destroy(ls_handle h) {
   (void)hipDeviceSynchronize();
   for (void *p : h->owned) (void)hipFree(p);
   if (h->ws_apply.ptr) (void)hipFree(h->ws_apply.ptr);
+  if (h->ws_ff.ptr) (void)hipFree(h->ws_ff.ptr);
   lsk::free_solve_ws(h);
   for (hipEvent_t e : h->ev_far) (void)hipEventDestroy(e);
   for (hipEvent_t e : h->ev_apply) (void)hipEventDestroy(e);
@@ -466,6 +467,73 @@ ls_status ls_profile_query(ls_handle h, ls_profile *out, int32_t reset) {
     h->ev_far.clear();
     h->ev_apply.clear();
   }
+  return LS_OK;
+}
+
+static ls_status ensure_ws(ls_ctx *h, lsk::Workspace &w, size_t need, hipStream_t st) {
+  if (need <= w.bytes) return LS_OK;
+  if (w.ptr) {
+    HIPCHK(h, hipStreamSynchronize(st));
+    HIPCHK(h, hipFree(w.ptr));
+    w.ptr = nullptr;
+    w.bytes = 0;
+  }
+  if (hipMalloc(&w.ptr, need) != hipSuccess) return fail(h, LS_ERR_ALLOC, "workspace allocation failed");
+  w.bytes = need;
+  return LS_OK;
+}
+
+ls_status ls_farfield(ls_handle h, int32_t s, const double *u, int32_t nrhs, int64_t ld, const double *thetas,
+                      int32_t R, const double *data, double *uinf, double *res, double *misfit, hipStream_t stream) {
+  if (!h) return fail(nullptr, LS_ERR_ARG, "null handle");
+  if (s < 0 || s >= (int32_t)h->sc.size()) return fail(h, LS_ERR_ARG, "bad scatterer index");
+  if (nrhs < 1 || R < 1 || !u || !thetas || !uinf) return fail(h, LS_ERR_ARG, "bad argument");
+  if (ld < h->n_total) return fail(h, LS_ERR_ARG, "ld < number of nodes");
+  if ((res || misfit) && !data) return fail(h, LS_ERR_ARG, "res and misfit need data");
+  for (int r = 0; r < R; ++r)
+    if (!std::isfinite(thetas[r])) return fail(h, LS_ERR_NONFINITE, "non-finite angle");
+  const Scat &sc = h->sc[s];
+  const size_t need = lsk::farfield_workspace_bytes(sc.n, R, nrhs);
+  ls_status st = ensure_ws(h, h->ws_ff, need, stream);
+  if (st != LS_OK) return st;
+  // angles at the end of the workspace, residual buffer before them when the caller gave none
+  const size_t th_off = (need - sizeof(double) * R - 256) & ~(size_t)255;
+  const size_t res_off = (th_off - sizeof(double2) * (size_t)R * nrhs - 256) & ~(size_t)255;
+  double *th = (double *)((char *)h->ws_ff.ptr + th_off);
+  double2 *res_tmp = (double2 *)((char *)h->ws_ff.ptr + res_off);
+  HIPCHK(h, hipMemcpyAsync(th, thetas, sizeof(double) * R, hipMemcpyHostToDevice, stream));
+  double *resp = res ? res : (data ? (double *)res_tmp : nullptr);
+  HIPCHK(h, lsk::launch_farfield(sc, u, nrhs, ld, th, R, data, uinf, resp, h->ws_ff.ptr, stream));
+  if (misfit) {
+    std::vector<double> hr(2 * (size_t)R * nrhs);
+    HIPCHK(h, hipMemcpyAsync(hr.data(), resp, sizeof(double) * hr.size(), hipMemcpyDeviceToHost, stream));
+    HIPCHK(h, hipStreamSynchronize(stream));
+    double J = 0.0;
+    for (double v : hr) J += v * v;
+    *misfit = 0.5 * J;
+  }
+  return LS_OK;
+}
+
+ls_status ls_farfield_adjoint(ls_handle h, int32_t s, const double *res, int32_t nrhs, int64_t ld,
+                              const double *thetas, int32_t R, double *a, double *rhs, hipStream_t stream) {
+  if (!h) return fail(nullptr, LS_ERR_ARG, "null handle");
+  if (s < 0 || s >= (int32_t)h->sc.size()) return fail(h, LS_ERR_ARG, "bad scatterer index");
+  if (nrhs < 1 || R < 1 || !res || !thetas || (!a && !rhs)) return fail(h, LS_ERR_ARG, "bad argument");
+  if (ld < h->n_total) return fail(h, LS_ERR_ARG, "ld < number of nodes");
+  const Scat &sc = h->sc[s];
+  const size_t need = lsk::farfield_workspace_bytes(sc.n, R, nrhs);
+  ls_status st = ensure_ws(h, h->ws_ff, need, stream);
+  if (st != LS_OK) return st;
+  double *th = (double *)((char *)h->ws_ff.ptr + ((need - sizeof(double) * R - 256) & ~(size_t)255));
+  HIPCHK(h, hipMemcpyAsync(th, thetas, sizeof(double) * R, hipMemcpyHostToDevice, stream));
+  HIPCHK(h, lsk::launch_farfield_adjoint(sc, res, nrhs, ld, th, R, a, rhs, stream));
+  return LS_OK;
+}
+
+ls_status ls_set_contrast(ls_handle h, const double *m, hipStream_t stream) {
+  if (!h || !m) return fail(h, LS_ERR_ARG, "null argument");
+  for (const Scat &sc : h->sc) HIPCHK(h, lsk::launch_set_contrast(sc, m, stream));
   return LS_OK;
 }
 

@@ -46,7 +46,7 @@ struct ls_ctx {
   int device = 0;
   ls_options opt{};
   std::string err;
-  lsk::Workspace ws_apply, ws_solve;
+  lsk::Workspace ws_apply, ws_solve, ws_ff;
   std::vector<void *> owned;  // device allocations freed by ls_destroy
 };
 
@@ -81,6 +81,13 @@ ls_status solve_gmres(ls_ctx *h, const double *b, double *x, int nrhs, int64_t l
 ls_status grad_contrast(ls_ctx *h, const double *u, const double *lam, const double *a, int nrhs, int64_t ld,
                         double *grad, hipStream_t st);
 void free_solve_ws(ls_ctx *h);
+// farfield.hip
+size_t farfield_workspace_bytes(int64_t n, int R, int nrhs);
+hipError_t launch_farfield(const Scat &s, const double *u, int nrhs, int64_t ld, const double *th_dev, int R,
+                           const double *data, double *uinf, double *res, void *ws, hipStream_t st);
+hipError_t launch_farfield_adjoint(const Scat &s, const double *res, int nrhs, int64_t ld, const double *th_dev,
+                                   int R, double *a, double *rhs, hipStream_t st);
+hipError_t launch_set_contrast(const Scat &s, const double *m_caller, hipStream_t st);
 int auto_source_split(int64_t n, int nrhs, int launches_per_split, int tpl);
 
 }  // namespace lsk
