@@ -173,6 +173,19 @@ ls_status ls_farfield_adjoint(ls_handle h, int32_t s, const double *res, int32_t
  * total nodes).  The correction C depends only on the geometry and k, so it is kept. */
 ls_status ls_set_contrast(ls_handle h, const double *m, hipStream_t stream);
 
+/* Batched matrix-core sum over several scatterers (handles with n_scatterers > 1 and either
+ * LS_MIXED or the FP64 tiles): the tile shape is mt 16-target tiles per wavefront (FP32: 2 or 4,
+ * FP64: 1 or 2) and split_len sources per work item.  ls_autotune times the candidate shapes on
+ * this handle's own geometry for nrhs right-hand sides (far sum only, synchronous) and keeps the
+ * fastest for later applications; ls_set_tile_shape sets one directly (e.g. from a cache). */
+typedef struct {
+  int32_t mt;
+  int32_t split_len;
+  double far_ms;
+} ls_tune_result;
+ls_status ls_autotune(ls_handle h, int32_t nrhs, ls_precision p, ls_tune_result *out, hipStream_t stream);
+ls_status ls_set_tile_shape(ls_handle h, ls_precision p, int32_t mt, int32_t split_len);
+
 /* Introspection. */
 int64_t ls_num_nodes(ls_handle h);                       /* total nodes */
 int32_t ls_num_scatterers(ls_handle h);

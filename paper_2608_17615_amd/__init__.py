@@ -50,6 +50,10 @@ class _Profile(ctypes.Structure):
                 ("apply_ms", ctypes.c_double)]
 
 
+class _TuneResult(ctypes.Structure):
+    _fields_ = [("mt", ctypes.c_int32), ("split_len", ctypes.c_int32), ("far_ms", ctypes.c_double)]
+
+
 class _Options(ctypes.Structure):
     _fields_ = [("source_split", ctypes.c_int32), ("rhs_chunk", ctypes.c_int32),
                 ("targets_per_lane", ctypes.c_int32), ("mixed_tile", ctypes.c_int32),
@@ -94,6 +98,8 @@ def lib():
         L.ls_farfield.argtypes = [vp, i32, vp, i32, i64, vp, i32, vp, vp, vp, vp, vp]
         L.ls_farfield_adjoint.argtypes = [vp, i32, vp, i32, i64, vp, i32, vp, vp, vp]
         L.ls_set_contrast.argtypes = [vp, vp, vp]
+        L.ls_autotune.argtypes = [vp, i32, i32, vp, vp]
+        L.ls_set_tile_shape.argtypes = [vp, i32, i32, i32]
         L.ls_profile_enable.argtypes = [vp, i32]
         L.ls_profile_query.argtypes = [vp, vp, i32]
         L.ls_destroy.argtypes = [vp]
@@ -290,6 +296,38 @@ class Operator:
         _check(lib().ls_farfield_adjoint(self._h, s, res.data_ptr(), B, self.n, th.ctypes.data, th.size,
                                          a.data_ptr(), rhs.data_ptr(), _stream()), self._h)
         return a, rhs
+
+    def autotune(self, nrhs, precision="mixed", cache=None):
+        """Pick the batched tile shape for nrhs right-hand sides by timing candidates on this
+        handle's geometry (see ls_autotune).  With cache (a JSON path) the choice is read from /
+        written to a table keyed by GPU architecture, size bucket, scatterer count, nrhs and
+        precision.  Returns (mt, split_len, far_ms or None when taken from the cache)."""
+        import json
+        import math
+
+        import torch
+        arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
+        key = f"{arch}|n2^{int(math.log2(max(self.n, 1)))}|s{self.n_scatterers}|b{nrhs}|{precision}"
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+        if key in table:
+            mt, sl = table[key]
+            _check(lib().ls_set_tile_shape(self._h, _PREC[precision], mt, sl), self._h)
+            return mt, sl, None
+        r = _TuneResult()
+        _check(lib().ls_autotune(self._h, int(nrhs), _PREC[precision], ctypes.byref(r), _stream()), self._h)
+        if cache:
+            table[key] = [r.mt, r.split_len]
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return r.mt, r.split_len, r.far_ms
+
+    def set_tile_shape(self, mt, split_len, precision="mixed"):
+        _check(lib().ls_set_tile_shape(self._h, _PREC[precision], int(mt), int(split_len)), self._h)
 
     def profile(self, enable=None, reset=False):
         """Turn kernel timing on/off (enable=True/False) or read the totals (enable=None)."""

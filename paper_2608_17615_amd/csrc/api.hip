@@ -216,6 +216,7 @@ void ls_destroy(ls_handle h) {
   for (void *p : h->owned) (void)hipFree(p);
   if (h->ws_apply.ptr) (void)hipFree(h->ws_apply.ptr);
   if (h->ws_ff.ptr) (void)hipFree(h->ws_ff.ptr);
+  if (h->batch_tables) (void)hipFree(h->batch_tables);
   lsk::free_solve_ws(h);
   for (hipEvent_t e : h->ev_far) (void)hipEventDestroy(e);
   for (hipEvent_t e : h->ev_apply) (void)hipEventDestroy(e);
@@ -338,12 +339,19 @@ ls_status apply_op(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, 
     return tiles ? lsk::tile_source_split(sc.n, nrhs, single)
                  : lsk::auto_source_split(sc.n, nrhs, std::max(1, nrhs / chunk), tpl);
   };
+  // several scatterers on the matrix cores: one persistent launch over all of them
+  const bool batch = tiles && h->sc.size() > 1;
+  const lsk::TileTune &tt = h->tune[single ? 1 : 0];
+  const int bmt = h->opt.mixed_tile > 0 ? h->opt.mixed_tile : (tt.mt > 0 ? tt.mt : (single ? 4 : 2));
+  const int bsplit = tt.split_len > 0 ? tt.split_len : lsk::batch_default_split_len(h, single);
   size_t need = 0;
-  for (const Scat &sc : h->sc) {
-    const int nsplit = splits(sc);
-    need = std::max(need, tiles ? lsk::tile_workspace_bytes(sc.n, nrhs, nsplit)
-                                : lsk::apply_workspace_bytes(sc.n, nrhs, nsplit));
-  }
+  if (batch) need = lsk::batch_workspace_bytes(h, nrhs, single, bsplit);
+  else
+    for (const Scat &sc : h->sc) {
+      const int nsplit = splits(sc);
+      need = std::max(need, tiles ? lsk::tile_workspace_bytes(sc.n, nrhs, nsplit)
+                                  : lsk::apply_workspace_bytes(sc.n, nrhs, nsplit));
+    }
   if (need > h->ws_apply.bytes) {
     if (h->ws_apply.ptr) {
       HIPCHK(h, hipStreamSynchronize(stream));
@@ -360,7 +368,18 @@ ls_status apply_op(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, 
     HIPCHK(h, hipEventCreate(&a1));
     HIPCHK(h, hipEventRecord(a0, stream));
   }
+  if (batch) {
+    hipEvent_t f0 = nullptr, f1 = nullptr;
+    if (h->prof) {
+      HIPCHK(h, hipEventCreate(&f0));
+      HIPCHK(h, hipEventCreate(&f1));
+      h->ev_far.push_back(f0);
+      h->ev_far.push_back(f1);
+    }
+    HIPCHK(h, lsk::launch_apply_batch(h, x, y, nrhs, ld, mode, single, bmt, bsplit, h->ws_apply.ptr, stream, f0, f1));
+  }
   for (const Scat &sc : h->sc) {
+    if (batch) break;
     const int nsplit = splits(sc);
     hipEvent_t f0 = nullptr, f1 = nullptr;
     if (h->prof) {
@@ -528,6 +547,58 @@ ls_status ls_farfield_adjoint(ls_handle h, int32_t s, const double *res, int32_t
   double *th = (double *)((char *)h->ws_ff.ptr + ((need - sizeof(double) * R - 256) & ~(size_t)255));
   HIPCHK(h, hipMemcpyAsync(th, thetas, sizeof(double) * R, hipMemcpyHostToDevice, stream));
   HIPCHK(h, lsk::launch_farfield_adjoint(sc, res, nrhs, ld, th, R, a, rhs, stream));
+  return LS_OK;
+}
+
+ls_status ls_autotune(ls_handle h, int32_t nrhs, ls_precision p, ls_tune_result *out, hipStream_t stream) {
+  if (!h || nrhs < 1 || (p != LS_FP64 && p != LS_MIXED)) return fail(h, LS_ERR_ARG, "bad argument");
+  const bool single = p == LS_MIXED;
+  const int mts[2] = {single ? 2 : 1, single ? 4 : 2};
+  const int lens[4] = {1024, 2048, 4096, 8192};
+  size_t need = 0;
+  for (int L : lens) need = std::max(need, lsk::batch_workspace_bytes(h, nrhs, single, L));
+  ls_status st = ensure_ws(h, h->ws_apply, need, stream);
+  if (st != LS_OK) return st;
+  HIPCHK(h, hipMemsetAsync(h->ws_apply.ptr, 0, need, stream));
+  hipEvent_t e0, e1;
+  HIPCHK(h, hipEventCreate(&e0));
+  HIPCHK(h, hipEventCreate(&e1));
+  lsk::TileTune best;
+  best.ms = 1e300;
+  for (int mt : mts)
+    for (int L : lens) {
+      // one untimed launch, then the mean of two timed ones (far sum only, all scatterers)
+      float ms = 0.f, tot = 0.f;
+      for (int rep = 0; rep < 3; ++rep) {
+        HIPCHK(h, lsk::launch_apply_batch(h, nullptr, nullptr, nrhs, h->n_total, lsk::Mode::Forward, single, mt, L,
+                                          h->ws_apply.ptr, stream, rep ? e0 : nullptr, rep ? e1 : nullptr, true));
+        if (rep) {
+          HIPCHK(h, hipEventSynchronize(e1));
+          HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
+          tot += ms;
+        }
+      }
+      if (tot / 2 < best.ms) best = lsk::TileTune{mt, L, tot / 2.0};
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->tune[single ? 1 : 0] = best;
+  h->batch_key = -1;
+  if (out) {
+    out->mt = best.mt;
+    out->split_len = best.split_len;
+    out->far_ms = best.ms;
+  }
+  return LS_OK;
+}
+
+ls_status ls_set_tile_shape(ls_handle h, ls_precision p, int32_t mt, int32_t split_len) {
+  if (!h || (p != LS_FP64 && p != LS_MIXED)) return fail(h, LS_ERR_ARG, "bad argument");
+  const bool single = p == LS_MIXED;
+  const bool mt_ok = single ? (mt == 2 || mt == 4) : (mt == 1 || mt == 2);
+  if (!mt_ok || split_len < 64) return fail(h, LS_ERR_ARG, "unsupported tile shape");
+  h->tune[single ? 1 : 0] = lsk::TileTune{mt, split_len, 0.0};
+  h->batch_key = -1;
   return LS_OK;
 }
 

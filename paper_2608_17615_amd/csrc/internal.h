@@ -31,6 +31,25 @@ struct Scat {
   std::vector<int32_t> perm_host;   // same as perm, on the host
 };
 
+// One scatterer of a batched launch and one unit of its far-sum work.
+struct BatchDesc {
+  int n, split_len;
+  double k2;
+  const double2 *pos;
+  const void *X;
+  double2 *part;
+};
+struct WorkItem {
+  int s, tblock, split, bgroup;
+};
+
+// Tile shape of the batched matrix-core sum: MT 16-target tiles per wavefront and the number of
+// sources per work item; chosen by ls_autotune (0 = defaults).
+struct TileTune {
+  int mt = 0, split_len = 0;
+  double ms = 0.0;
+};
+
 struct Workspace {
   void *ptr = nullptr;
   size_t bytes = 0;
@@ -47,6 +66,10 @@ struct ls_ctx {
   ls_options opt{};
   std::string err;
   lsk::Workspace ws_apply, ws_solve, ws_ff;
+  lsk::TileTune tune[2];                 // [single]
+  void *batch_tables = nullptr;          // device BatchDesc[] + WorkItem[] + counter
+  size_t batch_bytes = 0;
+  long long batch_key = -1;              // configuration the cached tables describe
   std::vector<void *> owned;  // device allocations freed by ls_destroy
 };
 
@@ -68,6 +91,11 @@ size_t tile_workspace_bytes(int64_t n, int nrhs, int nsplit);
 int tile_source_split(int64_t n, int nrhs, bool single);
 hipError_t launch_apply_tile(const Scat &s, const double *x, double *y, int nrhs, int64_t ld, Mode mode, bool single,
                              int nsplit, void *ws, hipStream_t st, hipEvent_t far_start, hipEvent_t far_stop);
+size_t batch_workspace_bytes(const ls_ctx *h, int nrhs, bool single, int split_len);
+hipError_t launch_apply_batch(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, Mode mode, bool single,
+                              int mt, int split_len, void *ws, hipStream_t st, hipEvent_t far_start,
+                              hipEvent_t far_stop, bool far_only = false);
+int batch_default_split_len(const ls_ctx *h, bool single);
 hipError_t launch_eval_green(const double *z2, double *g, int64_t n, int single, hipStream_t st);
 void eval_green_host(const double *z2, double *g, int64_t n);
 

@@ -12,6 +12,9 @@
 //                accumulation within one source split; splits are summed in FP64 by the epilogue.
 // Result rows: FP32 tiles return D[4 (l/16) + r][l % 16], FP64 tiles D[l/16 + 4 r][l % 16]
 // (r = accumulator register), both verified on gfx950.
+#include <algorithm>
+#include <vector>
+
 #include "hankel.h"
 #include "internal.h"
 
@@ -90,18 +93,17 @@ __global__ __launch_bounds__(kBlock) void prologue_tile_kernel(int64_t n, int nr
   }
 }
 
-// grid: (ceil(n / (4 * 16 * MT)), source splits, ldx / (16 * NT))
+// One wavefront's work: targets [t0, t0 + 16 MT), right-hand sides [b0, b0 + 16 NT), sources
+// [s0, s1) of one split; writes that split's FP64 partial sums part[(split * nrhs + b) * n + t].
 template <class T, int MT, int NT, bool CONJ>
-__global__ __launch_bounds__(kBlock) void far_tile_kernel(int n, const double2 *__restrict__ pos,
-                                                          const typename Tile<T>::cplx_t *__restrict__ X, int ldx,
-                                                          int nrhs, double k2, int split_len,
-                                                          double2 *__restrict__ part) {
+__device__ __forceinline__ void tile_body(int n, const double2 *__restrict__ pos,
+                                          const typename Tile<T>::cplx_t *__restrict__ X, int ldx, int nrhs,
+                                          double k2, int s0, int s1, int t0, int b0, int split,
+                                          double2 *__restrict__ part) {
   typedef Tile<T> TL;
   typedef typename TL::acc_t acc_t;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   const int kk = lane >> 4, col = lane & 15;
-  const int t0 = (blockIdx.x * 4 + wave) * 16 * MT;
-  const int b0 = blockIdx.z * 16 * NT;
   int tm[MT];
   double xt[MT], yt[MT];
 #pragma unroll
@@ -119,8 +121,6 @@ __global__ __launch_bounds__(kBlock) void far_tile_kernel(int n, const double2 *
       ar[mi][ni] = acc_t{0, 0, 0, 0};
       ai[mi][ni] = acc_t{0, 0, 0, 0};
     }
-  const int s0 = blockIdx.y * split_len;
-  const int s1 = min(n, s0 + split_len);
   for (int s = s0; s < s1; s += 4) {
     const int src = s + kk;
     const bool ok = src < s1;
@@ -163,8 +163,45 @@ __global__ __launch_bounds__(kBlock) void far_tile_kernel(int n, const double2 *
         const int t = t0 + 16 * mi + TL::row(lane, r);
         const int b = b0 + 16 * ni + col;
         if (t < n && b < nrhs)
-          part[((int64_t)blockIdx.y * nrhs + b) * n + t] = make_double2((double)ar[mi][ni][r], (double)ai[mi][ni][r]);
+          part[((int64_t)split * nrhs + b) * n + t] = make_double2((double)ar[mi][ni][r], (double)ai[mi][ni][r]);
       }
+}
+
+// grid: (ceil(n / (4 * 16 * MT)), source splits, ldx / (16 * NT))
+template <class T, int MT, int NT, bool CONJ>
+__global__ __launch_bounds__(kBlock) void far_tile_kernel(int n, const double2 *__restrict__ pos,
+                                                          const typename Tile<T>::cplx_t *__restrict__ X, int ldx,
+                                                          int nrhs, double k2, int split_len,
+                                                          double2 *__restrict__ part) {
+  const int wave = threadIdx.x >> 6;
+  const int s0 = blockIdx.y * split_len;
+  tile_body<T, MT, NT, CONJ>(n, pos, X, ldx, nrhs, k2, s0, min(n, s0 + split_len),
+                             (blockIdx.x * 4 + wave) * 16 * MT, blockIdx.z * 16 * NT, blockIdx.y, part);
+}
+
+// Uneven batch of scatterers in one launch: each workgroup repeatedly takes the next work item
+// (scatterer, block of 64 MT targets, source split, RHS group) from a global counter until the
+// list, ordered longest first, is exhausted.  Every item writes its own partials, so the result
+// does not depend on which workgroup took it.
+template <class T, int MT, int NT, bool CONJ>
+__global__ __launch_bounds__(kBlock) void far_tile_persistent(const BatchDesc *__restrict__ desc,
+                                                              const WorkItem *__restrict__ items, int n_items,
+                                                              int *__restrict__ counter, int ldx, int nrhs) {
+  __shared__ int next;
+  const int wave = threadIdx.x >> 6;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = next;
+    __syncthreads();
+    if (it >= n_items) break;
+    const WorkItem wi = items[it];
+    const BatchDesc d = desc[wi.s];
+    const int s0 = wi.split * d.split_len;
+    tile_body<T, MT, NT, CONJ>(d.n, d.pos, (const typename Tile<T>::cplx_t *)d.X, ldx, nrhs, d.k2, s0,
+                               min(d.n, s0 + d.split_len), (wi.tblock * 4 + wave) * 16 * MT, wi.bgroup * 16 * NT,
+                               wi.split, d.part);
+  }
 }
 
 template <class T, int MT, int NT>
@@ -192,9 +229,170 @@ void launch_tile_nt(const Scat &s, const void *X, int ldx, int nrhs, int split_l
     launch_tile<T, MT, 1>(s, X, ldx, nrhs, split_len, nsplit, part, conj, st);
 }
 
+__global__ void zero_counter_kernel(int *c) { *c = 0; }
+
+template <class T, int MT, int NT>
+void launch_persistent(const BatchDesc *desc, const WorkItem *items, int n_items, int *counter, int ldx, int nrhs,
+                       bool conj, hipStream_t st) {
+  // one full round of resident workgroups; each keeps taking items until none are left
+  int dev = 0, cus = 256, per_cu = 1;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (conj)
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, far_tile_persistent<T, MT, NT, true>, kBlock, 0);
+  else
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, far_tile_persistent<T, MT, NT, false>, kBlock, 0);
+  const int grid = std::max(1, std::min(n_items, cus * std::max(per_cu, 1)));
+  zero_counter_kernel<<<1, 1, 0, st>>>(counter);
+  if (conj)
+    far_tile_persistent<T, MT, NT, true><<<grid, kBlock, 0, st>>>(desc, items, n_items, counter, ldx, nrhs);
+  else
+    far_tile_persistent<T, MT, NT, false><<<grid, kBlock, 0, st>>>(desc, items, n_items, counter, ldx, nrhs);
+}
+
+template <class T, int MT>
+void launch_persistent_nt(const BatchDesc *desc, const WorkItem *items, int n_items, int *counter, int ldx, int nrhs,
+                          bool conj, hipStream_t st) {
+  const int groups = ldx / 16;
+  if (groups % 4 == 0)
+    launch_persistent<T, MT, 4>(desc, items, n_items, counter, ldx, nrhs, conj, st);
+  else if (groups % 2 == 0)
+    launch_persistent<T, MT, 2>(desc, items, n_items, counter, ldx, nrhs, conj, st);
+  else
+    launch_persistent<T, MT, 1>(desc, items, n_items, counter, ldx, nrhs, conj, st);
+}
+
+int nt_of(int ldx) { return (ldx / 16) % 4 == 0 ? 4 : ((ldx / 16) % 2 == 0 ? 2 : 1); }
+
 }  // namespace
 
 int tile_ldx(int nrhs) { return (nrhs + 15) / 16 * 16; }
+
+int batch_default_split_len(const ls_ctx *h, bool single) {
+  (void)h;
+  return single ? 4096 : 2048;
+}
+
+// per-scatterer layout of the batch workspace: X_s, f_s, part_s, each 256-byte aligned
+static size_t batch_layout(const ls_ctx *h, int nrhs, bool single, int split_len, std::vector<size_t> *offs) {
+  const int ldx = tile_ldx(nrhs);
+  size_t o = 0;
+  auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  for (const Scat &sc : h->sc) {
+    const int64_t nsplit = (sc.n + split_len - 1) / split_len;
+    if (offs) offs->push_back(o);
+    o = al(o + (single ? sizeof(float2) : sizeof(double2)) * (size_t)sc.n * ldx);
+    if (offs) offs->push_back(o);
+    o = al(o + sizeof(double2) * (size_t)sc.n * nrhs);
+    if (offs) offs->push_back(o);
+    o = al(o + sizeof(double2) * (size_t)sc.n * nrhs * nsplit);
+  }
+  return o + 256;
+}
+
+size_t batch_workspace_bytes(const ls_ctx *h, int nrhs, bool single, int split_len) {
+  return batch_layout(h, nrhs, single, split_len, nullptr);
+}
+
+hipError_t launch_apply_batch(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, Mode mode, bool single,
+                              int mt, int split_len, void *ws, hipStream_t st, hipEvent_t far_start,
+                              hipEvent_t far_stop, bool far_only) {
+  const int ldx = tile_ldx(nrhs);
+  const int nt = nt_of(ldx);
+  const int ns = (int)h->sc.size();
+  std::vector<size_t> offs;
+  batch_layout(h, nrhs, single, split_len, &offs);
+  char *base = (char *)ws;
+  // descriptor and work-item tables, cached for this (layout, shape) combination
+  const long long key = ((((long long)nrhs * 2 + single) * 8 + mt) << 24) ^ (long long)split_len ^
+                        ((long long)(uintptr_t)ws << 1);
+  std::vector<BatchDesc> desc(ns);
+  std::vector<WorkItem> items;
+  for (int i = 0; i < ns; ++i) {
+    const Scat &sc = h->sc[i];
+    const int nsplit = (int)((sc.n + split_len - 1) / split_len);
+    desc[i] = BatchDesc{(int)sc.n, split_len, sc.k * sc.k, sc.pos, base + offs[3 * i], (double2 *)(base + offs[3 * i + 2])};
+    const int tblocks = (int)((sc.n + 64 * mt - 1) / (64 * mt));
+    for (int tb = 0; tb < tblocks; ++tb)
+      for (int sp = 0; sp < nsplit; ++sp)
+        for (int g = 0; g < ldx / (16 * nt); ++g) items.push_back(WorkItem{i, tb, sp, g});
+  }
+  auto cost = [&](const WorkItem &w) {
+    const int64_t n = h->sc[w.s].n;
+    const int64_t t = std::min<int64_t>(64 * mt, n - (int64_t)w.tblock * 64 * mt);
+    const int64_t src = std::min<int64_t>(split_len, n - (int64_t)w.split * split_len);
+    return t * src;
+  };
+  std::stable_sort(items.begin(), items.end(), [&](const WorkItem &a, const WorkItem &b) { return cost(a) > cost(b); });
+  const size_t tb = sizeof(BatchDesc) * ns + sizeof(WorkItem) * items.size() + 512;
+  hipError_t e = hipSuccess;
+  if (tb > h->batch_bytes) {
+    if (h->batch_tables) (void)hipFree(h->batch_tables);
+    h->batch_tables = nullptr;
+    h->batch_bytes = 0;
+    e = hipMalloc(&h->batch_tables, tb);
+    if (e != hipSuccess) return e;
+    h->batch_bytes = tb;
+    h->batch_key = -1;
+  }
+  BatchDesc *ddesc = (BatchDesc *)h->batch_tables;
+  WorkItem *ditems = (WorkItem *)(ddesc + ns);
+  int *counter = (int *)(((uintptr_t)(ditems + items.size()) + 255) & ~(uintptr_t)255);
+  if (h->batch_key != key) {
+    e = hipMemcpyAsync(ddesc, desc.data(), sizeof(BatchDesc) * ns, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(ditems, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);   // host vectors go out of scope
+    if (e != hipSuccess) return e;
+    h->batch_key = key;
+  }
+  const bool fwd = mode == Mode::Forward;
+  const double2 *xc = (const double2 *)x;
+  if (!far_only)
+    for (int i = 0; i < ns; ++i) {
+      const Scat &sc = h->sc[i];
+      const unsigned gp = (unsigned)((sc.n * ldx + kBlock - 1) / kBlock);
+      double2 *f = (double2 *)(base + offs[3 * i + 1]);
+      if (single) {
+        if (fwd)
+          prologue_tile_kernel<float, Mode::Forward><<<gp, kBlock, 0, st>>>(sc.n, nrhs, ldx, sc.perm, sc.w, sc.m, xc, ld,
+                                                                            sc.off, (float2 *)desc[i].X, f);
+        else
+          prologue_tile_kernel<float, Mode::Adjoint><<<gp, kBlock, 0, st>>>(sc.n, nrhs, ldx, sc.perm, sc.w, sc.m, xc, ld,
+                                                                            sc.off, (float2 *)desc[i].X, f);
+      } else {
+        if (fwd)
+          prologue_tile_kernel<double, Mode::Forward><<<gp, kBlock, 0, st>>>(sc.n, nrhs, ldx, sc.perm, sc.w, sc.m, xc,
+                                                                             ld, sc.off, (double2 *)desc[i].X, f);
+        else
+          prologue_tile_kernel<double, Mode::Adjoint><<<gp, kBlock, 0, st>>>(sc.n, nrhs, ldx, sc.perm, sc.w, sc.m, xc,
+                                                                             ld, sc.off, (double2 *)desc[i].X, f);
+      }
+    }
+  if (far_start) (void)hipEventRecord(far_start, st);
+  const int n_items = (int)items.size();
+  if (single) {
+    if (mt == 2)
+      launch_persistent_nt<float, 2>(ddesc, ditems, n_items, counter, ldx, nrhs, !fwd, st);
+    else
+      launch_persistent_nt<float, 4>(ddesc, ditems, n_items, counter, ldx, nrhs, !fwd, st);
+  } else {
+    if (mt == 1)
+      launch_persistent_nt<double, 1>(ddesc, ditems, n_items, counter, ldx, nrhs, !fwd, st);
+    else
+      launch_persistent_nt<double, 2>(ddesc, ditems, n_items, counter, ldx, nrhs, !fwd, st);
+  }
+  if (far_stop) (void)hipEventRecord(far_stop, st);
+  e = hipGetLastError();
+  if (e != hipSuccess || far_only) return e;
+  for (int i = 0; i < ns; ++i) {
+    const Scat &sc = h->sc[i];
+    const int nsplit = (int)((sc.n + split_len - 1) / split_len);
+    e = launch_epilogue(sc, desc[i].part, nsplit, (const double2 *)(base + offs[3 * i + 1]), x, y, nrhs, ld, mode, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 
 size_t tile_workspace_bytes(int64_t n, int nrhs, int nsplit) {
   // X [n][ldx] (double2 upper bound), f [nrhs][n], part [nsplit][nrhs][n]
