@@ -31,6 +31,22 @@ sys.path.insert(0, ROOT)
 FLOPS_PER_PAIR_BASE = 102
 FLOPS_PER_PAIR_PER_RHS = 8
 PEAK_FP64_TFLOPS = 78.6       # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
+# HBM bytes per far-kernel launch in this workload, from two rocprofv3 counter passes
+# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors that make a 1 GiB copy read 1 GiB and write
+# 1 GiB; profiles/far_fp64_two_material_N58500_hbm_counters.md), valid for the kernel sources
+# with this digest only: after any change to them the field is reported as null.
+FAR_TRAFFIC_BYTES = 37_603_000 + 134_780_000
+FAR_TRAFFIC_SOURCES = ("apply.hip", "hankel.h", "hankel_tables.h")
+FAR_TRAFFIC_DIGEST = "cf724259aef9971a"
+
+
+def far_traffic():
+    import hashlib
+    h = hashlib.sha256()
+    for f in FAR_TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2608_17615_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return FAR_TRAFFIC_BYTES if h.hexdigest()[:16] == FAR_TRAFFIC_DIGEST else None
 
 
 def log(msg):
@@ -79,6 +95,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="first run one elementwise kernel that reads and writes BYTES each "
+                         "(calibrates a profiler's HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is described "
@@ -98,6 +117,14 @@ def main():
     import torch
 
     import paper_2608_17615_amd as lsg
+    if args.copy_probe:
+        src = torch.ones(args.copy_probe // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        log(f"copy probe: read and wrote {src.numel() * 8} bytes")
+        del src, dst
     log(f"setup: N={n}")
     t0 = time.perf_counter()
     op = lsg.Operator(lsg.Scatterer.from_mesh(prob.mesh, prob.m, prob.k))
@@ -151,7 +178,7 @@ def main():
                    "far_kernel_ms_avg": far_avg_s * 1e3,
                    "apply_ms_avg": prof["apply_ms"] / max(prof["apply_calls"], 1)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None},
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": far_traffic()},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

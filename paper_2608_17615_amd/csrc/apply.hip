@@ -9,10 +9,10 @@
 //   far      : the punctured Green's sum t_j = sum_{n != j} G(y_j, y_n) s_n over a chunk of
 //              sources.  One target per lane; every lane of a wavefront walks the same source,
 //              whose position and densities are uniform across the wave and are read through the
-//              scalar data path into SGPRs (no LDS staging or barriers needed); G is evaluated in
-//              registers (hankel.h) once per pair and reused for the RHS of the chunk;
-//   epilogue : sum the source-chunk partials in a fixed order (deterministic), add the CSR
-//              correction, apply the diagonal factors and scatter to the caller's order.
+//              scalar data path into SGPRs (no LDS staging or barriers needed); G/K is evaluated
+//              in registers (hankel.h) once per pair and reused for the RHS of the chunk;
+//   epilogue : sum the source-chunk partials in a fixed order (deterministic), scale by K, add
+//              the CSR correction, apply the diagonal factors and scatter to the caller's order.
 #include "hankel.h"
 #include "internal.h"
 
@@ -72,7 +72,7 @@ __device__ __forceinline__ void far_source(int j, const int (&it)[TPL], const do
     const double dx = xt[q] - p.x;
     const double dy = yt[q] - p.y;
     const double A = k2 * std::fma(dx, dx, dy * dy);
-    green(A, gr[q], gi[q], hankel_table());
+    green_unit(A, gr[q], gi[q], hankel_table());
     if (MASKED) {
       const bool self = (j == it[q]);
       gr[q] = self ? 0.0 : gr[q];
@@ -153,10 +153,10 @@ __global__ __launch_bounds__(kBlock) void epilogue_kernel(
     ar += p.x;
     ai += p.y;
   }
-  if (M != Mode::Forward) {
-    ar *= w[i];
-    ai *= w[i];
-  }
+  // the far kernels sum G/K (hankel.h); K and, for the adjoint, the weight are applied here
+  const double gs = M != Mode::Forward ? w[i] * G_SCALE : G_SCALE;
+  ar *= gs;
+  ai *= gs;
   const double2 *fb = f + (int64_t)b * n;
   double cr = 0.0, cim = 0.0;
   for (int64_t q = rp[i]; q < rp[i + 1]; ++q) {
@@ -188,8 +188,8 @@ __global__ void eval_green_kernel(const double *__restrict__ z2, double2 *__rest
   if (i >= n) return;
   if (single) {
     float gr, gi;
-    green32(z2[i], gr, gi, d_hankel);
-    g[i] = make_double2(gr, gi);
+    green32_unit(z2[i], gr, gi, d_hankel);
+    g[i] = make_double2((double)gr * G_SCALE, (double)gi * G_SCALE);
   } else {
     double gr, gi;
     green(z2[i], gr, gi, d_hankel);

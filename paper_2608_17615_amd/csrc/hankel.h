@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstring>
 
 #include "hankel_tables.h"
 
@@ -35,6 +36,22 @@ __host__ __device__ __forceinline__ double fma_uniform(double r, double x, doubl
 #endif
 }
 
+// x + c (or c - x with NEG) with c wave-uniform, kept as a separate add so the compiler does not
+// contract it with the product that formed x (that FMA would need c copied into a VGPR).
+template <bool NEG = false>
+__host__ __device__ __forceinline__ double add_uniform(double x, double c) {
+#ifdef __HIP_DEVICE_COMPILE__
+  double out;
+  if (NEG)
+    asm("v_add_f64 %0, %2, -%1" : "=v"(out) : "v"(x), "s"(c));
+  else
+    asm("v_add_f64 %0, %1, %2" : "=v"(out) : "v"(x), "s"(c));
+  return out;
+#else
+  return NEG ? c - x : x + c;
+#endif
+}
+
 // Horner evaluation, constant term first.  Arr is a double[N] member of a table that may live
 // in any address space (the kernels read it from the constant address space).
 template <class Arr>
@@ -43,6 +60,17 @@ __host__ __device__ __forceinline__ double horner(const Arr &c, double x) {
   double r = c[N - 1];
 #pragma unroll
   for (int i = N - 2; i >= 0; --i) r = fma_uniform(r, x, c[i]);
+  return r;
+}
+
+// Horner evaluation of q[0] + q[1] x + ... + q[N-1] x^(N-1) + (+-1) x^N: the leading
+// coefficient is +1 (or -1 with NEG), so the chain starts with one add of a scalar operand.
+template <bool NEG = false, class Arr>
+__host__ __device__ __forceinline__ double horner_lead1(const Arr &q, double x) {
+  constexpr int N = (int)(sizeof(Arr) / sizeof(double));
+  double r = add_uniform<NEG>(x, q[N - 1]);
+#pragma unroll
+  for (int i = N - 2; i >= 0; --i) r = fma_uniform(r, x, q[i]);
   return r;
 }
 
@@ -109,65 +137,88 @@ __host__ __device__ __forceinline__ double log_d(double u, const Tab &T) {
   return std::fma((double)e, T.consts[3], lm);
 }
 
-// (gre, gim) = M4 e^{i theta} rotated by i, theta = z + ph, M4 = |H0|/4
+// m with its sign flipped when the integer j = jm - RND_MAGIC is odd.  jm = x + RND_MAGIC is
+// x rounded to an integer (|x| < 2^51) sitting in the low mantissa bits, so its lowest bit is
+// the parity of j (RND_MAGIC = 1.5 * 2^52 is even).
+__host__ __device__ __forceinline__ double flip_if_odd(double m, double jm) {
+#ifdef __HIP_DEVICE_COMPILE__
+  const unsigned lo = (unsigned)__double_as_longlong(jm);
+  const long long b = __double_as_longlong(m) ^ ((long long)(lo << 31) << 32);
+  return __longlong_as_double(b);
+#else
+  long long bj, bm;
+  std::memcpy(&bj, &jm, 8);
+  std::memcpy(&bm, &m, 8);
+  bm ^= (long long)((unsigned long long)(bj & 1) << 63);
+  double out;
+  std::memcpy(&out, &bm, 8);
+  return out;
+#endif
+}
+
+constexpr double RND_MAGIC = 6755399441055744.0;   // 1.5 * 2^52
+
+// (gre, gim) = Mu e^{i theta} rotated by i, theta = zp = z + ph, Mu = |H0| / (4K).  The
+// multiple j of pi nearest to theta is removed with a two-constant Cody-Waite reduction (exact
+// products in the FMAs); (-1)^j flips the sign of the modulus.
 template <class Tab>
-__host__ __device__ __forceinline__ void phase_tail(double z, double ph, double M4, double &gre,
-                                                    double &gim, const Tab &T) {
-  const double jf = rint_d((z + ph) * T.consts[2]);
-  double r = std::fma(-jf, T.consts[0], z);
+__host__ __device__ __forceinline__ void phase_tail(double zp, double Mu, double &gre, double &gim,
+                                                    const Tab &T) {
+  const double jm = std::fma(zp, T.consts[2], RND_MAGIC);
+  const double jf = jm - RND_MAGIC;
+  double r = std::fma(-jf, T.consts[0], zp);
   r = std::fma(-jf, T.consts[1], r);
-  r = r + ph;
-  // (-1)^j: fract(j/2) is 0 or 1/2
-  const double sg = std::fma(-4.0, fract_d(0.5 * jf), 1.0);
-  const double Ms = M4 * sg;
+  const double Ms = flip_if_odd(Mu, jm);
   const double r2 = r * r;
-  const double sn = r * horner(T.sin_r, r2);
-  const double cs = horner(T.cos_r, r2);
-  // G = (i/4) H0 = i M4 (cos + i sin) = -M4 sin + i M4 cos
-  gre = -Ms * sn;
+  // sin r = c8 (sigma r) q_s(r^2), cos r = c8 q_c(r^2); c8 is part of K
+  const double sn = (r * T.consts[9]) * horner_lead1(T.sin_q, r2);
+  const double cs = horner_lead1(T.cos_q, r2);
+  // G/K = i Mu (cos + i sin) = -Mu sin + i Mu cos
+  gre = -(Ms * sn);
   gim = Ms * cs;
 }
 
 // ZS <= z: modulus-phase form.  Only the two polynomials depend on the argument range; the
 // inverse fourth root, the reduction and the sine/cosine are shared, so a wavefront whose lanes
-// straddle a range boundary repeats only the polynomial evaluation.
+// straddle a range boundary repeats only the polynomial evaluation.  Returns G/K.
 template <class Tab>
 __host__ __device__ __forceinline__ void green_modphase(double A, double &gre, double &gim, const Tab &T) {
   const double s = inv_fourth_root(A, T);  // z^(-1/2)
   const double t = s * s;                  // 1/z
-  const double z = A * t;
-  double mod, ph;
+  double mod, ph;                          // M sqrt(z) / (4 m8), theta - z
   if (A >= ZF2) {
     const double t2 = t * t;
-    mod = horner(T.far_mod, t2);
-    ph = std::fma(t, horner(T.far_ph, t2), T.consts[5]);
+    mod = horner_lead1(T.far_mod_q, t2);
+    ph = std::fma(t * T.consts[8], horner_lead1(T.far_ph_q, t2), T.consts[5]);
   } else if (A >= ZM2) {
-    const double x = (t - MID2_TA) * MID2_SCALE;
-    mod = horner(T.mid2_mod, x);
-    ph = horner(T.mid2_ph, x);
+    const double x = t - MID2_TA;
+    mod = horner_lead1<MID2_MOD_NEG>(T.mid2_mod_q, x * MID2_SM);
+    ph = horner_lead1<MID2_PH_NEG>(T.mid2_ph_q, x * MID2_SP);
   } else {
-    const double x = (t - MID1_TA) * MID1_SCALE;
-    mod = horner(T.mid1_mod, x);
-    ph = horner(T.mid1_ph, x);
+    const double x = t - MID1_TA;
+    mod = horner_lead1<MID1_MOD_NEG>(T.mid1_mod_q, x * MID1_SM);
+    ph = horner_lead1<MID1_PH_NEG>(T.mid1_ph_q, x * MID1_SP);
   }
-  phase_tail(z, ph, mod * s, gre, gim, T);
+  // z + ph = A t + ph in one rounding, the same error as z = A t alone
+  phase_tail(std::fma(A, t, ph), mod * s, gre, gim, T);
 }
 
-// 0 < z < ZS
+// 0 < z < ZS; returns G/K
 template <class Tab>
 __host__ __device__ __forceinline__ void green_small(double A, double &gre, double &gim, const Tab &T) {
   const double u = 0.25 * A;
-  const double j4 = horner(T.small_j, u);  // J0/4
-  const double r4 = horner(T.small_r, u);  // (Y0 - ln(u) J0 / pi)/4
+  const double j4 = horner(T.small_j_k, u);  // J0/(4K)
+  const double r4 = horner(T.small_r_k, u);  // (Y0 - ln(u) J0 / pi)/(4K)
   const double L = log_d(u, T);
   // G = (i/4)(J0 + i Y0) = -Y0/4 + i J0/4
   gre = -std::fma(T.consts[2] * L, j4, r4);
   gim = j4;
 }
 
-// G = (i/4) H0^(1)(z) for z^2 = A > 0 (any branch)
+// G/K for z^2 = A > 0 (any branch), K = G_SCALE.  The far sums accumulate G/K and multiply
+// the total by K once.
 template <class Tab>
-__host__ __device__ __forceinline__ void green(double A, double &gre, double &gim, const Tab &T) {
+__host__ __device__ __forceinline__ void green_unit(double A, double &gre, double &gim, const Tab &T) {
   if (A >= ZS2) {
     green_modphase(A, gre, gim, T);
   } else {
@@ -175,11 +226,19 @@ __host__ __device__ __forceinline__ void green(double A, double &gre, double &gi
   }
 }
 
+// G = (i/4) H0^(1)(z) for z^2 = A > 0
+template <class Tab>
+__host__ __device__ __forceinline__ void green(double A, double &gre, double &gim, const Tab &T) {
+  green_unit(A, gre, gim, T);
+  gre *= T.consts[7];
+  gim *= T.consts[7];
+}
+
 // ---------------------------------------------------------------- single precision
-// For the mixed-precision tiles: z >= 1 in FP32 (far form for z >= F32_ZF, one fitted
-// modulus-phase interval below), e^{i theta} from the hardware sine/cosine of the fractional
-// number of turns; z < 1 falls back to the FP64 series (its logarithm needs the precision).
-// Relative accuracy ~2e-5 at z ~ 100, limited by z itself in FP32.
+// For the mixed-precision tiles: G/K with z >= 1 in FP32 (far form for z >= F32_ZF, one
+// fitted modulus-phase interval below), e^{i theta} from the hardware sine/cosine of the
+// fractional number of turns; z < 1 falls back to the FP64 series (its logarithm needs the
+// precision).  Relative accuracy ~2e-5 at z ~ 100, limited by z itself in FP32.
 template <class Arr>
 __host__ __device__ __forceinline__ float hornerf(const Arr &c, float x) {
   constexpr int N = (int)(sizeof(Arr) / sizeof(float));
@@ -190,7 +249,7 @@ __host__ __device__ __forceinline__ float hornerf(const Arr &c, float x) {
 }
 
 template <class Tab>
-__host__ __device__ __forceinline__ void green32(double A, float &gre, float &gim, const Tab &T) {
+__host__ __device__ __forceinline__ void green32_unit(double A, float &gre, float &gim, const Tab &T) {
   if (A < 1.0) {
     double r, i;
     green_small(A, r, i, T);

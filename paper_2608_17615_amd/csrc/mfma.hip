@@ -11,7 +11,8 @@
 //   T = float  : v_mfma_f32_16x16x4f32 with FP32 Green's values (FP64 for z < 1) and FP32
 //                accumulation within one source split; splits are summed in FP64 by the epilogue.
 // Result rows: FP32 tiles return D[4 (l/16) + r][l % 16], FP64 tiles D[l/16 + 4 r][l % 16]
-// (r = accumulator register), both verified on gfx950.
+// (r = accumulator register), both verified on gfx950.  Green's values are G/K (hankel.h); the
+// shared epilogue multiplies the summed partials by K.
 #include <algorithm>
 #include <vector>
 
@@ -47,7 +48,9 @@ struct Tile<double> {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
-  static __device__ __forceinline__ void green(double A, double &gr, double &gi) { lsk::green(A, gr, gi, mtab()); }
+  static __device__ __forceinline__ void green(double A, double &gr, double &gi) {
+    lsk::green_unit(A, gr, gi, mtab());
+  }
   static __device__ __forceinline__ cplx_t make(double a, double b) { return make_double2(a, b); }
 };
 
@@ -59,7 +62,9 @@ struct Tile<float> {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
-  static __device__ __forceinline__ void green(double A, float &gr, float &gi) { lsk::green32(A, gr, gi, mtab()); }
+  static __device__ __forceinline__ void green(double A, float &gr, float &gi) {
+    lsk::green32_unit(A, gr, gi, mtab());
+  }
   static __device__ __forceinline__ cplx_t make(double a, double b) { return make_float2((float)a, (float)b); }
 };
 
