@@ -238,7 +238,8 @@ __host__ __device__ __forceinline__ void green(double A, double &gre, double &gi
 // For the mixed-precision tiles: G/K with z >= 1 in FP32 (far form for z >= F32_ZF, one
 // fitted modulus-phase interval below), e^{i theta} from the hardware sine/cosine of the
 // fractional number of turns; z < 1 falls back to the FP64 series (its logarithm needs the
-// precision).  Relative accuracy ~2e-5 at z ~ 100, limited by z itself in FP32.
+// precision).  The phase is reduced in FP64 (z refined by one Newton step), so the relative
+// accuracy stays at the FP32 level (a few 1e-7) for every z.
 template <class Arr>
 __host__ __device__ __forceinline__ float hornerf(const Arr &c, float x) {
   constexpr int N = (int)(sizeof(Arr) / sizeof(float));
@@ -275,12 +276,17 @@ __host__ __device__ __forceinline__ void green32_unit(double A, float &gre, floa
     ph = hornerf(F32_MID_PH, x);
   }
   const float m4 = mod * s;
-  const float rev = (z + ph) * 0.159154943f;   // turns
+  // Phase in FP64: z in FP32 carries a relative error ~2^-24, i.e. ~z 2^-24 radians of phase.
+  // One Newton step for sqrt(A) from the FP32 z restores z to ~1e-14 relative, and the number of
+  // turns (z + ph)/(2 pi) is reduced in FP64; only the fraction goes to the FP32 sine/cosine.
+  const double zd = (double)z;
+  const double z64 = std::fma(std::fma(-zd, zd, A), (double)(0.5f * t), zd);
+  const double rev = std::fma(z64, 0.15915494309189535, (double)(ph * 0.159154943f));   // turns
 #ifdef __HIP_DEVICE_COMPILE__
-  const float f = __builtin_amdgcn_fractf(rev);
+  const float f = (float)__builtin_amdgcn_fract(rev);
   const float sn = __builtin_amdgcn_sinf(f), cs = __builtin_amdgcn_cosf(f);
 #else
-  const float f = rev - std::floor(rev);
+  const float f = (float)(rev - std::floor(rev));
   const float sn = std::sin(6.283185307f * f), cs = std::cos(6.283185307f * f);
 #endif
   gre = -m4 * sn;

@@ -27,7 +27,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kEPT = 4;                      // elements per thread in the dot kernel
 constexpr int kTile = kBlock * kEPT;
-constexpr int kGroup = 4;                    // basis vectors per block reduction
+constexpr int kGroup = 8;                    // basis vectors per dot-product block
 
 typedef std::complex<double> cplx;
 
@@ -49,57 +49,57 @@ __device__ __forceinline__ double2 block_sum2(double2 v, double2 *lds) {
   return r;
 }
 
-// part[(tile * nrhs + c) * nv + i] = sum over the tile of conj(V_i[c][n]) w[c][n]
+// part[(tile * nrhs + c) * nv + i] = sum over the tile of conj(V_i[c][n]) w[c][n].
+// grid (tiles, ceil(nv / kGroup), nrhs): each block forms kGroup inner products over one tile, so
+// even a single short column (one right-hand side) spreads over many workgroups, and the
+// kGroup x kEPT loads of a thread are independent.
 __global__ __launch_bounds__(kBlock) void dots_kernel(int64_t n, int nrhs, int nv, const double2 *const *V,
                                                       int64_t ldv, const double2 *__restrict__ w, int64_t ldw,
                                                       double2 *__restrict__ part) {
   __shared__ double2 lds[kGroup][kBlock / 64];
   const int64_t t0 = (int64_t)blockIdx.x * kTile;
-  const int c = blockIdx.y;
+  const int i0 = blockIdx.y * kGroup;
+  const int c = blockIdx.z;
   double2 wv[kEPT];
 #pragma unroll
   for (int e = 0; e < kEPT; ++e) {
     const int64_t idx = t0 + e * kBlock + threadIdx.x;
     wv[e] = idx < n ? w[(int64_t)c * ldw + idx] : make_double2(0.0, 0.0);
   }
-  for (int i0 = 0; i0 < nv; i0 += kGroup) {
-    double2 acc[kGroup];
+  double2 acc[kGroup];
 #pragma unroll
-    for (int g = 0; g < kGroup; ++g) {
-      acc[g] = make_double2(0.0, 0.0);
-      if (i0 + g < nv) {
-        const double2 *v = V[i0 + g] + (int64_t)c * ldv;
+  for (int g = 0; g < kGroup; ++g) {
+    acc[g] = make_double2(0.0, 0.0);
+    if (i0 + g < nv) {
+      const double2 *v = V[i0 + g] + (int64_t)c * ldv;
 #pragma unroll
-        for (int e = 0; e < kEPT; ++e) {
-          const int64_t idx = t0 + e * kBlock + threadIdx.x;
-          if (idx < n) {
-            const double2 a = v[idx];
-            acc[g].x = std::fma(a.x, wv[e].x, std::fma(a.y, wv[e].y, acc[g].x));
-            acc[g].y = std::fma(a.x, wv[e].y, std::fma(-a.y, wv[e].x, acc[g].y));
-          }
+      for (int e = 0; e < kEPT; ++e) {
+        const int64_t idx = t0 + e * kBlock + threadIdx.x;
+        if (idx < n) {
+          const double2 a = v[idx];
+          acc[g].x = std::fma(a.x, wv[e].x, std::fma(a.y, wv[e].y, acc[g].x));
+          acc[g].y = std::fma(a.x, wv[e].y, std::fma(-a.y, wv[e].x, acc[g].y));
         }
       }
     }
-    // reduce the group with one pair of barriers per vector
+  }
 #pragma unroll
-    for (int g = 0; g < kGroup; ++g) {
-      double2 v = acc[g];
-      for (int o = 32; o > 0; o >>= 1) {
-        v.x += __shfl_xor(v.x, o);
-        v.y += __shfl_xor(v.y, o);
-      }
-      if ((threadIdx.x & 63) == 0) lds[g][threadIdx.x >> 6] = v;
+  for (int g = 0; g < kGroup; ++g) {
+    double2 v = acc[g];
+    for (int o = 32; o > 0; o >>= 1) {
+      v.x += __shfl_xor(v.x, o);
+      v.y += __shfl_xor(v.y, o);
     }
-    __syncthreads();
-    if (threadIdx.x < kGroup && i0 + threadIdx.x < nv) {
-      double2 r = make_double2(0.0, 0.0);
-      for (int k = 0; k < kBlock / 64; ++k) {
-        r.x += lds[threadIdx.x][k].x;
-        r.y += lds[threadIdx.x][k].y;
-      }
-      part[((int64_t)blockIdx.x * nrhs + c) * nv + i0 + threadIdx.x] = r;
+    if ((threadIdx.x & 63) == 0) lds[g][threadIdx.x >> 6] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kGroup && i0 + (int)threadIdx.x < nv) {
+    double2 r = make_double2(0.0, 0.0);
+    for (int k = 0; k < kBlock / 64; ++k) {
+      r.x += lds[threadIdx.x][k].x;
+      r.y += lds[threadIdx.x][k].y;
     }
-    __syncthreads();
+    part[((int64_t)blockIdx.x * nrhs + c) * nv + i0 + threadIdx.x] = r;
   }
 }
 
@@ -129,6 +129,7 @@ __global__ __launch_bounds__(kBlock) void update_kernel(int64_t n, int nv, const
   if (idx >= n) return;
   double ar = 0.0, ai = 0.0;
   const double2 *hc = hcoef + (int64_t)c * ldh;
+#pragma unroll 8
   for (int i = 0; i < nv; ++i) {
     const double2 v = V[i][(int64_t)c * ldv + idx];
     const double2 hh = hc[i];
@@ -192,8 +193,10 @@ struct Basis {
 
 struct SolveWs {
   Basis V, Z;                // Z: flexible GMRES preconditioned vectors
-  void *small = nullptr;     // part, h, beta, pointer table
+  void *small = nullptr;     // h, y, beta, pointer table
   size_t small_bytes = 0;
+  void *part = nullptr;      // per-tile partial inner products, grown with the basis
+  size_t part_bytes = 0;
   void *vecs = nullptr;      // r, t, inner workspaces
   size_t vec_bytes = 0;
 };
@@ -249,15 +252,13 @@ struct Gmres {
 
   hipError_t init(int maxvec) {
     max_vec = maxvec;
-    const size_t ntile = tiles_of(n);
-    const size_t need = sizeof(double2) * ntile * nrhs * (size_t)(maxvec + 1) +      // part
-                        2 * sizeof(double2) * (size_t)nrhs * (maxvec + 1) +          // h, y
+    const size_t need = 2 * sizeof(double2) * (size_t)nrhs * (maxvec + 1) +          // h, y
                         sizeof(double) * nrhs + sizeof(double2 *) * (size_t)(2 * maxvec + 8) + 1024;
     hipError_t e = ensure(ws->small, ws->small_bytes, need);
     if (e != hipSuccess) return e;
+    e = ensure_part(16);
+    if (e != hipSuccess) return e;
     char *p = (char *)ws->small;
-    part = (double2 *)p;
-    p += sizeof(double2) * ntile * nrhs * (size_t)(maxvec + 1);
     hbuf = (double2 *)p;
     p += sizeof(double2) * (size_t)nrhs * (maxvec + 1);
     ybuf = (double2 *)p;
@@ -269,9 +270,27 @@ struct Gmres {
     return hipSuccess;
   }
 
+  // partials for nv inner products per column; grows geometrically, after the stream has drained
+  // (the old buffer may still be read by a queued reduction)
+  hipError_t ensure_part(int nv) {
+    const size_t per = sizeof(double2) * tiles_of(n) * nrhs;
+    if (per * nv <= ws->part_bytes) {
+      part = (double2 *)ws->part;
+      return hipSuccess;
+    }
+    const int cap = std::min(max_vec + 1, std::max(nv, 2 * (int)(ws->part_bytes / per)));
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    e = ensure(ws->part, ws->part_bytes, per * std::max(cap, nv));
+    part = (double2 *)ws->part;
+    return e;
+  }
+
   // h[c][0..nv) = V[0..nv)^H w (device, hbuf), using the pointer table entries [0, nv)
   hipError_t dots(int nv, const double2 *w, double2 *out, int64_t ldo) {
-    dim3 g(tiles_of(n), nrhs);
+    hipError_t e0 = ensure_part(nv);
+    if (e0 != hipSuccess) return e0;
+    dim3 g(tiles_of(n), (unsigned)((nv + kGroup - 1) / kGroup), nrhs);
     dots_kernel<<<g, kBlock, 0, st>>>(n, nrhs, nv, ptrs, n, w, n, part);
     reduce_kernel<<<(unsigned)((nrhs * nv + 255) / 256), 256, 0, st>>>((int)tiles_of(n), nrhs, nv, part, out, ldo,
                                                                        nullptr);
@@ -281,7 +300,7 @@ struct Gmres {
   // beta[c] = ||w_c||
   hipError_t norms(const double2 *w, double2 **tbl_slot) {
     (void)tbl_slot;
-    dim3 g(tiles_of(n), nrhs);
+    dim3 g(tiles_of(n), 1, nrhs);
     dots_kernel<<<g, kBlock, 0, st>>>(n, nrhs, 1, ptrs + max_vec + 2, n, w, n, part);
     reduce_kernel<<<(unsigned)((nrhs + 255) / 256), 256, 0, st>>>((int)tiles_of(n), nrhs, 1, part, nullptr, 1, beta);
     return hipGetLastError();
@@ -327,14 +346,29 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
   HIPTRY(ensure(ws->vecs, ws->vec_bytes, 2 * vb));
   double2 *r = (double2 *)ws->vecs;
   double2 *t = r + (size_t)n * nrhs;
-  HIPTRY(ensure_chunks(ws->V, cyc + 1, n, nrhs));
-  if (o.flexible) HIPTRY(ensure_chunks(ws->Z, cyc, n, nrhs));
+  // the basis grows chunk by chunk as the iteration needs it (a solve that converges early never
+  // holds maxit vectors); new chunks enter the device pointer table as they arrive
+  HIPTRY(ensure_chunks(ws->V, 1, n, nrhs));
+  if (o.flexible) HIPTRY(ensure_chunks(ws->Z, 1, n, nrhs));
   std::vector<double2 *> tbl(2 * (cyc + 1) + 4, nullptr);
-  for (int i = 0; i <= cyc; ++i) tbl[i] = ws->V.vec(i, n, nrhs);
+  int have = 0;   // basis vectors whose pointers are in tbl and on the device
+  auto grow = [&](int nvec) -> hipError_t {
+    nvec = std::min(nvec, cyc + 1);
+    if (nvec <= have) return hipSuccess;
+    hipError_t e = ensure_chunks(ws->V, nvec, n, nrhs);
+    if (e != hipSuccess) return e;
+    const int upto = std::min(cyc + 1, (int)ws->V.chunks.size() * Basis::kChunk);
+    for (int i = have; i < upto; ++i) tbl[i] = ws->V.vec(i, n, nrhs);
+    e = hipMemcpyAsync(G.ptrs + have, tbl.data() + have, sizeof(double2 *) * (upto - have), hipMemcpyHostToDevice,
+                       st);
+    have = upto;
+    return e;
+  };
   const int slot = G.max_vec + 2;
   std::vector<double> bnorm(nrhs);
   tbl[slot] = (double2 *)b;
   HIPTRY(hipMemcpyAsync(G.ptrs, tbl.data(), sizeof(double2 *) * tbl.size(), hipMemcpyHostToDevice, st));
+  HIPTRY(grow(1));
   HIPTRY(G.norms(b, nullptr));
   HIPTRY(hipMemcpyAsync(bnorm.data(), G.beta, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
   HIPTRY(hipStreamSynchronize(st));
@@ -346,7 +380,10 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
   std::vector<double> est(nrhs, 1.0);
   int total_it = 0;
   bool first_cycle = true;
-  std::vector<cplx> H, cs, sn, g;
+  // Hessenberg columns packed per right-hand side: column j (rows 0..j+1) starts at j (j + 3) / 2,
+  // grown one column per step
+  std::vector<std::vector<cplx>> H(nrhs);
+  std::vector<cplx> cs, sn, g;
   std::vector<double2> hh((size_t)nrhs * (cyc + 1) * 2);
   std::vector<double> betah(nrhs);
   const dim3 gv(blocks_of(n), nrhs);
@@ -380,7 +417,7 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
     }
     if (all) break;
     const int m = cyc;
-    H.assign((size_t)nrhs * (m + 1) * m, cplx(0));
+    for (auto &hc : H) hc.clear();
     cs.assign((size_t)nrhs * m, cplx(0));
     sn.assign((size_t)nrhs * m, cplx(0));
     g.assign((size_t)nrhs * (m + 1), cplx(0));
@@ -392,10 +429,12 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
     }
     int j = 0;
     for (; j < m && total_it < maxit; ++j, ++total_it) {
+      HIPTRY(grow(j + 2));
       double2 *vj = tbl[j];
       double2 *w = tbl[j + 1];
       if (o.flexible) {
         // z_j ~ L^{-1} v_j by an inner GMRES with the mixed-precision operator, then w = L z_j
+        HIPTRY(ensure_chunks(ws->Z, j + 1, n, nrhs));
         double2 *zj = ws->Z.vec(j, n, nrhs);
         CoreOpts io{o.inner_tol, o.inner_maxit, 0, o.mode, LS_MIXED, false, 0.0, 0, false, 0.0};
         CoreResult ir;
@@ -441,8 +480,10 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
       bool any = false;
       for (int c = 0; c < nrhs; ++c) {
         if (!active[c]) continue;
-        cplx *Hc = &H[(size_t)c * (m + 1) * m];
-        auto Hat = [&](int r_, int c_) -> cplx & { return Hc[(size_t)r_ * m + c_]; };
+        std::vector<cplx> &Hv = H[c];
+        Hv.resize((size_t)(j + 1) * (j + 4) / 2, cplx(0));
+        cplx *Hc = Hv.data();
+        auto Hat = [&](int r_, int c_) -> cplx & { return Hc[(size_t)c_ * (c_ + 3) / 2 + r_]; };
         for (int i = 0; i < nv; ++i) {
           const double2 a = hh[(size_t)c * nv + i], bq = hh[(size_t)nrhs * nv + (size_t)c * nv + i];
           Hat(i, j) = cplx(a.x + bq.x, a.y + bq.y);
@@ -483,12 +524,13 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
     std::vector<double2> yv((size_t)nrhs * m, make_double2(0, 0));
     for (int c = 0; c < nrhs; ++c) {
       const int mm = mc[c];
-      cplx *Hc = &H[(size_t)c * (m + 1) * m];
+      const cplx *Hc = H[c].data();
+      auto Hat = [&](int r_, int c_) { return Hc[(size_t)c_ * (c_ + 3) / 2 + r_]; };
       std::vector<cplx> yc(mm);
       for (int i = mm - 1; i >= 0; --i) {
         cplx sacc = g[(size_t)c * (m + 1) + i];
-        for (int k2 = i + 1; k2 < mm; ++k2) sacc -= Hc[(size_t)i * m + k2] * yc[k2];
-        yc[i] = sacc / Hc[(size_t)i * m + i];
+        for (int k2 = i + 1; k2 < mm; ++k2) sacc -= Hat(i, k2) * yc[k2];
+        yc[i] = sacc / Hat(i, i);
       }
       for (int i = 0; i < mm; ++i) yv[(size_t)c * m + i] = make_double2(yc[i].real(), yc[i].imag());
     }
@@ -637,6 +679,7 @@ void free_solve_ws(ls_ctx *h) {
     for (void *p : ws->V.chunks) (void)hipFree(p);
     for (void *p : ws->Z.chunks) (void)hipFree(p);
     if (ws->small) (void)hipFree(ws->small);
+    if (ws->part) (void)hipFree(ws->part);
     if (ws->vecs) (void)hipFree(ws->vecs);
   }
   delete[] all;

@@ -36,4 +36,4 @@ def test_device_green_single_precision():
     err = np.abs(g - ref) / np.abs(ref)
     print("single-precision green: max rel err", err.max(), "(z<1)", err[z < 1].max(), flush=True)
     assert np.all(err[z < 1] <= 1e-7)                       # FP64 series, rounded to FP32
-    assert np.all(err <= 4e-7 * np.maximum(1.0, z))          # FP32 argument: ~z * 2^-24 phase error
+    assert np.all(err <= 5e-7)                               # phase reduced in FP64: FP32 level at every z

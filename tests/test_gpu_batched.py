@@ -35,8 +35,8 @@ def test_fp64_tiles_match_oracle(name, B):
 @pytest.mark.parametrize("name", ["disk2500", "twomat1040", "ellipse900"])
 @pytest.mark.parametrize("B", [1, 5, 16, 48])
 def test_mixed_tiles_error(name, B):
-    """FP32 Green's tiles with FP32 accumulation per source split: the error of L x stays at the
-    FP32 level (~1e-6 of the potential), well inside what the FP64 outer iteration corrects."""
+    """FP32 Green's tiles (phase reduced in FP64) with FP32 accumulation per source split: the
+    error of L x stays at the FP32 level (observed 1e-9 to 1e-7 of the largest entry)."""
     p, c, op = _op(name)
     x = torch.tensor(_cols(c, "x", B), device="cuda")
     y = op.apply(x, precision="mixed").cpu().numpy()
@@ -45,4 +45,4 @@ def test_mixed_tiles_error(name, B):
     ya = op.apply_adjoint(x, precision="mixed").cpu().numpy()
     ea = relmax(ya, _cols(c, "LHx", B))
     print(f"{name} B={B}: mixed apply {e:.2e} adjoint {ea:.2e}", flush=True)
-    assert e <= 3e-5 and ea <= 3e-5
+    assert e <= 1e-6 and ea <= 1e-6
