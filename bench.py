@@ -1,18 +1,29 @@
 #!/usr/bin/env python3
 """Benchmark of the Lippmann-Schwinger Nystrom hot path on one MI355X.
 
-Workload: the two-material disk (inclusion |x| < 0.5 with n = 3, annulus 0.5 < |x| < 1 with
-n = 1 + 0.5 exp(-|x|^2)), k = 20, O-grid/annulus mesh with 15 inner cells (N = 58 500 nodes),
-one plane wave along +x.  One step = one FP64 GMRES solve (no restart, x0 = 0) of L u = b to a
-relative residual of 1e-8, every operator application being the far-field Green's sum over all
-N(N-1) node pairs plus the sparse correction.
+Default workload (c2): the two-material disk (inclusion |x| < 0.5 with n = 3, annulus
+0.5 < |x| < 1 with n = 1 + 0.5 exp(-|x|^2)), k = 20, O-grid/annulus mesh with 15 inner cells
+(N = 58 500 nodes), one plane wave along +x.  One step = one FP64 GMRES solve (no restart,
+x0 = 0) of L u = b to a relative residual of 1e-8, every operator application being the
+far-field Green's sum over all N(N-1) node pairs plus the sparse correction.
 
-Reported: Green interactions per second over the timed solves (value), the time to a 1e-8
-residual (ms_per_step), the far-sum kernel's roofline position (average launch duration from
+Other workloads (--workload, one JSON line each):
+  c1  unit disk, n^2 = 2, k = 2 pi, N = 2 500, one plane wave (plain FP64);
+  c3  unit disk, n^2 = 2, k = 40, N = 122 500, 64 directions, forms p64 / b64 / bm;
+  c4  16 seeded scatterers of uneven size in one handle, 8 directions each, forms p64 / bm;
+  c5  two-material disk at k = 40, N = 114 660, 16 directions: far-field misfit and its contrast
+      gradient through the forward and adjoint solves, forms p64 / b64 / bm.
+Forms: p64 = FP64 VALU kernel, one right-hand side at a time (columns beyond --cols are
+extrapolated from the timed ones, and the line says so); b64 = all right-hand sides together on
+FP64 matrix-core tiles; bm = all together, FP32 matrix-core tiles inside FP64 GMRES (relaxed).
+
+Reported: Green interactions per second over the timed work (value), the time to a 1e-8
+residual (ms_per_step), the dominant kernel's roofline position (average launch duration from
 HIP events the library records around each launch on the caller's stream), and the oracle's
 own throughput on a bounded sample of the same far sum on the host cores.
 
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+Usage: python bench.py [--workload c2] [--form p64] [--steps K] [--warmup W] [--gpus 1]
+                       [--no-cpu-baseline]
 """
 import argparse
 import json
@@ -23,15 +34,21 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# FP64 operations of the far-sum kernel per (target, source) pair on its z >= 12 branch
-# (the smaller-argument branches do more): coordinates and k^2 r^2 (6), inverse fourth root
-# Halley step (9), 1/z, z, 1/z^2 (3), modulus and phase polynomials (34), modulus scaling (1),
-# reduction modulo pi, sign and sine/cosine (49), and 8 per right-hand side for the complex
-# multiply-accumulate.  FMA counts as 2.
-FLOPS_PER_PAIR_BASE = 102
-FLOPS_PER_PAIR_PER_RHS = 8
-PEAK_FP64_TFLOPS = 78.6       # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
-# HBM bytes per far-kernel launch in this workload, from two rocprofv3 counter passes
+METRIC = "Green interactions/s + time to 1e-8 residual, batched/mixed vs FP64 plain"
+
+# FP64 operations per (target, source) pair of the far-sum kernel, by the argument range the
+# pair falls in, counted on the gfx950 assembly of its loop body (add and multiply 1, FMA 2):
+# coordinates and k^2 r^2 (6), inverse fourth root and 1/z (10), modulus and phase polynomials
+# (far 34, z in [5, 12) 47, z in [2, 5) 61), reduction, sign and sine/cosine (45); the
+# small-argument series is 66 after the coordinates.  Each right-hand side adds 8 (complex
+# multiply-accumulate).  The per-pair figure of a workload weights the ranges by the measured
+# distribution of z = k |y_j - y_n| over a seeded sample of target rows.
+FLOPS_RANGE = {"small": 72, "mid1": 122, "mid2": 108, "far": 95}
+FLOPS_PER_RHS = 8
+Z_BOUNDS = (2.0, 5.0, 12.0)
+PEAK_FP64_TFLOPS = 78.6       # vector and matrix: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
+PEAK_FP32_MFMA_TFLOPS = 157.3
+# HBM bytes per far-kernel launch in the default workload, from two rocprofv3 counter passes
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors that make a 1 GiB copy read 1 GiB and write
 # 1 GiB; profiles/far_fp64_two_material_N58500_hbm_counters.md), valid for the kernel sources
 # with this digest only: after any change to them the field is reported as null.
@@ -53,6 +70,30 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def z_fractions(meshes_k, rows=256, seed=0):
+    """Fractions of node pairs in the far kernel's argument ranges (seeded row sample),
+    weighted by each scatterer's pair count."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    acc = np.zeros(4)
+    for mesh, k in meshes_k:
+        n = mesh.x.size
+        sel = rng.choice(n, min(rows, n), replace=False)
+        cnt = np.zeros(4)
+        for r in sel:
+            z = np.hypot(mesh.x - mesh.x[r], mesh.y - mesh.y[r]) * k
+            z[r] = -1.0
+            z = z[z >= 0]
+            cnt += np.histogram(z, bins=[0.0, *Z_BOUNDS, np.inf])[0]
+        acc += cnt / cnt.sum() * float(n) * (n - 1)
+    f = acc / acc.sum()
+    return dict(zip(("small", "mid1", "mid2", "far"), (float(v) for v in f)))
+
+
+def flops_per_pair(frac, nrhs=1):
+    return sum(frac[r] * FLOPS_RANGE[r] for r in FLOPS_RANGE) + FLOPS_PER_RHS * nrhs
+
+
 def _oracle_rows(args):
     """Worker: the oracle's punctured far sum for a block of target rows (host only)."""
     x, y, w, k, f, rows = args
@@ -71,7 +112,7 @@ def cpu_baseline(prob, rows_total=1024, workers=None):
     workers = workers or max(1, min(os.cpu_count() or 1, 16))
     n = prob.n_nodes
     rng = np.random.default_rng(0)
-    rows = np.sort(rng.choice(n, rows_total, replace=False))
+    rows = np.sort(rng.choice(n, min(rows_total, n), replace=False))
     f = prob.m * P.random_vectors(n, 1, 0)[0]
     chunks = np.array_split(rows, workers * 4)
     ctx = mp.get_context("spawn")
@@ -82,18 +123,254 @@ def cpu_baseline(prob, rows_total=1024, workers=None):
         dt = time.perf_counter() - t0
     gis = done * (n - 1) / dt / 1e9
     return {"value": gis, "unit": "GI/s", "cores": workers, "kind": "oracle",
-            "sample": f"punctured Green's far sum (SciPy AMOS H0) for {done} seeded target rows x {n - 1} "
-                      f"sources of the same workload ({done * (n - 1):.3g} interactions, {dt:.2f} s wall); "
-                      f"the sparse correction rows (10 per subdomain and row) are excluded"}
+            "sample": f"punctured Green's far sum (SciPy AMOS H0), one right-hand side, for {done} seeded "
+                      f"target rows x {n - 1} sources of the {prob.name} mesh ({done * (n - 1):.3g} "
+                      f"interactions, {dt:.2f} s wall); the sparse correction rows (10 per subdomain and "
+                      f"row) are excluded"}
+
+
+def line(value, ms, steps, warmup, dtype, config, roofline, cpu):
+    return {"metric": METRIC, "value": value, "unit": "GI/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": config, "roofline": roofline, "cpu_baseline": cpu}
+
+
+def roofline_valu(flops_pair, pairs, far_s, traffic=None):
+    achieved = flops_pair * pairs / far_s / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic}
+
+
+def roofline_mfma(pair_rhs, far_s, single):
+    peak = PEAK_FP32_MFMA_TFLOPS if single else PEAK_FP64_TFLOPS
+    achieved = FLOPS_PER_RHS * pair_rhs / far_s / 1e12
+    return {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": None}
+
+
+class Timer:
+    """Wall time of GPU work between two device synchronisations, plus the library's far-kernel
+    launch statistics over the same interval."""
+
+    def __init__(self, op):
+        self.op = op
+
+    def __enter__(self):
+        import torch
+        torch.cuda.synchronize()
+        self.op.profile(True)
+        self.op.profile(reset=True)
+        self.t0 = time.perf_counter()
+        return self
+
+    def __exit__(self, *exc):
+        import torch
+        torch.cuda.synchronize()
+        self.seconds = time.perf_counter() - self.t0
+        self.prof = self.op.profile(reset=True)
+        self.op.profile(False)
+        self.far_avg_s = self.prof["far_ms"] / max(self.prof["far_launches"], 1) / 1e3
+
+
+def far_kernel_avg(op, x, precision, reps=5):
+    """Average far-kernel launch time of reps applications (the dominant kernel of a form)."""
+    op.apply(x, precision=precision)
+    with Timer(op) as t:
+        for _ in range(reps):
+            op.apply(x, precision=precision)
+    return t.far_avg_s
+
+
+# ---------------------------------------------------------------- c2 (default) and c1
+def run_plain(args, prob, label):
+    import torch
+
+    import paper_2608_17615_amd as lsg
+    n = prob.n_nodes
+    log(f"setup: {prob.name}, N={n}")
+    t0 = time.perf_counter()
+    op = lsg.Operator(lsg.Scatterer.from_mesh(prob.mesh, prob.m, prob.k))
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    log(f"setup done in {setup_s:.2f} s (nnz {op.correction_nnz()})")
+    b = torch.tensor(prob.incident(), device="cuda")
+    for w in range(args.warmup):
+        x, info = op.solve(b, tol=args.tol, maxit=args.maxit)
+        log(f"warmup {w}: {int(info['iters'][0])} iterations, {info['seconds']:.3f} s")
+    infos = []
+    with Timer(op) as t:
+        for s in range(args.steps):
+            x, info = op.solve(b, tol=args.tol, maxit=args.maxit)
+            infos.append(info)
+            log(f"step {s}: {int(info['iters'][0])} iterations, relres {info['relres'][0]:.3e}, "
+                f"{info['seconds']:.3f} s")
+    n_apply = sum(int(i["n_apply_fp64"]) for i in infos)
+    pairs = n * (n - 1)
+    frac = z_fractions([(prob.mesh, prob.k)])
+    fpp = flops_per_pair(frac, 1)
+    cfg = {"workload": f"{label}, N={n}, one plane wave, FP64 GMRES (no restart) to relative residual "
+                       f"{args.tol:g}",
+           "n_nodes": n, "k": prob.k, "nrhs": 1, "tol": args.tol, "iterations": int(infos[-1]["iters"][0]),
+           "applies_per_solve": n_apply // args.steps, "final_relres": float(infos[-1]["relres"][0]),
+           "setup_s": setup_s, "far_kernel_ms_avg": t.far_avg_s * 1e3,
+           "apply_ms_avg": t.prof["apply_ms"] / max(t.prof["apply_calls"], 1),
+           "flops_per_pair": fpp, "z_range_fractions": frac}
+    traffic = far_traffic() if args.workload == "c2" else None
+    return line(n_apply * pairs / t.seconds / 1e9, t.seconds / args.steps * 1e3, args.steps, args.warmup, "f64", cfg,
+                roofline_valu(fpp, pairs, t.far_avg_s, traffic), None)
+
+
+# ---------------------------------------------------------------- batched forms (c3, c4, c5)
+def solve_form(op, b, form, args, adjoint=False):
+    """Solve with one form; returns (x, seconds, FP64 applies, mixed applies, timer, per-column
+    iterations, columns solved)."""
+    import numpy as np
+    import torch
+    B = b.shape[0]
+    if form == "p64":
+        cols = min(B, args.cols)
+        xs, its, applies = [], [], 0
+        with Timer(op) as t:
+            for c in range(cols):
+                x, info = op.solve(b[c:c + 1], tol=args.tol, maxit=args.maxit, adjoint=adjoint,
+                                   restart=args.restart)
+                xs.append(x)
+                its.append(int(info["iters"][0]))
+                applies += int(info["n_apply_fp64"])
+                log(f"  column {c}: {its[-1]} iterations, relres {info['relres'][0]:.2e}, {info['seconds']:.2f} s")
+        return torch.cat(xs), t.seconds, applies, 0, t, its, cols
+    prec = "mixed" if form == "bm" else "fp64"
+    batch = args.batch or B
+    xs, its, a64, amx = [], [], 0, 0
+    with Timer(op) as t:
+        for c0 in range(0, B, batch):
+            x, info = op.solve(b[c0:c0 + batch], tol=args.tol, maxit=args.maxit, precision=prec, adjoint=adjoint,
+                               restart=args.restart)
+            xs.append(x)
+            its += [int(v) for v in info["iters"]]
+            a64 += int(info["n_apply_fp64"])
+            amx += int(info["n_apply_mixed"])
+            log(f"  columns {c0}..{c0 + x.shape[0] - 1}: max {int(np.max(info['iters']))} iterations, "
+                f"max relres {np.max(info['relres']):.2e}, applies {info['n_apply_fp64']}+"
+                f"{info['n_apply_mixed']}, {info['seconds']:.2f} s")
+    return torch.cat(xs), t.seconds, a64, amx, t, its, B
+
+
+def run_batched(args, probs, label, B):
+    """c3 / c4: solve L u = b for B plane waves per scatterer with one form."""
+    import numpy as np
+    import torch
+
+    import paper_2608_17615_amd as lsg
+    form = args.form
+    log(f"setup: {label}, {len(probs)} scatterer(s), N = {sum(p.n_nodes for p in probs)}")
+    t0 = time.perf_counter()
+    op = lsg.Operator([lsg.Scatterer.from_mesh(p.mesh, p.m, p.k) for p in probs])
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    log(f"setup done in {setup_s:.2f} s")
+    n = op.n
+    b = torch.tensor(np.concatenate([p.incident() for p in probs], axis=1), device="cuda")
+    tune = None
+    if form == "bm" and len(probs) > 1:
+        tune = op.autotune(B, precision="mixed")
+        log(f"autotune: {tune}")
+    x, secs, a64, amx, t, its, cols = solve_form(op, b, form, args)
+    pairs = sum(p.n_nodes * (p.n_nodes - 1) for p in probs)
+    frac = z_fractions([(p.mesh, p.k) for p in probs])
+    if form == "p64":
+        # every column is its own solve: scale the timed columns to all B
+        value = a64 * pairs / secs / 1e9
+        total_s = secs * B / cols
+        roof = roofline_valu(flops_per_pair(frac, 1), pairs, t.far_avg_s)
+        dtype = "f64"
+    else:
+        applies = a64 + amx   # the library counts one application per column
+        value = applies * pairs / secs / 1e9
+        total_s = secs
+        single = form == "bm"
+        roof = roofline_mfma(pairs * B, far_kernel_avg(op, b, "mixed" if single else "fp64"), single)
+        dtype = "f32-mfma+f64" if single else "f64"
+    # true FP64 residual of the returned solution
+    r = b[:x.shape[0]] - op.apply(x)
+    relres = (torch.linalg.norm(r, dim=1) / torch.linalg.norm(b[:x.shape[0]], dim=1)).cpu().numpy()
+    cfg = {"workload": label, "form": form, "n_nodes": n, "scatterers": len(probs), "nrhs": B, "tol": args.tol,
+           "restart": args.restart, "batch": args.batch or B, "columns_timed": cols,
+           "time_to_tol_s": total_s, "extrapolated": cols < B,
+           "iterations_max": int(max(its)), "iterations_mean": float(np.mean(its)),
+           "applies_fp64": a64, "applies_mixed": amx, "final_fp64_relres_max": float(relres.max()),
+           "setup_s": setup_s, "far_kernel_ms_avg": t.far_avg_s * 1e3, "z_range_fractions": frac,
+           "autotune": tune}
+    return line(value, total_s * 1e3, 1, 0, dtype, cfg, roof, None), x
+
+
+def run_gradient(args, prob, label, B):
+    """c5: J(m) = 1/2 sum |u_inf - data|^2 at 128 receivers and dJ/dm by the adjoint solve."""
+    import torch
+
+    import paper_2608_17615_amd as lsg
+    from workloads import problems as P
+    form = args.form
+    log(f"setup: {label}, N = {prob.n_nodes}")
+    t0 = time.perf_counter()
+    op = lsg.Operator(lsg.Scatterer.from_mesh(prob.mesh, prob.m, prob.k))
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    n = op.n
+    b = torch.tensor(prob.incident(), device="cuda")
+    thetas = P.receivers(128)
+    # synthetic data: far field of the seeded contrast perturbation (input generation, untimed)
+    m0 = torch.tensor(prob.m, device="cuda").to(torch.complex128)
+    dm = torch.tensor(P.contrast_perturbation(prob.mesh), device="cuda").to(torch.complex128)
+    cols = B if form != "p64" else min(B, args.cols)
+    op.set_contrast(m0 + dm)
+    ud, _ = op.solve(b[:cols], tol=args.tol, maxit=args.maxit, precision="mixed", restart=args.restart)
+    data, _, _ = op.farfield(ud, thetas)
+    op.set_contrast(m0)
+    log("data synthesised")
+    fwd = solve_form(op, b[:cols], form, args)
+    u = fwd[0]
+    _, res, J = op.farfield(u, thetas, data)
+    a, rhs = op.farfield_adjoint(res, thetas)
+    adj = solve_form(op, rhs, form, args, adjoint=True)
+    lam = adj[0]
+    g = op.grad_contrast(u, lam, a)
+    torch.cuda.synchronize()
+    secs = fwd[1] + adj[1]
+    pairs = n * (n - 1)
+    applies = fwd[2] + fwd[3] + adj[2] + adj[3]
+    frac = z_fractions([(prob.mesh, prob.k)])
+    if form == "p64":
+        value = applies * pairs / secs / 1e9
+        total_s = secs * B / cols
+        roof = roofline_valu(flops_per_pair(frac, 1), pairs, fwd[4].far_avg_s)
+        dtype = "f64"
+    else:
+        value = applies * pairs / secs / 1e9   # applications are counted per column
+        total_s = secs
+        single = form == "bm"
+        roof = roofline_mfma(pairs * B, far_kernel_avg(op, b, "mixed" if single else "fp64"), single)
+        dtype = "f32-mfma+f64" if single else "f64"
+    cfg = {"workload": label, "form": form, "n_nodes": n, "nrhs": B, "receivers": 128, "tol": args.tol,
+           "restart": args.restart, "columns_timed": cols, "time_to_tol_s": total_s, "extrapolated": cols < B,
+           "forward_s": fwd[1], "adjoint_s": adj[1], "iterations_forward_max": int(max(fwd[5])),
+           "iterations_adjoint_max": int(max(adj[5])), "misfit_J": J,
+           "grad_norm": float(torch.linalg.norm(g).item()), "setup_s": setup_s, "z_range_fractions": frac}
+    return line(value, total_s * 1e3, 1, 0, dtype, cfg, roof, None), g
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--form", default=None, choices=["p64", "b64", "bm"])
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=2000)
+    ap.add_argument("--restart", type=int, default=0, help="GMRES restart length (0 = none)")
+    ap.add_argument("--cols", type=int, default=1, help="p64: columns solved and timed (the rest extrapolated)")
+    ap.add_argument("--batch", type=int, default=0, help="b64/bm: right-hand sides per solve (0 = all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="first run one elementwise kernel that reads and writes BYTES each "
@@ -105,18 +382,30 @@ def main():
         sys.exit(2)
 
     from workloads import problems as P
-    prob = P.config2()
-    n = prob.n_nodes
+    wl = args.workload
+    if wl == "c1":
+        probs, label = [P.config1()], "unit disk, n^2 = 2, k = 2 pi"
+    elif wl == "c2":
+        probs, label = [P.config2()], "two-material disk, k=20"
+    elif wl == "c3":
+        probs, label = [P.config3()], "unit disk, n^2 = 2, k = 40, 64 plane waves"
+    elif wl == "c4":
+        probs, label = P.config4(), "16 seeded disks and ellipses, k in [5, 40], 8 plane waves each"
+    else:
+        probs, label = [P.config5()], "two-material disk, k = 40, 16 plane waves, 128 receivers"
+    form = args.form or ("p64" if wl in ("c1", "c2") else "bm")
+    args.form = form
+    if wl in ("c1", "c2") and form != "p64":
+        ap.error("c1 and c2 are plain FP64 single-wave solves (form p64)")
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("cpu baseline: oracle far sum on a row sample")
-        cpu = cpu_baseline(prob)
+        big = max(probs, key=lambda p: p.n_nodes)
+        log(f"cpu baseline: oracle far sum on a row sample of {big.name}")
+        cpu = cpu_baseline(big)
         log(f"cpu baseline: {cpu['value']:.4f} GI/s on {cpu['cores']} processes")
 
     import torch
-
-    import paper_2608_17615_amd as lsg
     if args.copy_probe:
         src = torch.ones(args.copy_probe // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -125,62 +414,14 @@ def main():
         torch.cuda.synchronize()
         log(f"copy probe: read and wrote {src.numel() * 8} bytes")
         del src, dst
-    log(f"setup: N={n}")
-    t0 = time.perf_counter()
-    op = lsg.Operator(lsg.Scatterer.from_mesh(prob.mesh, prob.m, prob.k))
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
-    log(f"setup done in {setup_s:.2f} s (nnz {op.correction_nnz()})")
-    b = torch.tensor(prob.incident(), device="cuda")
 
-    for w in range(args.warmup):
-        x, info = op.solve(b, tol=args.tol, maxit=args.maxit)
-        log(f"warmup {w}: {info['iters']} iterations, {info['seconds']:.3f} s")
-    torch.cuda.synchronize()
-    op.profile(True)
-    op.profile(reset=True)
-    infos = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        x, info = op.solve(b, tol=args.tol, maxit=args.maxit)
-        infos.append(info)
-        log(f"step {s}: {int(info['iters'][0])} iterations, relres {info['relres'][0]:.3e}, {info['seconds']:.3f} s")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = op.profile(reset=True)
-    op.profile(False)
-
-    n_apply = sum(int(i["n_apply_fp64"]) for i in infos)
-    pairs = n * (n - 1)
-    gis = n_apply * pairs / elapsed / 1e9
-    far_avg_s = prof["far_ms"] / max(prof["far_launches"], 1) / 1e3
-    flops = pairs * (FLOPS_PER_PAIR_BASE + FLOPS_PER_PAIR_PER_RHS * 1)
-    achieved = flops / far_avg_s / 1e12
-    out = {
-        "metric": "Green interactions/s + time to 1e-8 residual, batched/mixed vs FP64 plain",
-        "value": gis,
-        "unit": "GI/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"two-material disk, k=20, N={n}, one plane wave, FP64 GMRES (no restart) "
-                               f"to relative residual {args.tol:g}",
-                   "n_nodes": n, "k": prob.k, "nrhs": 1, "tol": args.tol,
-                   "iterations": int(infos[-1]["iters"][0]), "applies_per_solve": n_apply // args.steps,
-                   "final_relres": float(infos[-1]["relres"][0]), "setup_s": setup_s,
-                   "far_kernel_ms_avg": far_avg_s * 1e3,
-                   "apply_ms_avg": prof["apply_ms"] / max(prof["apply_calls"], 1)},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": far_traffic()},
-        "cpu_baseline": cpu,
-    }
+    if wl in ("c1", "c2"):
+        out = run_plain(args, probs[0], label)
+    elif wl in ("c3", "c4"):
+        out, _ = run_batched(args, probs, label, probs[0].directions.size)
+    else:
+        out, _ = run_gradient(args, probs[0], label, probs[0].directions.size)
+    out["cpu_baseline"] = cpu
     print(json.dumps(out))
 
 

@@ -226,8 +226,8 @@ class Operator:
         return self.apply(x, precision, adjoint=True, out=out)
 
     def solve(self, b, tol=1e-8, maxit=1000, precision="fp64", adjoint=False, x0=None, inner_tol=0.0,
-              inner_maxit=0):
-        """Solve L x = b (or L^H x = b) by GMRES without restart; returns (x, info dict)."""
+              inner_maxit=0, restart=0):
+        """Solve L x = b (or L^H x = b) by GMRES (restart = 0: none); returns (x, info dict)."""
         import torch
         b2 = self._cols(b)
         if x0 is not None:
@@ -237,7 +237,7 @@ class Operator:
         B = b2.shape[0]
         iters = np.zeros(B, dtype=np.int32)
         relres = np.zeros(B, dtype=np.float64)
-        o = _SolveOpts(float(tol), int(maxit), 0, _PREC[precision], int(bool(adjoint)), int(x0 is not None),
+        o = _SolveOpts(float(tol), int(maxit), int(restart), _PREC[precision], int(bool(adjoint)), int(x0 is not None),
                        int(inner_maxit), float(inner_tol))
         info = _SolveInfo(iters.ctypes.data, relres.ctypes.data, 0, 0, 0.0)
         st = _check(lib().ls_solve_gmres(self._h, b2.data_ptr(), x.data_ptr(), B, self.n, ctypes.byref(o),

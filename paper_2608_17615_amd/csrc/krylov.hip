@@ -2,20 +2,34 @@
 // without restart; here unpreconditioned), per right-hand side, on the device, and the contrast
 // gradient of a far-field misfit.
 //
-// Arnoldi: classical Gram-Schmidt with one re-orthogonalisation pass (CGS2) in FP64.  Every
-// inner product is a two-stage deterministic reduction (fixed-order block partials, then a
-// fixed-order sum), so results do not depend on scheduling.  The basis lives in chunks of
-// device memory kept by the handle between solves.  Per iteration the host receives the new
-// Hessenberg column (2 (j+1) + 1 values per RHS) and applies the complex Givens rotations;
-// everything of size N stays on the device.
+// Independent systems: with several scatterers in one handle the operator is block diagonal, so
+// right-hand side c restricted to scatterer s is a system of its own (q = c * nseg + s) with its
+// own Krylov space, Hessenberg matrix and convergence test.  All systems step together (one
+// batched operator application per step covers every scatterer and column), but a converged
+// system drops out of the orthogonalisation, and each one takes only the iterations its own
+// scatterer needs.
 //
-// Mixed precision (LS_MIXED): flexible GMRES (FP64 outer Arnoldi, FP64 applies for the outer
-// Krylov vectors and for the residuals) whose preconditioner is an inner GMRES solve with the
-// mixed-precision operator; the outer iteration removes the inner solve's error.
+// Arnoldi: classical Gram-Schmidt with one re-orthogonalisation pass (CGS2) in FP64.  Every
+// inner product is a two-stage deterministic reduction (fixed-order partials over tiles that
+// never straddle two scatterers, then a fixed-order sum), so results do not depend on
+// scheduling.  The basis lives in chunks of device memory kept by the handle between solves and
+// grows with the iteration.  Per iteration the host receives the new Hessenberg column
+// (2 (j+1) + 1 values per system) and applies the complex Givens rotations; everything of size
+// N stays on the device.
+//
+// Mixed precision (LS_MIXED): relaxed GMRES (FP64 applications until the residual is small
+// enough for the mixed-precision operator's error, mixed after, FP64 refinement from the true
+// residual), or flexible GMRES whose preconditioner is an inner GMRES solve with the
+// mixed-precision operator; the outer FP64 iteration removes the inner solve's error.
+//
+// Progress: with the environment variable LS_PROGRESS=k the solver prints the step, the largest
+// residual estimate and the number of active systems every k steps to stderr.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "internal.h"
@@ -31,52 +45,42 @@ constexpr int kGroup = 8;                    // basis vectors per dot-product bl
 
 typedef std::complex<double> cplx;
 
-__device__ __forceinline__ double2 block_sum2(double2 v, double2 *lds) {
-  for (int o = 32; o > 0; o >>= 1) {
-    v.x += __shfl_xor(v.x, o);
-    v.y += __shfl_xor(v.y, o);
-  }
-  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
-  if (ln == 0) lds[wv] = v;
-  __syncthreads();
-  double2 r = make_double2(0.0, 0.0);
-  if (threadIdx.x == 0)
-    for (int k = 0; k < kBlock / 64; ++k) {
-      r.x += lds[k].x;
-      r.y += lds[k].y;
-    }
-  __syncthreads();
-  return r;
-}
+// A tile of at most kTile consecutive elements of one scatterer's segment.
+struct TileDesc {
+  int64_t start;
+  int len, seg;
+};
 
 // part[(tile * nrhs + c) * nv + i] = sum over the tile of conj(V_i[c][n]) w[c][n].
 // grid (tiles, ceil(nv / kGroup), nrhs): each block forms kGroup inner products over one tile, so
 // even a single short column (one right-hand side) spreads over many workgroups, and the
-// kGroup x kEPT loads of a thread are independent.
-__global__ __launch_bounds__(kBlock) void dots_kernel(int64_t n, int nrhs, int nv, const double2 *const *V,
+// kGroup x kEPT loads of a thread are independent.  Blocks of inactive systems return at once.
+__global__ __launch_bounds__(kBlock) void dots_kernel(int nrhs, int nv, int nseg, const TileDesc *__restrict__ tiles,
+                                                      const int *__restrict__ active, const double2 *const *V,
                                                       int64_t ldv, const double2 *__restrict__ w, int64_t ldw,
                                                       double2 *__restrict__ part) {
   __shared__ double2 lds[kGroup][kBlock / 64];
-  const int64_t t0 = (int64_t)blockIdx.x * kTile;
+  const TileDesc td = tiles[blockIdx.x];
   const int i0 = blockIdx.y * kGroup;
   const int c = blockIdx.z;
+  if (!active[c * nseg + td.seg]) return;
   double2 wv[kEPT];
 #pragma unroll
   for (int e = 0; e < kEPT; ++e) {
-    const int64_t idx = t0 + e * kBlock + threadIdx.x;
-    wv[e] = idx < n ? w[(int64_t)c * ldw + idx] : make_double2(0.0, 0.0);
+    const int loc = e * kBlock + threadIdx.x;
+    wv[e] = loc < td.len ? w[(int64_t)c * ldw + td.start + loc] : make_double2(0.0, 0.0);
   }
   double2 acc[kGroup];
 #pragma unroll
   for (int g = 0; g < kGroup; ++g) {
     acc[g] = make_double2(0.0, 0.0);
     if (i0 + g < nv) {
-      const double2 *v = V[i0 + g] + (int64_t)c * ldv;
+      const double2 *v = V[i0 + g] + (int64_t)c * ldv + td.start;
 #pragma unroll
       for (int e = 0; e < kEPT; ++e) {
-        const int64_t idx = t0 + e * kBlock + threadIdx.x;
-        if (idx < n) {
-          const double2 a = v[idx];
+        const int loc = e * kBlock + threadIdx.x;
+        if (loc < td.len) {
+          const double2 a = v[loc];
           acc[g].x = std::fma(a.x, wv[e].x, std::fma(a.y, wv[e].y, acc[g].x));
           acc[g].y = std::fma(a.x, wv[e].y, std::fma(-a.y, wv[e].x, acc[g].y));
         }
@@ -103,32 +107,43 @@ __global__ __launch_bounds__(kBlock) void dots_kernel(int64_t n, int nrhs, int n
   }
 }
 
-// out[c * ldo + i] = sum_tile part[(tile * nrhs + c) * nv + i]  (fixed order); optionally also
-// writes sqrt(real part) of entry 0 to beta[c] (norm mode)
-__global__ void reduce_kernel(int ntiles, int nrhs, int nv, const double2 *__restrict__ part, double2 *out,
+// out[q * ldo + i] = sum over the tiles [seg_tiles[s].x, seg_tiles[s].y) of system q = c nseg + s
+// (fixed order); zero for inactive systems.  Optionally writes sqrt(real part) of entry 0 to
+// beta[q] (norm mode).
+__global__ void reduce_kernel(int nrhs, int nv, int nseg, const int2 *__restrict__ seg_tiles,
+                              const int *__restrict__ active, const double2 *__restrict__ part, double2 *out,
                               int64_t ldo, double *beta) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nrhs * nv) return;
-  const int c = t / nv, i = t - c * nv;
+  if (t >= nrhs * nseg * nv) return;
+  const int q = t / nv, i = t - q * nv;
+  const int c = q / nseg, s = q - c * nseg;
   double2 r = make_double2(0.0, 0.0);
-  for (int k = 0; k < ntiles; ++k) {
-    const double2 p = part[((int64_t)k * nrhs + c) * nv + i];
-    r.x += p.x;
-    r.y += p.y;
+  if (active[q]) {
+    const int2 tr = seg_tiles[s];
+    for (int k = tr.x; k < tr.y; ++k) {
+      const double2 p = part[((int64_t)k * nrhs + c) * nv + i];
+      r.x += p.x;
+      r.y += p.y;
+    }
   }
-  if (out) out[(int64_t)c * ldo + i] = r;
-  if (beta) beta[c] = std::sqrt(r.x);
+  if (out) out[(int64_t)q * ldo + i] = r;
+  if (beta) beta[q] = std::sqrt(r.x);
 }
 
-// w[c][n] += sign * sum_{i < nv} V_i[c][n] h[c * ldh + i]
-__global__ __launch_bounds__(kBlock) void update_kernel(int64_t n, int nv, const double2 *const *V, int64_t ldv,
-                                                        const double2 *__restrict__ hcoef, int64_t ldh,
+// w[c][n] += sign * sum_{i < nv} V_i[c][n] h[q * ldh + i] for the system q of element n
+// (active systems only); grid (tiles * kEPT, nrhs)
+__global__ __launch_bounds__(kBlock) void update_kernel(int nv, int nseg, const TileDesc *__restrict__ tiles,
+                                                        const int *__restrict__ active, const double2 *const *V,
+                                                        int64_t ldv, const double2 *__restrict__ hcoef, int64_t ldh,
                                                         double sign, double2 *__restrict__ w, int64_t ldw) {
-  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const TileDesc td = tiles[blockIdx.x / kEPT];
+  const int loc = (blockIdx.x % kEPT) * kBlock + threadIdx.x;
   const int c = blockIdx.y;
-  if (idx >= n) return;
+  const int q = c * nseg + td.seg;
+  if (loc >= td.len || !active[q]) return;
+  const int64_t idx = td.start + loc;
   double ar = 0.0, ai = 0.0;
-  const double2 *hc = hcoef + (int64_t)c * ldh;
+  const double2 *hc = hcoef + (int64_t)q * ldh;
 #pragma unroll 8
   for (int i = 0; i < nv; ++i) {
     const double2 v = V[i][(int64_t)c * ldv + idx];
@@ -141,14 +156,26 @@ __global__ __launch_bounds__(kBlock) void update_kernel(int64_t n, int nv, const
   o.y = std::fma(sign, ai, o.y);
 }
 
-// y[c][n] = a[c][n] * (1 / beta[c])  (beta[c] > 0), with a and y possibly the same
-__global__ __launch_bounds__(kBlock) void scale_kernel(int64_t n, const double *__restrict__ beta, const double2 *a,
+// y[c][n] = a[c][n] * (1 / beta[q]) for active systems (beta[q] > 0), and 0 for inactive ones, a
+// and y possibly the same; grid (tiles * kEPT, nrhs).  Zeroing keeps the vectors of a finished
+// system bounded (the operator maps 0 to 0), so its later basis vectors, which enter the final
+// update with zero weights, stay exactly zero.
+__global__ __launch_bounds__(kBlock) void scale_kernel(int nseg, const TileDesc *__restrict__ tiles,
+                                                       const int *__restrict__ active,
+                                                       const double *__restrict__ beta, const double2 *a,
                                                        int64_t lda, double2 *y, int64_t ldy) {
-  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const TileDesc td = tiles[blockIdx.x / kEPT];
+  const int loc = (blockIdx.x % kEPT) * kBlock + threadIdx.x;
   const int c = blockIdx.y;
-  if (idx >= n) return;
-  const double bt = beta[c];
-  const double s = bt > 0.0 ? 1.0 / bt : 0.0;
+  const int q = c * nseg + td.seg;
+  if (loc >= td.len) return;
+  const int64_t idx = td.start + loc;
+  const double bt = beta[q];
+  if (!active[q] || !(bt > 0.0)) {
+    y[(int64_t)c * ldy + idx] = make_double2(0.0, 0.0);   // a may hold anything here
+    return;
+  }
+  const double s = 1.0 / bt;
   const double2 v = a[(int64_t)c * lda + idx];
   y[(int64_t)c * ldy + idx] = make_double2(v.x * s, v.y * s);
 }
@@ -197,6 +224,8 @@ struct SolveWs {
   size_t small_bytes = 0;
   void *part = nullptr;      // per-tile partial inner products, grown with the basis
   size_t part_bytes = 0;
+  void *meta = nullptr;      // tile table, per-scatterer tile ranges, active flags
+  size_t meta_bytes = 0;
   void *vecs = nullptr;      // r, t, inner workspaces
   size_t vec_bytes = 0;
 };
@@ -233,10 +262,9 @@ SolveWs *solve_ws(ls_ctx *h, int level) {
   return (SolveWs *)h->ws_solve.ptr + level;
 }
 
-unsigned tiles_of(int64_t n) { return (unsigned)((n + kTile - 1) / kTile); }
 unsigned blocks_of(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-// One GMRES cycle engine shared by the plain and the flexible variant.
+// One GMRES engine shared by the plain, relaxed and flexible variants.
 struct Gmres {
   ls_ctx *h;
   hipStream_t st;
@@ -244,36 +272,73 @@ struct Gmres {
   int nrhs;
   Mode mode;
   SolveWs *ws;
+  int nseg = 1, nsys = 1, ntile = 0;
   // device scratch
   double2 *part = nullptr, *hbuf = nullptr, *ybuf = nullptr;
   double *beta = nullptr;
-  double2 **ptrs = nullptr;   // device table of basis pointers
+  double2 **ptrs = nullptr;   // device table of basis pointers; entry max_vec + 2 is the norm slot
+  TileDesc *tiles = nullptr;
+  int2 *seg_tiles = nullptr;
+  int *active = nullptr;
   int max_vec = 0;
+  const double2 *slot_vec = nullptr;   // the vector in the norm slot (host copy of that entry)
 
   hipError_t init(int maxvec) {
     max_vec = maxvec;
-    const size_t need = 2 * sizeof(double2) * (size_t)nrhs * (maxvec + 1) +          // h, y
-                        sizeof(double) * nrhs + sizeof(double2 *) * (size_t)(2 * maxvec + 8) + 1024;
+    nseg = (int)h->sc.size();
+    nsys = nrhs * nseg;
+    // tiles of at most kTile elements inside each scatterer's segment
+    std::vector<TileDesc> tl;
+    std::vector<int2> sr(nseg);
+    for (int s = 0; s < nseg; ++s) {
+      const Scat &sc = h->sc[s];
+      sr[s].x = (int)tl.size();
+      for (int64_t a = 0; a < sc.n; a += kTile)
+        tl.push_back(TileDesc{sc.off + a, (int)std::min<int64_t>(kTile, sc.n - a), s});
+      sr[s].y = (int)tl.size();
+    }
+    ntile = (int)tl.size();
+    const size_t need = 2 * sizeof(double2) * (size_t)nsys * (maxvec + 1) +          // h, y
+                        sizeof(double) * nsys + sizeof(double2 *) * (size_t)(2 * maxvec + 8) + 1024;
     hipError_t e = ensure(ws->small, ws->small_bytes, need);
+    if (e != hipSuccess) return e;
+    const size_t mneed = sizeof(TileDesc) * tl.size() + sizeof(int2) * nseg + sizeof(int) * nsys + 1024;
+    e = ensure(ws->meta, ws->meta_bytes, mneed);
     if (e != hipSuccess) return e;
     e = ensure_part(16);
     if (e != hipSuccess) return e;
     char *p = (char *)ws->small;
     hbuf = (double2 *)p;
-    p += sizeof(double2) * (size_t)nrhs * (maxvec + 1);
+    p += sizeof(double2) * (size_t)nsys * (maxvec + 1);
     ybuf = (double2 *)p;
-    p += sizeof(double2) * (size_t)nrhs * (maxvec + 1);
+    p += sizeof(double2) * (size_t)nsys * (maxvec + 1);
     beta = (double *)p;
-    p += sizeof(double) * nrhs;
+    p += sizeof(double) * nsys;
     p = (char *)(((uintptr_t)p + 255) & ~(uintptr_t)255);
     ptrs = (double2 **)p;
-    return hipSuccess;
+    char *m = (char *)ws->meta;
+    tiles = (TileDesc *)m;
+    m += sizeof(TileDesc) * tl.size();
+    m = (char *)(((uintptr_t)m + 255) & ~(uintptr_t)255);
+    seg_tiles = (int2 *)m;
+    m += sizeof(int2) * nseg;
+    m = (char *)(((uintptr_t)m + 255) & ~(uintptr_t)255);
+    active = (int *)m;
+    e = hipMemcpyAsync(tiles, tl.data(), sizeof(TileDesc) * tl.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(seg_tiles, sr.data(), sizeof(int2) * nseg, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);   // host tables go out of scope
+    return e;
+  }
+
+  // device copy of the active flags (host vector of nsys entries)
+  hipError_t set_active(const std::vector<int> &flags) {
+    return hipMemcpyAsync(active, flags.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, st);
   }
 
   // partials for nv inner products per column; grows geometrically, after the stream has drained
   // (the old buffer may still be read by a queued reduction)
   hipError_t ensure_part(int nv) {
-    const size_t per = sizeof(double2) * tiles_of(n) * nrhs;
+    const size_t per = sizeof(double2) * (size_t)(ntile > 0 ? ntile : 1) * nrhs;
     if (per * nv <= ws->part_bytes) {
       part = (double2 *)ws->part;
       return hipSuccess;
@@ -286,25 +351,33 @@ struct Gmres {
     return e;
   }
 
-  // h[c][0..nv) = V[0..nv)^H w (device, hbuf), using the pointer table entries [0, nv)
+  // out[q][0..nv) = V[0..nv)^H w per active system, using the pointer table entries [0, nv)
   hipError_t dots(int nv, const double2 *w, double2 *out, int64_t ldo) {
     hipError_t e0 = ensure_part(nv);
     if (e0 != hipSuccess) return e0;
-    dim3 g(tiles_of(n), (unsigned)((nv + kGroup - 1) / kGroup), nrhs);
-    dots_kernel<<<g, kBlock, 0, st>>>(n, nrhs, nv, ptrs, n, w, n, part);
-    reduce_kernel<<<(unsigned)((nrhs * nv + 255) / 256), 256, 0, st>>>((int)tiles_of(n), nrhs, nv, part, out, ldo,
-                                                                       nullptr);
+    dim3 g((unsigned)ntile, (unsigned)((nv + kGroup - 1) / kGroup), nrhs);
+    dots_kernel<<<g, kBlock, 0, st>>>(nrhs, nv, nseg, tiles, active, ptrs, n, w, n, part);
+    reduce_kernel<<<(unsigned)((nsys * nv + 255) / 256), 256, 0, st>>>(nrhs, nv, nseg, seg_tiles, active, part, out,
+                                                                       ldo, nullptr);
     return hipGetLastError();
   }
 
-  // beta[c] = ||w_c||
-  hipError_t norms(const double2 *w, double2 **tbl_slot) {
-    (void)tbl_slot;
-    dim3 g(tiles_of(n), 1, nrhs);
-    dots_kernel<<<g, kBlock, 0, st>>>(n, nrhs, 1, ptrs + max_vec + 2, n, w, n, part);
-    reduce_kernel<<<(unsigned)((nrhs + 255) / 256), 256, 0, st>>>((int)tiles_of(n), nrhs, 1, part, nullptr, 1, beta);
+  // puts v in the norm slot of the device pointer table
+  hipError_t set_slot(const double2 *v) {
+    slot_vec = v;
+    return hipMemcpyAsync(ptrs + max_vec + 2, &slot_vec, sizeof(double2 *), hipMemcpyHostToDevice, st);
+  }
+
+  // beta[q] = ||v_q|| per active system for the vector v in the norm slot
+  hipError_t norms() {
+    dim3 g((unsigned)ntile, 1, nrhs);
+    dots_kernel<<<g, kBlock, 0, st>>>(nrhs, 1, nseg, tiles, active, ptrs + max_vec + 2, n, slot_vec, n, part);
+    reduce_kernel<<<(unsigned)((nsys + 255) / 256), 256, 0, st>>>(nrhs, 1, nseg, seg_tiles, active, part, nullptr, 1,
+                                                                  beta);
     return hipGetLastError();
   }
+
+  dim3 tile_grid() const { return dim3((unsigned)ntile * kEPT, nrhs); }
 };
 
 }  // namespace
@@ -319,19 +392,21 @@ struct CoreOpts {
   int inner_maxit;
   bool x0_given;
   double relax_eps;      // > 0: FP64 applies while the residual estimate exceeds tol / relax_eps, mixed after
+  int progress;          // > 0: print a progress line every this many steps
 };
 
 struct CoreResult {
-  std::vector<int> iters;
-  std::vector<char> done;
+  std::vector<int> iters;   // per system
+  std::vector<char> done;   // per system
   int64_t n_fp64 = 0, n_mixed = 0;
 };
 
-// GMRES on contiguous (ld = n) device vectors b, x of nrhs columns.  x holds the initial guess
-// when o.x0_given, the approximate solution on return.  ws is this level's workspace; the
-// flexible variant runs its inner solves with a second workspace.
+// GMRES on contiguous (ld = n) device vectors b, x of nrhs columns, one independent system per
+// (column, scatterer).  x holds the initial guess when o.x0_given, the approximate solution on
+// return.  Systems with (*only)[q] == 0 (when given) are left alone.  ws is this level's
+// workspace; the flexible variant runs its inner solves with a second workspace.
 ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b, double2 *x, int nrhs,
-                     const CoreOpts &o, CoreResult &res, hipStream_t st) {
+                     const CoreOpts &o, CoreResult &res, hipStream_t st, const std::vector<int> *only = nullptr) {
   const int64_t n = h->n_total;
   const int maxit = o.maxit;
   const int cyc = (o.restart > 0 && o.restart < maxit) ? o.restart : maxit;
@@ -342,6 +417,7 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
     if (e_ != hipSuccess) return setup_fail(h, LS_ERR_HIP, hipGetErrorString(e_)); \
   } while (0)
   HIPTRY(G.init(cyc + 1));
+  const int nseg = G.nseg, nsys = G.nsys;
   const size_t vb = sizeof(double2) * (size_t)n * nrhs;
   HIPTRY(ensure(ws->vecs, ws->vec_bytes, 2 * vb));
   double2 *r = (double2 *)ws->vecs;
@@ -350,7 +426,7 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
   // holds maxit vectors); new chunks enter the device pointer table as they arrive
   HIPTRY(ensure_chunks(ws->V, 1, n, nrhs));
   if (o.flexible) HIPTRY(ensure_chunks(ws->Z, 1, n, nrhs));
-  std::vector<double2 *> tbl(2 * (cyc + 1) + 4, nullptr);
+  std::vector<double2 *> tbl(cyc + 1, nullptr);
   int have = 0;   // basis vectors whose pointers are in tbl and on the device
   auto grow = [&](int nvec) -> hipError_t {
     nvec = std::min(nvec, cyc + 1);
@@ -361,32 +437,42 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
     for (int i = have; i < upto; ++i) tbl[i] = ws->V.vec(i, n, nrhs);
     e = hipMemcpyAsync(G.ptrs + have, tbl.data() + have, sizeof(double2 *) * (upto - have), hipMemcpyHostToDevice,
                        st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);   // tbl entries may move when tbl is reused
     have = upto;
     return e;
   };
-  const int slot = G.max_vec + 2;
-  std::vector<double> bnorm(nrhs);
-  tbl[slot] = (double2 *)b;
-  HIPTRY(hipMemcpyAsync(G.ptrs, tbl.data(), sizeof(double2 *) * tbl.size(), hipMemcpyHostToDevice, st));
+  auto norms_of = [&](const double2 *v, std::vector<double> &out) -> hipError_t {
+    hipError_t e = G.set_slot(v);
+    if (e == hipSuccess) e = G.norms();
+    if (e == hipSuccess) e = hipMemcpyAsync(out.data(), G.beta, sizeof(double) * nsys, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return e;
+  };
   HIPTRY(grow(1));
-  HIPTRY(G.norms(b, nullptr));
-  HIPTRY(hipMemcpyAsync(bnorm.data(), G.beta, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
-  HIPTRY(hipStreamSynchronize(st));
-  for (int c = 0; c < nrhs; ++c)
-    if (!std::isfinite(bnorm[c])) return setup_fail(h, LS_ERR_NONFINITE, "non-finite right-hand side");
+  // systems in play: all, or those the caller names; the others count as done from the start
+  std::vector<int> act(nsys, 1);
+  if (only)
+    for (int q = 0; q < nsys; ++q) act[q] = (*only)[q] ? 1 : 0;
+  HIPTRY(G.set_active(act));
+  std::vector<double> bnorm(nsys, 0.0);
+  HIPTRY(norms_of(b, bnorm));
+  for (int q = 0; q < nsys; ++q)
+    if (act[q] && !std::isfinite(bnorm[q])) return setup_fail(h, LS_ERR_NONFINITE, "non-finite right-hand side");
   if (!o.x0_given) HIPTRY(hipMemsetAsync(x, 0, vb, st));
-  res.iters.assign(nrhs, 0);
-  res.done.assign(nrhs, 0);
-  std::vector<double> est(nrhs, 1.0);
+  res.iters.assign(nsys, 0);
+  res.done.assign(nsys, 0);
+  for (int q = 0; q < nsys; ++q) res.done[q] = act[q] ? 0 : 1;
+  std::vector<double> est(nsys, 1.0);
   int total_it = 0;
   bool first_cycle = true;
-  // Hessenberg columns packed per right-hand side: column j (rows 0..j+1) starts at j (j + 3) / 2,
-  // grown one column per step
-  std::vector<std::vector<cplx>> H(nrhs);
+  // Hessenberg columns packed per system: column j (rows 0..j+1) starts at j (j + 3) / 2, grown
+  // one column per step
+  std::vector<std::vector<cplx>> H(nsys);
   std::vector<cplx> cs, sn, g;
-  std::vector<double2> hh((size_t)nrhs * (cyc + 1) * 2);
-  std::vector<double> betah(nrhs);
+  std::vector<double2> hh((size_t)nsys * (cyc + 1) * 2);
+  std::vector<double> betah(nsys), rnorm(nsys);
   const dim3 gv(blocks_of(n), nrhs);
+  const dim3 gt = G.tile_grid();
   while (total_it < maxit) {
     // r = b - L x (FP64), skipped while x = 0
     if (first_cycle && !o.x0_given) {
@@ -400,52 +486,49 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
       HIPTRY(hipGetLastError());
     }
     first_cycle = false;
-    tbl[slot] = r;
-    HIPTRY(hipMemcpyAsync(G.ptrs, tbl.data(), sizeof(double2 *) * tbl.size(), hipMemcpyHostToDevice, st));
-    HIPTRY(G.norms(r, nullptr));
-    std::vector<double> rnorm(nrhs);
-    HIPTRY(hipMemcpyAsync(rnorm.data(), G.beta, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
-    scale_kernel<<<gv, kBlock, 0, st>>>(n, G.beta, r, n, tbl[0], n);
-    HIPTRY(hipGetLastError());
-    HIPTRY(hipStreamSynchronize(st));
+    for (int q = 0; q < nsys; ++q) act[q] = res.done[q] ? 0 : 1;
+    HIPTRY(G.set_active(act));
+    HIPTRY(norms_of(r, rnorm));
     bool all = true;
-    for (int c = 0; c < nrhs; ++c) {
-      est[c] = bnorm[c] > 0 ? rnorm[c] / bnorm[c] : 0.0;
-      if (!std::isfinite(est[c])) return setup_fail(h, LS_ERR_NONFINITE, "non-finite residual");
-      res.done[c] = est[c] <= o.tol;
-      all = all && res.done[c];
+    for (int q = 0; q < nsys; ++q) {
+      if (res.done[q]) continue;
+      est[q] = bnorm[q] > 0 ? rnorm[q] / bnorm[q] : 0.0;
+      if (!std::isfinite(est[q])) return setup_fail(h, LS_ERR_NONFINITE, "non-finite residual");
+      res.done[q] = est[q] <= o.tol;
+      act[q] = res.done[q] ? 0 : 1;
+      all = all && res.done[q];
     }
     if (all) break;
+    HIPTRY(G.set_active(act));
+    scale_kernel<<<gt, kBlock, 0, st>>>(nseg, G.tiles, G.active, G.beta, r, n, tbl[0], n);
+    HIPTRY(hipGetLastError());
     const int m = cyc;
     for (auto &hc : H) hc.clear();
-    cs.assign((size_t)nrhs * m, cplx(0));
-    sn.assign((size_t)nrhs * m, cplx(0));
-    g.assign((size_t)nrhs * (m + 1), cplx(0));
-    std::vector<int> mc(nrhs, 0);
-    std::vector<char> active(nrhs);
-    for (int c = 0; c < nrhs; ++c) {
-      g[(size_t)c * (m + 1)] = rnorm[c];
-      active[c] = !res.done[c];
-    }
+    cs.assign((size_t)nsys * m, cplx(0));
+    sn.assign((size_t)nsys * m, cplx(0));
+    g.assign((size_t)nsys * (m + 1), cplx(0));
+    std::vector<int> mc(nsys, 0);
+    const std::vector<int> part_in(act);   // systems that take part in this cycle
+    for (int q = 0; q < nsys; ++q) g[(size_t)q * (m + 1)] = rnorm[q];
     int j = 0;
     for (; j < m && total_it < maxit; ++j, ++total_it) {
       HIPTRY(grow(j + 2));
       double2 *vj = tbl[j];
       double2 *w = tbl[j + 1];
       if (o.flexible) {
-        // z_j ~ L^{-1} v_j by an inner GMRES with the mixed-precision operator, then w = L z_j
+        // z_j ~ L^{-1} v_j by an inner GMRES with the mixed-precision operator (active systems
+        // only), then w = L z_j
         HIPTRY(ensure_chunks(ws->Z, j + 1, n, nrhs));
         double2 *zj = ws->Z.vec(j, n, nrhs);
-        CoreOpts io{o.inner_tol, o.inner_maxit, 0, o.mode, LS_MIXED, false, 0.0, 0, false, 0.0};
+        CoreOpts io{o.inner_tol, o.inner_maxit, 0, o.mode, LS_MIXED, false, 0.0, 0, false, 0.0, 0};
         CoreResult ir;
-        ls_status s2 = gmres_core(h, ws_inner, nullptr, vj, zj, nrhs, io, ir, st);
+        ls_status s2 = gmres_core(h, ws_inner, nullptr, vj, zj, nrhs, io, ir, st, &act);
         if (s2 < 0) return s2;
         res.n_mixed += ir.n_mixed;
         res.n_fp64 += ir.n_fp64;
         s2 = apply_op(h, (const double *)zj, (double *)w, nrhs, n, o.mode, LS_FP64, st);
         if (s2 != LS_OK) return s2;
         ++res.n_fp64;
-        tbl[slot] = r;   // the inner solve used its own pointer table; ours is intact
       } else {
         // relaxed inexact Arnoldi: an application error of relative size eps perturbs the
         // residual by about eps times the current residual, so once the largest active residual
@@ -453,8 +536,8 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
         ls_precision pj = o.matvec;
         if (o.relax_eps > 0) {
           double worst = 0.0;
-          for (int c = 0; c < nrhs; ++c)
-            if (active[c]) worst = std::max(worst, est[c]);
+          for (int q = 0; q < nsys; ++q)
+            if (act[q]) worst = std::max(worst, est[q]);
           pj = worst * o.relax_eps <= o.tol ? LS_MIXED : LS_FP64;
         }
         ls_status s2 = apply_op(h, (const double *)vj, (double *)w, nrhs, n, o.mode, pj, st);
@@ -465,32 +548,32 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
       const int nv = j + 1;
       double2 *h1 = G.hbuf, *h2 = G.ybuf;
       HIPTRY(G.dots(nv, w, h1, nv));
-      update_kernel<<<gv, kBlock, 0, st>>>(n, nv, G.ptrs, n, h1, nv, -1.0, w, n);
+      update_kernel<<<gt, kBlock, 0, st>>>(nv, nseg, G.tiles, G.active, G.ptrs, n, h1, nv, -1.0, w, n);
       HIPTRY(G.dots(nv, w, h2, nv));
-      update_kernel<<<gv, kBlock, 0, st>>>(n, nv, G.ptrs, n, h2, nv, -1.0, w, n);
-      tbl[slot] = w;
-      HIPTRY(hipMemcpyAsync(G.ptrs + slot, &tbl[slot], sizeof(double2 *), hipMemcpyHostToDevice, st));
-      HIPTRY(G.norms(w, nullptr));
-      scale_kernel<<<gv, kBlock, 0, st>>>(n, G.beta, w, n, w, n);
-      HIPTRY(hipMemcpyAsync(hh.data(), h1, sizeof(double2) * nrhs * nv, hipMemcpyDeviceToHost, st));
-      HIPTRY(hipMemcpyAsync(hh.data() + (size_t)nrhs * nv, h2, sizeof(double2) * nrhs * nv, hipMemcpyDeviceToHost,
+      update_kernel<<<gt, kBlock, 0, st>>>(nv, nseg, G.tiles, G.active, G.ptrs, n, h2, nv, -1.0, w, n);
+      HIPTRY(G.set_slot(w));
+      HIPTRY(G.norms());
+      scale_kernel<<<gt, kBlock, 0, st>>>(nseg, G.tiles, G.active, G.beta, w, n, w, n);
+      HIPTRY(hipMemcpyAsync(hh.data(), h1, sizeof(double2) * nsys * nv, hipMemcpyDeviceToHost, st));
+      HIPTRY(hipMemcpyAsync(hh.data() + (size_t)nsys * nv, h2, sizeof(double2) * nsys * nv, hipMemcpyDeviceToHost,
                             st));
-      HIPTRY(hipMemcpyAsync(betah.data(), G.beta, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+      HIPTRY(hipMemcpyAsync(betah.data(), G.beta, sizeof(double) * nsys, hipMemcpyDeviceToHost, st));
       HIPTRY(hipStreamSynchronize(st));
-      bool any = false;
-      for (int c = 0; c < nrhs; ++c) {
-        if (!active[c]) continue;
-        std::vector<cplx> &Hv = H[c];
+      bool any = false, changed = false;
+      double worst = 0.0;
+      for (int q = 0; q < nsys; ++q) {
+        if (!act[q]) continue;
+        std::vector<cplx> &Hv = H[q];
         Hv.resize((size_t)(j + 1) * (j + 4) / 2, cplx(0));
         cplx *Hc = Hv.data();
         auto Hat = [&](int r_, int c_) -> cplx & { return Hc[(size_t)c_ * (c_ + 3) / 2 + r_]; };
         for (int i = 0; i < nv; ++i) {
-          const double2 a = hh[(size_t)c * nv + i], bq = hh[(size_t)nrhs * nv + (size_t)c * nv + i];
+          const double2 a = hh[(size_t)q * nv + i], bq = hh[(size_t)nsys * nv + (size_t)q * nv + i];
           Hat(i, j) = cplx(a.x + bq.x, a.y + bq.y);
         }
-        Hat(j + 1, j) = betah[c];
-        if (!std::isfinite(betah[c])) return setup_fail(h, LS_ERR_BREAKDOWN, "non-finite Arnoldi vector");
-        cplx *csc = &cs[(size_t)c * m], *snc = &sn[(size_t)c * m], *gc = &g[(size_t)c * (m + 1)];
+        Hat(j + 1, j) = betah[q];
+        if (!std::isfinite(betah[q])) return setup_fail(h, LS_ERR_BREAKDOWN, "non-finite Arnoldi vector");
+        cplx *csc = &cs[(size_t)q * m], *snc = &sn[(size_t)q * m], *gc = &g[(size_t)q * (m + 1)];
         for (int i = 0; i < j; ++i) {
           const cplx tq = csc[i] * Hat(i, j) + snc[i] * Hat(i + 1, j);
           Hat(i + 1, j) = -std::conj(snc[i]) * Hat(i, j) + std::conj(csc[i]) * Hat(i + 1, j);
@@ -504,51 +587,65 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
         Hat(j + 1, j) = 0.0;
         gc[j + 1] = -std::conj(snc[j]) * gc[j];
         gc[j] = csc[j] * gc[j];
-        mc[c] = j + 1;
-        res.iters[c]++;
-        est[c] = bnorm[c] > 0 ? std::abs(gc[j + 1]) / bnorm[c] : 0.0;
-        if (est[c] <= o.tol || betah[c] == 0.0) {
-          active[c] = 0;
-          res.done[c] = 1;
+        mc[q] = j + 1;
+        res.iters[q]++;
+        est[q] = bnorm[q] > 0 ? std::abs(gc[j + 1]) / bnorm[q] : 0.0;
+        if (est[q] <= o.tol || betah[q] == 0.0) {
+          act[q] = 0;
+          res.done[q] = 1;
+          changed = true;
         } else {
           any = true;
+          worst = std::max(worst, est[q]);
         }
+      }
+      if (o.progress > 0 && (total_it + 1) % o.progress == 0) {
+        int na = 0;
+        for (int q = 0; q < nsys; ++q) na += act[q];
+        std::fprintf(stderr, "[ls gmres] step %d: largest residual estimate %.3e, %d of %d systems active\n",
+                     total_it + 1, worst, na, nsys);
+        std::fflush(stderr);
       }
       if (!any) {
         ++j;
         ++total_it;
         break;
       }
+      if (changed) HIPTRY(G.set_active(act));
     }
-    // x += V y (or Z y for the flexible variant) per column
-    std::vector<double2> yv((size_t)nrhs * m, make_double2(0, 0));
-    for (int c = 0; c < nrhs; ++c) {
-      const int mm = mc[c];
-      const cplx *Hc = H[c].data();
+    // x += V y (or Z y for the flexible variant) per system that took part in the cycle
+    std::vector<double2> yv((size_t)nsys * m, make_double2(0, 0));
+    for (int q = 0; q < nsys; ++q) {
+      const int mm = mc[q];
+      if (mm == 0) continue;
+      const cplx *Hc = H[q].data();
       auto Hat = [&](int r_, int c_) { return Hc[(size_t)c_ * (c_ + 3) / 2 + r_]; };
       std::vector<cplx> yc(mm);
       for (int i = mm - 1; i >= 0; --i) {
-        cplx sacc = g[(size_t)c * (m + 1) + i];
+        cplx sacc = g[(size_t)q * (m + 1) + i];
         for (int k2 = i + 1; k2 < mm; ++k2) sacc -= Hat(i, k2) * yc[k2];
         yc[i] = sacc / Hat(i, i);
       }
-      for (int i = 0; i < mm; ++i) yv[(size_t)c * m + i] = make_double2(yc[i].real(), yc[i].imag());
+      for (int i = 0; i < mm; ++i) yv[(size_t)q * m + i] = make_double2(yc[i].real(), yc[i].imag());
     }
     const int mmax = std::max(1, *std::max_element(mc.begin(), mc.end()));
-    HIPTRY(hipMemcpyAsync(G.hbuf, yv.data(), sizeof(double2) * nrhs * m, hipMemcpyHostToDevice, st));
+    HIPTRY(hipMemcpyAsync(G.hbuf, yv.data(), sizeof(double2) * nsys * m, hipMemcpyHostToDevice, st));
+    HIPTRY(G.set_active(part_in));
+    std::vector<double2 *> ztbl;
     if (o.flexible) {
-      std::vector<double2 *> ztbl(mmax);
+      ztbl.resize(mmax);
       for (int i = 0; i < mmax; ++i) ztbl[i] = ws->Z.vec(i, n, nrhs);
       HIPTRY(hipMemcpyAsync(G.ptrs + G.max_vec + 4, ztbl.data(), sizeof(double2 *) * mmax, hipMemcpyHostToDevice,
                             st));
-      update_kernel<<<gv, kBlock, 0, st>>>(n, mmax, G.ptrs + G.max_vec + 4, n, G.hbuf, m, 1.0, x, n);
+      update_kernel<<<gt, kBlock, 0, st>>>(mmax, nseg, G.tiles, G.active, G.ptrs + G.max_vec + 4, n, G.hbuf, m, 1.0,
+                                           x, n);
     } else {
-      update_kernel<<<gv, kBlock, 0, st>>>(n, mmax, G.ptrs, n, G.hbuf, m, 1.0, x, n);
+      update_kernel<<<gt, kBlock, 0, st>>>(mmax, nseg, G.tiles, G.active, G.ptrs, n, G.hbuf, m, 1.0, x, n);
     }
     HIPTRY(hipGetLastError());
-    HIPTRY(hipStreamSynchronize(st));
+    HIPTRY(hipStreamSynchronize(st));   // yv and ztbl go out of scope
     bool all_done = true;
-    for (int c = 0; c < nrhs; ++c) all_done = all_done && res.done[c];
+    for (int q = 0; q < nsys; ++q) all_done = all_done && res.done[q];
     if (all_done || cyc >= maxit) break;
   }
   return LS_OK;
@@ -576,24 +673,27 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
   if (o.x0_given)
     HIPTRY(hipMemcpy2DAsync(xs, n * sizeof(double2), x_out, ld * sizeof(double2), n * sizeof(double2), nrhs,
                             hipMemcpyDeviceToDevice, st));
+  const char *pe = std::getenv("LS_PROGRESS");
+  const int progress = pe ? std::max(0, std::atoi(pe)) : 0;
   // LS_MIXED: with inner_maxit > 0, flexible GMRES whose preconditioner is inner_maxit steps of
   // mixed-precision GMRES (to inner_tol); otherwise relaxed GMRES switching to the mixed operator
   // once the residual is below tol / inner_tol (inner_tol = relative accuracy granted to it),
   // followed by FP64 refinement passes from the true residual if that missed tol
   const bool mixed = o.prec == LS_MIXED;
   const bool flexible = mixed && o.inner_maxit > 0;
-  const double relax = (mixed && !flexible) ? (o.inner_tol > 0 ? o.inner_tol : 1e-3) : 0.0;
+  const double relax = (mixed && !flexible) ? (o.inner_tol > 0 ? o.inner_tol : 1e-6) : 0.0;
   // the relaxed iteration aims its residual estimate below 0.3 tol so that its FP64 residual,
   // perturbed by the mixed applications, still meets tol without a (Krylov-space-losing) restart
   CoreOpts co{relax > 0 ? 0.3 * o.tol : o.tol, o.maxit, o.restart, mode, LS_FP64, flexible,
-              o.inner_tol > 0 ? o.inner_tol : 1e-12, o.inner_maxit, o.x0_given != 0, relax};
+              o.inner_tol > 0 ? o.inner_tol : 1e-12, o.inner_maxit, o.x0_given != 0, relax, progress};
   CoreResult res;
   ls_status status = gmres_core(h, ws, wi, bb, xs, nrhs, co, res, st);
   if (status < 0) return status;
+  const int nsys = (int)res.iters.size();
   for (int pass = 0; pass < 3 && relax > 0; ++pass) {
-    // refinement from the FP64 residual for columns the relaxed iteration left above tol
+    // refinement from the FP64 residual for systems the relaxed iteration left above tol
     int used = 0;
-    for (int c = 0; c < nrhs; ++c) used = std::max(used, res.iters[c]);
+    for (int q = 0; q < nsys; ++q) used = std::max(used, res.iters[q]);
     if (used >= o.maxit) break;
     CoreOpts ro = co;
     ro.x0_given = true;
@@ -603,14 +703,14 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
     status = gmres_core(h, ws, wi, bb, xs, nrhs, ro, rr, st);
     if (status < 0) return status;
     int more = 0;
-    for (int c = 0; c < nrhs; ++c) {
-      res.iters[c] += rr.iters[c];
-      res.done[c] = rr.done[c];
-      more += rr.iters[c];
+    for (int q = 0; q < nsys; ++q) {
+      res.iters[q] += rr.iters[q];
+      res.done[q] = rr.done[q];
+      more += rr.iters[q];
     }
     res.n_fp64 += rr.n_fp64;
     res.n_mixed += rr.n_mixed;
-    if (more == 0) break;   // every column met tol on its FP64 residual
+    if (more == 0) break;   // every system met tol on its FP64 residual
   }
   // true residuals with the FP64 apply
   ls_status s2 = apply_op(h, (const double *)xs, (double *)t, nrhs, n, mode, LS_FP64, st);
@@ -618,29 +718,40 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
   ++res.n_fp64;
   {
     Gmres G{h, st, n, nrhs, mode, ws};
-    HIPTRY(G.init(std::max(1, (o.restart > 0 && o.restart < o.maxit) ? o.restart : o.maxit) + 1));
+    HIPTRY(G.init(1));
+    const int nseg = G.nseg;
     const dim3 gv(blocks_of(n), nrhs);
     axpy_kernel<<<gv, kBlock, 0, st>>>(n, bb, n, -1.0, t, n, r, n);
-    std::vector<double2 *> tbl(G.max_vec + 3, nullptr);
-    tbl[G.max_vec + 2] = r;
-    HIPTRY(hipMemcpyAsync(G.ptrs, tbl.data(), sizeof(double2 *) * tbl.size(), hipMemcpyHostToDevice, st));
-    HIPTRY(G.norms(r, nullptr));
-    std::vector<double> rn(nrhs), bn(nrhs);
-    HIPTRY(hipMemcpyAsync(rn.data(), G.beta, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
-    HIPTRY(hipStreamSynchronize(st));
-    tbl[G.max_vec + 2] = bb;
-    HIPTRY(hipMemcpyAsync(G.ptrs, tbl.data(), sizeof(double2 *) * tbl.size(), hipMemcpyHostToDevice, st));
-    HIPTRY(G.norms(bb, nullptr));
-    HIPTRY(hipMemcpyAsync(bn.data(), G.beta, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+    const std::vector<int> all(nsys, 1);
+    HIPTRY(G.set_active(all));
+    std::vector<double> rn(nsys), bn(nsys);
+    for (int pass = 0; pass < 2; ++pass) {
+      HIPTRY(G.set_slot(pass == 0 ? r : bb));
+      HIPTRY(G.norms());
+      HIPTRY(hipMemcpyAsync((pass == 0 ? rn : bn).data(), G.beta, sizeof(double) * nsys, hipMemcpyDeviceToHost, st));
+      HIPTRY(hipStreamSynchronize(st));
+    }
     HIPTRY(hipMemcpy2DAsync(x_out, ld * sizeof(double2), xs, n * sizeof(double2), n * sizeof(double2), nrhs,
                             hipMemcpyDeviceToDevice, st));
     HIPTRY(hipStreamSynchronize(st));
     status = LS_OK;
     for (int c = 0; c < nrhs; ++c) {
-      const double rr = bn[c] > 0 ? rn[c] / bn[c] : 0.0;
+      // a column's relative residual over all its scatterers; its iterations are the most any
+      // of its systems took
+      double r2 = 0.0, b2 = 0.0;
+      int it = 0;
+      bool done = true;
+      for (int s = 0; s < nseg; ++s) {
+        const int q = c * nseg + s;
+        r2 += rn[q] * rn[q];
+        b2 += bn[q] * bn[q];
+        it = std::max(it, res.iters[q]);
+        done = done && res.done[q];
+      }
+      const double rr = b2 > 0 ? std::sqrt(r2 / b2) : 0.0;
       if (info && info->relres) info->relres[c] = rr;
-      if (info && info->iters) info->iters[c] = res.iters[c];
-      if (!res.done[c]) status = LS_NOT_CONVERGED;
+      if (info && info->iters) info->iters[c] = it;
+      if (!done) status = LS_NOT_CONVERGED;
     }
   }
   if (info) {
@@ -680,6 +791,7 @@ void free_solve_ws(ls_ctx *h) {
     for (void *p : ws->Z.chunks) (void)hipFree(p);
     if (ws->small) (void)hipFree(ws->small);
     if (ws->part) (void)hipFree(ws->part);
+    if (ws->meta) (void)hipFree(ws->meta);
     if (ws->vecs) (void)hipFree(ws->vecs);
   }
   delete[] all;
