@@ -278,15 +278,15 @@ def run_batched(args, probs, label, B):
     x, secs, a64, amx, t, its, cols = solve_form(op, b, form, args)
     pairs = sum(p.n_nodes * (p.n_nodes - 1) for p in probs)
     frac = z_fractions([(p.mesh, p.k) for p in probs])
+    # interactions the far sums evaluated (the library leaves out scatterers whose systems have
+    # all finished, so this is not applications x pairs for several scatterers)
+    value = t.prof["pair_rhs"] / secs / 1e9
     if form == "p64":
         # every column is its own solve: scale the timed columns to all B
-        value = a64 * pairs / secs / 1e9
         total_s = secs * B / cols
         roof = roofline_valu(flops_per_pair(frac, 1), pairs, t.far_avg_s)
         dtype = "f64"
     else:
-        applies = a64 + amx   # the library counts one application per column
-        value = applies * pairs / secs / 1e9
         total_s = secs
         single = form == "bm"
         roof = roofline_mfma(pairs * B, far_kernel_avg(op, b, "mixed" if single else "fp64"), single)
@@ -338,15 +338,13 @@ def run_gradient(args, prob, label, B):
     torch.cuda.synchronize()
     secs = fwd[1] + adj[1]
     pairs = n * (n - 1)
-    applies = fwd[2] + fwd[3] + adj[2] + adj[3]
     frac = z_fractions([(prob.mesh, prob.k)])
+    value = (fwd[4].prof["pair_rhs"] + adj[4].prof["pair_rhs"]) / secs / 1e9
     if form == "p64":
-        value = applies * pairs / secs / 1e9
         total_s = secs * B / cols
         roof = roofline_valu(flops_per_pair(frac, 1), pairs, fwd[4].far_avg_s)
         dtype = "f64"
     else:
-        value = applies * pairs / secs / 1e9   # applications are counted per column
         total_s = secs
         single = form == "bm"
         roof = roofline_mfma(pairs * B, far_kernel_avg(op, b, "mixed" if single else "fp64"), single)

@@ -128,8 +128,12 @@ typedef struct {
    *                    inner_maxit steps of GMRES with the mixed operator (to inner_tol,
    *                    default 1e-12, i.e. exactly inner_maxit steps).
    *   inner_maxit = 0: relaxed GMRES; FP64 applications while the residual estimate exceeds
-   *                    0.3 tol / inner_tol (default inner_tol 1e-3), mixed ones after, then FP64
-   *                    refinement passes from the true residual if tol was missed. */
+   *                    0.3 tol / inner_tol (default inner_tol 1e-5, about the measured relative
+   *                    error of the mixed operator at N ~ 1e5), mixed ones after, then FP64
+   *                    refinement passes from the true residual if tol was missed.
+   * With several scatterers in the handle, every (column, scatterer) pair is an independent
+   * system with its own Krylov space and convergence test; iters reports the most steps any
+   * scatterer of the column took, relres the residual over the whole column. */
 } ls_solve_opts;
 
 typedef struct {
@@ -141,7 +145,9 @@ typedef struct {
 } ls_solve_info;
 
 /* Solve L x = b (or L^H x = b) by GMRES without restart, x0 = 0 unless x0_given, each column
- * independently.  Synchronous.  Returns LS_NOT_CONVERGED if any column missed tol. */
+ * (and each scatterer of it) independently.  Synchronous.  Returns LS_NOT_CONVERGED if any
+ * column missed tol.  The environment variable LS_PROGRESS=k prints a progress line to stderr
+ * every k steps. */
 ls_status ls_solve_gmres(ls_handle h, const double *b, double *x, int32_t nrhs, int64_t ld,
                          const ls_solve_opts *o, ls_solve_info *info, hipStream_t stream);
 
@@ -209,6 +215,8 @@ typedef struct {
   double far_ms;
   int64_t apply_calls;
   double apply_ms;
+  double pair_rhs;      /* Green's interactions evaluated: sum over applications of
+                         * N_s (N_s - 1) x right-hand sides over the scatterers computed */
 } ls_profile;
 ls_status ls_profile_enable(ls_handle h, int32_t on);
 ls_status ls_profile_query(ls_handle h, ls_profile *out, int32_t reset);

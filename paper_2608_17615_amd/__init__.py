@@ -47,7 +47,7 @@ class _Scatterer(ctypes.Structure):
 
 class _Profile(ctypes.Structure):
     _fields_ = [("far_launches", ctypes.c_int64), ("far_ms", ctypes.c_double), ("apply_calls", ctypes.c_int64),
-                ("apply_ms", ctypes.c_double)]
+                ("apply_ms", ctypes.c_double), ("pair_rhs", ctypes.c_double)]
 
 
 class _TuneResult(ctypes.Structure):
@@ -337,7 +337,7 @@ class Operator:
         p = _Profile()
         _check(lib().ls_profile_query(self._h, ctypes.byref(p), int(bool(reset))), self._h)
         return {"far_launches": p.far_launches, "far_ms": p.far_ms, "apply_calls": p.apply_calls,
-                "apply_ms": p.apply_ms}
+                "apply_ms": p.apply_ms, "pair_rhs": p.pair_rhs}
 
     def correction_nnz(self, s=0):
         return int(lib().ls_correction_nnz(self._h, s))

@@ -364,6 +364,9 @@ ls_status apply_op(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, 
   }
   hipEvent_t a0 = nullptr, a1 = nullptr;
   if (h->prof) {
+    for (size_t si = 0; si < h->sc.size(); ++si)
+      if (h->scat_skip.empty() || !h->scat_skip[si])
+        h->prof_pairs += (double)h->sc[si].n * (double)(h->sc[si].n - 1) * nrhs;
     HIPCHK(h, hipEventCreate(&a0));
     HIPCHK(h, hipEventCreate(&a1));
     HIPCHK(h, hipEventRecord(a0, stream));
@@ -378,8 +381,9 @@ ls_status apply_op(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, 
     }
     HIPCHK(h, lsk::launch_apply_batch(h, x, y, nrhs, ld, mode, single, bmt, bsplit, h->ws_apply.ptr, stream, f0, f1));
   }
-  for (const Scat &sc : h->sc) {
-    if (batch) break;
+  for (size_t si = 0; si < h->sc.size() && !batch; ++si) {
+    if (!h->scat_skip.empty() && h->scat_skip[si]) continue;
+    const Scat &sc = h->sc[si];
     const int nsplit = splits(sc);
     hipEvent_t f0 = nullptr, f1 = nullptr;
     if (h->prof) {
@@ -468,6 +472,7 @@ ls_status ls_profile_query(ls_handle h, ls_profile *out, int32_t reset) {
   out->far_launches = (int64_t)h->ev_far.size() / 2;
   out->apply_calls = (int64_t)h->ev_apply.size() / 2;
   out->far_ms = out->apply_ms = 0.0;
+  out->pair_rhs = h->prof_pairs;
   for (size_t i = 0; i + 1 < h->ev_far.size(); i += 2) {
     float ms = 0.f;
     HIPCHK(h, hipEventSynchronize(h->ev_far[i + 1]));
@@ -485,6 +490,7 @@ ls_status ls_profile_query(ls_handle h, ls_profile *out, int32_t reset) {
     for (hipEvent_t e : h->ev_apply) (void)hipEventDestroy(e);
     h->ev_far.clear();
     h->ev_apply.clear();
+    h->prof_pairs = 0.0;
   }
   return LS_OK;
 }

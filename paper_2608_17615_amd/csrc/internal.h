@@ -61,6 +61,7 @@ struct ls_ctx {
   std::vector<lsk::Scat> sc;
   bool prof = false;
   std::vector<hipEvent_t> ev_far, ev_apply;   // start/stop pairs, in launch order
+  double prof_pairs = 0.0;                     // interactions evaluated while profiling
   int64_t n_total = 0;
   int device = 0;
   ls_options opt{};
@@ -70,6 +71,10 @@ struct ls_ctx {
   void *batch_tables = nullptr;          // device BatchDesc[] + WorkItem[] + counter
   size_t batch_bytes = 0;
   long long batch_key = -1;              // configuration the cached tables describe
+  // scatterers an operator application may leave out (empty: none).  Set only by the solver for
+  // the duration of its own applications: the output segments of skipped scatterers are left
+  // unwritten, and the solver never reads them (their systems have all finished).
+  std::vector<char> scat_skip;
   std::vector<void *> owned;  // device allocations freed by ls_destroy
 };
 

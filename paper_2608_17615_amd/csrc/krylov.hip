@@ -449,6 +449,17 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
     return e;
   };
   HIPTRY(grow(1));
+  // applications leave out scatterers none of whose systems is in play (cleared on every exit)
+  struct SkipReset {
+    ls_ctx *h;
+    ~SkipReset() { h->scat_skip.clear(); }
+  } skip_reset{h};
+  auto set_skip = [&](const std::vector<int> &flags) {
+    if (nseg == 1) return;
+    h->scat_skip.assign(nseg, 1);
+    for (int q = 0; q < nsys; ++q)
+      if (flags[q]) h->scat_skip[q % nseg] = 0;
+  };
   // systems in play: all, or those the caller names; the others count as done from the start
   std::vector<int> act(nsys, 1);
   if (only)
@@ -479,6 +490,8 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
       HIPTRY(hipMemcpyAsync(r, b, vb, hipMemcpyDeviceToDevice, st));
     } else {
       const ls_precision pr = (o.flexible || o.relax_eps > 0) ? LS_FP64 : o.matvec;
+      for (int q = 0; q < nsys; ++q) act[q] = res.done[q] ? 0 : 1;
+      set_skip(act);
       ls_status s2 = apply_op(h, (const double *)x, (double *)t, nrhs, n, o.mode, pr, st);
       if (s2 != LS_OK) return s2;
       if (pr == LS_FP64) ++res.n_fp64; else ++res.n_mixed;
@@ -526,6 +539,7 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
         if (s2 < 0) return s2;
         res.n_mixed += ir.n_mixed;
         res.n_fp64 += ir.n_fp64;
+        set_skip(act);
         s2 = apply_op(h, (const double *)zj, (double *)w, nrhs, n, o.mode, LS_FP64, st);
         if (s2 != LS_OK) return s2;
         ++res.n_fp64;
@@ -540,6 +554,7 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
             if (act[q]) worst = std::max(worst, est[q]);
           pj = worst * o.relax_eps <= o.tol ? LS_MIXED : LS_FP64;
         }
+        set_skip(act);
         ls_status s2 = apply_op(h, (const double *)vj, (double *)w, nrhs, n, o.mode, pj, st);
         if (s2 != LS_OK) return s2;
         if (pj == LS_FP64) ++res.n_fp64; else ++res.n_mixed;
@@ -681,7 +696,7 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
   // followed by FP64 refinement passes from the true residual if that missed tol
   const bool mixed = o.prec == LS_MIXED;
   const bool flexible = mixed && o.inner_maxit > 0;
-  const double relax = (mixed && !flexible) ? (o.inner_tol > 0 ? o.inner_tol : 1e-6) : 0.0;
+  const double relax = (mixed && !flexible) ? (o.inner_tol > 0 ? o.inner_tol : 1e-5) : 0.0;
   // the relaxed iteration aims its residual estimate below 0.3 tol so that its FP64 residual,
   // perturbed by the mixed applications, still meets tol without a (Krylov-space-losing) restart
   CoreOpts co{relax > 0 ? 0.3 * o.tol : o.tol, o.maxit, o.restart, mode, LS_FP64, flexible,

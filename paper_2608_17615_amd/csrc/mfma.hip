@@ -308,15 +308,21 @@ hipError_t launch_apply_batch(ls_ctx *h, const double *x, double *y, int nrhs, i
   std::vector<size_t> offs;
   batch_layout(h, nrhs, single, split_len, &offs);
   char *base = (char *)ws;
-  // descriptor and work-item tables, cached for this (layout, shape) combination
-  const long long key = ((((long long)nrhs * 2 + single) * 8 + mt) << 24) ^ (long long)split_len ^
-                        ((long long)(uintptr_t)ws << 1);
+  // descriptor and work-item tables, cached for this (layout, shape, skipped scatterers)
+  // combination; skipped scatterers get no work items, prologue or epilogue
+  const bool masked = !h->scat_skip.empty();
+  auto skip = [&](int i) { return masked && h->scat_skip[i]; };
+  long long mask_hash = 0;
+  for (int i = 0; i < ns && masked; ++i) mask_hash = mask_hash * 1000003LL + (h->scat_skip[i] ? 7 : 3);
+  const long long key = (((((long long)nrhs * 2 + single) * 8 + mt) << 24) ^ (long long)split_len ^
+                         ((long long)(uintptr_t)ws << 1)) ^ (mask_hash * 0x9E3779B97F4A7C15LL);
   std::vector<BatchDesc> desc(ns);
   std::vector<WorkItem> items;
   for (int i = 0; i < ns; ++i) {
     const Scat &sc = h->sc[i];
     const int nsplit = (int)((sc.n + split_len - 1) / split_len);
     desc[i] = BatchDesc{(int)sc.n, split_len, sc.k * sc.k, sc.pos, base + offs[3 * i], (double2 *)(base + offs[3 * i + 2])};
+    if (skip(i)) continue;
     const int tblocks = (int)((sc.n + 64 * mt - 1) / (64 * mt));
     for (int tb = 0; tb < tblocks; ++tb)
       for (int sp = 0; sp < nsplit; ++sp)
@@ -355,6 +361,7 @@ hipError_t launch_apply_batch(ls_ctx *h, const double *x, double *y, int nrhs, i
   const double2 *xc = (const double2 *)x;
   if (!far_only)
     for (int i = 0; i < ns; ++i) {
+      if (skip(i)) continue;
       const Scat &sc = h->sc[i];
       const unsigned gp = (unsigned)((sc.n * ldx + kBlock - 1) / kBlock);
       double2 *f = (double2 *)(base + offs[3 * i + 1]);
@@ -391,6 +398,7 @@ hipError_t launch_apply_batch(ls_ctx *h, const double *x, double *y, int nrhs, i
   e = hipGetLastError();
   if (e != hipSuccess || far_only) return e;
   for (int i = 0; i < ns; ++i) {
+    if (skip(i)) continue;
     const Scat &sc = h->sc[i];
     const int nsplit = (int)((sc.n + split_len - 1) / split_len);
     e = launch_epilogue(sc, desc[i].part, nsplit, (const double2 *)(base + offs[3 * i + 1]), x, y, nrhs, ld, mode, st);
