@@ -76,3 +76,15 @@ def farfield_from_coefficients(k, nus, bcoef, thetas, theta_d=0.0):
     th = np.atleast_1d(thetas)
     ph = np.exp(1j * np.outer(th - theta_d, nus)) * ((-1j) ** nus)[None, :]
     return np.sqrt(2 / (np.pi * k)) * np.exp(-0.25j * np.pi) * (ph @ bcoef)
+
+
+def scattered_from_coefficients(k, nus, bcoef, x, y, theta_d=0.0):
+    """Exterior scattered field sum_nu b_nu H_nu(k r) e^{i nu (theta - theta_d)} at (x, y)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    r = np.hypot(x, y)
+    th = np.arctan2(y, x)
+    u = np.zeros(np.shape(x), dtype=np.complex128)
+    for nu, b in zip(nus, bcoef):
+        u = u + b * special.hankel1(nu, k * r) * np.exp(1j * nu * (th - theta_d))
+    return u
