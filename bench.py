@@ -12,7 +12,9 @@ Other workloads (--workload, one JSON line each):
   c3  unit disk, n^2 = 2, k = 40, N = 122 500, 64 directions, forms p64 / b64 / bm;
   c4  16 seeded scatterers of uneven size in one handle, 8 directions each, forms p64 / bm;
   c5  two-material disk at k = 40, N = 114 660, 16 directions: far-field misfit and its contrast
-      gradient through the forward and adjoint solves, forms p64 / b64 / bm.
+      gradient through the forward and adjoint solves, forms p64 / b64 / bm;
+  field  the scattered field (eq. field_recovery) of 16 plane waves on the c3 mesh at the exterior
+      points of a Cartesian grid over the enclosing square.
 Forms: p64 = FP64 VALU kernel, one right-hand side at a time (columns beyond --cols are
 extrapolated from the timed ones, and the line says so); b64 = all right-hand sides together on
 FP64 matrix-core tiles; bm = all together, FP32 matrix-core tiles inside FP64 GMRES (relaxed).
@@ -357,10 +359,49 @@ def run_gradient(args, prob, label, B):
     return line(value, total_s * 1e3, 1, 0, dtype, cfg, roof, None), g
 
 
+def run_field(args, prob, label, B):
+    """Field recovery: the scattered field of B plane waves at the exterior points of a Cartesian
+    grid over the enclosing square (the paper's exterior measurement set)."""
+    import numpy as np
+    import torch
+
+    import paper_2608_17615_amd as lsg
+    log(f"setup: {label}, N = {prob.n_nodes}")
+    op = lsg.Operator(lsg.Scatterer.from_mesh(prob.mesh, prob.m, prob.k))
+    n = op.n
+    g = np.linspace(-1.5, 1.5, args.grid)
+    X, Y = np.meshgrid(g, g)
+    keep = np.hypot(X, Y) > 1.0 + 1.0 / args.grid
+    tx, ty = X[keep], Y[keep]
+    nt = tx.size
+    u = torch.tensor(prob.incident()[:B], device="cuda")
+    op.field(u, tx[:64], ty[:64])   # warm-up
+    with Timer(op) as t:
+        out = op.field(u, tx, ty)
+    pairs = n * nt
+    # per-pair flops weighted by the distribution of k |x_t - y_n|
+    rng = np.random.default_rng(0)
+    sel = rng.choice(nt, min(256, nt), replace=False)
+    cnt = np.zeros(4)
+    for r in sel:
+        z = np.hypot(prob.mesh.x - tx[r], prob.mesh.y - ty[r]) * prob.k
+        cnt += np.histogram(z, bins=[0.0, *Z_BOUNDS, np.inf])[0]
+    frac = dict(zip(("small", "mid1", "mid2", "far"), (float(v) for v in cnt / cnt.sum())))
+    fpp = flops_per_pair(frac, B)
+    cfg = {"workload": f"{label}: scattered field of {B} plane waves at {nt} exterior points of a "
+                       f"{args.grid} x {args.grid} grid on [-1.5, 1.5]^2", "form": "field", "n_nodes": n,
+           "targets": nt, "nrhs": B, "time_s": t.seconds, "far_kernel_ms": t.far_avg_s * 1e3,
+           "assembly_and_other_s": t.seconds - t.far_avg_s, "flops_per_pair": fpp, "z_range_fractions": frac,
+           "finite": bool(torch.isfinite(out).all().item())}
+    return line(pairs * B / t.seconds / 1e9, t.seconds * 1e3, 1, 0, "f64", cfg,
+                roofline_valu(fpp, pairs, t.far_avg_s), None)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "field"])
+    ap.add_argument("--grid", type=int, default=256, help="field: points per side of the Cartesian grid")
     ap.add_argument("--form", default=None, choices=["p64", "b64", "bm"])
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
@@ -391,9 +432,11 @@ def main():
         probs, label = [P.config3()], "unit disk, n^2 = 2, k = 40, 64 plane waves"
     elif wl == "c4":
         probs, label = P.config4(), "16 seeded disks and ellipses, k in [5, 40], 8 plane waves each"
-    else:
+    elif wl == "c5":
         probs, label = [P.config5()], "two-material disk, k = 40, 16 plane waves, 128 receivers"
-    form = args.form or ("p64" if wl in ("c1", "c2") else "bm")
+    else:
+        probs, label = [P.config3(B=16)], "unit disk, n^2 = 2, k = 40, N = 122500"
+    form = args.form or ("p64" if wl in ("c1", "c2", "field") else "bm")
     args.form = form
     if wl in ("c1", "c2") and form != "p64":
         ap.error("c1 and c2 are plain FP64 single-wave solves (form p64)")
@@ -415,7 +458,9 @@ def main():
         log(f"copy probe: read and wrote {src.numel() * 8} bytes")
         del src, dst
 
-    if wl in ("c1", "c2"):
+    if wl == "field":
+        out = run_field(args, probs[0], label, 16)
+    elif wl in ("c1", "c2"):
         out = run_plain(args, probs[0], label)
     elif wl in ("c3", "c4"):
         out, _ = run_batched(args, probs, label, probs[0].directions.size)

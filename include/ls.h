@@ -169,6 +169,21 @@ ls_status ls_farfield(ls_handle h, int32_t s, const double *u, int32_t nrhs, int
                       int32_t R, const double *data, double *uinf, double *res, double *misfit,
                       hipStream_t stream);
 
+/* Field recovery (Section 3, eq. field_recovery, the discrete representation formula of
+ * Section 2): the scattered field u_s(x) = u(x) - u_inc(x) = -k^2 V~_Omega[m u](x) of scatterer s
+ * at nt points x_t = (tx[t], ty[t]) outside it, for the nodal solution u:
+ *   u_s(x_t) = -k^2 ( sum_n G(x_t, y_n) w_n m_n u_n + sum_c C_tc m_c u_c ),
+ * with a correction row C_t per point built like the operator's (the VDIM map at a target that
+ * is not a node: in every subdomain the element with the nearest centroid, and the exact
+ * polynomial potential with the point outside).  tx, ty: host [nt] (any order).  u: device,
+ * nrhs columns with leading dimension ld (all scatterers' layout; scatterer s's segment is
+ * read).  out: device, nrhs x nt complex (row-major, leading dimension nt).  Points on or
+ * inside a curve that encloses a subdomain of s are rejected with LS_ERR_ARG; non-finite
+ * points with LS_ERR_NONFINITE.  Synchronous: the correction rows are assembled per call (host
+ * threads and the GPU) in a workspace allocated and freed by the call. */
+ls_status ls_field(ls_handle h, int32_t s, const double *tx, const double *ty, int64_t nt, const double *u,
+                   int32_t nrhs, int64_t ld, double *out, hipStream_t stream);
+
 /* Adjoint of the far-field map of scatterer s: a = A^H res and rhs = conj(m) a (the right-hand
  * side of the adjoint solve L^H lam = conj(m) a), each written for scatterer s's nodes of nrhs
  * columns with leading dimension ld (device; either may be NULL). */

@@ -97,6 +97,7 @@ def lib():
         L.ls_eval_green_host.argtypes = [vp, vp, i64]
         L.ls_farfield.argtypes = [vp, i32, vp, i32, i64, vp, i32, vp, vp, vp, vp, vp]
         L.ls_farfield_adjoint.argtypes = [vp, i32, vp, i32, i64, vp, i32, vp, vp, vp]
+        L.ls_field.argtypes = [vp, i32, vp, vp, i64, vp, i32, i64, vp, vp]
         L.ls_set_contrast.argtypes = [vp, vp, vp]
         L.ls_autotune.argtypes = [vp, i32, i32, vp, vp]
         L.ls_set_tile_shape.argtypes = [vp, i32, i32, i32]
@@ -284,6 +285,20 @@ class Operator:
         if data is not None:
             J = Jh.value
         return uinf, res, J
+
+    def field(self, u, tx, ty, s=0):
+        """Scattered field -k^2 V~[m u] of scatterer s at points (tx, ty) outside it (host
+        arrays); u: (B, N) nodal solution.  Returns a (B, T) complex128 CUDA tensor."""
+        import torch
+        u2 = self._cols(u)
+        tx = np.ascontiguousarray(tx, dtype=np.float64).ravel()
+        ty = np.ascontiguousarray(ty, dtype=np.float64).ravel()
+        if tx.size != ty.size:
+            raise ValueError("tx and ty differ in length")
+        out = torch.empty((u2.shape[0], tx.size), dtype=torch.complex128, device=u2.device)
+        _check(lib().ls_field(self._h, s, tx.ctypes.data, ty.ctypes.data, tx.size, u2.data_ptr(), u2.shape[0],
+                              self.n, out.data_ptr(), _stream()), self._h)
+        return out
 
     def farfield_adjoint(self, res, thetas, s=0):
         """(a, rhs) with a = A^H res and rhs = conj(m) a on scatterer s (zero elsewhere)."""

@@ -295,7 +295,7 @@ ls_status ls_setup_from_csr(const ls_scatterer *s, const int64_t *rowptr, const 
   sc.off = 0;
   h->n_total = n;
   const std::vector<int32_t> eord = lsk::element_order(*s);
-  if ((st = lsk::upload_nodes(h, sc, *s, eord)) != LS_OK) {
+  if ((st = lsk::upload_nodes(h, sc, *s, eord)) != LS_OK || (st = lsk::build_geometry(h, sc, *s, eord)) != LS_OK) {
     ls_destroy(h);
     return st;
   }
@@ -342,7 +342,7 @@ ls_status apply_op(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, 
   // several scatterers on the matrix cores: one persistent launch over all of them
   const bool batch = tiles && h->sc.size() > 1;
   const lsk::TileTune &tt = h->tune[single ? 1 : 0];
-  const int bmt = h->opt.mixed_tile > 0 ? h->opt.mixed_tile : (tt.mt > 0 ? tt.mt : (single ? 4 : 2));
+  const int bmt = h->opt.mixed_tile > 0 ? h->opt.mixed_tile : (tt.mt > 0 ? tt.mt : (single ? 2 : 1));
   const int bsplit = tt.split_len > 0 ? tt.split_len : lsk::batch_default_split_len(h, single);
   size_t need = 0;
   if (batch) need = lsk::batch_workspace_bytes(h, nrhs, single, bsplit);
@@ -537,6 +537,60 @@ ls_status ls_farfield(ls_handle h, int32_t s, const double *u, int32_t nrhs, int
     for (double v : hr) J += v * v;
     *misfit = 0.5 * J;
   }
+  return LS_OK;
+}
+
+ls_status ls_field(ls_handle h, int32_t s, const double *tx, const double *ty, int64_t nt, const double *u,
+                   int32_t nrhs, int64_t ld, double *out, hipStream_t stream) {
+  if (!h) return fail(nullptr, LS_ERR_ARG, "null handle");
+  if (s < 0 || s >= (int32_t)h->sc.size()) return fail(h, LS_ERR_ARG, "bad scatterer index");
+  if (nrhs < 1 || nt < 1 || nt > (int64_t)INT32_MAX / 2 || !tx || !ty || !u || !out)
+    return fail(h, LS_ERR_ARG, "bad argument");
+  if (ld < h->n_total) return fail(h, LS_ERR_ARG, "ld < number of nodes");
+  const Scat &sc = h->sc[s];
+  if (!sc.geom) return fail(h, LS_ERR_UNSUPPORTED, "no geometry for this scatterer");
+  for (int64_t t = 0; t < nt; ++t) {
+    if (!std::isfinite(tx[t]) || !std::isfinite(ty[t])) return fail(h, LS_ERR_NONFINITE, "non-finite point");
+    if (!lsk::outside_scatterer(sc, tx[t], ty[t])) return fail(h, LS_ERR_ARG, "a point lies inside the scatterer");
+  }
+  // correction rows of the targets (host threads and the GPU), then the sums
+  std::vector<int64_t> rp;
+  std::vector<int32_t> ci;
+  std::vector<double> cv;
+  ls_status st = lsk::field_correction(h, sc, nt, tx, ty, stream, rp, ci, cv);
+  if (st != LS_OK) return st;
+  const int nsplit = lsk::field_source_split(sc.n, nt, nrhs);
+  auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const size_t b_rp = al(sizeof(int64_t) * rp.size()), b_ci = al(sizeof(int32_t) * ci.size()),
+               b_cv = al(sizeof(double) * cv.size()), b_t = al(sizeof(double) * 2 * nt);
+  const size_t need = b_rp + b_ci + b_cv + b_t + lsk::field_workspace_bytes(sc.n, nrhs, nt, nsplit);
+  void *ws = nullptr;
+  if (hipMalloc(&ws, need) != hipSuccess) return fail(h, LS_ERR_ALLOC, "field workspace");
+  char *p = (char *)ws;
+  int64_t *drp = (int64_t *)p;
+  int32_t *dci = (int32_t *)(p + b_rp);
+  double *dcv = (double *)(p + b_rp + b_ci);
+  double *dt = (double *)(p + b_rp + b_ci + b_cv);
+  void *rest = p + b_rp + b_ci + b_cv + b_t;
+  hipError_t e = hipMemcpyAsync(drp, rp.data(), sizeof(int64_t) * rp.size(), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(dci, ci.data(), sizeof(int32_t) * ci.size(), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(dcv, cv.data(), sizeof(double) * cv.size(), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(dt, tx, sizeof(double) * nt, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(dt + nt, ty, sizeof(double) * nt, hipMemcpyHostToDevice, stream);
+  hipEvent_t f0 = nullptr, f1 = nullptr;
+  if (e == hipSuccess && h->prof) {
+    (void)hipEventCreate(&f0);
+    (void)hipEventCreate(&f1);
+    h->ev_far.push_back(f0);
+    h->ev_far.push_back(f1);
+    h->prof_pairs += (double)sc.n * (double)nt * nrhs;
+  }
+  if (e == hipSuccess)
+    e = lsk::launch_field(sc, u, nrhs, ld, nt, dt, dt + nt, drp, dci, (const double2 *)dcv, nsplit, out, rest, stream,
+                          f0, f1);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);   // host vectors and the workspace go away
+  (void)hipFree(ws);
+  if (e != hipSuccess) return fail(h, LS_ERR_HIP, hipGetErrorString(e));
   return LS_OK;
 }
 

@@ -210,6 +210,63 @@ void launch_far(const Scat &s, const double2 *pos, const double2 *sd, int nrhs, 
                                                           split_len, part);
 }
 
+// Field recovery (paper, Section 3, eq. field_recovery): the far sum at nt targets that are
+// not nodes, part[(split * nrhs + c0 + b) * nt + t] = sum over the split's sources of
+// G/K(x_t, y_n) sd[n][c0 + b].  One target per lane; no pair is left out.
+template <int BC>
+__global__ __launch_bounds__(kBlock) void field_far_kernel(int nt, const double *__restrict__ tx,
+                                                          const double *__restrict__ ty, int n,
+                                                          const double2 *__restrict__ pos,
+                                                          const double2 *__restrict__ sd, int nrhs, double k2,
+                                                          int split_len, double2 *__restrict__ part) {
+  const int c0 = blockIdx.z * BC;
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const int ti = t < nt ? t : nt - 1;
+  const int it[1] = {-1};   // no source index matches
+  const double xt[1] = {tx[ti]}, yt[1] = {ty[ti]};
+  const int s0 = blockIdx.y * split_len;
+  const int s1 = min(n, s0 + split_len);
+  double ar[1][BC], ai[1][BC];
+#pragma unroll
+  for (int b = 0; b < BC; ++b) ar[0][b] = ai[0][b] = 0.0;
+  for (int j = s0; j < s1; ++j)
+    far_source<1, BC, false, false>(j, it, xt, yt, k2, pos, sd + (int64_t)j * nrhs + c0, ar, ai);
+  if (t < nt) {
+#pragma unroll
+    for (int b = 0; b < BC; ++b)
+      part[((int64_t)blockIdx.y * nrhs + c0 + b) * nt + t] = make_double2(ar[0][b], ai[0][b]);
+  }
+}
+
+// out[b * nt + t] = -k^2 (K sum_split part + sum_c C_tc f_b[c]): the scattered field
+__global__ __launch_bounds__(kBlock) void field_epilogue_kernel(int64_t nt, int nrhs, int nsplit,
+                                                               const double2 *__restrict__ part,
+                                                               const int64_t *__restrict__ rp,
+                                                               const int32_t *__restrict__ ci,
+                                                               const double2 *__restrict__ cv,
+                                                               const double2 *__restrict__ f, int64_t n, double k2,
+                                                               double2 *__restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int b = blockIdx.y;
+  if (t >= nt) return;
+  double ar = 0.0, ai = 0.0;
+  for (int sp = 0; sp < nsplit; ++sp) {
+    const double2 p = part[((int64_t)sp * nrhs + b) * nt + t];
+    ar += p.x;
+    ai += p.y;
+  }
+  ar *= G_SCALE;
+  ai *= G_SCALE;
+  const double2 *fb = f + (int64_t)b * n;
+  for (int64_t q = rp[t]; q < rp[t + 1]; ++q) {
+    const double2 c = cv[q];
+    const double2 v = fb[ci[q]];
+    ar = std::fma(c.x, v.x, std::fma(-c.y, v.y, ar));
+    ai = std::fma(c.x, v.y, std::fma(c.y, v.x, ai));
+  }
+  out[(int64_t)b * nt + t] = make_double2(-k2 * ar, -k2 * ai);
+}
+
 }  // namespace
 
 int auto_source_split(int64_t n, int nrhs, int launches_per_split, int tpl) {
@@ -240,7 +297,6 @@ hipError_t launch_apply_fp64(const Scat &s, const double *x, double *y, int nrhs
   double2 *part = f + n * nrhs;
   const double2 *pos = s.pos;
   const double2 *xc = (const double2 *)x;
-  double2 *yc = (double2 *)y;
   const unsigned gp = (unsigned)((n * nrhs + kBlock - 1) / kBlock);
   if (mode == Mode::Forward)
     prologue_kernel<Mode::Forward><<<gp, kBlock, 0, st>>>(n, nrhs, s.perm, s.w, s.m, xc, ld, s.off, sd, f);
@@ -300,6 +356,57 @@ void eval_green_host(const double *z2, double *g, int64_t n) {
 hipError_t launch_eval_green(const double *z2, double *g, int64_t n, int single, hipStream_t st) {
   if (n == 0) return hipSuccess;
   eval_green_kernel<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(z2, (double2 *)g, n, single);
+  return hipGetLastError();
+}
+
+}  // namespace lsk
+
+namespace lsk {
+
+int field_source_split(int64_t n, int64_t nt, int nrhs) {
+  // about 128 waves per SIMD over the launch, partials capped at 512 MiB
+  const int64_t waves = (nt + 63) / 64;
+  int64_t s = (131072 + waves - 1) / waves;
+  const int64_t cap = ((int64_t)512 << 20) / ((int64_t)16 * nt * nrhs);
+  if (s > cap) s = cap;
+  if (s < 1) s = 1;
+  if (s > 256) s = 256;
+  if (s > n) s = n;
+  return (int)s;
+}
+
+size_t field_workspace_bytes(int64_t n, int nrhs, int64_t nt, int nsplit) {
+  // sd [n][nrhs], f [nrhs][n], part [nsplit][nrhs][nt]  (double2 each), 256-byte aligned
+  return sizeof(double2) * ((size_t)2 * n * nrhs + (size_t)nsplit * nrhs * nt) + 1024;
+}
+
+hipError_t launch_field(const Scat &s, const double *u, int nrhs, int64_t ld, int64_t nt, const double *tx,
+                        const double *ty, const int64_t *rp, const int32_t *ci, const double2 *cv, int nsplit,
+                        double *out, void *ws, hipStream_t st, hipEvent_t far_start, hipEvent_t far_stop) {
+  const int64_t n = s.n;
+  auto al = [](char *p) { return (char *)(((uintptr_t)p + 255) & ~(uintptr_t)255); };
+  char *p = al((char *)ws);
+  double2 *sd = (double2 *)p;
+  p = al(p + sizeof(double2) * n * nrhs);
+  double2 *f = (double2 *)p;
+  p = al(p + sizeof(double2) * n * nrhs);
+  double2 *part = (double2 *)p;
+  prologue_kernel<Mode::Forward><<<(unsigned)((n * nrhs + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+      n, nrhs, s.perm, s.w, s.m, (const double2 *)u, ld, s.off, sd, f);
+  const int split_len = (int)((n + nsplit - 1) / nsplit);
+  const int bc = nrhs % 16 == 0 ? 16 : (nrhs % 8 == 0 ? 8 : (nrhs % 4 == 0 ? 4 : 1));
+  dim3 grid((unsigned)((nt + kBlock - 1) / kBlock), (unsigned)nsplit, (unsigned)(nrhs / bc));
+  if (far_start) (void)hipEventRecord(far_start, st);
+  const double k2 = s.k * s.k;
+  switch (bc) {
+    case 16: field_far_kernel<16><<<grid, kBlock, 0, st>>>((int)nt, tx, ty, (int)n, s.pos, sd, nrhs, k2, split_len, part); break;
+    case 8: field_far_kernel<8><<<grid, kBlock, 0, st>>>((int)nt, tx, ty, (int)n, s.pos, sd, nrhs, k2, split_len, part); break;
+    case 4: field_far_kernel<4><<<grid, kBlock, 0, st>>>((int)nt, tx, ty, (int)n, s.pos, sd, nrhs, k2, split_len, part); break;
+    default: field_far_kernel<1><<<grid, kBlock, 0, st>>>((int)nt, tx, ty, (int)n, s.pos, sd, nrhs, k2, split_len, part);
+  }
+  if (far_stop) (void)hipEventRecord(far_stop, st);
+  dim3 ge((unsigned)((nt + kBlock - 1) / kBlock), (unsigned)nrhs);
+  field_epilogue_kernel<<<ge, kBlock, 0, st>>>(nt, nrhs, nsplit, part, rp, ci, cv, f, n, k2, (double2 *)out);
   return hipGetLastError();
 }
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -14,6 +15,11 @@ namespace lsk {
 struct alignas(32) Src4 {
   double x, y, sr, si;
 };
+
+// Host geometry of one scatterer kept after setup (element frames, interpolation matrices,
+// boundary curves); defined and used by setup.hip, for the correction rows of the operator and
+// of field-recovery targets.
+struct GeomData;
 
 // One scatterer, all device arrays in the internal (sorted) node order.
 struct Scat {
@@ -29,6 +35,7 @@ struct Scat {
   int32_t *ci = nullptr, *ciH = nullptr;
   double2 *cv = nullptr, *cvH = nullptr;
   std::vector<int32_t> perm_host;   // same as perm, on the host
+  std::shared_ptr<GeomData> geom;
 };
 
 // One scatterer of a batched launch and one unit of its far-sum work.
@@ -122,5 +129,17 @@ hipError_t launch_farfield_adjoint(const Scat &s, const double *res, int nrhs, i
                                    int R, double *a, double *rhs, hipStream_t st);
 hipError_t launch_set_contrast(const Scat &s, const double *m_caller, hipStream_t st);
 int auto_source_split(int64_t n, int nrhs, int launches_per_split, int tpl);
+// field recovery (setup.hip: geometry and target correction rows; apply.hip: the sums)
+ls_status build_geometry(ls_ctx *h, Scat &sc, const ls_scatterer &s, const std::vector<int32_t> &eord);
+ls_status field_correction(ls_ctx *h, const Scat &sc, int64_t nt, const double *tx, const double *ty,
+                           hipStream_t st, std::vector<int64_t> &rp, std::vector<int32_t> &ci,
+                           std::vector<double> &cv);
+bool outside_scatterer(const Scat &sc, double x, double y);
+int field_source_split(int64_t n, int64_t nt, int nrhs);
+size_t field_workspace_bytes(int64_t n, int nrhs, int64_t nt, int nsplit);
+hipError_t launch_field(const Scat &s, const double *u, int nrhs, int64_t ld, int64_t nt, const double *tx,
+                        const double *ty, const int64_t *rp, const int32_t *ci, const double2 *cv, int nsplit,
+                        double *out, void *ws, hipStream_t st, hipEvent_t far_start = nullptr,
+                        hipEvent_t far_stop = nullptr);
 
 }  // namespace lsk

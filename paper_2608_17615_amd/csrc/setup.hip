@@ -32,6 +32,20 @@ ls_status upload_nodes(ls_ctx *h, Scat &sc, const ls_scatterer &s, const std::ve
 ls_status upload_correction(ls_ctx *h, Scat &sc, const std::vector<int64_t> &rp, const std::vector<int32_t> &ci,
                             const std::vector<double> &cv);
 
+struct CurveH {
+  int kind, orient, sub;
+  double cx, cy, a, b;
+  void eval(double t, double &px, double &py, double &sp, double &nx, double &ny) const {
+    const double ct = std::cos(t), st = std::sin(t);
+    px = cx + a * ct;
+    py = cy + b * st;
+    const double tx = -a * st, ty = b * ct;
+    sp = std::hypot(tx, ty);
+    nx = orient * ty / sp;
+    ny = -orient * tx / sp;
+  }
+};
+
 namespace {
 
 constexpr int kBlock = 256;
@@ -48,16 +62,18 @@ __device__ __forceinline__ ConstTab &table() {
   return *t;
 }
 
-// out[split][j][a] = sum_{q in [q0, q1) of this split, q != j} G(y_j, y_q) w_q P_a((y_q - c_j)/s_j)
-__global__ __launch_bounds__(kBlock) void poly_sums_kernel(int n, const double *__restrict__ px,
-                                                           const double *__restrict__ py,
+// out[split][j][a] = sum_{q in [q0, q1) of this split} G(x_j, y_q) w_q P_a((y_q - c_j)/s_j) for the
+// targets x_j = (tx[j], ty[j]); PUNCT: the targets are the nodes themselves and q = j is left out
+template <bool PUNCT>
+__global__ __launch_bounds__(kBlock) void poly_sums_kernel(int n, const double *__restrict__ tx,
+                                                           const double *__restrict__ ty,
                                                            const double2 *__restrict__ pos,
                                                            const double *__restrict__ w, int q0, int q1,
                                                            const double4 *__restrict__ frame, double k2,
                                                            int split_len, double2 *__restrict__ out) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   const int ii = i < n ? i : n - 1;
-  const double xt = px[ii], yt = py[ii];
+  const double xt = tx[ii], yt = ty[ii];
   const double4 fr = frame[ii];   // (cx, cy, 1/s, unused)
   const int s0 = q0 + blockIdx.y * split_len;
   const int s1 = min(q1, s0 + split_len);
@@ -71,7 +87,7 @@ __global__ __launch_bounds__(kBlock) void poly_sums_kernel(int n, const double *
     const double A = k2 * std::fma(dx, dx, dy * dy);
     double gr, gi;
     green(A, gr, gi, table());
-    const bool self = (q == i);
+    const bool self = PUNCT && (q == i);
     gr = self ? 0.0 : gr * wq;
     gi = self ? 0.0 : gi * wq;
     const double u = (p.x - fr.x) * fr.z, v = (p.y - fr.y) * fr.z;
@@ -116,20 +132,6 @@ struct GaussLegendre {
         w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
       }
     }
-  }
-};
-
-struct CurveH {
-  int kind, orient, sub;
-  double cx, cy, a, b;
-  void eval(double t, double &px, double &py, double &sp, double &nx, double &ny) const {
-    const double ct = std::cos(t), st = std::sin(t);
-    px = cx + a * ct;
-    py = cy + b * st;
-    const double tx = -a * st, ty = b * ct;
-    sp = std::hypot(tx, ty);
-    nx = orient * ty / sp;
-    ny = -orient * tx / sp;
   }
 };
 
@@ -273,76 +275,118 @@ void parallel_for(int64_t n, int threads, F f) {
 
 }  // namespace
 
-// Build C for scatterer sc (nodes already uploaded in internal order) and upload it.
-ls_status build_correction(ls_ctx *h, Scat &sc, const ls_scatterer &s, const std::vector<int32_t> &eord,
-                           hipStream_t st) {
+// Host geometry of a scatterer in the internal node order: element frames (node-mean centroid,
+// largest node distance), LU factors of the transposed cubic Vandermonde matrices, subdomain
+// node ranges and element lists, and the boundary curves of every subdomain.
+struct GeomData {
+  int64_t n = 0;
+  int32_t ne = 0;
+  int nsub = 1;
+  double k = 0;
+  std::vector<double> px, py;
+  std::vector<int32_t> esub, ecaller;
+  std::vector<double> ecx, ecy, esc, LU;
+  std::vector<int> piv;
+  std::vector<int64_t> sub_lo, sub_hi;
+  std::vector<std::vector<int32_t>> sub_elems;
+  std::vector<std::vector<CurveH>> curves;
+};
+
+ls_status build_geometry(ls_ctx *h, Scat &sc, const ls_scatterer &s, const std::vector<int32_t> &eord) {
+  auto g = std::make_shared<GeomData>();
   const int64_t n = sc.n;
   const int32_t ne = (int32_t)(n / 10);
-  const int nsub = sc.n_sub;
-  int threads = h->opt.n_threads_host > 0 ? h->opt.n_threads_host : (int)std::thread::hardware_concurrency();
-  threads = std::max(1, std::min(threads, 64));
-  // internal-order host copies
-  std::vector<double> px(n), py(n);
-  std::vector<int32_t> esub(ne), ecaller(ne);
+  g->n = n;
+  g->ne = ne;
+  g->nsub = sc.n_sub;
+  g->k = sc.k;
+  g->px.resize(n);
+  g->py.resize(n);
+  g->esub.resize(ne);
+  g->ecaller.resize(ne);
   for (int32_t e = 0; e < ne; ++e) {
-    esub[e] = s.elem_subdomain[eord[e]];
-    ecaller[e] = eord[e];
+    g->esub[e] = s.elem_subdomain[eord[e]];
+    g->ecaller[e] = eord[e];
   }
   for (int64_t i = 0; i < n; ++i) {
-    px[i] = s.x[sc.perm_host[i]];
-    py[i] = s.y[sc.perm_host[i]];
+    g->px[i] = s.x[sc.perm_host[i]];
+    g->py[i] = s.y[sc.perm_host[i]];
   }
-  // element frames and Vandermonde LU
-  std::vector<double> ecx(ne), ecy(ne), esc(ne), LU((size_t)ne * NA * NA);
-  std::vector<int> piv((size_t)ne * NA);
+  g->ecx.resize(ne);
+  g->ecy.resize(ne);
+  g->esc.resize(ne);
+  g->LU.resize((size_t)ne * NA * NA);
+  g->piv.resize((size_t)ne * NA);
   bool ok = true;
   for (int32_t e = 0; e < ne; ++e) {
+    const double *X = &g->px[10 * (int64_t)e], *Y = &g->py[10 * (int64_t)e];
     double ax = 0, ay = 0, d = 0;
     for (int q = 0; q < 10; ++q) {
-      ax += px[10 * (int64_t)e + q];
-      ay += py[10 * (int64_t)e + q];
+      ax += X[q];
+      ay += Y[q];
     }
-    ecx[e] = ax / 10;
-    ecy[e] = ay / 10;
+    g->ecx[e] = ax / 10;
+    g->ecy[e] = ay / 10;
     for (int p = 0; p < 10; ++p)
-      for (int q = 0; q < 10; ++q)
-        d = std::max(d, std::hypot(px[10 * (int64_t)e + p] - px[10 * (int64_t)e + q],
-                                   py[10 * (int64_t)e + p] - py[10 * (int64_t)e + q]));
-    esc[e] = d;
+      for (int q = 0; q < 10; ++q) d = std::max(d, std::hypot(X[p] - X[q], Y[p] - Y[q]));
+    g->esc[e] = d;
     // V^T[a][i] = P_a(node i): factor V^T so that V^T r = D is one solve
-    double *A = &LU[(size_t)e * NA * NA];
+    double *A = &g->LU[(size_t)e * NA * NA];
     for (int i = 0; i < 10; ++i) {
-      const double u = (px[10 * (int64_t)e + i] - ecx[e]) / d, v = (py[10 * (int64_t)e + i] - ecy[e]) / d;
+      const double u = (X[i] - g->ecx[e]) / d, v = (Y[i] - g->ecy[e]) / d;
       for (int a = 0; a < NA; ++a) A[a * NA + i] = mono(u, v, AX[a], AY[a]);
     }
-    ok = ok && lu10(A, &piv[(size_t)e * NA]);
+    ok = ok && lu10(A, &g->piv[(size_t)e * NA]);
   }
   if (!ok) return setup_fail(h, LS_ERR_ARG, "an element's 10 nodes are not unisolvent for cubics");
   // subdomain ranges (internal order groups subdomains contiguously)
-  std::vector<int64_t> sub_lo(nsub, n), sub_hi(nsub, 0);
-  std::vector<std::vector<int32_t>> sub_elems(nsub);
+  const int nsub = g->nsub;
+  g->sub_lo.assign(nsub, n);
+  g->sub_hi.assign(nsub, 0);
+  g->sub_elems.assign(nsub, {});
   for (int32_t e = 0; e < ne; ++e) {
-    sub_lo[esub[e]] = std::min<int64_t>(sub_lo[esub[e]], 10 * (int64_t)e);
-    sub_hi[esub[e]] = std::max<int64_t>(sub_hi[esub[e]], 10 * (int64_t)e + 10);
-    sub_elems[esub[e]].push_back(e);
+    const int l = g->esub[e];
+    g->sub_lo[l] = std::min<int64_t>(g->sub_lo[l], 10 * (int64_t)e);
+    g->sub_hi[l] = std::max<int64_t>(g->sub_hi[l], 10 * (int64_t)e + 10);
+    g->sub_elems[l].push_back(e);
   }
-  std::vector<std::vector<CurveH>> curves(nsub);
+  for (int l = 0; l < nsub; ++l)
+    if (g->sub_elems[l].empty()) return setup_fail(h, LS_ERR_ARG, "a subdomain has no elements");
+  g->curves.assign(nsub, {});
   for (int c = 0; c < s.n_curves; ++c) {
     const ls_curve &cv = s.curves[c];
-    curves[cv.subdomain].push_back({cv.kind, cv.orientation, cv.subdomain, cv.cx, cv.cy, cv.a, cv.b});
+    g->curves[cv.subdomain].push_back({cv.kind, cv.orientation, cv.subdomain, cv.cx, cv.cy, cv.a, cv.b});
   }
-  // interpolation element for each (row, subdomain): own element, else nearest centroid
-  // (uniform bucket grid per subdomain; ties to the smaller caller element index)
-  std::vector<int32_t> tau((size_t)n * nsub);
+  sc.geom = g;
+  return LS_OK;
+}
+
+namespace {
+
+// Correction rows (10 entries per subdomain) for nt targets, in CSR form on the host.
+//   nodes = true : the targets are the scatterer's own nodes (internal order); a node's own
+//                  element serves its own subdomain, it lies inside that subdomain, and the
+//                  monomial sums leave out the node itself;
+//   nodes = false: external targets (tx, ty), all outside the scatterer: the nearest element
+//                  serves every subdomain and nothing is left out.
+ls_status correction_rows(ls_ctx *h, const Scat &sc, int64_t nt, const double *tx, const double *ty, bool nodes,
+                          hipStream_t st, std::vector<int64_t> &rp, std::vector<int32_t> &ci,
+                          std::vector<double> &cv) {
+  const GeomData &g = *sc.geom;
+  const int nsub = g.nsub;
+  int threads = h->opt.n_threads_host > 0 ? h->opt.n_threads_host : (int)std::thread::hardware_concurrency();
+  threads = std::max(1, std::min(threads, 64));
+  // interpolation element for each (target, subdomain): the node's own element, else the
+  // nearest centroid (uniform bucket grid per subdomain; ties to the smaller caller index)
+  std::vector<int32_t> tau((size_t)nt * nsub);
   for (int l = 0; l < nsub; ++l) {
-    const auto &E = sub_elems[l];
-    if (E.empty()) return setup_fail(h, LS_ERR_ARG, "a subdomain has no elements");
+    const auto &E = g.sub_elems[l];
     double bx0 = 1e300, bx1 = -1e300, by0 = 1e300, by1 = -1e300;
     for (int32_t e : E) {
-      bx0 = std::min(bx0, ecx[e]);
-      bx1 = std::max(bx1, ecx[e]);
-      by0 = std::min(by0, ecy[e]);
-      by1 = std::max(by1, ecy[e]);
+      bx0 = std::min(bx0, g.ecx[e]);
+      bx1 = std::max(bx1, g.ecx[e]);
+      by0 = std::min(by0, g.ecy[e]);
+      by1 = std::max(by1, g.ecy[e]);
     }
     const int G = std::max(1, (int)std::sqrt((double)E.size() / 2));
     const double gx = std::max(bx1 - bx0, 1e-12) / G, gy = std::max(by1 - by0, 1e-12) / G;
@@ -353,17 +397,17 @@ ls_status build_correction(ls_ctx *h, Scat &sc, const ls_scatterer &s, const std
     };
     for (int32_t e : E) {
       int ix, iy;
-      cell(ecx[e], ecy[e], ix, iy);
+      cell(g.ecx[e], g.ecy[e], ix, iy);
       bucket[(size_t)iy * G + ix].push_back(e);
     }
-    parallel_for(n, threads, [&](int64_t j) {
-      const int32_t own = (int32_t)(j / 10);
-      if (esub[own] == l) {
-        tau[(size_t)j * nsub + l] = own;
+    parallel_for(nt, threads, [&](int64_t j) {
+      if (nodes && g.esub[j / 10] == l) {
+        tau[(size_t)j * nsub + l] = (int32_t)(j / 10);
         return;
       }
+      const double xj = nodes ? g.px[j] : tx[j], yj = nodes ? g.py[j] : ty[j];
       int ix, iy;
-      cell(px[j], py[j], ix, iy);
+      cell(xj, yj, ix, iy);
       double best = 1e300;
       int32_t be = -1;
       for (int r = 0; r <= 2 * G; ++r) {
@@ -376,8 +420,8 @@ ls_status build_correction(ls_ctx *h, Scat &sc, const ls_scatterer &s, const std
             const int cx = ix + dx, cy = iy + dy;
             if (cx < 0 || cy < 0 || cx >= G || cy >= G) continue;
             for (int32_t e : bucket[(size_t)cy * G + cx]) {
-              const double d = std::hypot(ecx[e] - px[j], ecy[e] - py[j]);
-              if (d < best || (d == best && ecaller[e] < ecaller[be])) {
+              const double d = std::hypot(g.ecx[e] - xj, g.ecy[e] - yj);
+              if (d < best || (d == best && g.ecaller[e] < g.ecaller[be])) {
                 best = d;
                 be = e;
               }
@@ -389,69 +433,89 @@ ls_status build_correction(ls_ctx *h, Scat &sc, const ls_scatterer &s, const std
   }
   // exact polynomial potentials (host threads)
   GaussLegendre gl;
-  std::vector<double> Er((size_t)n * nsub * NA), Ei((size_t)n * nsub * NA);
-  const double k = sc.k;
-  parallel_for(n * nsub, threads, [&](int64_t jl) {
+  std::vector<double> Er((size_t)nt * nsub * NA), Ei((size_t)nt * nsub * NA);
+  const double k = g.k;
+  parallel_for(nt * nsub, threads, [&](int64_t jl) {
     const int64_t j = jl / nsub;
     const int l = (int)(jl % nsub);
     const int32_t e = tau[(size_t)jl];
-    const bool inside = esub[j / 10] == l;
-    poly_potential(curves[l], inside, px[j], py[j], ecx[e], ecy[e], esc[e], k, gl, &Er[(size_t)jl * NA],
+    const bool inside = nodes && g.esub[j / 10] == l;
+    const double xj = nodes ? g.px[j] : tx[j], yj = nodes ? g.py[j] : ty[j];
+    poly_potential(g.curves[l], inside, xj, yj, g.ecx[e], g.ecy[e], g.esc[e], k, gl, &Er[(size_t)jl * NA],
                    &Ei[(size_t)jl * NA]);
   });
-  // punctured monomial sums on the GPU
-  std::vector<double> S((size_t)n * nsub * NA * 2);
+  // monomial sums on the GPU
+  std::vector<double> S((size_t)nt * nsub * NA * 2);
   {
-    const int nsplit = std::max(1, std::min(16, (int)(8192 / ((n + 63) / 64))));
-    void *dframe = nullptr, *dout = nullptr;
-    if (hipMalloc(&dframe, sizeof(double4) * n) != hipSuccess) return setup_fail(h, LS_ERR_ALLOC, "frame");
-    if (hipMalloc(&dout, sizeof(double2) * NA * n * (size_t)nsplit) != hipSuccess) {
-      (void)hipFree(dframe);
-      return setup_fail(h, LS_ERR_ALLOC, "poly sums");
+    const int nsplit = std::max(1, std::min(16, (int)(8192 / ((nt + 63) / 64))));
+    void *dframe = nullptr, *dout = nullptr, *dtgt = nullptr;
+    auto release = [&]() {
+      if (dframe) (void)hipFree(dframe);
+      if (dout) (void)hipFree(dout);
+      if (dtgt) (void)hipFree(dtgt);
+    };
+    if (hipMalloc(&dframe, sizeof(double4) * nt) != hipSuccess ||
+        hipMalloc(&dout, sizeof(double2) * NA * nt * (size_t)nsplit) != hipSuccess ||
+        (!nodes && hipMalloc(&dtgt, sizeof(double) * 2 * nt) != hipSuccess)) {
+      release();
+      return setup_fail(h, LS_ERR_ALLOC, "monomial sums");
     }
-    std::vector<double> frame(4 * n), part((size_t)NA * 2 * n * nsplit);
+    const double *dtx = sc.px, *dty = sc.py;
     hipError_t err = hipSuccess;
+    if (!nodes) {
+      err = hipMemcpyAsync(dtgt, tx, sizeof(double) * nt, hipMemcpyHostToDevice, st);
+      if (err == hipSuccess)
+        err = hipMemcpyAsync((double *)dtgt + nt, ty, sizeof(double) * nt, hipMemcpyHostToDevice, st);
+      dtx = (const double *)dtgt;
+      dty = (const double *)dtgt + nt;
+    }
+    std::vector<double> frame(4 * nt), part((size_t)NA * 2 * nt * nsplit);
     for (int l = 0; l < nsub && err == hipSuccess; ++l) {
-      for (int64_t j = 0; j < n; ++j) {
+      for (int64_t j = 0; j < nt; ++j) {
         const int32_t e = tau[(size_t)j * nsub + l];
-        frame[4 * j] = ecx[e];
-        frame[4 * j + 1] = ecy[e];
-        frame[4 * j + 2] = 1.0 / esc[e];
+        frame[4 * j] = g.ecx[e];
+        frame[4 * j + 1] = g.ecy[e];
+        frame[4 * j + 2] = 1.0 / g.esc[e];
         frame[4 * j + 3] = 0.0;
       }
-      err = hipMemcpyAsync(dframe, frame.data(), sizeof(double) * 4 * n, hipMemcpyHostToDevice, st);
-      const int q0 = (int)sub_lo[l], q1 = (int)sub_hi[l];
+      err = hipMemcpyAsync(dframe, frame.data(), sizeof(double) * 4 * nt, hipMemcpyHostToDevice, st);
+      const int q0 = (int)g.sub_lo[l], q1 = (int)g.sub_hi[l];
       const int split_len = (q1 - q0 + nsplit - 1) / nsplit;
-      dim3 grid((unsigned)((n + kBlock - 1) / kBlock), (unsigned)nsplit);
-      if (err == hipSuccess)
-        poly_sums_kernel<<<grid, kBlock, 0, st>>>((int)n, sc.px, sc.py, sc.pos, sc.w, q0, q1,
-                                                  (const double4 *)dframe, k * k, split_len, (double2 *)dout);
-      if (err == hipSuccess) err = hipGetLastError();
+      dim3 grid((unsigned)((nt + kBlock - 1) / kBlock), (unsigned)nsplit);
+      if (err == hipSuccess) {
+        if (nodes)
+          poly_sums_kernel<true><<<grid, kBlock, 0, st>>>((int)nt, dtx, dty, sc.pos, sc.w, q0, q1,
+                                                          (const double4 *)dframe, k * k, split_len, (double2 *)dout);
+        else
+          poly_sums_kernel<false><<<grid, kBlock, 0, st>>>((int)nt, dtx, dty, sc.pos, sc.w, q0, q1,
+                                                           (const double4 *)dframe, k * k, split_len, (double2 *)dout);
+        err = hipGetLastError();
+      }
       if (err == hipSuccess)
         err = hipMemcpyAsync(part.data(), dout, sizeof(double) * part.size(), hipMemcpyDeviceToHost, st);
       if (err == hipSuccess) err = hipStreamSynchronize(st);
       if (err != hipSuccess) break;
-      for (int64_t j = 0; j < n; ++j)
+      for (int64_t j = 0; j < nt; ++j)
         for (int a = 0; a < NA; ++a) {
           double sr = 0, si = 0;
           for (int sp = 0; sp < nsplit; ++sp) {
-            sr += part[(((size_t)sp * n + j) * NA + a) * 2];
-            si += part[(((size_t)sp * n + j) * NA + a) * 2 + 1];
+            sr += part[(((size_t)sp * nt + j) * NA + a) * 2];
+            si += part[(((size_t)sp * nt + j) * NA + a) * 2 + 1];
           }
           S[(((size_t)j * nsub + l) * NA + a) * 2] = sr;
           S[(((size_t)j * nsub + l) * NA + a) * 2 + 1] = si;
         }
     }
-    (void)hipFree(dframe);
-    (void)hipFree(dout);
+    if (err == hipSuccess) err = hipStreamSynchronize(st);
+    release();
     if (err != hipSuccess) return setup_fail(h, LS_ERR_HIP, hipGetErrorString(err));
   }
-  // rows of C: V^T r = E - S per (row, subdomain)
-  std::vector<int64_t> rp(n + 1);
-  for (int64_t j = 0; j <= n; ++j) rp[j] = j * NA * nsub;
-  std::vector<int32_t> ci((size_t)n * NA * nsub);
-  std::vector<double> cv((size_t)n * NA * nsub * 2);
-  parallel_for(n, threads, [&](int64_t j) {
+  // rows: V^T r = E - S per (target, subdomain)
+  rp.resize(nt + 1);
+  for (int64_t j = 0; j <= nt; ++j) rp[j] = j * NA * nsub;
+  ci.resize((size_t)nt * NA * nsub);
+  cv.resize((size_t)nt * NA * nsub * 2);
+  parallel_for(nt, threads, [&](int64_t j) {
     for (int l = 0; l < nsub; ++l) {
       const size_t jl = (size_t)j * nsub + l;
       const int32_t e = tau[jl];
@@ -460,8 +524,8 @@ ls_status build_correction(ls_ctx *h, Scat &sc, const ls_scatterer &s, const std
         dr[a] = Er[jl * NA + a] - S[(jl * NA + a) * 2];
         di[a] = Ei[jl * NA + a] - S[(jl * NA + a) * 2 + 1];
       }
-      lu10_solve(&LU[(size_t)e * NA * NA], &piv[(size_t)e * NA], dr);
-      lu10_solve(&LU[(size_t)e * NA * NA], &piv[(size_t)e * NA], di);
+      lu10_solve(&g.LU[(size_t)e * NA * NA], &g.piv[(size_t)e * NA], dr);
+      lu10_solve(&g.LU[(size_t)e * NA * NA], &g.piv[(size_t)e * NA], di);
       for (int i = 0; i < NA; ++i) {
         const size_t d = (size_t)rp[j] + (size_t)l * NA + i;
         ci[d] = 10 * e + i;
@@ -470,7 +534,42 @@ ls_status build_correction(ls_ctx *h, Scat &sc, const ls_scatterer &s, const std
       }
     }
   });
+  return LS_OK;
+}
+
+}  // namespace
+
+// Build the geometry and C for scatterer sc (nodes already uploaded in internal order) and
+// upload C.
+ls_status build_correction(ls_ctx *h, Scat &sc, const ls_scatterer &s, const std::vector<int32_t> &eord,
+                           hipStream_t st) {
+  ls_status rc = build_geometry(h, sc, s, eord);
+  if (rc != LS_OK) return rc;
+  std::vector<int64_t> rp;
+  std::vector<int32_t> ci;
+  std::vector<double> cv;
+  rc = correction_rows(h, sc, sc.n, nullptr, nullptr, true, st, rp, ci, cv);
+  if (rc != LS_OK) return rc;
   return upload_correction(h, sc, rp, ci, cv);
+}
+
+// Correction rows of field-recovery targets outside the scatterer (CSR over the scatterer's
+// internal node order).
+ls_status field_correction(ls_ctx *h, const Scat &sc, int64_t nt, const double *tx, const double *ty,
+                           hipStream_t st, std::vector<int64_t> &rp, std::vector<int32_t> &ci,
+                           std::vector<double> &cv) {
+  return correction_rows(h, sc, nt, tx, ty, false, st, rp, ci, cv);
+}
+
+// True when (x, y) lies outside every curve that encloses a subdomain of the scatterer.
+bool outside_scatterer(const Scat &sc, double x, double y) {
+  for (const auto &cl : sc.geom->curves)
+    for (const CurveH &c : cl) {
+      if (c.orient != 1) continue;
+      const double u = (x - c.cx) / c.a, v = (y - c.cy) / c.b;
+      if (u * u + v * v <= 1.0) return false;
+    }
+  return true;
 }
 
 }  // namespace lsk
