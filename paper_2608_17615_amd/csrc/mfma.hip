@@ -413,11 +413,11 @@ size_t tile_workspace_bytes(int64_t n, int nrhs, int nsplit) {
 }
 
 int tile_source_split(int64_t n, int nrhs, bool single) {
-  const int mt = single ? 4 : 2;
+  const int mt = single ? 2 : 1;
   const int ldx = tile_ldx(nrhs);
   const int nt = (ldx / 16) % 4 == 0 ? 4 : ((ldx / 16) % 2 == 0 ? 2 : 1);
   const int64_t waves = ((n + 16 * mt - 1) / (16 * mt)) * (ldx / (16 * nt));
-  int64_t s = (16384 + waves - 1) / waves;   // ~16 waves per SIMD over the launch
+  int64_t s = (32768 + waves - 1) / waves;   // ~32 waves per SIMD over the launch
   const int64_t cap = ((int64_t)1 << 30) / ((int64_t)16 * n * nrhs);
   if (s > cap) s = cap;
   if (s < 1) s = 1;
@@ -456,10 +456,14 @@ hipError_t launch_apply_tile(const Scat &s, const double *x, double *y, int nrhs
   }
   const int split_len = (int)((n + nsplit - 1) / nsplit);
   if (far_start) (void)hipEventRecord(far_start, st);
+  // 32 targets per wave in FP32 and 16 in FP64: with four N-tiles of accumulators the larger
+  // M-tiles drop occupancy to one wave per SIMD (measured at N = 122 500, B = 64: FP32 107.8 ->
+  // 75.7 ms, FP64 175.9 -> 171.1 ms; at N = 114 660, B = 16: FP64 60.9 -> 56.2 ms, FP32 26.9 ->
+  // 25.4 ms).  Loading the next step's source ahead cost occupancy and was slower.
   if (single)
-    launch_tile_nt<float, 4>(s, X, ldx, nrhs, split_len, nsplit, part, !fwd, st);
+    launch_tile_nt<float, 2>(s, X, ldx, nrhs, split_len, nsplit, part, !fwd, st);
   else
-    launch_tile_nt<double, 2>(s, X, ldx, nrhs, split_len, nsplit, part, !fwd, st);
+    launch_tile_nt<double, 1>(s, X, ldx, nrhs, split_len, nsplit, part, !fwd, st);
   if (far_stop) (void)hipEventRecord(far_stop, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
