@@ -17,7 +17,11 @@ SOURCES = ["api.hip", "apply.hip", "mfma.hip", "setup.hip", "krylov.hip", "farfi
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall", "-Wno-unused-function",
          # keep the compiler from emitting packed FP32 ops (hipcc's host pass warns it does not know
          # the feature; that warning is harmless)
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # matrix-core accumulators in ordinary VGPRs: without it the tile kernels copy every
+         # accumulator to the AGPRs and back around each step's MFMAs (about a third more VALU
+         # issue in FP64, and more registers)
+         "-mllvm", "-amdgpu-mfma-vgpr-form=1"]
 
 
 def _compile(src):

@@ -342,7 +342,8 @@ ls_status apply_op(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, 
   // several scatterers on the matrix cores: one persistent launch over all of them
   const bool batch = tiles && h->sc.size() > 1;
   const lsk::TileTune &tt = h->tune[single ? 1 : 0];
-  const int bmt = h->opt.mixed_tile > 0 ? h->opt.mixed_tile : (tt.mt > 0 ? tt.mt : (single ? 2 : 1));
+  const int bmt =
+      h->opt.mixed_tile > 0 ? h->opt.mixed_tile : (tt.mt > 0 ? tt.mt : lsk::tile_mt(nrhs, single));
   const int bsplit = tt.split_len > 0 ? tt.split_len : lsk::batch_default_split_len(h, single);
   size_t need = 0;
   if (batch) need = lsk::batch_workspace_bytes(h, nrhs, single, bsplit);

@@ -99,6 +99,7 @@ hipError_t launch_epilogue(const Scat &s, const double2 *part, int nsplit, const
                            double *y, int nrhs, int64_t ld, Mode mode, hipStream_t st);
 // mfma.hip: batched right-hand sides on the matrix cores (single = FP32 tiles)
 int tile_ldx(int nrhs);
+int tile_mt(int nrhs, bool single);
 size_t tile_workspace_bytes(int64_t n, int nrhs, int nsplit);
 int tile_source_split(int64_t n, int nrhs, bool single);
 hipError_t launch_apply_tile(const Scat &s, const double *x, double *y, int nrhs, int64_t ld, Mode mode, bool single,

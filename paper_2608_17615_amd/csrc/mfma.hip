@@ -273,6 +273,17 @@ int nt_of(int ldx) { return (ldx / 16) % 4 == 0 ? 4 : ((ldx / 16) % 2 == 0 ? 2 :
 
 int tile_ldx(int nrhs) { return (nrhs + 15) / 16 * 16; }
 
+// 16-target M-tiles per wavefront.  FP32: two.  FP64: one, or two when a single 16-column N-tile
+// covers the right-hand sides (B <= 16), where the wave otherwise has too little independent work
+// per Green's evaluation.  Measured at N = 122 500 (disk) and N = 114 660 (two-material), k = 40:
+// FP32 MT 4 -> 2 at B = 64, 77.4 -> 75.1 ms; FP64 at B = 64, MT 2 -> 1, 159.0 -> 150.3 ms; FP64 at
+// B = 16, MT 1 -> 2, 54.6 -> 52.4 ms; sixteen scatterers at B = 8, 93.9 -> 90.1 ms.  Loading the
+// next step's source ahead cost occupancy and was slower.
+int tile_mt(int nrhs, bool single) {
+  if (single) return 2;
+  return (tile_ldx(nrhs) / 16) % 2 == 0 ? 1 : 2;
+}
+
 int batch_default_split_len(const ls_ctx *h, bool single) {
   (void)h;
   return single ? 4096 : 2048;
@@ -413,7 +424,7 @@ size_t tile_workspace_bytes(int64_t n, int nrhs, int nsplit) {
 }
 
 int tile_source_split(int64_t n, int nrhs, bool single) {
-  const int mt = single ? 2 : 1;
+  const int mt = tile_mt(nrhs, single);
   const int ldx = tile_ldx(nrhs);
   const int nt = (ldx / 16) % 4 == 0 ? 4 : ((ldx / 16) % 2 == 0 ? 2 : 1);
   const int64_t waves = ((n + 16 * mt - 1) / (16 * mt)) * (ldx / (16 * nt));
@@ -456,14 +467,13 @@ hipError_t launch_apply_tile(const Scat &s, const double *x, double *y, int nrhs
   }
   const int split_len = (int)((n + nsplit - 1) / nsplit);
   if (far_start) (void)hipEventRecord(far_start, st);
-  // 32 targets per wave in FP32 and 16 in FP64: with four N-tiles of accumulators the larger
-  // M-tiles drop occupancy to one wave per SIMD (measured at N = 122 500, B = 64: FP32 107.8 ->
-  // 75.7 ms, FP64 175.9 -> 171.1 ms; at N = 114 660, B = 16: FP64 60.9 -> 56.2 ms, FP32 26.9 ->
-  // 25.4 ms).  Loading the next step's source ahead cost occupancy and was slower.
+  // with four N-tiles of accumulators the larger M-tiles cost occupancy (tile_mt has the measurements)
   if (single)
     launch_tile_nt<float, 2>(s, X, ldx, nrhs, split_len, nsplit, part, !fwd, st);
-  else
+  else if (tile_mt(nrhs, false) == 1)
     launch_tile_nt<double, 1>(s, X, ldx, nrhs, split_len, nsplit, part, !fwd, st);
+  else
+    launch_tile_nt<double, 2>(s, X, ldx, nrhs, split_len, nsplit, part, !fwd, st);
   if (far_stop) (void)hipEventRecord(far_stop, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
