@@ -247,7 +247,8 @@ def solve_form(op, b, form, args, adjoint=False):
     with Timer(op) as t:
         for c0 in range(0, B, batch):
             x, info = op.solve(b[c0:c0 + batch], tol=args.tol, maxit=args.maxit, precision=prec, adjoint=adjoint,
-                               restart=args.restart, inner_maxit=args.inner if form == "bm" else 0)
+                               restart=args.restart, inner_maxit=args.inner if form == "bm" else 0,
+                               inner_tol=args.relax if form == "bm" else 0.0)
             xs.append(x)
             its += [int(v) for v in info["iters"]]
             a64 += int(info["n_apply_fp64"])
@@ -297,7 +298,8 @@ def run_batched(args, probs, label, B):
     r = b[:x.shape[0]] - op.apply(x)
     relres = (torch.linalg.norm(r, dim=1) / torch.linalg.norm(b[:x.shape[0]], dim=1)).cpu().numpy()
     cfg = {"workload": label, "form": form, "n_nodes": n, "scatterers": len(probs), "nrhs": B, "tol": args.tol,
-           "restart": args.restart, "inner": args.inner, "batch": args.batch or B, "columns_timed": cols,
+           "restart": args.restart, "inner": args.inner, "relax": args.relax, "batch": args.batch or B,
+           "columns_timed": cols,
            "time_to_tol_s": total_s, "extrapolated": cols < B,
            "iterations_max": int(max(its)), "iterations_mean": float(np.mean(its)),
            "applies_fp64": a64, "applies_mixed": amx, "final_fp64_relres_max": float(relres.max()),
@@ -412,6 +414,9 @@ def main():
     ap.add_argument("--batch", type=int, default=0, help="b64/bm: right-hand sides per solve (0 = all)")
     ap.add_argument("--inner", type=int, default=0,
                     help="bm: > 0 selects flexible GMRES with this many inner mixed-precision steps")
+    ap.add_argument("--relax", type=float, default=0.0,
+                    help="bm: accuracy granted to the mixed operator (relaxed GMRES) or inner tolerance "
+                         "(flexible); 0 = the library default")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="first run one elementwise kernel that reads and writes BYTES each "

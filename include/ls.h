@@ -198,7 +198,9 @@ ls_status ls_set_contrast(ls_handle h, const double *m, hipStream_t stream);
  * LS_MIXED or the FP64 tiles): the tile shape is mt 16-target tiles per wavefront (FP32: 2 or 4,
  * FP64: 1 or 2) and split_len sources per work item.  ls_autotune times the candidate shapes on
  * this handle's own geometry for nrhs right-hand sides (far sum only, synchronous) and keeps the
- * fastest for later applications; ls_set_tile_shape sets one directly (e.g. from a cache). */
+ * fastest for later applications; ls_set_tile_shape sets one directly (e.g. from a cache).  The
+ * candidate split lengths are 1024 .. 8192 in FP64 and 1024 or 2048 in FP32, whose partial sums
+ * lose accuracy with length (default 2048 for both). */
 typedef struct {
   int32_t mt;
   int32_t split_len;

@@ -615,7 +615,9 @@ ls_status ls_autotune(ls_handle h, int32_t nrhs, ls_precision p, ls_tune_result 
   if (!h || nrhs < 1 || (p != LS_FP64 && p != LS_MIXED)) return fail(h, LS_ERR_ARG, "bad argument");
   const bool single = p == LS_MIXED;
   const int mts[2] = {single ? 2 : 1, single ? 4 : 2};
-  const int lens[4] = {1024, 2048, 4096, 8192};
+  // FP32 partial sums over more than 2 048 sources lose accuracy (see tile_source_split)
+  const int lens_all[4] = {1024, 2048, 4096, 8192};
+  const std::vector<int> lens(lens_all, lens_all + (single ? 2 : 4));
   size_t need = 0;
   for (int L : lens) need = std::max(need, lsk::batch_workspace_bytes(h, nrhs, single, L));
   ls_status st = ensure_ws(h, h->ws_apply, need, stream);

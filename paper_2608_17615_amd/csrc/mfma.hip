@@ -1,12 +1,14 @@
 // Far-field Green's sum for a block of right-hand sides on the matrix cores.
 //
 // For a wavefront's 16*MT targets and 16*NT right-hand sides, each step over 4 sources forms
-// the complex tile  Y[16 x 16] += G[16 x 4] X[4 x 16]  per (M-tile, N-tile) with four real
-// 16x16x4 MFMAs (Re Re, -Im Im, Re Im, Im Re).  In the 16x16x4 operand layout lane l supplies
-// A[l % 16][l / 16] and B[l / 16][l % 16], so lane l evaluates G for exactly the pair (target
-// l % 16 of the tile, source l / 16 of the step) it feeds to the matrix core: the Green's tile is
-// built on the VALU in registers and never moves.  B operands are the densities of the 4 sources
-// for 16 consecutive right-hand sides ([source][rhs] layout, coalesced 16-wide rows).
+// the complex tile  Y[16 x 16] += G[16 x 4] X[4 x 16]  per (M-tile, N-tile) with three real
+// 16x16x4 MFMAs (Gauss's three-product form).  The four-product form took 11-15% longer in FP64
+// and FP32 alike: the matrix products compete with the Green's evaluation for SIMD cycles.  In
+// the 16x16x4 operand layout lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16], so lane l
+// evaluates G for exactly the pair (target l % 16 of the tile, source l / 16 of the step) it feeds
+// to the matrix core: the Green's tile is built on the VALU in registers and never moves.  B
+// operands are the densities of the 4 sources for 16 consecutive right-hand sides ([source][rhs]
+// layout, coalesced 16-wide rows).
 //   T = double : v_mfma_f64_16x16x4f64, FP64 everywhere (exact variant of the batched sum);
 //   T = float  : v_mfma_f32_16x16x4f32 with FP32 Green's values (FP64 for z < 1) and FP32
 //                accumulation within one source split; splits are summed in FP64 by the epilogue.
@@ -118,20 +120,23 @@ __device__ __forceinline__ void tile_body(int n, const double2 *__restrict__ pos
     xt[mi] = p.x;
     yt[mi] = p.y;
   }
-  acc_t ar[MT][NT], ai[MT][NT];
+  // three real products per complex tile (Gauss): P0 = Re G Re X, P1 = Im G Im X and
+  // P2 = (Re G + Im G)(Re X + Im X); Re = P0 - P1 and Im = P2 - P0 - P1 are formed once, at the end
+  acc_t p0[MT][NT], p1[MT][NT], p2[MT][NT];
 #pragma unroll
   for (int mi = 0; mi < MT; ++mi)
 #pragma unroll
     for (int ni = 0; ni < NT; ++ni) {
-      ar[mi][ni] = acc_t{0, 0, 0, 0};
-      ai[mi][ni] = acc_t{0, 0, 0, 0};
+      p0[mi][ni] = acc_t{0, 0, 0, 0};
+      p1[mi][ni] = acc_t{0, 0, 0, 0};
+      p2[mi][ni] = acc_t{0, 0, 0, 0};
     }
   for (int s = s0; s < s1; s += 4) {
     const int src = s + kk;
     const bool ok = src < s1;
     const int sc = ok ? src : s0;
     const double2 p = pos[sc];
-    T gr[MT], gi[MT], gn[MT];
+    T gr[MT], gi[MT], g2[MT];
 #pragma unroll
     for (int mi = 0; mi < MT; ++mi) {
       const double dx = xt[mi] - p.x, dy = yt[mi] - p.y;
@@ -141,22 +146,23 @@ __device__ __forceinline__ void tile_body(int n, const double2 *__restrict__ pos
       gr[mi] = zero ? (T)0 : gr[mi];
       gi[mi] = zero ? (T)0 : gi[mi];
       if (CONJ) gi[mi] = -gi[mi];
-      gn[mi] = -gi[mi];
+      g2[mi] = gr[mi] + gi[mi];
     }
     typename TL::cplx_t xb[NT];
+    T x2[NT];
 #pragma unroll
     for (int ni = 0; ni < NT; ++ni) {
       xb[ni] = X[(int64_t)sc * ldx + b0 + 16 * ni + col];
       if (!ok) xb[ni] = TL::make(0.0, 0.0);
+      x2[ni] = xb[ni].x + xb[ni].y;
     }
 #pragma unroll
     for (int mi = 0; mi < MT; ++mi)
 #pragma unroll
       for (int ni = 0; ni < NT; ++ni) {
-        ar[mi][ni] = TL::mma(gr[mi], xb[ni].x, ar[mi][ni]);
-        ar[mi][ni] = TL::mma(gn[mi], xb[ni].y, ar[mi][ni]);
-        ai[mi][ni] = TL::mma(gr[mi], xb[ni].y, ai[mi][ni]);
-        ai[mi][ni] = TL::mma(gi[mi], xb[ni].x, ai[mi][ni]);
+        p0[mi][ni] = TL::mma(gr[mi], xb[ni].x, p0[mi][ni]);
+        p1[mi][ni] = TL::mma(gi[mi], xb[ni].y, p1[mi][ni]);
+        p2[mi][ni] = TL::mma(g2[mi], x2[ni], p2[mi][ni]);
       }
   }
 #pragma unroll
@@ -167,8 +173,10 @@ __device__ __forceinline__ void tile_body(int n, const double2 *__restrict__ pos
       for (int r = 0; r < 4; ++r) {
         const int t = t0 + 16 * mi + TL::row(lane, r);
         const int b = b0 + 16 * ni + col;
-        if (t < n && b < nrhs)
-          part[((int64_t)split * nrhs + b) * n + t] = make_double2((double)ar[mi][ni][r], (double)ai[mi][ni][r]);
+        if (t < n && b < nrhs) {
+          const double a = (double)p0[mi][ni][r], c = (double)p1[mi][ni][r];
+          part[((int64_t)split * nrhs + b) * n + t] = make_double2(a - c, (double)p2[mi][ni][r] - a - c);
+        }
       }
 }
 
@@ -286,7 +294,7 @@ int tile_mt(int nrhs, bool single) {
 
 int batch_default_split_len(const ls_ctx *h, bool single) {
   (void)h;
-  return single ? 4096 : 2048;
+  return 2048;   // FP32: bounds the accumulation error, as in tile_source_split
 }
 
 // per-scatterer layout of the batch workspace: X_s, f_s, part_s, each 256-byte aligned
@@ -429,7 +437,15 @@ int tile_source_split(int64_t n, int nrhs, bool single) {
   const int nt = (ldx / 16) % 4 == 0 ? 4 : ((ldx / 16) % 2 == 0 ? 2 : 1);
   const int64_t waves = ((n + 16 * mt - 1) / (16 * mt)) * (ldx / (16 * nt));
   int64_t s = (32768 + waves - 1) / waves;   // ~32 waves per SIMD over the launch
-  const int64_t cap = ((int64_t)1 << 30) / ((int64_t)16 * n * nrhs);
+  int64_t cap = ((int64_t)1 << 30) / ((int64_t)16 * n * nrhs);   // FP64 partials <= 1 GiB
+  if (single) {
+    // The FP32 accumulation error grows with the number of sources one split sums, so aim at
+    // about 2 048 per split, with up to 4 GiB of partials.  At N = 122 500, B = 64 going from 9 to
+    // 32 splits took the operator's relative error from 1.9e-6 to 6.7e-7 (2-norm; 5.9e-6 to 2.1e-6
+    // entrywise) at the same launch time; 64 splits gave 4.1e-7.
+    s = std::max<int64_t>(s, (n + 2047) / 2048);
+    cap = ((int64_t)1 << 32) / ((int64_t)16 * n * nrhs);
+  }
   if (s > cap) s = cap;
   if (s < 1) s = 1;
   if (s > 128) s = 128;
