@@ -255,7 +255,7 @@ def solve_form(op, b, form, args, adjoint=False):
             amx += int(info["n_apply_mixed"])
             log(f"  columns {c0}..{c0 + x.shape[0] - 1}: max {int(np.max(info['iters']))} iterations, "
                 f"max relres {np.max(info['relres']):.2e}, applies {info['n_apply_fp64']}+"
-                f"{info['n_apply_mixed']}, {info['seconds']:.2f} s")
+                f"{info['n_apply_mixed']}, second Gram-Schmidt passes {info['n_reorth']}, {info['seconds']:.2f} s")
     return torch.cat(xs), t.seconds, a64, amx, t, its, B
 
 

@@ -142,6 +142,7 @@ typedef struct {
   int64_t n_apply_fp64; /* FP64 operator applications (per column count summed) */
   int64_t n_apply_mixed;
   double seconds;
+  int64_t n_reorth;     /* Arnoldi steps (summed over systems) that needed a second Gram-Schmidt pass */
 } ls_solve_info;
 
 /* Solve L x = b (or L^H x = b) by GMRES without restart, x0 = 0 unless x0_given, each column

@@ -68,7 +68,7 @@ class _SolveOpts(ctypes.Structure):
 
 class _SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_void_p), ("relres", ctypes.c_void_p), ("n_apply_fp64", ctypes.c_int64),
-                ("n_apply_mixed", ctypes.c_int64), ("seconds", ctypes.c_double)]
+                ("n_apply_mixed", ctypes.c_int64), ("seconds", ctypes.c_double), ("n_reorth", ctypes.c_int64)]
 
 
 def lib():
@@ -240,12 +240,12 @@ class Operator:
         relres = np.zeros(B, dtype=np.float64)
         o = _SolveOpts(float(tol), int(maxit), int(restart), _PREC[precision], int(bool(adjoint)), int(x0 is not None),
                        int(inner_maxit), float(inner_tol))
-        info = _SolveInfo(iters.ctypes.data, relres.ctypes.data, 0, 0, 0.0)
+        info = _SolveInfo(iters.ctypes.data, relres.ctypes.data, 0, 0, 0.0, 0)
         st = _check(lib().ls_solve_gmres(self._h, b2.data_ptr(), x.data_ptr(), B, self.n, ctypes.byref(o),
                                          ctypes.byref(info), _stream()), self._h)
         return x.reshape(b.shape), {"converged": st == LS_OK, "iters": iters, "relres": relres,
                                     "n_apply_fp64": info.n_apply_fp64, "n_apply_mixed": info.n_apply_mixed,
-                                    "seconds": info.seconds}
+                                    "seconds": info.seconds, "n_reorth": info.n_reorth}
 
     def grad_contrast(self, u, lam, a):
         import torch

@@ -156,6 +156,29 @@ __global__ __launch_bounds__(kBlock) void update_kernel(int nv, int nseg, const 
   o.y = std::fma(sign, ai, o.y);
 }
 
+// flag[q] = 1 for an active system whose vector w kept less than a twentieth of its norm after
+// the first Gram-Schmidt projection h (h[q ldh + i], i < nv; h[q ldh + nv] = ||w||^2 before it):
+// the test of Daniel, Gragg, Kaufman and Stewart with eta = 1/20, against a cancellation that
+// would cost more than a digit of orthogonality.  Their usual eta = 1/sqrt(2) flags nearly every
+// step of these solves (||w_after|| / ||w_before|| has a median of about 0.4).  One classical pass
+// took the same steps as two in dense runs (N = 6 400, k = 20: 264 steps, basis orthogonal to
+// 5e-7 at the end; N = 10 000, k = 40: 4e-13 after 3 000 steps), and the same 1 054 steps at
+// N = 122 500, k = 40, with half the basis traffic.
+__global__ void reorth_flags_kernel(int nsys, int nv, const int *__restrict__ active, const double2 *__restrict__ h,
+                                    int64_t ldh, int *__restrict__ flag) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nsys) return;
+  int f = 0;
+  if (active[q]) {
+    const double2 *hq = h + (int64_t)q * ldh;
+    double proj = 0.0;
+    for (int i = 0; i < nv; ++i) proj = std::fma(hq[i].x, hq[i].x, std::fma(hq[i].y, hq[i].y, proj));
+    const double w0 = hq[nv].x;
+    f = (w0 - proj) < (1.0 / 400.0) * w0 ? 1 : 0;
+  }
+  flag[q] = f;
+}
+
 // y[c][n] = a[c][n] * (1 / beta[q]) for active systems (beta[q] > 0), and 0 for inactive ones, a
 // and y possibly the same; grid (tiles * kEPT, nrhs).  Zeroing keeps the vectors of a finished
 // system bounded (the operator maps 0 to 0), so its later basis vectors, which enter the final
@@ -280,6 +303,7 @@ struct Gmres {
   TileDesc *tiles = nullptr;
   int2 *seg_tiles = nullptr;
   int *active = nullptr;
+  int *reorth = nullptr;   // per system: a second Gram-Schmidt pass runs in this step
   int max_vec = 0;
   const double2 *slot_vec = nullptr;   // the vector in the norm slot (host copy of that entry)
 
@@ -302,7 +326,7 @@ struct Gmres {
                         sizeof(double) * nsys + sizeof(double2 *) * (size_t)(2 * maxvec + 8) + 1024;
     hipError_t e = ensure(ws->small, ws->small_bytes, need);
     if (e != hipSuccess) return e;
-    const size_t mneed = sizeof(TileDesc) * tl.size() + sizeof(int2) * nseg + sizeof(int) * nsys + 1024;
+    const size_t mneed = sizeof(TileDesc) * tl.size() + sizeof(int2) * nseg + 2 * sizeof(int) * nsys + 1024;
     e = ensure(ws->meta, ws->meta_bytes, mneed);
     if (e != hipSuccess) return e;
     e = ensure_part(16);
@@ -324,6 +348,9 @@ struct Gmres {
     m += sizeof(int2) * nseg;
     m = (char *)(((uintptr_t)m + 255) & ~(uintptr_t)255);
     active = (int *)m;
+    m += sizeof(int) * nsys;
+    m = (char *)(((uintptr_t)m + 255) & ~(uintptr_t)255);
+    reorth = (int *)m;
     e = hipMemcpyAsync(tiles, tl.data(), sizeof(TileDesc) * tl.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(seg_tiles, sr.data(), sizeof(int2) * nseg, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);   // host tables go out of scope
@@ -351,13 +378,15 @@ struct Gmres {
     return e;
   }
 
-  // out[q][0..nv) = V[0..nv)^H w per active system, using the pointer table entries [0, nv)
-  hipError_t dots(int nv, const double2 *w, double2 *out, int64_t ldo) {
+  // out[q][0..nv) = V[0..nv)^H w per system flagged in mask (default: the active ones; zero for
+  // the others), using the pointer table entries [0, nv)
+  hipError_t dots(int nv, const double2 *w, double2 *out, int64_t ldo, const int *mask = nullptr) {
     hipError_t e0 = ensure_part(nv);
     if (e0 != hipSuccess) return e0;
+    if (!mask) mask = active;
     dim3 g((unsigned)ntile, (unsigned)((nv + kGroup - 1) / kGroup), nrhs);
-    dots_kernel<<<g, kBlock, 0, st>>>(nrhs, nv, nseg, tiles, active, ptrs, n, w, n, part);
-    reduce_kernel<<<(unsigned)((nsys * nv + 255) / 256), 256, 0, st>>>(nrhs, nv, nseg, seg_tiles, active, part, out,
+    dots_kernel<<<g, kBlock, 0, st>>>(nrhs, nv, nseg, tiles, mask, ptrs, n, w, n, part);
+    reduce_kernel<<<(unsigned)((nsys * nv + 255) / 256), 256, 0, st>>>(nrhs, nv, nseg, seg_tiles, mask, part, out,
                                                                        ldo, nullptr);
     return hipGetLastError();
   }
@@ -399,6 +428,7 @@ struct CoreResult {
   std::vector<int> iters;   // per system
   std::vector<char> done;   // per system
   int64_t n_fp64 = 0, n_mixed = 0;
+  int64_t n_reorth = 0;     // system-steps that took a second Gram-Schmidt pass
 };
 
 // GMRES on contiguous (ld = n) device vectors b, x of nrhs columns, one independent system per
@@ -480,7 +510,8 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
   // one column per step
   std::vector<std::vector<cplx>> H(nsys);
   std::vector<cplx> cs, sn, g;
-  std::vector<double2> hh((size_t)nsys * (cyc + 1) * 2);
+  std::vector<double2> hh((size_t)nsys * (cyc + 2) * 2);
+  std::vector<int> rflag(nsys, 0);
   std::vector<double> betah(nsys), rnorm(nsys);
   const dim3 gv(blocks_of(n), nrhs);
   const dim3 gt = G.tile_grid();
@@ -539,6 +570,7 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
         if (s2 < 0) return s2;
         res.n_mixed += ir.n_mixed;
         res.n_fp64 += ir.n_fp64;
+        res.n_reorth += ir.n_reorth;
         set_skip(act);
         s2 = apply_op(h, (const double *)zj, (double *)w, nrhs, n, o.mode, LS_FP64, st);
         if (s2 != LS_OK) return s2;
@@ -559,21 +591,25 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
         if (s2 != LS_OK) return s2;
         if (pj == LS_FP64) ++res.n_fp64; else ++res.n_mixed;
       }
-      // CGS2 against V[0..j]
+      // Gram-Schmidt against V[0..j]: one classical pass, whose dot products include ||w||^2 (w is
+      // the table entry j + 1), and a second pass only for the systems reorth_flags_kernel flags
       const int nv = j + 1;
       double2 *h1 = G.hbuf, *h2 = G.ybuf;
-      HIPTRY(G.dots(nv, w, h1, nv));
-      update_kernel<<<gt, kBlock, 0, st>>>(nv, nseg, G.tiles, G.active, G.ptrs, n, h1, nv, -1.0, w, n);
-      HIPTRY(G.dots(nv, w, h2, nv));
-      update_kernel<<<gt, kBlock, 0, st>>>(nv, nseg, G.tiles, G.active, G.ptrs, n, h2, nv, -1.0, w, n);
+      HIPTRY(G.dots(nv + 1, w, h1, nv + 1));
+      update_kernel<<<gt, kBlock, 0, st>>>(nv, nseg, G.tiles, G.active, G.ptrs, n, h1, nv + 1, -1.0, w, n);
+      reorth_flags_kernel<<<(unsigned)((nsys + 255) / 256), 256, 0, st>>>(nsys, nv, G.active, h1, nv + 1, G.reorth);
+      HIPTRY(G.dots(nv, w, h2, nv, G.reorth));
+      update_kernel<<<gt, kBlock, 0, st>>>(nv, nseg, G.tiles, G.reorth, G.ptrs, n, h2, nv, -1.0, w, n);
       HIPTRY(G.set_slot(w));
       HIPTRY(G.norms());
       scale_kernel<<<gt, kBlock, 0, st>>>(nseg, G.tiles, G.active, G.beta, w, n, w, n);
-      HIPTRY(hipMemcpyAsync(hh.data(), h1, sizeof(double2) * nsys * nv, hipMemcpyDeviceToHost, st));
-      HIPTRY(hipMemcpyAsync(hh.data() + (size_t)nsys * nv, h2, sizeof(double2) * nsys * nv, hipMemcpyDeviceToHost,
-                            st));
+      HIPTRY(hipMemcpyAsync(hh.data(), h1, sizeof(double2) * nsys * (nv + 1), hipMemcpyDeviceToHost, st));
+      HIPTRY(hipMemcpyAsync(hh.data() + (size_t)nsys * (nv + 1), h2, sizeof(double2) * nsys * nv,
+                            hipMemcpyDeviceToHost, st));
       HIPTRY(hipMemcpyAsync(betah.data(), G.beta, sizeof(double) * nsys, hipMemcpyDeviceToHost, st));
+      HIPTRY(hipMemcpyAsync(rflag.data(), G.reorth, sizeof(int) * nsys, hipMemcpyDeviceToHost, st));
       HIPTRY(hipStreamSynchronize(st));
+      for (int q = 0; q < nsys; ++q) res.n_reorth += rflag[q];
       bool any = false, changed = false;
       double worst = 0.0;
       for (int q = 0; q < nsys; ++q) {
@@ -583,7 +619,7 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
         cplx *Hc = Hv.data();
         auto Hat = [&](int r_, int c_) -> cplx & { return Hc[(size_t)c_ * (c_ + 3) / 2 + r_]; };
         for (int i = 0; i < nv; ++i) {
-          const double2 a = hh[(size_t)q * nv + i], bq = hh[(size_t)nsys * nv + (size_t)q * nv + i];
+          const double2 a = hh[(size_t)q * (nv + 1) + i], bq = hh[(size_t)nsys * (nv + 1) + (size_t)q * nv + i];
           Hat(i, j) = cplx(a.x + bq.x, a.y + bq.y);
         }
         Hat(j + 1, j) = betah[q];
@@ -725,6 +761,7 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
     }
     res.n_fp64 += rr.n_fp64;
     res.n_mixed += rr.n_mixed;
+    res.n_reorth += rr.n_reorth;
     if (more == 0) break;   // every system met tol on its FP64 residual
   }
   // true residuals with the FP64 apply
@@ -773,6 +810,7 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
     info->n_apply_fp64 = res.n_fp64 * nrhs;
     info->n_apply_mixed = res.n_mixed * nrhs;
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    info->n_reorth = res.n_reorth;
   }
   return status;
 #undef HIPTRY

@@ -63,3 +63,4 @@ def test_workspace_and_options_structs_match_header():
     assert ctypes.sizeof(lsg._SolveOpts) == 40
     assert ctypes.sizeof(lsg._Options) == 24
     assert ctypes.sizeof(lsg._Profile) == 40
+    assert ctypes.sizeof(lsg._SolveInfo) == 48
