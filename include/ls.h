@@ -128,9 +128,11 @@ typedef struct {
    *                    inner_maxit steps of GMRES with the mixed operator (to inner_tol,
    *                    default 1e-12, i.e. exactly inner_maxit steps).
    *   inner_maxit = 0: relaxed GMRES; FP64 applications while the residual estimate exceeds
-   *                    0.3 tol / inner_tol (default inner_tol 1e-5, about the measured relative
-   *                    error of the mixed operator at N ~ 1e5), mixed ones after, then FP64
-   *                    refinement passes from the true residual if tol was missed.
+   *                    0.3 tol / inner_tol, mixed ones after, then FP64 refinement passes from
+   *                    the true residual if tol was missed.  Default inner_tol 1e-4 (switch at
+   *                    3e-5 for tol 1e-8): the mixed operator's error is below 1e-6 at N ~ 1e5,
+   *                    but switching earlier (inner_tol 1e-5 or 3e-5) slowed the k = 40 disk
+   *                    solve from 1 069 to 1 471-1 560 steps.
    * With several scatterers in the handle, every (column, scatterer) pair is an independent
    * system with its own Krylov space and convergence test; iters reports the most steps any
    * scatterer of the column took, relres the residual over the whole column. */

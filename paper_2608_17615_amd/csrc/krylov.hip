@@ -728,11 +728,12 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
   const int progress = pe ? std::max(0, std::atoi(pe)) : 0;
   // LS_MIXED: with inner_maxit > 0, flexible GMRES whose preconditioner is inner_maxit steps of
   // mixed-precision GMRES (to inner_tol); otherwise relaxed GMRES switching to the mixed operator
-  // once the residual is below tol / inner_tol (inner_tol = relative accuracy granted to it),
+  // once the residual is below tol / inner_tol (inner_tol = relative accuracy granted to it,
+  // default 1e-4: a later switch than the operator error alone would allow; see ls.h),
   // followed by FP64 refinement passes from the true residual if that missed tol
   const bool mixed = o.prec == LS_MIXED;
   const bool flexible = mixed && o.inner_maxit > 0;
-  const double relax = (mixed && !flexible) ? (o.inner_tol > 0 ? o.inner_tol : 1e-5) : 0.0;
+  const double relax = (mixed && !flexible) ? (o.inner_tol > 0 ? o.inner_tol : 1e-4) : 0.0;
   // the relaxed iteration aims its residual estimate below 0.3 tol so that its FP64 residual,
   // perturbed by the mixed applications, still meets tol without a (Krylov-space-losing) restart
   CoreOpts co{relax > 0 ? 0.3 * o.tol : o.tol, o.maxit, o.restart, mode, LS_FP64, flexible,
