@@ -13,6 +13,8 @@
 //              in registers (hankel.h) once per pair and reused for the RHS of the chunk;
 //   epilogue : sum the source-chunk partials in a fixed order (deterministic), scale by K, add
 //              the CSR correction, apply the diagonal factors and scatter to the caller's order.
+#include <vector>
+
 #include "hankel.h"
 #include "internal.h"
 
@@ -23,6 +25,7 @@ namespace {
 constexpr int kBlock = 256;
 
 __constant__ HankelTable d_hankel = kHankelTable;
+__constant__ SinCosTable d_sincos = kSinCosTable;
 
 typedef __attribute__((address_space(4))) const HankelTable ConstTab;
 
@@ -63,8 +66,8 @@ __global__ __launch_bounds__(kBlock) void prologue_kernel(int64_t n, int nrhs, c
 template <int TPL, int BC, bool CONJ, bool MASKED>
 __device__ __forceinline__ void far_source(int j, const int (&it)[TPL], const double (&xt)[TPL],
                                            const double (&yt)[TPL], double k2, const double2 *__restrict__ pos,
-                                           const double2 *__restrict__ d, double (&ar)[TPL][BC],
-                                           double (&ai)[TPL][BC]) {
+                                           const double2 *__restrict__ d, const double2 *sct,
+                                           double (&ar)[TPL][BC], double (&ai)[TPL][BC]) {
   const double2 p = pos[j];
   double gr[TPL], gi[TPL];
 #pragma unroll
@@ -72,7 +75,7 @@ __device__ __forceinline__ void far_source(int j, const int (&it)[TPL], const do
     const double dx = xt[q] - p.x;
     const double dy = yt[q] - p.y;
     const double A = k2 * std::fma(dx, dx, dy * dy);
-    green_unit(A, gr[q], gi[q], hankel_table());
+    green_unit<true>(A, gr[q], gi[q], hankel_table(), sct);
     if (MASKED) {
       const bool self = (j == it[q]);
       gr[q] = self ? 0.0 : gr[q];
@@ -100,6 +103,8 @@ __global__ __launch_bounds__(kBlock) void far_fp64_kernel(int n, const double *_
                                                          const double2 *__restrict__ sd, int nrhs,
                                                          double k2, int split_len,
                                                          double2 *__restrict__ part) {
+  __shared__ double2 sct[SINCOS_N];
+  load_sincos(sct, d_sincos);
   const int c0 = blockIdx.z * BC;
   const int w0 = __builtin_amdgcn_readfirstlane(blockIdx.x * kBlock * TPL + (threadIdx.x >> 6) * 64 * TPL);
   const int lane = threadIdx.x & 63;
@@ -124,11 +129,11 @@ __global__ __launch_bounds__(kBlock) void far_fp64_kernel(int n, const double *_
   const int e0 = min(s1, max(s0, w0));
   const int e1 = min(s1, max(s0, w0 + 64 * TPL));
   for (int j = s0; j < e0; ++j)
-    far_source<TPL, BC, CONJ, false>(j, it, xt, yt, k2, pos, sd + (int64_t)j * nrhs + c0, ar, ai);
+    far_source<TPL, BC, CONJ, false>(j, it, xt, yt, k2, pos, sd + (int64_t)j * nrhs + c0, sct, ar, ai);
   for (int j = e0; j < e1; ++j)
-    far_source<TPL, BC, CONJ, true>(j, it, xt, yt, k2, pos, sd + (int64_t)j * nrhs + c0, ar, ai);
+    far_source<TPL, BC, CONJ, true>(j, it, xt, yt, k2, pos, sd + (int64_t)j * nrhs + c0, sct, ar, ai);
   for (int j = e1; j < s1; ++j)
-    far_source<TPL, BC, CONJ, false>(j, it, xt, yt, k2, pos, sd + (int64_t)j * nrhs + c0, ar, ai);
+    far_source<TPL, BC, CONJ, false>(j, it, xt, yt, k2, pos, sd + (int64_t)j * nrhs + c0, sct, ar, ai);
 #pragma unroll
   for (int q = 0; q < TPL; ++q)
     if (it[q] < n) {
@@ -183,7 +188,10 @@ __global__ __launch_bounds__(kBlock) void epilogue_kernel(
   y[c] = make_double2(std::fma(k2, ar, xv.x), std::fma(k2, ai, xv.y));
 }
 
-__global__ void eval_green_kernel(const double *__restrict__ z2, double2 *__restrict__ g, int64_t n, int single) {
+__global__ __launch_bounds__(kBlock) void eval_green_kernel(const double *__restrict__ z2, double2 *__restrict__ g,
+                                                            int64_t n, int single) {
+  __shared__ double2 sct[SINCOS_N];
+  load_sincos(sct, d_sincos);
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   if (single) {
@@ -192,7 +200,7 @@ __global__ void eval_green_kernel(const double *__restrict__ z2, double2 *__rest
     g[i] = make_double2((double)gr * G_SCALE, (double)gi * G_SCALE);
   } else {
     double gr, gi;
-    green(z2[i], gr, gi, d_hankel);
+    green<true>(z2[i], gr, gi, d_hankel, sct);
     g[i] = make_double2(gr, gi);
   }
 }
@@ -219,6 +227,8 @@ __global__ __launch_bounds__(kBlock) void field_far_kernel(int nt, const double 
                                                           const double2 *__restrict__ pos,
                                                           const double2 *__restrict__ sd, int nrhs, double k2,
                                                           int split_len, double2 *__restrict__ part) {
+  __shared__ double2 sct[SINCOS_N];
+  load_sincos(sct, d_sincos);
   const int c0 = blockIdx.z * BC;
   const int t = blockIdx.x * kBlock + threadIdx.x;
   const int ti = t < nt ? t : nt - 1;
@@ -230,7 +240,7 @@ __global__ __launch_bounds__(kBlock) void field_far_kernel(int nt, const double 
 #pragma unroll
   for (int b = 0; b < BC; ++b) ar[0][b] = ai[0][b] = 0.0;
   for (int j = s0; j < s1; ++j)
-    far_source<1, BC, false, false>(j, it, xt, yt, k2, pos, sd + (int64_t)j * nrhs + c0, ar, ai);
+    far_source<1, BC, false, false>(j, it, xt, yt, k2, pos, sd + (int64_t)j * nrhs + c0, sct, ar, ai);
   if (t < nt) {
 #pragma unroll
     for (int b = 0; b < BC; ++b)
@@ -349,8 +359,14 @@ hipError_t launch_epilogue(const Scat &s, const double2 *part, int nsplit, const
   return hipGetLastError();
 }
 
+// The kernels' arithmetic on the host, table tail included (for checks on a CPU).
 void eval_green_host(const double *z2, double *g, int64_t n) {
-  for (int64_t i = 0; i < n; ++i) green(z2[i], g[2 * i], g[2 * i + 1], kHankelTable);
+  static const std::vector<double2> sct = [] {
+    std::vector<double2> t(SINCOS_N);
+    for (int i = 0; i < SINCOS_N; ++i) t[i] = make_double2(kSinCosTable.v[2 * i], kSinCosTable.v[2 * i + 1]);
+    return t;
+  }();
+  for (int64_t i = 0; i < n; ++i) green<true>(z2[i], g[2 * i], g[2 * i + 1], kHankelTable, sct.data());
 }
 
 hipError_t launch_eval_green(const double *z2, double *g, int64_t n, int single, hipStream_t st) {

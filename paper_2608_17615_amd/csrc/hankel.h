@@ -7,7 +7,9 @@
 //   ZS <= z < ZF : modulus-phase form H0 = M e^{i theta} with two fitted intervals in 1/z;
 //   z >= ZF : modulus-phase form from the even/odd Hankel asymptotic structure in 1/z.
 // e^{i theta} uses a reduction modulo pi (two-constant Cody-Waite with FMA) and minimax
-// sine/cosine on [-pi/2, pi/2]; the parity of the multiple of pi flips the sign.
+// sine/cosine on [-pi/2, pi/2], the parity of the multiple of pi flipping the sign; or, in the
+// kernels that keep a 512-entry table of e^{i j pi/256} in LDS, a reduction modulo pi/256, one
+// table entry and short Taylor series.
 // All coefficients are produced by gen_hankel_tables.py and passed in as one HankelTable, so a
 // kernel can keep them in memory read through the scalar data path instead of pinning ~130
 // doubles in vector registers.  Functions are host+device so the same arithmetic can be
@@ -178,11 +180,43 @@ __host__ __device__ __forceinline__ void phase_tail(double zp, double Mu, double
   gim = Ms * cs;
 }
 
+// The same result by a table: theta = j pi/256 + r with |r| <= pi/512, SC[j mod 512] =
+// e^{i j pi/256}/c8 (kSinCosTable, copied by the kernels into LDS with load_sincos) rotated by e^{i r} - 1 from short
+// Taylor series (tail_k); 21 instructions against 27 for the reduction modulo pi and the two
+// polynomials on [-pi/2, pi/2].  jm's low mantissa bits hold j (RND_MAGIC has none set).
+template <class Tab>
+__host__ __device__ __forceinline__ void phase_tail_table(double zp, double Mu, double &gre, double &gim,
+                                                          const Tab &T, const double2 *SC) {
+  const double jm = std::fma(zp, T.tail_k[0], RND_MAGIC);
+  const double jf = jm - RND_MAGIC;
+  double r = std::fma(-jf, T.tail_k[1], zp);
+  r = std::fma(-jf, T.tail_k[2], r);
+  unsigned long long bits;
+  std::memcpy(&bits, &jm, sizeof bits);
+  const double2 e = SC[(unsigned)bits & (SINCOS_N - 1)];
+  const double r2 = r * r;
+  const double sr = std::fma(r2 * (r * T.tail_k[3]), add_uniform(r2, T.tail_k[4]), r);   // sin r
+  const double cm = (r2 * T.tail_k[7]) * fma_uniform(add_uniform(r2, T.tail_k[5]), r2, T.tail_k[6]);  // cos r - 1
+  const double C = std::fma(e.x, cm, std::fma(-e.y, sr, e.x));
+  const double S = std::fma(e.y, cm, std::fma(e.x, sr, e.y));
+  // G/K = i Mu (C + i S)
+  gre = -(Mu * S);
+  gim = Mu * C;
+}
+
+// Copies the table of phase_tail_table into the workgroup's LDS array lds[SINCOS_N] (all threads
+// of the block take part; the barrier makes it visible to every wavefront).
+__device__ __forceinline__ void load_sincos(double2 *lds, const SinCosTable &t) {
+  for (int i = threadIdx.x; i < SINCOS_N; i += blockDim.x) lds[i] = make_double2(t.v[2 * i], t.v[2 * i + 1]);
+  __syncthreads();
+}
+
 // ZS <= z: modulus-phase form.  Only the two polynomials depend on the argument range; the
 // inverse fourth root, the reduction and the sine/cosine are shared, so a wavefront whose lanes
 // straddle a range boundary repeats only the polynomial evaluation.  Returns G/K.
-template <class Tab>
-__host__ __device__ __forceinline__ void green_modphase(double A, double &gre, double &gim, const Tab &T) {
+template <bool TBL = false, class Tab>
+__host__ __device__ __forceinline__ void green_modphase(double A, double &gre, double &gim, const Tab &T,
+                                                        const double2 *SC = nullptr) {
   const double s = inv_fourth_root(A, T);  // z^(-1/2)
   const double t = s * s;                  // 1/z
   double mod, ph;                          // M sqrt(z) / (4 m8), theta - z
@@ -200,7 +234,10 @@ __host__ __device__ __forceinline__ void green_modphase(double A, double &gre, d
     ph = horner_lead1<MID1_PH_NEG>(T.mid1_ph_q, x * MID1_SP);
   }
   // z + ph = A t + ph in one rounding, the same error as z = A t alone
-  phase_tail(std::fma(A, t, ph), mod * s, gre, gim, T);
+  if constexpr (TBL)
+    phase_tail_table(std::fma(A, t, ph), mod * s, gre, gim, T, SC);
+  else
+    phase_tail(std::fma(A, t, ph), mod * s, gre, gim, T);
 }
 
 // 0 < z < ZS; returns G/K
@@ -217,19 +254,22 @@ __host__ __device__ __forceinline__ void green_small(double A, double &gre, doub
 
 // G/K for z^2 = A > 0 (any branch), K = G_SCALE.  The far sums accumulate G/K and multiply
 // the total by K once.
-template <class Tab>
-__host__ __device__ __forceinline__ void green_unit(double A, double &gre, double &gim, const Tab &T) {
+// TBL: e^{i theta} from the table SC (phase_tail_table) instead of the polynomials.
+template <bool TBL = false, class Tab>
+__host__ __device__ __forceinline__ void green_unit(double A, double &gre, double &gim, const Tab &T,
+                                                    const double2 *SC = nullptr) {
   if (A >= ZS2) {
-    green_modphase(A, gre, gim, T);
+    green_modphase<TBL>(A, gre, gim, T, SC);
   } else {
     green_small(A, gre, gim, T);
   }
 }
 
 // G = (i/4) H0^(1)(z) for z^2 = A > 0
-template <class Tab>
-__host__ __device__ __forceinline__ void green(double A, double &gre, double &gim, const Tab &T) {
-  green_unit(A, gre, gim, T);
+template <bool TBL = false, class Tab>
+__host__ __device__ __forceinline__ void green(double A, double &gre, double &gim, const Tab &T,
+                                               const double2 *SC = nullptr) {
+  green_unit<TBL>(A, gre, gim, T, SC);
   gre *= T.consts[7];
   gim *= T.consts[7];
 }

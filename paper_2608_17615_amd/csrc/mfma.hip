@@ -16,6 +16,7 @@
 // (r = accumulator register), both verified on gfx950.  Green's values are G/K (hankel.h); the
 // shared epilogue multiplies the summed partials by K.
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "hankel.h"
@@ -28,6 +29,7 @@ namespace {
 constexpr int kBlock = 256;
 
 __constant__ HankelTable m_hankel = kHankelTable;
+__constant__ SinCosTable m_sincos = kSinCosTable;
 typedef __attribute__((address_space(4))) const HankelTable ConstTab;
 
 __device__ __forceinline__ ConstTab &mtab() {
@@ -35,6 +37,9 @@ __device__ __forceinline__ ConstTab &mtab() {
   asm volatile("" : "+s"(t));
   return *t;
 }
+
+template <class T>
+constexpr bool kFP64 = std::is_same<T, double>::value;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -50,8 +55,8 @@ struct Tile<double> {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
-  static __device__ __forceinline__ void green(double A, double &gr, double &gi) {
-    lsk::green_unit(A, gr, gi, mtab());
+  static __device__ __forceinline__ void green(double A, double &gr, double &gi, const double2 *sct) {
+    lsk::green_unit<true>(A, gr, gi, mtab(), sct);
   }
   static __device__ __forceinline__ cplx_t make(double a, double b) { return make_double2(a, b); }
 };
@@ -64,7 +69,7 @@ struct Tile<float> {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
-  static __device__ __forceinline__ void green(double A, float &gr, float &gi) {
+  static __device__ __forceinline__ void green(double A, float &gr, float &gi, const double2 *) {
     lsk::green32_unit(A, gr, gi, mtab());
   }
   static __device__ __forceinline__ cplx_t make(double a, double b) { return make_float2((float)a, (float)b); }
@@ -106,7 +111,7 @@ template <class T, int MT, int NT, bool CONJ>
 __device__ __forceinline__ void tile_body(int n, const double2 *__restrict__ pos,
                                           const typename Tile<T>::cplx_t *__restrict__ X, int ldx, int nrhs,
                                           double k2, int s0, int s1, int t0, int b0, int split,
-                                          double2 *__restrict__ part) {
+                                          double2 *__restrict__ part, const double2 *sct) {
   typedef Tile<T> TL;
   typedef typename TL::acc_t acc_t;
   const int lane = threadIdx.x & 63;
@@ -141,7 +146,7 @@ __device__ __forceinline__ void tile_body(int n, const double2 *__restrict__ pos
     for (int mi = 0; mi < MT; ++mi) {
       const double dx = xt[mi] - p.x, dy = yt[mi] - p.y;
       const double A = k2 * std::fma(dx, dx, dy * dy);
-      TL::green(A, gr[mi], gi[mi]);
+      TL::green(A, gr[mi], gi[mi], sct);
       const bool zero = !ok || src == tm[mi];
       gr[mi] = zero ? (T)0 : gr[mi];
       gi[mi] = zero ? (T)0 : gi[mi];
@@ -186,10 +191,13 @@ __global__ __launch_bounds__(kBlock) void far_tile_kernel(int n, const double2 *
                                                           const typename Tile<T>::cplx_t *__restrict__ X, int ldx,
                                                           int nrhs, double k2, int split_len,
                                                           double2 *__restrict__ part) {
+  // the FP64 Green's values take e^{i theta} from a table in LDS (hankel.h, phase_tail_table)
+  __shared__ double2 sct[kFP64<T> ? SINCOS_N : 1];
+  if constexpr (kFP64<T>) load_sincos(sct, m_sincos);
   const int wave = threadIdx.x >> 6;
   const int s0 = blockIdx.y * split_len;
   tile_body<T, MT, NT, CONJ>(n, pos, X, ldx, nrhs, k2, s0, min(n, s0 + split_len),
-                             (blockIdx.x * 4 + wave) * 16 * MT, blockIdx.z * 16 * NT, blockIdx.y, part);
+                             (blockIdx.x * 4 + wave) * 16 * MT, blockIdx.z * 16 * NT, blockIdx.y, part, sct);
 }
 
 // Uneven batch of scatterers in one launch: each workgroup repeatedly takes the next work item
@@ -201,6 +209,8 @@ __global__ __launch_bounds__(kBlock) void far_tile_persistent(const BatchDesc *_
                                                               const WorkItem *__restrict__ items, int n_items,
                                                               int *__restrict__ counter, int ldx, int nrhs) {
   __shared__ int next;
+  __shared__ double2 sct[kFP64<T> ? SINCOS_N : 1];
+  if constexpr (kFP64<T>) load_sincos(sct, m_sincos);
   const int wave = threadIdx.x >> 6;
   for (;;) {
     if (threadIdx.x == 0) next = atomicAdd(counter, 1);
@@ -213,7 +223,7 @@ __global__ __launch_bounds__(kBlock) void far_tile_persistent(const BatchDesc *_
     const int s0 = wi.split * d.split_len;
     tile_body<T, MT, NT, CONJ>(d.n, d.pos, (const typename Tile<T>::cplx_t *)d.X, ldx, nrhs, d.k2, s0,
                                min(d.n, s0 + d.split_len), (wi.tblock * 4 + wave) * 16 * MT, wi.bgroup * 16 * NT,
-                               wi.split, d.part);
+                               wi.split, d.part, sct);
   }
 }
 
