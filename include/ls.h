@@ -212,6 +212,36 @@ typedef struct {
 ls_status ls_autotune(ls_handle h, int32_t nrhs, ls_precision p, ls_tune_result *out, hipStream_t stream);
 ls_status ls_set_tile_shape(ls_handle h, ls_precision p, int32_t mt, int32_t split_len);
 
+/* Transfer operators between scatterer s's nodes and a Cartesian grid, and the last step of
+ * the preconditioner built from them (paper, Section 4).  The grid's node (ix, iy), 0 <= ix < nx,
+ * 0 <= iy < ny, sits at (x0 + ix h, y0 + iy h) and is numbered j = iy nx + ix; grid vectors are
+ * [nrhs][ldc] interleaved complex (device), ldc >= nx ny.  Node vectors x, y are the handle's
+ * [nrhs][ld] vectors in caller order (ld >= total nodes); only scatterer s's segment is read or
+ * written.  All three transfer calls are asynchronous on stream and allocate nothing. */
+typedef struct {
+  double x0, y0; /* grid origin */
+  double h;      /* spacing > 0 */
+  int32_t nx, ny;/* nodes per direction, >= 2 each, nx ny < 2^31 */
+} ls_grid;
+
+/* Builds T_C^Q (bilinear hat functions of the cell containing each node, eq. psi_def; a node on
+ * a grid line takes the cell above/right of it, on the last line the one below/left) and
+ * T_Q^C = D^-1 (T_C^Q)^T (Approach II, eqs. T_H^C_def and D_def; D_jj = 1 where no node reaches
+ * j with a positive weight) for scatterer s, replacing an earlier grid.  Every node must lie in
+ * [x0, x0 + (nx-1) h] x [y0, y0 + (ny-1) h], else LS_ERR_ARG.  Synchronous. */
+ls_status ls_transfer_setup(ls_handle h, int32_t s, const ls_grid *g);
+/* c = T_Q^C x (grid values from scatterer s's node values). */
+ls_status ls_quad_to_cart(ls_handle h, int32_t s, const double *x, int64_t ld, double *c, int64_t ldc,
+                          int32_t nrhs, hipStream_t stream);
+/* y = T_C^Q c on scatterer s's nodes (the rest of y is left alone). */
+ls_status ls_cart_to_quad(ls_handle h, int32_t s, const double *c, int64_t ldc, double *y, int64_t ld,
+                          int32_t nrhs, hipStream_t stream);
+/* y = x + T_C^Q (sc - c) on scatterer s's nodes: with c = T_Q^C x (ls_quad_to_cart) and sc = S c
+ * for the caller's Cartesian approximate inverse S, this is y = P x with
+ * P = I + T_C^Q (S - I) T_Q^C (eq. preconditioner_factored).  y may be x. */
+ls_status ls_precond_finish(ls_handle h, int32_t s, const double *x, int64_t ld, const double *c, const double *sc,
+                            int64_t ldc, double *y, int32_t nrhs, hipStream_t stream);
+
 /* Introspection. */
 int64_t ls_num_nodes(ls_handle h);                       /* total nodes */
 int32_t ls_num_scatterers(ls_handle h);

@@ -40,10 +40,12 @@ class Grid:
 
 def containing_cell(grid, x, y):
     """Lower-left vertex (ix, iy) of the cell containing each point (the reading above)."""
-    ix = np.floor((np.asarray(x) - grid.x0) / grid.h).astype(np.int64)
-    iy = np.floor((np.asarray(y) - grid.y0) / grid.h).astype(np.int64)
-    if np.any(ix < 0) or np.any(iy < 0) or np.any(ix > grid.nx - 1) or np.any(iy > grid.ny - 1):
+    sx = (np.asarray(x) - grid.x0) / grid.h
+    sy = (np.asarray(y) - grid.y0) / grid.h
+    if np.any(sx < 0) or np.any(sy < 0) or np.any(sx > grid.nx - 1) or np.any(sy > grid.ny - 1):
         raise ValueError("a node lies outside the grid")
+    ix = np.floor(sx).astype(np.int64)
+    iy = np.floor(sy).astype(np.int64)
     return np.minimum(ix, grid.nx - 2), np.minimum(iy, grid.ny - 2)
 
 

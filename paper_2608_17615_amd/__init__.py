@@ -18,7 +18,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libls.so")
 
-LS_OK, LS_NOT_CONVERGED = 0, 1
+LS_OK, LS_NOT_CONVERGED, LS_ERR_ARG = 0, 1, -1
 FP64, MIXED = 0, 1
 _PREC = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}
 CIRCLE, ELLIPSE = 0, 1
@@ -99,6 +99,10 @@ def lib():
         L.ls_farfield_adjoint.argtypes = [vp, i32, vp, i32, i64, vp, i32, vp, vp, vp]
         L.ls_field.argtypes = [vp, i32, vp, vp, i64, vp, i32, i64, vp, vp]
         L.ls_set_contrast.argtypes = [vp, vp, vp]
+        L.ls_transfer_setup.argtypes = [vp, i32, vp]
+        L.ls_quad_to_cart.argtypes = [vp, i32, vp, i64, vp, i64, i32, vp]
+        L.ls_cart_to_quad.argtypes = [vp, i32, vp, i64, vp, i64, i32, vp]
+        L.ls_precond_finish.argtypes = [vp, i32, vp, i64, vp, vp, i64, vp, i32, vp]
         L.ls_autotune.argtypes = [vp, i32, i32, vp, vp]
         L.ls_set_tile_shape.argtypes = [vp, i32, i32, i32]
         L.ls_profile_enable.argtypes = [vp, i32]
@@ -123,6 +127,11 @@ def _check(status, handle=None):
 def _stream():
     import torch
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_double), ("y0", ctypes.c_double), ("h", ctypes.c_double),
+                ("nx", ctypes.c_int32), ("ny", ctypes.c_int32)]
 
 
 @dataclass
@@ -299,6 +308,57 @@ class Operator:
         _check(lib().ls_field(self._h, s, tx.ctypes.data, ty.ctypes.data, tx.size, u2.data_ptr(), u2.shape[0],
                               self.n, out.data_ptr(), _stream()), self._h)
         return out
+
+    def set_grid(self, x0, y0, h, nx, ny, s=0):
+        """Cartesian grid of the transfer operators of scatterer s (node (ix, iy) at
+        (x0 + ix h, y0 + iy h), numbered iy nx + ix); see ls_transfer_setup."""
+        g = _Grid(float(x0), float(y0), float(h), int(nx), int(ny))
+        _check(lib().ls_transfer_setup(self._h, s, ctypes.byref(g)), self._h)
+        self._grids = getattr(self, "_grids", {})
+        self._grids[s] = int(nx) * int(ny)
+
+    def _grid_n(self, s):
+        n = getattr(self, "_grids", {}).get(s)
+        if n is None:
+            raise LSError(LS_ERR_ARG, "no grid for this scatterer (set_grid)")
+        return n
+
+    def quad_to_cart(self, x, s=0):
+        """T_Q^C x: grid values (B, nx ny) from the node values of scatterer s in x (B, N)."""
+        import torch
+        x2 = self._cols(x)
+        c = torch.empty((x2.shape[0], self._grid_n(s)), dtype=torch.complex128, device=x2.device)
+        _check(lib().ls_quad_to_cart(self._h, s, x2.data_ptr(), self.n, c.data_ptr(), c.shape[1], x2.shape[0],
+                                     _stream()), self._h)
+        return c
+
+    def cart_to_quad(self, c, s=0):
+        """T_C^Q c on scatterer s's nodes: (B, N), zero on the other scatterers."""
+        import torch
+        c = c.to(torch.complex128).contiguous()
+        if c.dim() == 1:
+            c = c[None, :]
+        if c.shape[1] != self._grid_n(s):
+            raise ValueError("grid vectors must have nx ny entries")
+        y = torch.zeros((c.shape[0], self.n), dtype=torch.complex128, device=c.device)
+        _check(lib().ls_cart_to_quad(self._h, s, c.data_ptr(), c.shape[1], y.data_ptr(), self.n, c.shape[0],
+                                     _stream()), self._h)
+        return y
+
+    def precondition(self, x, S, s=0):
+        """P x = x + T_C^Q (S - I) T_Q^C x on scatterer s (eq. preconditioner_factored), for a
+        Cartesian approximate inverse S given as a callable on (B, nx ny) CUDA tensors; the other
+        scatterers' entries of x are returned unchanged."""
+        import torch
+        x2 = self._cols(x)
+        c = self.quad_to_cart(x2, s)
+        sc = S(c).to(torch.complex128).contiguous()
+        if sc.shape != c.shape:
+            raise ValueError("S must return a grid vector of the shape it was given")
+        y = x2.clone()
+        _check(lib().ls_precond_finish(self._h, s, x2.data_ptr(), self.n, c.data_ptr(), sc.data_ptr(), c.shape[1],
+                                       y.data_ptr(), x2.shape[0], _stream()), self._h)
+        return y.reshape(x.shape)
 
     def farfield_adjoint(self, res, thetas, s=0):
         """(a, rhs) with a = A^H res and rhs = conj(m) a on scatterer s (zero elsewhere)."""

@@ -21,6 +21,20 @@ struct alignas(32) Src4 {
 // of field-recovery targets.
 struct GeomData;
 
+// Transfer operators between one scatterer's nodes and a Cartesian grid (transfer.hip): per
+// node (internal order) the grid index of its cell's lower-left vertex and the four bilinear
+// weights; T_Q^C = D^-1 (T_C^Q)^T as CSR over the grid nodes.  Device arrays are in ls_ctx::owned.
+struct TransferData {
+  double x0 = 0, y0 = 0, h = 0;
+  int32_t nx = 0, ny = 0;
+  int32_t *cell = nullptr;
+  double4 *w = nullptr;             // weights of the vertices (ix, iy), (ix+1, iy), (ix, iy+1), (ix+1, iy+1)
+  int64_t *rp = nullptr;            // [nx ny + 1]
+  int32_t *col = nullptr;           // caller index of the node within the scatterer
+  double *val = nullptr;
+  std::vector<void *> bufs;         // the allocations above
+};
+
 // One scatterer, all device arrays in the internal (sorted) node order.
 struct Scat {
   int64_t n = 0, off = 0;     // nodes, offset in the concatenated caller vectors
@@ -36,6 +50,7 @@ struct Scat {
   double2 *cv = nullptr, *cvH = nullptr;
   std::vector<int32_t> perm_host;   // same as perm, on the host
   std::shared_ptr<GeomData> geom;
+  std::shared_ptr<TransferData> tr; // set by ls_transfer_setup
 };
 
 // One scatterer of a batched launch and one unit of its far-sum work.
@@ -136,6 +151,8 @@ ls_status field_correction(ls_ctx *h, const Scat &sc, int64_t nt, const double *
                            hipStream_t st, std::vector<int64_t> &rp, std::vector<int32_t> &ci,
                            std::vector<double> &cv);
 bool outside_scatterer(const Scat &sc, double x, double y);
+const double *geom_x(const Scat &sc);   // host node positions, internal order (nullptr without geometry)
+const double *geom_y(const Scat &sc);
 int field_source_split(int64_t n, int64_t nt, int nrhs);
 size_t field_workspace_bytes(int64_t n, int nrhs, int64_t nt, int nsplit);
 hipError_t launch_field(const Scat &s, const double *u, int nrhs, int64_t ld, int64_t nt, const double *tx,

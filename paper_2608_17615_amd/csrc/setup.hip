@@ -292,6 +292,9 @@ struct GeomData {
   std::vector<std::vector<CurveH>> curves;
 };
 
+const double *geom_x(const Scat &sc) { return sc.geom ? sc.geom->px.data() : nullptr; }
+const double *geom_y(const Scat &sc) { return sc.geom ? sc.geom->py.data() : nullptr; }
+
 ls_status build_geometry(ls_ctx *h, Scat &sc, const ls_scatterer &s, const std::vector<int32_t> &eord) {
   auto g = std::make_shared<GeomData>();
   const int64_t n = sc.n;

@@ -1,0 +1,115 @@
+"""Transfer operators and the preconditioner wrapper (Section 4) against the oracle's dense
+matrices, and their defining properties at full size."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2608_17615_amd as lsg
+from oracle import transfer as tr
+from tests.gpu_cases import relmax
+from workloads import problems as P
+
+pytestmark = pytest.mark.gpu
+
+
+def _grid_over(prob, h, pad=0.02):
+    x, y = prob.mesh.x, prob.mesh.y
+    x0, y0 = x.min() - pad, y.min() - pad
+    nx = int(np.ceil((x.max() + pad - x0) / h)) + 1
+    ny = int(np.ceil((y.max() + pad - y0) / h)) + 1
+    return tr.Grid(x0, y0, h, nx, ny)
+
+
+def _rand(B, n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((B, n)) + 1j * rng.standard_normal((B, n))
+
+
+@pytest.mark.parametrize("name,h", [("disk", 0.17), ("two-material", 0.11)])
+def test_transfer_operators_match_oracle(name, h):
+    prob = P.disk_problem(4, 2 * np.pi, 2.0) if name == "disk" else P.graded_two_material(2, 8.0)
+    g = _grid_over(prob, h)
+    op = lsg.Operator(lsg.Scatterer.from_mesh(prob.mesh, prob.m, prob.k))
+    op.set_grid(g.x0, g.y0, g.h, g.nx, g.ny)
+    T = tr.cart_to_quad(g, prob.mesh.x, prob.mesh.y)
+    Tq = tr.quad_to_cart(T)
+    x = _rand(3, prob.n_nodes, 0)
+    c = _rand(3, g.n, 1)
+    got_c = op.quad_to_cart(torch.tensor(x, device="cuda")).cpu().numpy()
+    got_y = op.cart_to_quad(torch.tensor(c, device="cuda")).cpu().numpy()
+    e1, e2 = relmax(got_c, x @ Tq.T), relmax(got_y, c @ T.T)
+    # S: a fixed dense perturbation of the identity, applied by torch on the device and by numpy
+    rng = np.random.default_rng(3)
+    Sm = np.eye(g.n) + 0.05 * (rng.standard_normal((g.n, g.n)) + 1j * rng.standard_normal((g.n, g.n)))
+    St = torch.tensor(Sm.T.copy(), device="cuda")
+    got_p = op.precondition(torch.tensor(x, device="cuda"), lambda v: v @ St).cpu().numpy()
+    e3 = relmax(got_p, tr.precondition(T, x, lambda v: v @ Sm.T))
+    print(f"{name} N={prob.n_nodes}, grid {g.nx}x{g.ny}: T_Q^C {e1:.1e}, T_C^Q {e2:.1e}, P {e3:.1e}", flush=True)
+    assert e1 <= 1e-14 and e2 <= 1e-14 and e3 <= 1e-13
+
+
+def test_second_scatterer_segment_and_errors():
+    a = P.disk_problem(3, 9.0, 2.0)
+    b = P.graded_two_material(2, 8.0)
+    big = lsg.Operator([lsg.Scatterer.from_mesh(p.mesh, p.m, p.k) for p in (a, b)])
+    one = lsg.Operator(lsg.Scatterer.from_mesh(b.mesh, b.m, b.k))
+    g = _grid_over(b, 0.13)
+    with pytest.raises(lsg.LSError):
+        big.quad_to_cart(torch.zeros((1, big.n), dtype=torch.complex128, device="cuda"), s=1)
+    for o, s in ((big, 1), (one, 0)):
+        o.set_grid(g.x0, g.y0, g.h, g.nx, g.ny, s=s)
+    x = torch.tensor(_rand(2, big.n, 4), device="cuda")
+    S = lambda v: 1.5 * v + 0.25j * torch.roll(v, 1, dims=1)
+    y = big.precondition(x, S, s=1).cpu().numpy()
+    yb = one.precondition(x[:, a.n_nodes:].contiguous(), S).cpu().numpy()
+    xa = x.cpu().numpy()
+    assert np.array_equal(y[:, :a.n_nodes], xa[:, :a.n_nodes])
+    assert relmax(y[:, a.n_nodes:], yb) <= 1e-15
+    with pytest.raises(lsg.LSError):                     # the grid must cover every node
+        one.set_grid(g.x0 + 0.5, g.y0, g.h, g.nx, g.ny)
+    with pytest.raises(lsg.LSError):
+        one.set_grid(g.x0, g.y0, -1.0, g.nx, g.ny)
+
+
+def test_full_size_properties_and_rate():
+    """N = 122 500 (unit disk), k = 40 with k h_C = 0.125 as in the paper's runs: rows of T_C^Q
+    sum to one, bilinear fields are reproduced, T_Q^C keeps constants on the pixelation nodes,
+    and P is the identity for S = I; 64 right-hand sides."""
+    prob = P.config3(B=1)
+    g = _grid_over(prob, 0.125 / 40.0)
+    op = lsg.Operator(lsg.Scatterer.from_mesh(prob.mesh, prob.m, prob.k))
+    op.set_grid(g.x0, g.y0, g.h, g.nx, g.ny)
+    zx, zy = g.nodes()
+    f = lambda u, v: 0.3 - 1.7 * u + 2.2 * v + 0.9 * u * v
+    B = 64
+    c = torch.tensor(f(zx, zy), device="cuda", dtype=torch.complex128).repeat(B, 1)
+    y = op.cart_to_quad(c)
+    e_bil = relmax(y[0].cpu().numpy(), f(prob.mesh.x, prob.mesh.y))
+    ones = torch.ones((B, prob.n_nodes), dtype=torch.complex128, device="cuda")
+    back = op.quad_to_cart(ones)[0].cpu().numpy()
+    hit = back != 0
+    e_one = np.abs(back[hit] - 1).max()
+    x = torch.tensor(_rand(B, prob.n_nodes, 5), device="cuda")
+    e_id = relmax(op.precondition(x, lambda v: v).cpu().numpy(), x.cpu().numpy())
+    # timing of the three transfer kernels (current stream)
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    cc = op.quad_to_cart(x)
+    torch.cuda.synchronize()
+    reps = 10
+    s0.record()
+    for _ in range(reps):
+        cc = op.quad_to_cart(x)
+    s1.record()
+    torch.cuda.synchronize()
+    t_qc = s0.elapsed_time(s1) / reps
+    s0.record()
+    for _ in range(reps):
+        y = op.cart_to_quad(cc)
+    s1.record()
+    torch.cuda.synchronize()
+    t_cq = s0.elapsed_time(s1) / reps
+    gb_qc = 16 * B * (prob.n_nodes + g.n) / (t_qc * 1e-3) / 1e9
+    print(f"grid {g.nx}x{g.ny} ({g.n} nodes), N={prob.n_nodes}, B={B}: bilinear {e_bil:.1e}, "
+          f"constants {e_one:.1e} on {int(hit.sum())} pixelation nodes, P(S=I) {e_id:.1e}; "
+          f"T_Q^C {t_qc:.3f} ms (~{gb_qc:.0f} GB/s of vectors), T_C^Q {t_cq:.3f} ms (incl. zero fill)", flush=True)
+    assert e_bil <= 1e-13 and e_one <= 1e-14 and e_id == 0.0

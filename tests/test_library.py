@@ -43,6 +43,9 @@ def test_argument_validation_before_any_device_call():
     s = lsg._Scatterer(25, 2, 10, None, None, None, None, None, 1.0, 0, 0, None)
     assert L.ls_setup_from_csr(ctypes.byref(s), None, None, None, None, ctypes.byref(y)) == -1
     assert L.ls_eval_green_host(None, None, -1) == -1
+    assert L.ls_transfer_setup(None, 0, None) == -1
+    assert L.ls_quad_to_cart(None, 0, None, 1, None, 1, 1, None) == -1
+    assert L.ls_precond_finish(None, 0, None, 1, None, None, 1, None, 1, None) == -1
 
 
 def test_host_green_matches_mpmath():
@@ -64,3 +67,4 @@ def test_workspace_and_options_structs_match_header():
     assert ctypes.sizeof(lsg._Options) == 24
     assert ctypes.sizeof(lsg._Profile) == 40
     assert ctypes.sizeof(lsg._SolveInfo) == 48
+    assert ctypes.sizeof(lsg._Grid) == 32
