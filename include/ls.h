@@ -150,7 +150,7 @@ typedef struct {
 /* Solve L x = b (or L^H x = b) by GMRES without restart, x0 = 0 unless x0_given, each column
  * (and each scatterer of it) independently.  Synchronous.  Returns LS_NOT_CONVERGED if any
  * column missed tol.  The environment variable LS_PROGRESS=k prints a progress line to stderr
- * every k steps. */
+ * every k steps (flexible GMRES: every outer step). */
 ls_status ls_solve_gmres(ls_handle h, const double *b, double *x, int32_t nrhs, int64_t ld,
                          const ls_solve_opts *o, ls_solve_info *info, hipStream_t stream);
 

@@ -23,7 +23,8 @@
 // mixed-precision operator; the outer FP64 iteration removes the inner solve's error.
 //
 // Progress: with the environment variable LS_PROGRESS=k the solver prints the step, the largest
-// residual estimate and the number of active systems every k steps to stderr.
+// residual estimate and the number of active systems every k steps (flexible GMRES: every outer
+// step) to stderr.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -650,7 +651,8 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
           worst = std::max(worst, est[q]);
         }
       }
-      if (o.progress > 0 && (total_it + 1) % o.progress == 0) {
+      // flexible outer steps each hold a whole inner solve, so every one of them is reported
+      if (o.progress > 0 && (o.flexible || (total_it + 1) % o.progress == 0)) {
         int na = 0;
         for (int q = 0; q < nsys; ++q) na += act[q];
         std::fprintf(stderr, "[ls gmres] step %d: largest residual estimate %.3e, %d of %d systems active\n",
