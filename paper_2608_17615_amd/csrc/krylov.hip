@@ -572,6 +572,20 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
         res.n_mixed += ir.n_mixed;
         res.n_fp64 += ir.n_fp64;
         res.n_reorth += ir.n_reorth;
+        // an inner solve that took no step (its tolerance already met by z = 0) leaves z_j = 0, a
+        // useless direction: those systems take z_j = v_j (no preconditioning in this step)
+        std::vector<int> idle(nsys, 0);
+        bool any_idle = false;
+        for (int q = 0; q < nsys; ++q)
+          if (act[q] && ir.iters[q] == 0) idle[q] = any_idle = 1;
+        if (any_idle) {
+          const std::vector<double2> one(nsys, make_double2(1.0, 0.0));
+          HIPTRY(hipMemcpyAsync(G.reorth, idle.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, st));
+          HIPTRY(hipMemcpyAsync(G.ybuf, one.data(), sizeof(double2) * nsys, hipMemcpyHostToDevice, st));
+          update_kernel<<<gt, kBlock, 0, st>>>(1, nseg, G.tiles, G.reorth, G.ptrs + j, n, G.ybuf, 1, 1.0, zj, n);
+          HIPTRY(hipGetLastError());
+          HIPTRY(hipStreamSynchronize(st));   // idle and one go out of scope
+        }
         set_skip(act);
         s2 = apply_op(h, (const double *)zj, (double *)w, nrhs, n, o.mode, LS_FP64, st);
         if (s2 != LS_OK) return s2;

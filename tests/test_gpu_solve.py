@@ -136,3 +136,17 @@ def test_mixed_relaxed_gmres(name, tol, B):
           f"mixed {info['n_apply_mixed'] // B} relres {info['relres'].max():.2e} vs LU {e:.2e}", flush=True)
     assert info["converged"] and np.all(info["relres"] <= 1.5 * tol) and info["n_apply_mixed"] > 0
     assert e <= 1e3 * tol
+
+
+def test_flexible_gmres_survives_a_useless_inner_solver():
+    """inner_tol = 1: every inner solve is done before its first step (z = 0).  The outer flexible
+    iteration then takes z = v, i.e. it becomes plain FP64 GMRES, and must still converge."""
+    p, c, op = _golden_op("disk2500")
+    b = torch.tensor(c["b"], device="cuda")
+    x, info = op.solve(b, tol=1e-10, maxit=200, precision="mixed", inner_tol=1.0, inner_maxit=5)
+    x64, i64 = op.solve(b, tol=1e-10, maxit=200)
+    e = relmax(x.cpu().numpy(), c["u"])
+    print(f"useless inner solver: outer iters {info['iters']} (plain GMRES {i64['iters']}), mixed applies "
+          f"{info['n_apply_mixed']}, relres {info['relres']}, vs LU {e:.2e}", flush=True)
+    assert info["converged"] and np.all(info["relres"] <= 1.5e-10)
+    assert info["iters"][0] == i64["iters"][0]
