@@ -298,6 +298,12 @@ def run_batched(args, probs, label, B):
     # true FP64 residual of the returned solution
     r = b[:x.shape[0]] - op.apply(x)
     relres = (torch.linalg.norm(r, dim=1) / torch.linalg.norm(b[:x.shape[0]], dim=1)).cpu().numpy()
+    check = None
+    if form == "bm":
+        # untimed: distance of the mixed-precision solution's first column from an FP64 solve of it
+        x64, _ = op.solve(b[:1], tol=args.tol, maxit=args.maxit, restart=args.restart)
+        check = float(((x[:1] - x64).abs().max() / x64.abs().max()).item())
+        log(f"first column against FP64 GMRES: {check:.2e}")
     cfg = {"workload": label, "form": form, "n_nodes": n, "scatterers": len(probs), "nrhs": B, "tol": args.tol,
            "restart": args.restart, "inner": args.inner, "relax": args.relax, "batch": args.batch or B,
            "columns_timed": cols,
@@ -305,7 +311,7 @@ def run_batched(args, probs, label, B):
            "iterations_max": int(max(its)), "iterations_mean": float(np.mean(its)),
            "applies_fp64": a64, "applies_mixed": amx, "final_fp64_relres_max": float(relres.max()),
            "setup_s": setup_s, "far_kernel_ms_avg": t.far_avg_s * 1e3, "z_range_fractions": frac,
-           "autotune": tune}
+           "autotune": tune, "error_vs_fp64_column0": check}
     return line(value, total_s * 1e3, 1, 0, dtype, cfg, roof, None), x
 
 
@@ -354,11 +360,23 @@ def run_gradient(args, prob, label, B):
         single = form == "bm"
         roof = roofline_mfma(pairs * B, far_kernel_avg(op, b, "mixed" if single else "fp64"), single)
         dtype = "f32-mfma+f64" if single else "f64"
+    check = None
+    if form == "bm":
+        # untimed: the same misfit and gradient through FP64 solves (batched FP64 tiles)
+        u64 = solve_form(op, b[:cols], "b64", args)[0]
+        _, res64, J64 = op.farfield(u64, thetas, data)
+        a64_, rhs64 = op.farfield_adjoint(res64, thetas)
+        lam64 = solve_form(op, rhs64, "b64", args, adjoint=True)[0]
+        g64 = op.grad_contrast(u64, lam64, a64_)
+        check = {"misfit": abs(J - J64) / abs(J64),
+                 "gradient": float(((g - g64).abs().max() / g64.abs().max()).item())}
+        log(f"against FP64 solves: misfit {check['misfit']:.2e}, gradient {check['gradient']:.2e}")
     cfg = {"workload": label, "form": form, "n_nodes": n, "nrhs": B, "receivers": 128, "tol": args.tol,
            "restart": args.restart, "columns_timed": cols, "time_to_tol_s": total_s, "extrapolated": cols < B,
            "forward_s": fwd[1], "adjoint_s": adj[1], "iterations_forward_max": int(max(fwd[5])),
            "iterations_adjoint_max": int(max(adj[5])), "misfit_J": J,
-           "grad_norm": float(torch.linalg.norm(g).item()), "setup_s": setup_s, "z_range_fractions": frac}
+           "grad_norm": float(torch.linalg.norm(g).item()), "setup_s": setup_s, "z_range_fractions": frac,
+           "error_vs_fp64": check}
     return line(value, total_s * 1e3, 1, 0, dtype, cfg, roof, None), g
 
 
