@@ -22,9 +22,14 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// Each thread serves one node (or grid node) for kCols consecutive right-hand sides, so the cell
+// weights and the CSR rows are read once per kCols columns instead of once per column.
+constexpr int kCols = 8;
+
 // y[c][off + perm[i]] = (xa ? xa[c][off + perm[i]] : 0) + sum over the four vertices v of node i's
-// cell of w_v(i) (g[c][j_v] - (g2 ? g2[c][j_v] : 0)); grid (ceil(n / kBlock), nrhs).
-__global__ __launch_bounds__(kBlock) void cart_to_quad_kernel(int64_t n, int nx, const int32_t *__restrict__ cell,
+// cell of w_v(i) (g[c][j_v] - (g2 ? g2[c][j_v] : 0)); grid (ceil(n / kBlock), ceil(nrhs / kCols)).
+__global__ __launch_bounds__(kBlock) void cart_to_quad_kernel(int64_t n, int nrhs, int nx,
+                                                             const int32_t *__restrict__ cell,
                                                              const double4 *__restrict__ w,
                                                              const int32_t *__restrict__ perm, int64_t off,
                                                              const double2 *__restrict__ g,
@@ -32,53 +37,84 @@ __global__ __launch_bounds__(kBlock) void cart_to_quad_kernel(int64_t n, int nx,
                                                              const double2 *xa, double2 *y, int64_t ld) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  const int64_t c = blockIdx.y;
   const int64_t j = cell[i];
   const double4 wv = w[i];
-  const double2 *gc = g + c * ldg;
-  double2 v0 = gc[j], v1 = gc[j + 1], v2 = gc[j + nx], v3 = gc[j + nx + 1];
-  if (g2) {
-    const double2 *hc = g2 + c * ldg;
-    const double2 u0 = hc[j], u1 = hc[j + 1], u2 = hc[j + nx], u3 = hc[j + nx + 1];
-    v0 = make_double2(v0.x - u0.x, v0.y - u0.y);
-    v1 = make_double2(v1.x - u1.x, v1.y - u1.y);
-    v2 = make_double2(v2.x - u2.x, v2.y - u2.y);
-    v3 = make_double2(v3.x - u3.x, v3.y - u3.y);
+  const int64_t dst = off + perm[i];
+  const int c1 = min(nrhs, (int)(blockIdx.y + 1) * kCols);
+  for (int64_t c = (int64_t)blockIdx.y * kCols; c < c1; ++c) {
+    const double2 *gc = g + c * ldg;
+    double2 v0 = gc[j], v1 = gc[j + 1], v2 = gc[j + nx], v3 = gc[j + nx + 1];
+    if (g2) {
+      const double2 *hc = g2 + c * ldg;
+      const double2 u0 = hc[j], u1 = hc[j + 1], u2 = hc[j + nx], u3 = hc[j + nx + 1];
+      v0 = make_double2(v0.x - u0.x, v0.y - u0.y);
+      v1 = make_double2(v1.x - u1.x, v1.y - u1.y);
+      v2 = make_double2(v2.x - u2.x, v2.y - u2.y);
+      v3 = make_double2(v3.x - u3.x, v3.y - u3.y);
+    }
+    double re = wv.x * v0.x, im = wv.x * v0.y;
+    re = std::fma(wv.y, v1.x, re);
+    im = std::fma(wv.y, v1.y, im);
+    re = std::fma(wv.z, v2.x, re);
+    im = std::fma(wv.z, v2.y, im);
+    re = std::fma(wv.w, v3.x, re);
+    im = std::fma(wv.w, v3.y, im);
+    const int64_t idx = c * ld + dst;
+    if (xa) {
+      const double2 a = xa[idx];
+      re += a.x;
+      im += a.y;
+    }
+    y[idx] = make_double2(re, im);
   }
-  double re = wv.x * v0.x, im = wv.x * v0.y;
-  re = std::fma(wv.y, v1.x, re);
-  im = std::fma(wv.y, v1.y, im);
-  re = std::fma(wv.z, v2.x, re);
-  im = std::fma(wv.z, v2.y, im);
-  re = std::fma(wv.w, v3.x, re);
-  im = std::fma(wv.w, v3.y, im);
-  const int64_t idx = c * ld + off + perm[i];
-  if (xa) {
-    const double2 a = xa[idx];
-    re += a.x;
-    im += a.y;
-  }
-  y[idx] = make_double2(re, im);
 }
 
-// g[c][j] = sum over CSR row j of val * x[c][off + col]; grid (ceil(nc / kBlock), nrhs).
-__global__ __launch_bounds__(kBlock) void quad_to_cart_kernel(int64_t nc, const int64_t *__restrict__ rp,
+// g[c][j] = sum over CSR row j of val * x[c][off + col]; grid (ceil(nc / kBlock), ceil(nrhs / kCols)).
+// Rows of up to kRow entries are held in registers across the columns.
+constexpr int kRow = 8;
+__global__ __launch_bounds__(kBlock) void quad_to_cart_kernel(int64_t nc, int nrhs, const int64_t *__restrict__ rp,
                                                              const int32_t *__restrict__ col,
                                                              const double *__restrict__ val, int64_t off,
                                                              const double2 *__restrict__ x, int64_t ld,
                                                              double2 *__restrict__ g, int64_t ldg) {
   const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (j >= nc) return;
-  const int64_t c = blockIdx.y;
-  const double2 *xc = x + c * ld + off;
-  double re = 0.0, im = 0.0;
-  for (int64_t e = rp[j]; e < rp[j + 1]; ++e) {
-    const double v = val[e];
-    const double2 a = xc[col[e]];
-    re = std::fma(v, a.x, re);
-    im = std::fma(v, a.y, im);
+  const int64_t e0 = rp[j], e1 = rp[j + 1];
+  const int c1 = min(nrhs, (int)(blockIdx.y + 1) * kCols);
+  if (e1 - e0 <= kRow) {
+    const int m = (int)(e1 - e0);
+    int32_t cl[kRow];
+    double vl[kRow];
+#pragma unroll
+    for (int e = 0; e < kRow; ++e) {
+      cl[e] = e < m ? col[e0 + e] : 0;
+      vl[e] = e < m ? val[e0 + e] : 0.0;
+    }
+    for (int64_t c = (int64_t)blockIdx.y * kCols; c < c1; ++c) {
+      const double2 *xc = x + c * ld + off;
+      double re = 0.0, im = 0.0;
+#pragma unroll
+      for (int e = 0; e < kRow; ++e)
+        if (e < m) {
+          const double2 a = xc[cl[e]];
+          re = std::fma(vl[e], a.x, re);
+          im = std::fma(vl[e], a.y, im);
+        }
+      g[c * ldg + j] = make_double2(re, im);
+    }
+  } else {
+    for (int64_t c = (int64_t)blockIdx.y * kCols; c < c1; ++c) {
+      const double2 *xc = x + c * ld + off;
+      double re = 0.0, im = 0.0;
+      for (int64_t e = e0; e < e1; ++e) {
+        const double v = val[e];
+        const double2 a = xc[col[e]];
+        re = std::fma(v, a.x, re);
+        im = std::fma(v, a.y, im);
+      }
+      g[c * ldg + j] = make_double2(re, im);
+    }
   }
-  g[c * ldg + j] = make_double2(re, im);
 }
 
 ls_status tfail(ls_ctx *h, ls_status st, const char *msg) { return setup_fail(h, st, msg); }
@@ -201,9 +237,9 @@ ls_status ls_quad_to_cart(ls_handle h, int32_t s, const double *x, int64_t ld, d
   const Scat &sc = h->sc[s];
   const TransferData &t = *sc.tr;
   const int64_t nc = (int64_t)t.nx * t.ny;
-  dim3 grid((unsigned)((nc + lsk::kBlock - 1) / lsk::kBlock), (unsigned)nrhs);
-  lsk::quad_to_cart_kernel<<<grid, lsk::kBlock, 0, stream>>>(nc, t.rp, t.col, t.val, sc.off, (const double2 *)x, ld,
-                                                             (double2 *)c, ldc);
+  dim3 grid((unsigned)((nc + lsk::kBlock - 1) / lsk::kBlock), (unsigned)((nrhs + lsk::kCols - 1) / lsk::kCols));
+  lsk::quad_to_cart_kernel<<<grid, lsk::kBlock, 0, stream>>>(nc, nrhs, t.rp, t.col, t.val, sc.off,
+                                                             (const double2 *)x, ld, (double2 *)c, ldc);
   if (hipGetLastError() != hipSuccess) return lsk::tfail(h, LS_ERR_HIP, "quad_to_cart launch");
   return LS_OK;
 }
@@ -216,8 +252,8 @@ ls_status ls_cart_to_quad(ls_handle h, int32_t s, const double *c, int64_t ldc, 
   if (!c || !y) return lsk::tfail(h, LS_ERR_ARG, "null vector");
   const Scat &sc = h->sc[s];
   const TransferData &t = *sc.tr;
-  dim3 grid((unsigned)((sc.n + lsk::kBlock - 1) / lsk::kBlock), (unsigned)nrhs);
-  lsk::cart_to_quad_kernel<<<grid, lsk::kBlock, 0, stream>>>(sc.n, t.nx, t.cell, t.w, sc.perm, sc.off,
+  dim3 grid((unsigned)((sc.n + lsk::kBlock - 1) / lsk::kBlock), (unsigned)((nrhs + lsk::kCols - 1) / lsk::kCols));
+  lsk::cart_to_quad_kernel<<<grid, lsk::kBlock, 0, stream>>>(sc.n, nrhs, t.nx, t.cell, t.w, sc.perm, sc.off,
                                                              (const double2 *)c, nullptr, ldc, nullptr,
                                                              (double2 *)y, ld);
   if (hipGetLastError() != hipSuccess) return lsk::tfail(h, LS_ERR_HIP, "cart_to_quad launch");
@@ -232,8 +268,8 @@ ls_status ls_precond_finish(ls_handle h, int32_t s, const double *x, int64_t ld,
   if (!x || !c || !sc_ || !y) return lsk::tfail(h, LS_ERR_ARG, "null vector");
   const Scat &sc = h->sc[s];
   const TransferData &t = *sc.tr;
-  dim3 grid((unsigned)((sc.n + lsk::kBlock - 1) / lsk::kBlock), (unsigned)nrhs);
-  lsk::cart_to_quad_kernel<<<grid, lsk::kBlock, 0, stream>>>(sc.n, t.nx, t.cell, t.w, sc.perm, sc.off,
+  dim3 grid((unsigned)((sc.n + lsk::kBlock - 1) / lsk::kBlock), (unsigned)((nrhs + lsk::kCols - 1) / lsk::kCols));
+  lsk::cart_to_quad_kernel<<<grid, lsk::kBlock, 0, stream>>>(sc.n, nrhs, t.nx, t.cell, t.w, sc.perm, sc.off,
                                                              (const double2 *)sc_, (const double2 *)c, ldc,
                                                              (const double2 *)x, (double2 *)y, ld);
   if (hipGetLastError() != hipSuccess) return lsk::tfail(h, LS_ERR_HIP, "precond_finish launch");
