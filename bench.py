@@ -442,8 +442,8 @@ def main():
                          "(calibrates a profiler's HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is described "
-              f"in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); a multi-GPU layout (target rows, or "
+              f"whole scatterers, per GPU) is not built", file=sys.stderr)
         sys.exit(2)
 
     from workloads import problems as P
