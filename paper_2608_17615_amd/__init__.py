@@ -103,6 +103,7 @@ def lib():
         L.ls_quad_to_cart.argtypes = [vp, i32, vp, i64, vp, i64, i32, vp]
         L.ls_cart_to_quad.argtypes = [vp, i32, vp, i64, vp, i64, i32, vp]
         L.ls_precond_finish.argtypes = [vp, i32, vp, i64, vp, vp, i64, vp, i32, vp]
+        L.ls_solve_gmres_precond.argtypes = [vp, vp, vp, i32, i64, vp, i32, _GridOp, vp, vp, vp, i64, vp, vp]
         L.ls_autotune.argtypes = [vp, i32, i32, vp, vp]
         L.ls_set_tile_shape.argtypes = [vp, i32, i32, i32]
         L.ls_profile_enable.argtypes = [vp, i32]
@@ -127,6 +128,10 @@ def _check(status, handle=None):
 def _stream():
     import torch
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+_GridOp = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                           ctypes.c_void_p, ctypes.c_void_p)
 
 
 class _Grid(ctypes.Structure):
@@ -359,6 +364,42 @@ class Operator:
         _check(lib().ls_precond_finish(self._h, s, x2.data_ptr(), self.n, c.data_ptr(), sc.data_ptr(), c.shape[1],
                                        y.data_ptr(), x2.shape[0], _stream()), self._h)
         return y.reshape(x.shape)
+
+    def solve_precond(self, b, S, s=0, tol=1e-8, maxit=1000, restart=0, adjoint=False):
+        """FP64 GMRES preconditioned on the right by P = I + T_C^Q (S - I) T_Q^C of scatterer s
+        (set_grid first); S is a callable on (B, nx ny) CUDA tensors.  Returns (x, info)."""
+        import torch
+        b2 = self._cols(b)
+        B = b2.shape[0]
+        nc = self._grid_n(s)
+        c = torch.empty((B, nc), dtype=torch.complex128, device=b2.device)
+        sc = torch.empty_like(c)
+        failed = []
+
+        def cb(cp, scp, nrhs, ldc, user, stream):
+            try:
+                out = S(c)
+                if out.shape != c.shape:
+                    raise ValueError("S must return a grid vector of the shape it was given")
+                sc.copy_(out)
+                return LS_OK
+            except Exception as e:   # reported after the library returns
+                failed.append(e)
+                return LS_ERR_ARG
+
+        fn = _GridOp(cb)
+        x = torch.zeros_like(b2)
+        iters = np.zeros(B, dtype=np.int32)
+        relres = np.zeros(B, dtype=np.float64)
+        o = _SolveOpts(float(tol), int(maxit), int(restart), FP64, int(bool(adjoint)), 0, 0, 0.0)
+        info = _SolveInfo(iters.ctypes.data, relres.ctypes.data, 0, 0, 0.0, 0)
+        st = lib().ls_solve_gmres_precond(self._h, b2.data_ptr(), x.data_ptr(), B, self.n, ctypes.byref(o), s, fn,
+                                          None, c.data_ptr(), sc.data_ptr(), nc, ctypes.byref(info), _stream())
+        if failed:
+            raise failed[0]
+        _check(st, self._h)
+        return x.reshape(b.shape), {"converged": st == LS_OK, "iters": iters, "relres": relres,
+                                    "n_apply_fp64": info.n_apply_fp64, "seconds": info.seconds}
 
     def farfield_adjoint(self, res, thetas, s=0):
         """(a, rhs) with a = A^H res and rhs = conj(m) a on scatterer s (zero elsewhere)."""

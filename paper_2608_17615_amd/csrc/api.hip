@@ -439,6 +439,35 @@ ls_status ls_solve_gmres(ls_handle h, const double *b, double *x, int32_t nrhs, 
   return lsk::solve_gmres(h, b, x, nrhs, ld, *o, info, stream);
 }
 
+ls_status ls_solve_gmres_precond(ls_handle h, const double *b, double *x, int32_t nrhs, int64_t ld,
+                                 const ls_solve_opts *o, int32_t s, ls_grid_op S, void *user, double *c, double *sc,
+                                 int64_t ldc, ls_solve_info *info, hipStream_t stream) {
+  if (!h) return fail(nullptr, LS_ERR_ARG, "null handle");
+  if (!o) return fail(h, LS_ERR_ARG, "null options");
+  if (nrhs < 0 || nrhs > 65535) return fail(h, LS_ERR_ARG, "bad nrhs");
+  if (nrhs == 0) return LS_OK;
+  if (!b || !x) return fail(h, LS_ERR_ARG, "null vector");
+  if (b == x) return fail(h, LS_ERR_ARG, "b and x must not alias");
+  if (ld < h->n_total) return fail(h, LS_ERR_ARG, "ld < number of nodes");
+  if (!(o->tol > 0) || !std::isfinite(o->tol)) return fail(h, LS_ERR_ARG, "tol must be > 0");
+  if (o->maxit < 1) return fail(h, LS_ERR_ARG, "maxit must be >= 1");
+  if (o->restart < 0) return fail(h, LS_ERR_ARG, "restart < 0");
+  if (o->prec != LS_FP64) return fail(h, LS_ERR_ARG, "the preconditioned solve is FP64 only");
+  if (s < 0 || s >= (int32_t)h->sc.size()) return fail(h, LS_ERR_ARG, "bad scatterer index");
+  const Scat &sct = h->sc[s];
+  if (!sct.tr) return fail(h, LS_ERR_ARG, "no grid for this scatterer (ls_transfer_setup)");
+  if (!S || !c || !sc) return fail(h, LS_ERR_ARG, "null preconditioner argument");
+  if (ldc < (int64_t)sct.tr->nx * sct.tr->ny) return fail(h, LS_ERR_ARG, "ldc < number of grid nodes");
+  lsk::PrecondCb pc;
+  pc.s = s;
+  pc.S = S;
+  pc.user = user;
+  pc.c = (double2 *)c;
+  pc.sc = (double2 *)sc;
+  pc.ldc = ldc;
+  return lsk::solve_gmres(h, b, x, nrhs, ld, *o, info, stream, &pc);
+}
+
 ls_status ls_grad_contrast(ls_handle h, const double *u, const double *lam, const double *a, int32_t nrhs,
                            int64_t ld, double *grad, hipStream_t stream) {
   if (!h) return fail(nullptr, LS_ERR_ARG, "null handle");

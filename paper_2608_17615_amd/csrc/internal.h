@@ -105,6 +105,15 @@ namespace lsk {
 // Forward: y = L x;  Adjoint: y = L^H x;  AdjointPotential: y = V^H x = W conj(G~) x + C^H x.
 enum class Mode { Forward, Adjoint, AdjointPotential };
 
+// krylov.hip: the right preconditioner P = I + T_C^Q (S - I) T_Q^C of scatterer s with the caller's S
+struct PrecondCb {
+  int s = 0;
+  ls_grid_op S = nullptr;
+  void *user = nullptr;
+  double2 *c = nullptr, *sc = nullptr;   // the caller's grid buffers
+  int64_t ldc = 0;
+};
+
 // apply.hip
 hipError_t launch_apply_fp64(const Scat &s, const double *x, double *y, int nrhs, int64_t ld,
                              Mode mode, int source_split, int rhs_chunk, int tpl, void *ws, hipStream_t st,
@@ -133,7 +142,7 @@ ls_status apply_op(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, 
 ls_status setup_fail(ls_ctx *h, ls_status st, const char *msg);
 // krylov.hip
 ls_status solve_gmres(ls_ctx *h, const double *b, double *x, int nrhs, int64_t ld, const ls_solve_opts &o,
-                      ls_solve_info *info, hipStream_t st);
+                      ls_solve_info *info, hipStream_t st, const PrecondCb *pc = nullptr);
 ls_status grad_contrast(ls_ctx *h, const double *u, const double *lam, const double *a, int nrhs, int64_t ld,
                         double *grad, hipStream_t st);
 void free_solve_ws(ls_ctx *h);
@@ -154,6 +163,12 @@ bool outside_scatterer(const Scat &sc, double x, double y);
 const double *geom_x(const Scat &sc);   // host node positions, internal order (nullptr without geometry)
 const double *geom_y(const Scat &sc);
 int field_source_split(int64_t n, int64_t nt, int nrhs);
+// transfer.hip: c = T_Q^C x, and y = x + T_C^Q (sc - c) (y = x outside scatterer s's segment is
+// the caller's business); x, y [nrhs][ld] caller order, c, sc [nrhs][ldc]
+hipError_t launch_quad_to_cart(const Scat &s, const double2 *x, int64_t ld, double2 *c, int64_t ldc, int nrhs,
+                               hipStream_t st);
+hipError_t launch_precond_finish(const Scat &s, const double2 *x, int64_t ld, const double2 *c, const double2 *sc,
+                                 int64_t ldc, double2 *y, int nrhs, hipStream_t st);
 size_t field_workspace_bytes(int64_t n, int nrhs, int64_t nt, int nsplit);
 hipError_t launch_field(const Scat &s, const double *u, int nrhs, int64_t ld, int64_t nt, const double *tx,
                         const double *ty, const int64_t *rp, const int32_t *ci, const double2 *cv, int nsplit,

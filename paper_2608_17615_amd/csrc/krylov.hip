@@ -423,6 +423,7 @@ struct CoreOpts {
   bool x0_given;
   double relax_eps;      // > 0: FP64 applies while the residual estimate exceeds tol / relax_eps, mixed after
   int progress;          // > 0: print a progress line every this many steps
+  const PrecondCb *pc = nullptr;   // flexible: z_j = P v_j instead of an inner solve
 };
 
 struct CoreResult {
@@ -560,7 +561,22 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
       HIPTRY(grow(j + 2));
       double2 *vj = tbl[j];
       double2 *w = tbl[j + 1];
-      if (o.flexible) {
+      if (o.flexible && o.pc) {
+        // z_j = P v_j = v_j + T_C^Q (S c - c), c = T_Q^C v_j (scatterer pc->s only), then w = L z_j
+        HIPTRY(ensure_chunks(ws->Z, j + 1, n, nrhs));
+        double2 *zj = ws->Z.vec(j, n, nrhs);
+        const PrecondCb &pc = *o.pc;
+        const Scat &scp = h->sc[pc.s];
+        HIPTRY(hipMemcpyAsync(zj, vj, sizeof(double2) * (size_t)n * nrhs, hipMemcpyDeviceToDevice, st));
+        HIPTRY(launch_quad_to_cart(scp, vj, n, pc.c, pc.ldc, nrhs, st));
+        const ls_status sst = pc.S((const double *)pc.c, (double *)pc.sc, nrhs, pc.ldc, pc.user, st);
+        if (sst < 0) return setup_fail(h, sst, "the preconditioner's S failed");
+        HIPTRY(launch_precond_finish(scp, vj, n, pc.c, pc.sc, pc.ldc, zj, nrhs, st));
+        set_skip(act);
+        ls_status s2 = apply_op(h, (const double *)zj, (double *)w, nrhs, n, o.mode, LS_FP64, st);
+        if (s2 != LS_OK) return s2;
+        ++res.n_fp64;
+      } else if (o.flexible) {
         // z_j ~ L^{-1} v_j by an inner GMRES with the mixed-precision operator (active systems
         // only), then w = L z_j
         HIPTRY(ensure_chunks(ws->Z, j + 1, n, nrhs));
@@ -720,7 +736,7 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
 }
 
 ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, int64_t ld, const ls_solve_opts &o,
-                      ls_solve_info *info, hipStream_t st) {
+                      ls_solve_info *info, hipStream_t st, const PrecondCb *pc) {
   const auto t_start = std::chrono::steady_clock::now();
   const int64_t n = h->n_total;
   const Mode mode = o.adjoint ? Mode::Adjoint : Mode::Forward;
@@ -747,13 +763,14 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
   // once the residual is below tol / inner_tol (inner_tol = relative accuracy granted to it,
   // default 1e-4: a later switch than the operator error alone would allow; see ls.h),
   // followed by FP64 refinement passes from the true residual if that missed tol
-  const bool mixed = o.prec == LS_MIXED;
-  const bool flexible = mixed && o.inner_maxit > 0;
+  // with the preconditioner P (pc): FP64 flexible GMRES with z_j = P v_j
+  const bool mixed = o.prec == LS_MIXED && !pc;
+  const bool flexible = (mixed && o.inner_maxit > 0) || pc;
   const double relax = (mixed && !flexible) ? (o.inner_tol > 0 ? o.inner_tol : 1e-4) : 0.0;
   // the relaxed iteration aims its residual estimate below 0.3 tol so that its FP64 residual,
   // perturbed by the mixed applications, still meets tol without a (Krylov-space-losing) restart
   CoreOpts co{relax > 0 ? 0.3 * o.tol : o.tol, o.maxit, o.restart, mode, LS_FP64, flexible,
-              o.inner_tol > 0 ? o.inner_tol : 1e-12, o.inner_maxit, o.x0_given != 0, relax, progress};
+              o.inner_tol > 0 ? o.inner_tol : 1e-12, o.inner_maxit, o.x0_given != 0, relax, progress, pc};
   CoreResult res;
   ls_status status = gmres_core(h, ws, wi, bb, xs, nrhs, co, res, st);
   if (status < 0) return status;

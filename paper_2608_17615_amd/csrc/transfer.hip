@@ -121,6 +121,23 @@ ls_status tfail(ls_ctx *h, ls_status st, const char *msg) { return setup_fail(h,
 
 }  // namespace
 
+hipError_t launch_quad_to_cart(const Scat &sc, const double2 *x, int64_t ld, double2 *c, int64_t ldc, int nrhs,
+                               hipStream_t st) {
+  const TransferData &t = *sc.tr;
+  const int64_t nc = (int64_t)t.nx * t.ny;
+  dim3 grid((unsigned)((nc + kBlock - 1) / kBlock), (unsigned)((nrhs + kCols - 1) / kCols));
+  quad_to_cart_kernel<<<grid, kBlock, 0, st>>>(nc, nrhs, t.rp, t.col, t.val, sc.off, x, ld, c, ldc);
+  return hipGetLastError();
+}
+
+hipError_t launch_precond_finish(const Scat &sc, const double2 *x, int64_t ld, const double2 *c, const double2 *s,
+                                 int64_t ldc, double2 *y, int nrhs, hipStream_t st) {
+  const TransferData &t = *sc.tr;
+  dim3 grid((unsigned)((sc.n + kBlock - 1) / kBlock), (unsigned)((nrhs + kCols - 1) / kCols));
+  cart_to_quad_kernel<<<grid, kBlock, 0, st>>>(sc.n, nrhs, t.nx, t.cell, t.w, sc.perm, sc.off, s, c, ldc, x, y, ld);
+  return hipGetLastError();
+}
+
 }  // namespace lsk
 
 using lsk::Scat;
@@ -234,13 +251,8 @@ ls_status ls_quad_to_cart(ls_handle h, int32_t s, const double *x, int64_t ld, d
   if (st != LS_OK) return st;
   if (nrhs == 0) return LS_OK;
   if (!x || !c) return lsk::tfail(h, LS_ERR_ARG, "null vector");
-  const Scat &sc = h->sc[s];
-  const TransferData &t = *sc.tr;
-  const int64_t nc = (int64_t)t.nx * t.ny;
-  dim3 grid((unsigned)((nc + lsk::kBlock - 1) / lsk::kBlock), (unsigned)((nrhs + lsk::kCols - 1) / lsk::kCols));
-  lsk::quad_to_cart_kernel<<<grid, lsk::kBlock, 0, stream>>>(nc, nrhs, t.rp, t.col, t.val, sc.off,
-                                                             (const double2 *)x, ld, (double2 *)c, ldc);
-  if (hipGetLastError() != hipSuccess) return lsk::tfail(h, LS_ERR_HIP, "quad_to_cart launch");
+  if (lsk::launch_quad_to_cart(h->sc[s], (const double2 *)x, ld, (double2 *)c, ldc, nrhs, stream) != hipSuccess)
+    return lsk::tfail(h, LS_ERR_HIP, "quad_to_cart launch");
   return LS_OK;
 }
 
@@ -266,13 +278,9 @@ ls_status ls_precond_finish(ls_handle h, int32_t s, const double *x, int64_t ld,
   if (st != LS_OK) return st;
   if (nrhs == 0) return LS_OK;
   if (!x || !c || !sc_ || !y) return lsk::tfail(h, LS_ERR_ARG, "null vector");
-  const Scat &sc = h->sc[s];
-  const TransferData &t = *sc.tr;
-  dim3 grid((unsigned)((sc.n + lsk::kBlock - 1) / lsk::kBlock), (unsigned)((nrhs + lsk::kCols - 1) / lsk::kCols));
-  lsk::cart_to_quad_kernel<<<grid, lsk::kBlock, 0, stream>>>(sc.n, nrhs, t.nx, t.cell, t.w, sc.perm, sc.off,
-                                                             (const double2 *)sc_, (const double2 *)c, ldc,
-                                                             (const double2 *)x, (double2 *)y, ld);
-  if (hipGetLastError() != hipSuccess) return lsk::tfail(h, LS_ERR_HIP, "precond_finish launch");
+  if (lsk::launch_precond_finish(h->sc[s], (const double2 *)x, ld, (const double2 *)c, (const double2 *)sc_, ldc,
+                                 (double2 *)y, nrhs, stream) != hipSuccess)
+    return lsk::tfail(h, LS_ERR_HIP, "precond_finish launch");
   return LS_OK;
 }
 

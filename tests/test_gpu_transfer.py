@@ -1,5 +1,7 @@
 """Transfer operators and the preconditioner wrapper (Section 4) against the oracle's dense
 matrices, and their defining properties at full size."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -113,3 +115,38 @@ def test_full_size_properties_and_rate():
           f"constants {e_one:.1e} on {int(hit.sum())} pixelation nodes, P(S=I) {e_id:.1e}; "
           f"T_Q^C {t_qc:.3f} ms (~{gb_qc:.0f} GB/s of vectors), T_C^Q {t_cq:.3f} ms (incl. zero fill)", flush=True)
     assert e_bil <= 1e-13 and e_one <= 1e-14 and e_id == 0.0
+
+
+def test_preconditioned_gmres():
+    """S = I makes P = I: the preconditioned solve is plain GMRES, step for step.  With S = 1.5 I
+    or a dense perturbation of the identity, P is another nonsingular right preconditioner and the
+    solution is unchanged (checked against dense LU)."""
+    from tests.gpu_cases import golden_problem, load_case, scatterer
+    p = golden_problem("disk2500")
+    c = load_case("disk2500")
+    op = lsg.Operator(scatterer(p), correction=(c["rowptr"], c["col"], c["val"]))
+    g = _grid_over(p, 0.1)
+    op.set_grid(g.x0, g.y0, g.h, g.nx, g.ny)
+    b = torch.tensor(c["b"], device="cuda")
+    x0, i0 = op.solve(b, tol=1e-12, maxit=400)
+    x1, i1 = op.solve_precond(b, lambda v: v, tol=1e-12, maxit=400)
+    assert i1["converged"] and int(i1["iters"][0]) == int(i0["iters"][0])
+    assert relmax(x1.cpu().numpy(), x0.cpu().numpy()) <= 1e-14
+    x2, i2 = op.solve_precond(b, lambda v: 1.5 * v, tol=1e-12, maxit=400)
+    rng = np.random.default_rng(9)
+    Sm = torch.tensor((np.eye(g.n) + 0.2 * rng.standard_normal((g.n, g.n)) / np.sqrt(g.n)).T.copy(),
+                      dtype=torch.complex128, device="cuda")
+    x3, i3 = op.solve_precond(b, lambda v: v @ Sm, tol=1e-12, maxit=400)
+    e2, e3 = relmax(x2.cpu().numpy(), c["u"]), relmax(x3.cpu().numpy(), c["u"])
+    print(f"preconditioned GMRES: S = I {i1['iters'][0]} steps (plain {i0['iters'][0]}), S = 1.5 I "
+          f"{i2['iters'][0]} steps, {e2:.1e} vs LU; dense S {i3['iters'][0]} steps, {e3:.1e}", flush=True)
+    assert i2["converged"] and i3["converged"] and e2 <= 1e-10 and e3 <= 1e-10
+    with pytest.raises(ValueError):
+        op.solve_precond(b, lambda v: v[:, :3], tol=1e-12, maxit=10)
+    with pytest.raises(lsg.LSError):                     # FP64 only
+        o = lsg._SolveOpts(1e-8, 10, 0, lsg.MIXED, 0, 0, 0, 0.0)
+        cc = torch.empty((1, g.n), dtype=torch.complex128, device="cuda")
+        st = lsg.lib().ls_solve_gmres_precond(op._h, b.data_ptr(), x0.data_ptr(), 1, op.n, ctypes.byref(o), 0,
+                                              lsg._GridOp(lambda *a: 0), None, cc.data_ptr(), cc.data_ptr(),
+                                              g.n, None, lsg._stream())
+        lsg._check(st, op._h)
