@@ -150,3 +150,36 @@ def test_preconditioned_gmres():
                                               lsg._GridOp(lambda *a: 0), None, cc.data_ptr(), cc.data_ptr(),
                                               g.n, None, lsg._stream())
         lsg._check(st, op._h)
+
+
+def _crude_cartesian_inverse(g, k, m_inside):
+    """Dense inverse of a first-order Cartesian discretization of L on the grid (the caller's S,
+    built here on the CPU): off-diagonal h^2 G(z_i, z_j), the cell's own term integrated over the
+    disk of the cell's area, contrast m_inside at nodes inside the unit circle."""
+    from scipy.special import hankel1
+    zx, zy = g.nodes()
+    d = np.hypot(zx[:, None] - zx[None, :], zy[:, None] - zy[None, :])
+    np.fill_diagonal(d, 1.0)
+    V = g.h ** 2 * 0.25j * hankel1(0, k * d)
+    a = g.h / np.sqrt(np.pi)
+    np.fill_diagonal(V, (-1 + 0.5j * np.pi * a * k * hankel1(1, k * a)) / k ** 2)
+    m = np.where(np.hypot(zx, zy) < 1.0, m_inside, 0.0)
+    return np.linalg.inv(np.eye(g.n) + k * k * V * m[None, :])
+
+
+@pytest.mark.parametrize("k,n", [(2 * np.pi, 5), (10.0, 6)])
+def test_cartesian_preconditioner_cuts_iterations(k, n):
+    """With S the inverse of even a first-order Cartesian discretization (k h = 0.31-0.5), P cuts
+    the GMRES steps to 1e-8 several times over and the solution is the unpreconditioned one."""
+    prob = P.disk_problem(n, k, 2.0)
+    op = lsg.Operator(lsg.Scatterer.from_mesh(prob.mesh, prob.m, prob.k))
+    g = _grid_over(prob, 0.05)
+    op.set_grid(g.x0, g.y0, g.h, g.nx, g.ny)
+    S = torch.tensor(_crude_cartesian_inverse(g, k, float(np.real(prob.m[0]))).T.copy(), device="cuda")
+    b = torch.tensor(prob.incident(), device="cuda")
+    x0, i0 = op.solve(b, tol=1e-8, maxit=1000)
+    x1, i1 = op.solve_precond(b, lambda v: v @ S, tol=1e-8, maxit=1000)
+    e = relmax(x1.cpu().numpy(), x0.cpu().numpy())
+    print(f"k={k:.2f} N={prob.n_nodes}, grid {g.nx}x{g.ny}: GMRES {i0['iters'][0]} steps, with P "
+          f"{i1['iters'][0]} steps, solutions differ by {e:.1e}", flush=True)
+    assert i1["converged"] and int(i1["iters"][0]) * 4 <= int(i0["iters"][0]) and e <= 1e-7
