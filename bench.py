@@ -242,6 +242,15 @@ def solve_form(op, b, form, args, adjoint=False):
                 applies += int(info["n_apply_fp64"])
                 log(f"  column {c}: {its[-1]} iterations, relres {info['relres'][0]:.2e}, {info['seconds']:.2f} s")
         return torch.cat(xs), t.seconds, applies, 0, t, its, cols
+    if form == "pc":
+        ST = args._cartesian_S
+        with Timer(op) as t:
+            x, info = op.solve_precond(b, lambda v: v @ ST, tol=args.tol, maxit=args.maxit, restart=args.restart,
+                                       adjoint=adjoint)
+        its = [int(v) for v in info["iters"]]
+        log(f"  preconditioned: max {max(its)} iterations, max relres {np.max(info['relres']):.2e}, "
+            f"{info['seconds']:.2f} s")
+        return x, t.seconds, int(info["n_apply_fp64"]), 0, t, its, B
     prec = "mixed" if form == "bm" else "fp64"
     batch = args.batch or B
     xs, its, a64, amx = [], [], 0, 0
@@ -260,6 +269,49 @@ def solve_form(op, b, form, args, adjoint=False):
     return torch.cat(xs), t.seconds, a64, amx, t, its, B
 
 
+def cartesian_inverse(op, prob, kh):
+    """The caller's S for the preconditioned form: the dense inverse of a first-order Cartesian
+    discretization of L for a constant-contrast disk (off-diagonal h^2 G(z_i, z_j) from the
+    library's own Green's evaluation, the cell's own term integrated over the disk of the cell's
+    area, contrast at grid nodes inside the disk) on a grid of spacing kh / k, inverted by host
+    LAPACK.  A stand-in for the sparsifying preconditioner, which is not built.  Registers the grid
+    with the operator and returns (S^T on the device, grid size, seconds)."""
+    import math
+
+    import numpy as np
+    import torch
+    from scipy.special import hankel1
+
+    import paper_2608_17615_amd as lsg
+    t0 = time.perf_counter()
+    k, h, pad = prob.k, kh / prob.k, 0.02
+    x, y = prob.mesh.x, prob.mesh.y
+    x0, y0 = x.min() - pad, y.min() - pad
+    nx = int(math.ceil((x.max() + pad - x0) / h)) + 1
+    ny = int(math.ceil((y.max() + pad - y0) / h)) + 1
+    iy, ix = np.divmod(np.arange(nx * ny), nx)
+    zx = torch.tensor(x0 + ix * h, device="cuda")
+    zy = torch.tensor(y0 + iy * h, device="cuda")
+    z2 = (k * k) * ((zx[:, None] - zx[None, :]) ** 2 + (zy[:, None] - zy[None, :]) ** 2)
+    z2.fill_diagonal_(1.0)
+    L = lsg.eval_green(z2)
+    del z2
+    a = h / math.sqrt(math.pi)
+    L.mul_(h * h)
+    L.diagonal().fill_((-1 + 0.5j * math.pi * a * k * complex(hankel1(1, k * a))) / k ** 2)
+    radius = float(np.hypot(x, y).max())
+    m = torch.where(torch.hypot(zx, zy) < radius, complex(prob.m[0]), 0.0).to(torch.complex128)
+    L.mul_((k * k) * m[None, :])
+    L.diagonal().add_(1.0)
+    Lh = L.cpu().numpy()
+    del L
+    torch.cuda.empty_cache()
+    ST = torch.tensor(np.linalg.inv(Lh).T.copy(), device="cuda")
+    op.set_grid(x0, y0, h, nx, ny)
+    torch.cuda.synchronize()
+    return ST, nx * ny, time.perf_counter() - t0
+
+
 def run_batched(args, probs, label, B):
     """c3 / c4: solve L u = b for B plane waves per scatterer with one form."""
     import numpy as np
@@ -276,6 +328,13 @@ def run_batched(args, probs, label, B):
     n = op.n
     b = torch.tensor(np.concatenate([p.incident() for p in probs], axis=1), device="cuda")
     tune = None
+    pre = None
+    if form == "pc":
+        if len(probs) != 1 or np.abs(probs[0].m - probs[0].m[0]).max() != 0:
+            raise SystemExit("--form pc needs one constant-contrast disk (the c3 workload)")
+        args._cartesian_S, nc, pre_s = cartesian_inverse(op, probs[0], args.kh)
+        pre = {"k_h": args.kh, "grid_nodes": nc, "build_s": pre_s}
+        log(f"Cartesian S: {nc} grid nodes, built in {pre_s:.1f} s")
     if form == "bm" and len(probs) > 1:
         tune = op.autotune(B, precision="mixed")
         log(f"autotune: {tune}")
@@ -311,7 +370,7 @@ def run_batched(args, probs, label, B):
            "iterations_max": int(max(its)), "iterations_mean": float(np.mean(its)),
            "applies_fp64": a64, "applies_mixed": amx, "final_fp64_relres_max": float(relres.max()),
            "setup_s": setup_s, "far_kernel_ms_avg": t.far_avg_s * 1e3, "z_range_fractions": frac,
-           "autotune": tune, "error_vs_fp64_column0": check}
+           "autotune": tune, "error_vs_fp64_column0": check, "preconditioner": pre}
     return line(value, total_s * 1e3, 1, 0, dtype, cfg, roof, None), x
 
 
@@ -423,7 +482,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "field"])
     ap.add_argument("--grid", type=int, default=256, help="field: points per side of the Cartesian grid")
-    ap.add_argument("--form", default=None, choices=["p64", "b64", "bm"])
+    ap.add_argument("--form", default=None, choices=["p64", "b64", "bm", "pc"],
+                    help="pc: FP64 GMRES right-preconditioned by P = I + T_C^Q (S - I) T_Q^C with a dense "
+                         "first-order Cartesian inverse as S (c3 only)")
+    ap.add_argument("--kh", type=float, default=0.8, help="pc: k times the Cartesian grid spacing")
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-8)
