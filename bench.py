@@ -243,7 +243,8 @@ def solve_form(op, b, form, args, adjoint=False):
                 log(f"  column {c}: {its[-1]} iterations, relres {info['relres'][0]:.2e}, {info['seconds']:.2f} s")
         return torch.cat(xs), t.seconds, applies, 0, t, its, cols
     if form == "pc":
-        ST = args._cartesian_S
+        # the adjoint system L^H takes S^H, the inverse of the Cartesian L^H
+        ST = args._cartesian_S.conj() if adjoint else args._cartesian_S
         with Timer(op) as t:
             x, info = op.solve_precond(b, lambda v: v @ ST, tol=args.tol, maxit=args.maxit, restart=args.restart,
                                        adjoint=adjoint)
@@ -271,10 +272,9 @@ def solve_form(op, b, form, args, adjoint=False):
 
 def cartesian_inverse(op, prob, kh):
     """The caller's S for the preconditioned form: the dense inverse of a first-order Cartesian
-    discretization of L for a constant-contrast disk (off-diagonal h^2 G(z_i, z_j) from the
-    library's own Green's evaluation, the cell's own term integrated over the disk of the cell's
-    area, contrast at grid nodes inside the disk) on a grid of spacing kh / k, inverted by host
-    LAPACK.  A stand-in for the sparsifying preconditioner, which is not built.  Registers the grid
+    discretization of L (off-diagonal h^2 G(z_i, z_j) from the library's own Green's evaluation,
+    the cell's own term integrated over the disk of the cell's area, the medium's contrast at the
+    grid nodes) on a grid of spacing kh / k, inverted by host LAPACK.  A stand-in for the sparsifying preconditioner, which is not built.  Registers the grid
     with the operator and returns (S^T on the device, grid size, seconds)."""
     import math
 
@@ -299,8 +299,7 @@ def cartesian_inverse(op, prob, kh):
     a = h / math.sqrt(math.pi)
     L.mul_(h * h)
     L.diagonal().fill_((-1 + 0.5j * math.pi * a * k * complex(hankel1(1, k * a))) / k ** 2)
-    radius = float(np.hypot(x, y).max())
-    m = torch.where(torch.hypot(zx, zy) < radius, complex(prob.m[0]), 0.0).to(torch.complex128)
+    m = torch.tensor(np.asarray(prob.m_at(x0 + ix * h, y0 + iy * h), dtype=np.complex128), device="cuda")
     L.mul_((k * k) * m[None, :])
     L.diagonal().add_(1.0)
     Lh = L.cpu().numpy()
@@ -330,8 +329,8 @@ def run_batched(args, probs, label, B):
     tune = None
     pre = None
     if form == "pc":
-        if len(probs) != 1 or np.abs(probs[0].m - probs[0].m[0]).max() != 0:
-            raise SystemExit("--form pc needs one constant-contrast disk (the c3 workload)")
+        if len(probs) != 1 or probs[0].m_at is None:
+            raise SystemExit("--form pc needs one scatterer whose contrast is known off the nodes")
         args._cartesian_S, nc, pre_s = cartesian_inverse(op, probs[0], args.kh)
         pre = {"k_h": args.kh, "grid_nodes": nc, "build_s": pre_s}
         log(f"Cartesian S: {nc} grid nodes, built in {pre_s:.1f} s")
@@ -389,6 +388,13 @@ def run_gradient(args, prob, label, B):
     n = op.n
     b = torch.tensor(prob.incident(), device="cuda")
     thetas = P.receivers(128)
+    pre = None
+    if form == "pc":
+        if prob.m_at is None:
+            raise SystemExit("--form pc needs a scatterer whose contrast is known off the nodes")
+        args._cartesian_S, nc, pre_s = cartesian_inverse(op, prob, args.kh)
+        pre = {"k_h": args.kh, "grid_nodes": nc, "build_s": pre_s}
+        log(f"Cartesian S: {nc} grid nodes, built in {pre_s:.1f} s")
     # synthetic data: far field of the seeded contrast perturbation (input generation, untimed)
     m0 = torch.tensor(prob.m, device="cuda").to(torch.complex128)
     dm = torch.tensor(P.contrast_perturbation(prob.mesh), device="cuda").to(torch.complex128)
@@ -435,7 +441,7 @@ def run_gradient(args, prob, label, B):
            "forward_s": fwd[1], "adjoint_s": adj[1], "iterations_forward_max": int(max(fwd[5])),
            "iterations_adjoint_max": int(max(adj[5])), "misfit_J": J,
            "grad_norm": float(torch.linalg.norm(g).item()), "setup_s": setup_s, "z_range_fractions": frac,
-           "error_vs_fp64": check}
+           "error_vs_fp64": check, "preconditioner": pre}
     return line(value, total_s * 1e3, 1, 0, dtype, cfg, roof, None), g
 
 
@@ -484,7 +490,7 @@ def main():
     ap.add_argument("--grid", type=int, default=256, help="field: points per side of the Cartesian grid")
     ap.add_argument("--form", default=None, choices=["p64", "b64", "bm", "pc"],
                     help="pc: FP64 GMRES right-preconditioned by P = I + T_C^Q (S - I) T_Q^C with a dense "
-                         "first-order Cartesian inverse as S (c3 only)")
+                         "first-order Cartesian inverse as S (c3, c5)")
     ap.add_argument("--kh", type=float, default=0.8, help="pc: k times the Cartesian grid spacing")
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)

@@ -19,6 +19,7 @@ class Problem:
     m: np.ndarray                   # contrast 1 - n at the nodes (complex128 or float64)
     name: str = ''
     directions: np.ndarray = field(default_factory=lambda: np.zeros(1))   # incidence angles
+    m_at: object = None             # contrast at arbitrary points (x, y) -> m, 0 outside; None if unknown
 
     @property
     def n_nodes(self):
@@ -49,8 +50,9 @@ def const(v):
 
 def disk_problem(n, k, index=2.0, R=1.0, directions=(0.0,), name='disk'):
     msh = _mesh.ogrid_disk(n, R)
+    m_at = lambda x, y: np.where(np.hypot(x, y) < R, 1.0 - index, 0.0)
     return Problem(msh, k, contrast_from_index(msh, [const(index)]), name,
-                   np.asarray(directions, dtype=np.float64))
+                   np.asarray(directions, dtype=np.float64), m_at)
 
 
 def two_layer_constant(n_i, k, n_in, n_out, directions=(0.0,)):
@@ -63,8 +65,13 @@ def two_layer_constant(n_i, k, n_in, n_out, directions=(0.0,)):
 def graded_two_material(n_i, k, directions=(0.0,)):
     """Inclusion |x| < 0.5 with n = 3; annulus 0.5 < |x| < 1 with n = 1 + 0.5 exp(-|x|^2)."""
     msh = _mesh.two_material_disk(n_i)
-    m = contrast_from_index(msh, [const(3.0), lambda x, y: 1.0 + 0.5 * np.exp(-(x * x + y * y))])
-    return Problem(msh, k, m, 'two-material', np.asarray(directions, dtype=np.float64))
+    graded = lambda x, y: 1.0 + 0.5 * np.exp(-(x * x + y * y))
+    m = contrast_from_index(msh, [const(3.0), graded])
+
+    def m_at(x, y):
+        r = np.hypot(x, y)
+        return np.where(r < 0.5, 1.0 - 3.0, np.where(r < 1.0, 1.0 - graded(x, y), 0.0))
+    return Problem(msh, k, m, 'two-material', np.asarray(directions, dtype=np.float64), m_at)
 
 
 def even_directions(B):
