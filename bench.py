@@ -243,8 +243,13 @@ def solve_form(op, b, form, args, adjoint=False):
                 log(f"  column {c}: {its[-1]} iterations, relres {info['relres'][0]:.2e}, {info['seconds']:.2f} s")
         return torch.cat(xs), t.seconds, applies, 0, t, its, cols
     if form == "pc":
-        # the adjoint system L^H takes S^H, the inverse of the Cartesian L^H
-        ST = args._cartesian_S.conj() if adjoint else args._cartesian_S
+        ST = args._cartesian_S
+        if adjoint:
+            # the adjoint system takes P^H = I + T_C^Q (D^-1 S^H D - I) T_Q^C (D: ls_transfer_colsums)
+            if getattr(args, "_cartesian_S_adj", None) is None:
+                d = torch.tensor(op.transfer_colsums(), device="cuda")
+                args._cartesian_S_adj = (d[:, None] * ST.conj().T / d[None, :]).contiguous()
+            ST = args._cartesian_S_adj
         with Timer(op) as t:
             x, info = op.solve_precond(b, lambda v: v @ ST, tol=args.tol, maxit=args.maxit, restart=args.restart,
                                        adjoint=adjoint)

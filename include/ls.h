@@ -230,6 +230,10 @@ typedef struct {
  * j with a positive weight) for scatterer s, replacing an earlier grid.  Every node must lie in
  * [x0, x0 + (nx-1) h] x [y0, y0 + (ny-1) h], else LS_ERR_ARG.  Synchronous. */
 ls_status ls_transfer_setup(ls_handle h, int32_t s, const ls_grid *g);
+/* D of eq. D_def for scatterer s's grid: d[j] = column sum of T_C^Q (1 where it is zero), nx ny
+ * doubles written to host memory.  With it, P^H = I + T_C^Q (D^-1 S^H D - I) T_Q^C, the right
+ * preconditioner for the adjoint system when P is the one for L. */
+ls_status ls_transfer_colsums(ls_handle h, int32_t s, double *d);
 /* c = T_Q^C x (grid values from scatterer s's node values). */
 ls_status ls_quad_to_cart(ls_handle h, int32_t s, const double *x, int64_t ld, double *c, int64_t ldc,
                           int32_t nrhs, hipStream_t stream);

@@ -101,6 +101,7 @@ def lib():
         L.ls_set_contrast.argtypes = [vp, vp, vp]
         L.ls_transfer_setup.argtypes = [vp, i32, vp]
         L.ls_quad_to_cart.argtypes = [vp, i32, vp, i64, vp, i64, i32, vp]
+        L.ls_transfer_colsums.argtypes = [vp, i32, vp]
         L.ls_cart_to_quad.argtypes = [vp, i32, vp, i64, vp, i64, i32, vp]
         L.ls_precond_finish.argtypes = [vp, i32, vp, i64, vp, vp, i64, vp, i32, vp]
         L.ls_solve_gmres_precond.argtypes = [vp, vp, vp, i32, i64, vp, i32, _GridOp, vp, vp, vp, i64, vp, vp]
@@ -327,6 +328,12 @@ class Operator:
         if n is None:
             raise LSError(LS_ERR_ARG, "no grid for this scatterer (set_grid)")
         return n
+
+    def transfer_colsums(self, s=0):
+        """D of eq. D_def (column sums of T_C^Q, 1 where zero) for scatterer s's grid, host array."""
+        d = np.empty(self._grid_n(s), dtype=np.float64)
+        _check(lib().ls_transfer_colsums(self._h, s, d.ctypes.data), self._h)
+        return d
 
     def quad_to_cart(self, x, s=0):
         """T_Q^C x: grid values (B, nx ny) from the node values of scatterer s in x (B, N)."""

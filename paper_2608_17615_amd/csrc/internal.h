@@ -33,6 +33,7 @@ struct TransferData {
   int32_t *col = nullptr;           // caller index of the node within the scatterer
   double *val = nullptr;
   std::vector<void *> bufs;         // the allocations above
+  std::vector<double> colsum;       // D: column sums of T_C^Q per grid node (1 where zero), host
 };
 
 // One scatterer, all device arrays in the internal (sorted) node order.

@@ -199,10 +199,12 @@ ls_status ls_transfer_setup(ls_handle h, int32_t s, const ls_grid *g) {
       val[e] = wv[v];
     }
   }
+  std::vector<double> colsum(nc);
   for (int64_t j = 0; j < nc; ++j) {
     double d = 0.0;
     for (int64_t e = rp[j]; e < rp[j + 1]; ++e) d += val[e];
     const double dj = d > 0 ? d : 1.0;   // D_jj = 1 where no node reaches j with a positive weight
+    colsum[j] = dj;
     for (int64_t e = rp[j]; e < rp[j + 1]; ++e) val[e] /= dj;
   }
   // replace an earlier grid of this scatterer
@@ -212,6 +214,7 @@ ls_status ls_transfer_setup(ls_handle h, int32_t s, const ls_grid *g) {
   t->h = g->h;
   t->nx = g->nx;
   t->ny = g->ny;
+  t->colsum = std::move(colsum);
   auto up = [&](void **dst, const void *src, size_t bytes) -> bool {
     if (hipMalloc(dst, std::max<size_t>(bytes, 16)) != hipSuccess) return false;
     t->bufs.push_back(*dst);
@@ -242,6 +245,16 @@ static ls_status transfer_args(ls_handle h, int32_t s, int64_t ld, int64_t ldc, 
   if (ld < h->n_total) return lsk::tfail(h, LS_ERR_ARG, "ld < number of nodes");
   const TransferData &t = *h->sc[s].tr;
   if (ldc < (int64_t)t.nx * t.ny) return lsk::tfail(h, LS_ERR_ARG, "ldc < number of grid nodes");
+  return LS_OK;
+}
+
+ls_status ls_transfer_colsums(ls_handle h, int32_t s, double *d) {
+  if (!h) return lsk::setup_fail(nullptr, LS_ERR_ARG, "null handle");
+  if (s < 0 || s >= (int32_t)h->sc.size()) return lsk::tfail(h, LS_ERR_ARG, "bad scatterer index");
+  if (!h->sc[s].tr) return lsk::tfail(h, LS_ERR_ARG, "no grid for this scatterer (ls_transfer_setup)");
+  if (!d) return lsk::tfail(h, LS_ERR_ARG, "null output");
+  const std::vector<double> &cs = h->sc[s].tr->colsum;
+  std::copy(cs.begin(), cs.end(), d);
   return LS_OK;
 }
 

@@ -180,6 +180,14 @@ def test_cartesian_preconditioner_cuts_iterations(k, n):
     x0, i0 = op.solve(b, tol=1e-8, maxit=1000)
     x1, i1 = op.solve_precond(b, lambda v: v @ S, tol=1e-8, maxit=1000)
     e = relmax(x1.cpu().numpy(), x0.cpu().numpy())
+    # the adjoint system with P^H = I + T_C^Q (D^-1 S^H D - I) T_Q^C
+    d = torch.tensor(op.transfer_colsums(), device="cuda")
+    SaT = (d[:, None] * S.conj().T / d[None, :]).contiguous()
+    xa0, ia0 = op.solve(b, tol=1e-8, maxit=1000, adjoint=True)
+    xa1, ia1 = op.solve_precond(b, lambda v: v @ SaT, tol=1e-8, maxit=1000, adjoint=True)
+    ea = relmax(xa1.cpu().numpy(), xa0.cpu().numpy())
     print(f"k={k:.2f} N={prob.n_nodes}, grid {g.nx}x{g.ny}: GMRES {i0['iters'][0]} steps, with P "
-          f"{i1['iters'][0]} steps, solutions differ by {e:.1e}", flush=True)
+          f"{i1['iters'][0]} steps ({e:.1e}); adjoint {ia0['iters'][0]} steps, with P^H {ia1['iters'][0]} "
+          f"steps ({ea:.1e})", flush=True)
     assert i1["converged"] and int(i1["iters"][0]) * 4 <= int(i0["iters"][0]) and e <= 1e-7
+    assert ia1["converged"] and int(ia1["iters"][0]) * 4 <= int(ia0["iters"][0]) and ea <= 1e-7
