@@ -81,3 +81,16 @@ def precondition(T, x, S):
     vectors of the same leading shape."""
     c = np.asarray(x) @ quad_to_cart(T).T
     return np.asarray(x) + (S(c) - c) @ T.T
+
+
+def column_sums(T):
+    """D of eq. D_def: column sums of T_C^Q, 1 where a column sums to zero."""
+    d = T.sum(axis=0)
+    return np.where(d > 0, d, 1.0)
+
+
+def precondition_adjoint(T, x, SH):
+    """P^H x for P of precondition(): since T_C^Q is real and T_Q^C = D^-1 (T_C^Q)^T,
+    P^H = I + T_C^Q (D^-1 S^H D - I) T_Q^C, where SH applies S^H to grid vectors."""
+    d = column_sums(T)
+    return precondition(T, x, lambda c: SH(c * d) / d)

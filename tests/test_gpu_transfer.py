@@ -46,8 +46,10 @@ def test_transfer_operators_match_oracle(name, h):
     St = torch.tensor(Sm.T.copy(), device="cuda")
     got_p = op.precondition(torch.tensor(x, device="cuda"), lambda v: v @ St).cpu().numpy()
     e3 = relmax(got_p, tr.precondition(T, x, lambda v: v @ Sm.T))
-    print(f"{name} N={prob.n_nodes}, grid {g.nx}x{g.ny}: T_Q^C {e1:.1e}, T_C^Q {e2:.1e}, P {e3:.1e}", flush=True)
-    assert e1 <= 1e-14 and e2 <= 1e-14 and e3 <= 1e-13
+    e4 = relmax(op.transfer_colsums(), tr.column_sums(T))
+    print(f"{name} N={prob.n_nodes}, grid {g.nx}x{g.ny}: T_Q^C {e1:.1e}, T_C^Q {e2:.1e}, P {e3:.1e}, D {e4:.1e}",
+          flush=True)
+    assert e1 <= 1e-14 and e2 <= 1e-14 and e3 <= 1e-13 and e4 <= 1e-14
 
 
 def test_second_scatterer_segment_and_errors():

@@ -76,6 +76,22 @@ def test_preconditioner_forms_agree():
     assert np.abs(tr.precondition(T, v, lambda c: c) - v).max() < 1e-14
 
 
+def test_adjoint_preconditioner_is_the_adjoint():
+    """<P x, y> = <x, P^H y> for the factored form of P^H (and D is the column sums of T_C^Q)."""
+    x, y, g, T = _setup()
+    rng = np.random.default_rng(4)
+    Sm = np.eye(g.n) + 0.1 * (rng.standard_normal((g.n, g.n)) + 1j * rng.standard_normal((g.n, g.n)))
+    u = rng.standard_normal(len(x)) + 1j * rng.standard_normal(len(x))
+    v = rng.standard_normal(len(x)) + 1j * rng.standard_normal(len(x))
+    Pu = tr.precondition(T, u, lambda c: c @ Sm.T)
+    PHv = tr.precondition_adjoint(T, v, lambda c: c @ Sm.conj())
+    assert abs(np.vdot(v, Pu) - np.vdot(PHv, u)) <= 1e-12 * np.linalg.norm(u) * np.linalg.norm(v) * 10
+    P = np.stack([tr.precondition(T, e, lambda c: c @ Sm.T) for e in np.eye(len(x))], axis=1)
+    PH = np.stack([tr.precondition_adjoint(T, e, lambda c: c @ Sm.conj()) for e in np.eye(len(x))], axis=1)
+    assert np.abs(PH - P.conj().T).max() < 1e-12
+    assert np.array_equal(tr.column_sums(T)[tr.pixelation(T)], T.sum(axis=0)[tr.pixelation(T)])
+
+
 def test_nodes_outside_the_grid_are_rejected():
     x, y, g, _ = _setup()
     with pytest.raises(ValueError):
