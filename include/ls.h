@@ -252,12 +252,14 @@ ls_status ls_precond_finish(ls_handle h, int32_t s, const double *x, int64_t ld,
 typedef ls_status (*ls_grid_op)(const double *c, double *sc, int32_t nrhs, int64_t ldc, void *user,
                                 hipStream_t stream);
 
-/* FP64 GMRES with the right preconditioner P = I + T_C^Q (S - I) T_Q^C of scatterer s (eq.
+/* GMRES with the right preconditioner P = I + T_C^Q (S - I) T_Q^C of scatterer s (eq.
  * preconditioner_factored; ls_transfer_setup first): flexible GMRES with z_j = P v_j, so S may be
  * inexact or change between calls; the other scatterers' segments are not preconditioned.  c and sc
  * are the caller's grid workspaces [nrhs][ldc] (device, ldc >= nx ny): the library writes T_Q^C v_j
- * into c and calls S(c, sc, ...) once per step.  o->prec must be LS_FP64; the inner fields are
- * ignored; everything else is as for ls_solve_gmres. */
+ * into c and calls S(c, sc, ...) once per step.  With o->prec = LS_MIXED the operator
+ * applications switch to the mixed precision once the residual allows it, as in relaxed GMRES
+ * (o->inner_tol is the granted accuracy, default 1e-4), followed by FP64 refinement; o->inner_maxit
+ * is ignored.  Everything else is as for ls_solve_gmres. */
 ls_status ls_solve_gmres_precond(ls_handle h, const double *b, double *x, int32_t nrhs, int64_t ld,
                                  const ls_solve_opts *o, int32_t s, ls_grid_op S, void *user, double *c, double *sc,
                                  int64_t ldc, ls_solve_info *info, hipStream_t stream);

@@ -372,9 +372,11 @@ class Operator:
                                        y.data_ptr(), x2.shape[0], _stream()), self._h)
         return y.reshape(x.shape)
 
-    def solve_precond(self, b, S, s=0, tol=1e-8, maxit=1000, restart=0, adjoint=False):
-        """FP64 GMRES preconditioned on the right by P = I + T_C^Q (S - I) T_Q^C of scatterer s
-        (set_grid first); S is a callable on (B, nx ny) CUDA tensors.  Returns (x, info)."""
+    def solve_precond(self, b, S, s=0, tol=1e-8, maxit=1000, restart=0, adjoint=False, precision="fp64",
+                      inner_tol=0.0):
+        """GMRES preconditioned on the right by P = I + T_C^Q (S - I) T_Q^C of scatterer s
+        (set_grid first); S is a callable on (B, nx ny) CUDA tensors.  precision="mixed" relaxes the
+        operator applications to the FP32 tiles late in the iteration.  Returns (x, info)."""
         import torch
         b2 = self._cols(b)
         B = b2.shape[0]
@@ -398,7 +400,8 @@ class Operator:
         x = torch.zeros_like(b2)
         iters = np.zeros(B, dtype=np.int32)
         relres = np.zeros(B, dtype=np.float64)
-        o = _SolveOpts(float(tol), int(maxit), int(restart), FP64, int(bool(adjoint)), 0, 0, 0.0)
+        o = _SolveOpts(float(tol), int(maxit), int(restart), _PREC[precision], int(bool(adjoint)), 0, 0,
+                       float(inner_tol))
         info = _SolveInfo(iters.ctypes.data, relres.ctypes.data, 0, 0, 0.0, 0)
         st = lib().ls_solve_gmres_precond(self._h, b2.data_ptr(), x.data_ptr(), B, self.n, ctypes.byref(o), s, fn,
                                           None, c.data_ptr(), sc.data_ptr(), nc, ctypes.byref(info), _stream())
@@ -406,7 +409,8 @@ class Operator:
             raise failed[0]
         _check(st, self._h)
         return x.reshape(b.shape), {"converged": st == LS_OK, "iters": iters, "relres": relres,
-                                    "n_apply_fp64": info.n_apply_fp64, "seconds": info.seconds}
+                                    "n_apply_fp64": info.n_apply_fp64, "n_apply_mixed": info.n_apply_mixed,
+                                    "seconds": info.seconds}
 
     def farfield_adjoint(self, res, thetas, s=0):
         """(a, rhs) with a = A^H res and rhs = conj(m) a on scatterer s (zero elsewhere)."""

@@ -452,7 +452,7 @@ ls_status ls_solve_gmres_precond(ls_handle h, const double *b, double *x, int32_
   if (!(o->tol > 0) || !std::isfinite(o->tol)) return fail(h, LS_ERR_ARG, "tol must be > 0");
   if (o->maxit < 1) return fail(h, LS_ERR_ARG, "maxit must be >= 1");
   if (o->restart < 0) return fail(h, LS_ERR_ARG, "restart < 0");
-  if (o->prec != LS_FP64) return fail(h, LS_ERR_ARG, "the preconditioned solve is FP64 only");
+  if (o->prec != LS_FP64 && o->prec != LS_MIXED) return fail(h, LS_ERR_ARG, "bad precision");
   if (s < 0 || s >= (int32_t)h->sc.size()) return fail(h, LS_ERR_ARG, "bad scatterer index");
   const Scat &sct = h->sc[s];
   if (!sct.tr) return fail(h, LS_ERR_ARG, "no grid for this scatterer (ls_transfer_setup)");

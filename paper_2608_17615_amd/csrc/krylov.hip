@@ -572,10 +572,18 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
         const ls_status sst = pc.S((const double *)pc.c, (double *)pc.sc, nrhs, pc.ldc, pc.user, st);
         if (sst < 0) return setup_fail(h, sst, "the preconditioner's S failed");
         HIPTRY(launch_precond_finish(scp, vj, n, pc.c, pc.sc, pc.ldc, zj, nrhs, st));
+        // relaxed: the mixed-precision operator once the residual allows it (as below)
+        ls_precision pj = LS_FP64;
+        if (o.relax_eps > 0) {
+          double worst = 0.0;
+          for (int q = 0; q < nsys; ++q)
+            if (act[q]) worst = std::max(worst, est[q]);
+          pj = worst * o.relax_eps <= o.tol ? LS_MIXED : LS_FP64;
+        }
         set_skip(act);
-        ls_status s2 = apply_op(h, (const double *)zj, (double *)w, nrhs, n, o.mode, LS_FP64, st);
+        ls_status s2 = apply_op(h, (const double *)zj, (double *)w, nrhs, n, o.mode, pj, st);
         if (s2 != LS_OK) return s2;
-        ++res.n_fp64;
+        if (pj == LS_FP64) ++res.n_fp64; else ++res.n_mixed;
       } else if (o.flexible) {
         // z_j ~ L^{-1} v_j by an inner GMRES with the mixed-precision operator (active systems
         // only), then w = L z_j
@@ -763,10 +771,11 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
   // once the residual is below tol / inner_tol (inner_tol = relative accuracy granted to it,
   // default 1e-4: a later switch than the operator error alone would allow; see ls.h),
   // followed by FP64 refinement passes from the true residual if that missed tol
-  // with the preconditioner P (pc): FP64 flexible GMRES with z_j = P v_j
-  const bool mixed = o.prec == LS_MIXED && !pc;
-  const bool flexible = (mixed && o.inner_maxit > 0) || pc;
-  const double relax = (mixed && !flexible) ? (o.inner_tol > 0 ? o.inner_tol : 1e-4) : 0.0;
+  // with the preconditioner P (pc): flexible GMRES with z_j = P v_j, its operator applications
+  // relaxed to the mixed precision as above when LS_MIXED is asked for
+  const bool mixed = o.prec == LS_MIXED;
+  const bool flexible = (mixed && o.inner_maxit > 0 && !pc) || pc;
+  const double relax = (mixed && (!flexible || pc)) ? (o.inner_tol > 0 ? o.inner_tol : 1e-4) : 0.0;
   // the relaxed iteration aims its residual estimate below 0.3 tol so that its FP64 residual,
   // perturbed by the mixed applications, still meets tol without a (Krylov-space-losing) restart
   CoreOpts co{relax > 0 ? 0.3 * o.tol : o.tol, o.maxit, o.restart, mode, LS_FP64, flexible,

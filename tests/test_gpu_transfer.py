@@ -145,13 +145,11 @@ def test_preconditioned_gmres():
     assert i2["converged"] and i3["converged"] and e2 <= 1e-10 and e3 <= 1e-10
     with pytest.raises(ValueError):
         op.solve_precond(b, lambda v: v[:, :3], tol=1e-12, maxit=10)
-    with pytest.raises(lsg.LSError):                     # FP64 only
-        o = lsg._SolveOpts(1e-8, 10, 0, lsg.MIXED, 0, 0, 0, 0.0)
-        cc = torch.empty((1, g.n), dtype=torch.complex128, device="cuda")
-        st = lsg.lib().ls_solve_gmres_precond(op._h, b.data_ptr(), x0.data_ptr(), 1, op.n, ctypes.byref(o), 0,
-                                              lsg._GridOp(lambda *a: 0), None, cc.data_ptr(), cc.data_ptr(),
-                                              g.n, None, lsg._stream())
-        lsg._check(st, op._h)
+    # relaxed mixed precision inside the preconditioned solve still meets the FP64 tolerance
+    x4, i4 = op.solve_precond(b, lambda v: v @ Sm, tol=1e-10, maxit=400, precision="mixed")
+    print(f"mixed preconditioned: {i4['iters'][0]} steps, applies {i4['n_apply_fp64']} + {i4['n_apply_mixed']}, "
+          f"relres {i4['relres'][0]:.1e}", flush=True)
+    assert i4["converged"] and i4["relres"][0] <= 1.5e-10 and i4["n_apply_mixed"] > 0
 
 
 def _crude_cartesian_inverse(g, k, m_inside):
