@@ -66,7 +66,7 @@ __global__ __launch_bounds__(kBlock) void prologue_kernel(int64_t n, int nrhs, c
 template <int TPL, int BC, bool CONJ, bool MASKED>
 __device__ __forceinline__ void far_source(int j, const int (&it)[TPL], const double (&xt)[TPL],
                                            const double (&yt)[TPL], double k2, const double2 *__restrict__ pos,
-                                           const double2 *__restrict__ d, const double2 *sct,
+                                           const double2 *__restrict__ d, const PhaseLds &sct,
                                            double (&ar)[TPL][BC], double (&ai)[TPL][BC]) {
   const double2 p = pos[j];
   double gr[TPL], gi[TPL];
@@ -103,8 +103,8 @@ __global__ __launch_bounds__(kBlock) void far_fp64_kernel(int n, const double *_
                                                          const double2 *__restrict__ sd, int nrhs,
                                                          double k2, int split_len,
                                                          double2 *__restrict__ part) {
-  __shared__ double2 sct[SINCOS_N];
-  load_sincos(sct, d_sincos);
+  __shared__ double2 sct_lds[SINCOS_N];
+  const PhaseLds sct = load_sincos(sct_lds, d_sincos);
   const int c0 = blockIdx.z * BC;
   const int w0 = __builtin_amdgcn_readfirstlane(blockIdx.x * kBlock * TPL + (threadIdx.x >> 6) * 64 * TPL);
   const int lane = threadIdx.x & 63;
@@ -190,8 +190,8 @@ __global__ __launch_bounds__(kBlock) void epilogue_kernel(
 
 __global__ __launch_bounds__(kBlock) void eval_green_kernel(const double *__restrict__ z2, double2 *__restrict__ g,
                                                             int64_t n, int single) {
-  __shared__ double2 sct[SINCOS_N];
-  load_sincos(sct, d_sincos);
+  __shared__ double2 sct_lds[SINCOS_N];
+  const PhaseLds sct = load_sincos(sct_lds, d_sincos);
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   if (single) {
@@ -227,8 +227,8 @@ __global__ __launch_bounds__(kBlock) void field_far_kernel(int nt, const double 
                                                           const double2 *__restrict__ pos,
                                                           const double2 *__restrict__ sd, int nrhs, double k2,
                                                           int split_len, double2 *__restrict__ part) {
-  __shared__ double2 sct[SINCOS_N];
-  load_sincos(sct, d_sincos);
+  __shared__ double2 sct_lds[SINCOS_N];
+  const PhaseLds sct = load_sincos(sct_lds, d_sincos);
   const int c0 = blockIdx.z * BC;
   const int t = blockIdx.x * kBlock + threadIdx.x;
   const int ti = t < nt ? t : nt - 1;
@@ -366,7 +366,8 @@ void eval_green_host(const double *z2, double *g, int64_t n) {
     for (int i = 0; i < SINCOS_N; ++i) t[i] = make_double2(kSinCosTable.v[2 * i], kSinCosTable.v[2 * i + 1]);
     return t;
   }();
-  for (int64_t i = 0; i < n; ++i) green<true>(z2[i], g[2 * i], g[2 * i + 1], kHankelTable, sct.data());
+  const PhaseLds ph = host_phase_lds(sct.data());
+  for (int64_t i = 0; i < n; ++i) green<true>(z2[i], g[2 * i], g[2 * i + 1], kHankelTable, ph);
 }
 
 hipError_t launch_eval_green(const double *z2, double *g, int64_t n, int single, hipStream_t st) {

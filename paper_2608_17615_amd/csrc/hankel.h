@@ -180,24 +180,56 @@ __host__ __device__ __forceinline__ void phase_tail(double zp, double Mu, double
   gim = Ms * cs;
 }
 
+// x c + v with c wave-uniform (an SGPR pair) and v a loop-invariant vector register: a VOP3 FMA
+// may read one scalar operand only.
+__host__ __device__ __forceinline__ double fma_uniform_v(double x, double c, double v) {
+#ifdef __HIP_DEVICE_COMPILE__
+  double out;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(out) : "v"(x), "s"(c), "v"(v));
+  return out;
+#else
+  return std::fma(x, c, v);
+#endif
+}
+
+// x c - 1/2 with c wave-uniform: -0.5 is an inline constant of the instruction encoding, so the
+// FMA needs no register for it.
+__host__ __device__ __forceinline__ double fma_uniform_mhalf(double x, double c) {
+#ifdef __HIP_DEVICE_COMPILE__
+  double out;
+  asm("v_fma_f64 %0, %1, %2, -0.5" : "=v"(out) : "v"(x), "s"(c));
+  return out;
+#else
+  return std::fma(x, c, -0.5);
+#endif
+}
+
+// The LDS copy of kSinCosTable, and -1/6 (the cubic coefficient of sin r below) in a vector
+// register: a VOP3 FMA may read only one scalar operand, and a value the compiler knows to be a
+// constant it copies from its SGPR again inside every loop.
+struct PhaseLds {
+  const double2 *e;
+  double m6;
+};
+
 // The same result by a table: theta = j pi/256 + r with |r| <= pi/512, SC[j mod 512] =
-// e^{i j pi/256}/c8 (kSinCosTable, copied by the kernels into LDS with load_sincos) rotated by e^{i r} - 1 from short
-// Taylor series (tail_k); six instructions per pair fewer than the reduction modulo pi and the two
-// polynomials on [-pi/2, pi/2] (77.1 -> 71.1 per pair in the far sum's counters).  jm's low
-// mantissa bits hold j (RND_MAGIC has none set).
+// e^{i j pi/256}/c8 (kSinCosTable, copied by the kernels into LDS with load_sincos) rotated by
+// e^{i r} - 1: sin r = r + r^3 (r^2/120 - 1/6) and cos r - 1 = r^2 (c4 r^2 - 1/2), c4 the minimax
+// coefficient on |r| <= pi/512 (tail_k; truncation below 1e-17).  jm's low mantissa bits hold j
+// (RND_MAGIC has none set).
 template <class Tab>
 __host__ __device__ __forceinline__ void phase_tail_table(double zp, double Mu, double &gre, double &gim,
-                                                          const Tab &T, const double2 *SC) {
+                                                          const Tab &T, const PhaseLds &SC) {
   const double jm = std::fma(zp, T.tail_k[0], RND_MAGIC);
   const double jf = jm - RND_MAGIC;
   double r = std::fma(-jf, T.tail_k[1], zp);
   r = std::fma(-jf, T.tail_k[2], r);
   unsigned long long bits;
   std::memcpy(&bits, &jm, sizeof bits);
-  const double2 e = SC[(unsigned)bits & (SINCOS_N - 1)];
+  const double2 e = SC.e[(unsigned)bits & (SINCOS_N - 1)];
   const double r2 = r * r;
-  const double sr = std::fma(r2 * (r * T.tail_k[3]), add_uniform(r2, T.tail_k[4]), r);   // sin r
-  const double cm = (r2 * T.tail_k[7]) * fma_uniform(add_uniform(r2, T.tail_k[5]), r2, T.tail_k[6]);  // cos r - 1
+  const double sr = std::fma(r2 * r, fma_uniform_v(r2, T.tail_k[3], SC.m6), r);   // sin r
+  const double cm = r2 * fma_uniform_mhalf(r2, T.tail_k[5]);                   // cos r - 1
   const double C = std::fma(e.x, cm, std::fma(-e.y, sr, e.x));
   const double S = std::fma(e.y, cm, std::fma(e.x, sr, e.y));
   // G/K = i Mu (C + i S)
@@ -206,18 +238,26 @@ __host__ __device__ __forceinline__ void phase_tail_table(double zp, double Mu, 
 }
 
 // Copies the table of phase_tail_table into the workgroup's LDS array lds[SINCOS_N] (all threads
-// of the block take part; the barrier makes it visible to every wavefront).
-__device__ __forceinline__ void load_sincos(double2 *lds, const SinCosTable &t) {
+// of the block take part; the barrier makes it visible to every wavefront) and returns it with
+// -1/6 placed in a vector register once per kernel (the empty asm hides the value from the
+// compiler, so it stays in that register).
+__device__ __forceinline__ PhaseLds load_sincos(double2 *lds, const SinCosTable &t) {
   for (int i = threadIdx.x; i < SINCOS_N; i += blockDim.x) lds[i] = make_double2(t.v[2 * i], t.v[2 * i + 1]);
   __syncthreads();
+  double m6 = kHankelTable.tail_k[4];
+  asm volatile("" : "+v"(m6));
+  return PhaseLds{lds, m6};
 }
+
+// The same object over a host copy of the table (host evaluation of the same arithmetic).
+inline PhaseLds host_phase_lds(const double2 *table) { return PhaseLds{table, kHankelTable.tail_k[4]}; }
 
 // ZS <= z: modulus-phase form.  Only the two polynomials depend on the argument range; the
 // inverse fourth root, the reduction and the sine/cosine are shared, so a wavefront whose lanes
 // straddle a range boundary repeats only the polynomial evaluation.  Returns G/K.
 template <bool TBL = false, class Tab>
 __host__ __device__ __forceinline__ void green_modphase(double A, double &gre, double &gim, const Tab &T,
-                                                        const double2 *SC = nullptr) {
+                                                        const PhaseLds &SC = PhaseLds{}) {
   const double s = inv_fourth_root(A, T);  // z^(-1/2)
   const double t = s * s;                  // 1/z
   double mod, ph;                          // M sqrt(z) / (4 m8), theta - z
@@ -258,7 +298,7 @@ __host__ __device__ __forceinline__ void green_small(double A, double &gre, doub
 // TBL: e^{i theta} from the table SC (phase_tail_table) instead of the polynomials.
 template <bool TBL = false, class Tab>
 __host__ __device__ __forceinline__ void green_unit(double A, double &gre, double &gim, const Tab &T,
-                                                    const double2 *SC = nullptr) {
+                                                    const PhaseLds &SC = PhaseLds{}) {
   if (A >= ZS2) {
     green_modphase<TBL>(A, gre, gim, T, SC);
   } else {
@@ -269,7 +309,7 @@ __host__ __device__ __forceinline__ void green_unit(double A, double &gre, doubl
 // G = (i/4) H0^(1)(z) for z^2 = A > 0
 template <bool TBL = false, class Tab>
 __host__ __device__ __forceinline__ void green(double A, double &gre, double &gim, const Tab &T,
-                                               const double2 *SC = nullptr) {
+                                               const PhaseLds &SC = PhaseLds{}) {
   green_unit<TBL>(A, gre, gim, T, SC);
   gre *= T.consts[7];
   gim *= T.consts[7];

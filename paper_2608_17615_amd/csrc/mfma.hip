@@ -55,7 +55,7 @@ struct Tile<double> {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
-  static __device__ __forceinline__ void green(double A, double &gr, double &gi, const double2 *sct) {
+  static __device__ __forceinline__ void green(double A, double &gr, double &gi, const PhaseLds &sct) {
     lsk::green_unit<true>(A, gr, gi, mtab(), sct);
   }
   static __device__ __forceinline__ cplx_t make(double a, double b) { return make_double2(a, b); }
@@ -69,7 +69,7 @@ struct Tile<float> {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
-  static __device__ __forceinline__ void green(double A, float &gr, float &gi, const double2 *) {
+  static __device__ __forceinline__ void green(double A, float &gr, float &gi, const PhaseLds &) {
     lsk::green32_unit(A, gr, gi, mtab());
   }
   static __device__ __forceinline__ cplx_t make(double a, double b) { return make_float2((float)a, (float)b); }
@@ -111,7 +111,7 @@ template <class T, int MT, int NT, bool CONJ>
 __device__ __forceinline__ void tile_body(int n, const double2 *__restrict__ pos,
                                           const typename Tile<T>::cplx_t *__restrict__ X, int ldx, int nrhs,
                                           double k2, int s0, int s1, int t0, int b0, int split,
-                                          double2 *__restrict__ part, const double2 *sct) {
+                                          double2 *__restrict__ part, const PhaseLds &sct) {
   typedef Tile<T> TL;
   typedef typename TL::acc_t acc_t;
   const int lane = threadIdx.x & 63;
@@ -192,8 +192,9 @@ __global__ __launch_bounds__(kBlock) void far_tile_kernel(int n, const double2 *
                                                           int nrhs, double k2, int split_len,
                                                           double2 *__restrict__ part) {
   // the FP64 Green's values take e^{i theta} from a table in LDS (hankel.h, phase_tail_table)
-  __shared__ double2 sct[kFP64<T> ? SINCOS_N : 1];
-  if constexpr (kFP64<T>) load_sincos(sct, m_sincos);
+  __shared__ double2 sct_lds[kFP64<T> ? SINCOS_N : 1];
+  PhaseLds sct{sct_lds, 0.0};
+  if constexpr (kFP64<T>) sct = load_sincos(sct_lds, m_sincos);
   const int wave = threadIdx.x >> 6;
   const int s0 = blockIdx.y * split_len;
   tile_body<T, MT, NT, CONJ>(n, pos, X, ldx, nrhs, k2, s0, min(n, s0 + split_len),
@@ -209,8 +210,9 @@ __global__ __launch_bounds__(kBlock) void far_tile_persistent(const BatchDesc *_
                                                               const WorkItem *__restrict__ items, int n_items,
                                                               int *__restrict__ counter, int ldx, int nrhs) {
   __shared__ int next;
-  __shared__ double2 sct[kFP64<T> ? SINCOS_N : 1];
-  if constexpr (kFP64<T>) load_sincos(sct, m_sincos);
+  __shared__ double2 sct_lds[kFP64<T> ? SINCOS_N : 1];
+  PhaseLds sct{sct_lds, 0.0};
+  if constexpr (kFP64<T>) sct = load_sincos(sct_lds, m_sincos);
   const int wave = threadIdx.x >> 6;
   for (;;) {
     if (threadIdx.x == 0) next = atomicAdd(counter, 1);
