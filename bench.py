@@ -57,7 +57,7 @@ PEAK_FP32_MFMA_TFLOPS = 157.3
 # with this digest only: after any change to them the field is reported as null.
 FAR_TRAFFIC_BYTES = 37_694_000 + 134_784_000
 FAR_TRAFFIC_SOURCES = ("apply.hip", "hankel.h", "hankel_tables.h")
-FAR_TRAFFIC_DIGEST = "ad1e67bcd853a9e0"
+FAR_TRAFFIC_DIGEST = "57aa3428bd671f22"
 
 
 def far_traffic():

@@ -9,7 +9,7 @@
 // e^{i theta} uses a reduction modulo pi (two-constant Cody-Waite with FMA) and minimax
 // sine/cosine on [-pi/2, pi/2], the parity of the multiple of pi flipping the sign; or, in the
 // kernels that keep a 512-entry table of e^{i j pi/256} in LDS, a reduction modulo pi/256, one
-// table entry and short Taylor series.
+// table entry and short series of the remainder.
 // All coefficients are produced by gen_hankel_tables.py and passed in as one HankelTable, so a
 // kernel can keep them in memory read through the scalar data path instead of pinning ~130
 // doubles in vector registers.  Functions are host+device so the same arithmetic can be
