@@ -69,3 +69,38 @@ def test_workspace_and_options_structs_match_header():
     assert ctypes.sizeof(lsg._Profile) == 40
     assert ctypes.sizeof(lsg._SolveInfo) == 48
     assert ctypes.sizeof(lsg._Grid) == 32
+
+
+def _table(name):
+    txt = open(os.path.join(ROOT, "paper_2608_17615_amd", "csrc", "hankel_tables.h")).read()
+    body = re.search(name + r"[^=]*=\s*\{+([^}]*)\}", txt).group(1)
+    return np.array([float(v) for v in body.split(",") if v.strip()])
+
+
+def test_phase_table_and_remainder_series():
+    """The shipped table holds e^{i j pi/256} up to one common scale (to a rounding of each entry),
+    and the short forms of the remainder r = theta - j pi/256, |r| <= pi/512, are within 1e-17 of
+    sin r and cos r - 1 (checked in 40-digit arithmetic, independent of the generator's check)."""
+    mp.mp.dps = 40
+    v = _table("kSinCosTable")
+    assert v.size == 1024
+    c8 = v[0]
+    j = np.arange(512)
+    cs = np.array([float(mp.cos(mp.pi * int(i) / 256)) for i in j])
+    sn = np.array([float(mp.sin(mp.pi * int(i) / 256)) for i in j])
+    assert np.abs(v[0::2] / c8 - cs).max() <= 3e-16
+    assert np.abs(v[1::2] / c8 - sn).max() <= 3e-16
+    k = _table("TAIL_K")
+    assert abs(k[0] * k[1] - 1) < 1e-15 and abs(mp.mpf(k[1]) + mp.mpf(k[2]) - mp.pi / 256) < mp.mpf(10) ** -33
+    rmax = mp.pi / 512 * (1 + mp.mpf(2) ** -20)
+    err = 0
+    for i in range(-200, 201):
+        r = rmax * i / 200
+        sr = r + r ** 3 * (r * r * mp.mpf(k[3]) + mp.mpf(k[4]))
+        cm = r * r * (mp.mpf(k[5]) * r * r - mp.mpf(1) / 2)
+        err = max(err, abs(sr - mp.sin(r)), abs(cm - (mp.cos(r) - 1)))
+    assert err < 1e-17, float(err)
+    # the plain Taylor coefficient 1/24 in place of the minimax one misses the bound (about 7e-17
+    # at the interval's end): the check has teeth
+    r = rmax
+    assert abs(r * r * (r * r / 24 - mp.mpf(1) / 2) - (mp.cos(r) - 1)) > 1e-17
