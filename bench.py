@@ -276,35 +276,109 @@ def solve_form(op, b, form, args, adjoint=False):
     return torch.cat(xs), t.seconds, a64, amx, t, its, B
 
 
-def cartesian_inverse(op, prob, kh):
-    """The caller's S for the preconditioned form: the dense inverse of a first-order Cartesian
-    discretization of L (off-diagonal h^2 G(z_i, z_j) from the library's own Green's evaluation,
-    the cell's own term integrated over the disk of the cell's area, the medium's contrast at the
-    grid nodes) on a grid of spacing kh / k, inverted by host LAPACK.  A stand-in for the sparsifying preconditioner, which is not built.  Registers the grid
-    with the operator and returns (S^T on the device, grid size, seconds)."""
+def cartesian_grid(prob, kh, pad=0.02):
+    """(x0, y0, h, nx, ny) of the Cartesian grid of spacing kh / k over the scatterer's nodes."""
     import math
-
-    import numpy as np
-    import torch
-    from scipy.special import hankel1
-
-    import paper_2608_17615_amd as lsg
-    t0 = time.perf_counter()
-    k, h, pad = prob.k, kh / prob.k, 0.02
+    h = kh / prob.k
     x, y = prob.mesh.x, prob.mesh.y
     x0, y0 = x.min() - pad, y.min() - pad
     nx = int(math.ceil((x.max() + pad - x0) / h)) + 1
     ny = int(math.ceil((y.max() + pad - y0) / h)) + 1
+    return x0, y0, h, nx, ny
+
+
+def cell_self_term(k, h):
+    """Integral of G over the disk of area h^2 centred on the node: (-1 + (i pi/2) k a H1(k a)) / k^2."""
+    import math
+
+    from scipy.special import hankel1
+    a = h / math.sqrt(math.pi)
+    return (-1 + 0.5j * math.pi * a * k * complex(hankel1(1, k * a))) / k ** 2
+
+
+def sparsifying_S(x0, y0, h, nx, ny, k, m):
+    """S^(C) = (C^(C))^-1 A of the sparsifying preconditioner (paper, Section 4, eqs.
+    sparsifying_min and LC_def), built on the host as a dense (nx ny)^2 array for the first-order
+    Cartesian system L^(C) = I + k^2 V^(C) M^(C): V^(C) is h^2 G off the diagonal (the library's
+    host Green's evaluation) and the cell's own term on it, m the contrast at the grid nodes.
+    The 3 x 3 stencil weights v are the smallest left singular vector of V^(C)(N(j0), N(j0)^c) at
+    the central node j0; A carries v on every row (an edge row keeps the neighbours that exist);
+    C^(C) is A L^(C) restricted to the 3 x 3 pattern, which needs V^(C) only at the 25 offsets
+    of at most two steps (the grid is uniform)."""
+    import numpy as np
+
+    import paper_2608_17615_amd as lsg
+    nc = nx * ny
+    iy, ix = np.divmod(np.arange(nc), nx)
+    vself = cell_self_term(k, h)
+
+    def vgrid(dx, dy):
+        """V^(C) between nodes dx, dy steps apart (arrays)."""
+        d2 = np.asarray(dx * dx + dy * dy, dtype=np.float64)
+        out = h * h * lsg.eval_green_host((k * h) ** 2 * np.where(d2 > 0, d2, 1.0))
+        return np.where(d2 > 0, out, vself)
+
+    offs = [(dx, dy) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+    j0 = (ny // 2) * nx + nx // 2
+    nb = np.array([j0 + dy * nx + dx for dx, dy in offs])
+    rest = np.setdiff1d(np.arange(nc), nb)
+    B = vgrid(ix[rest][None, :] - ix[nb][:, None], iy[rest][None, :] - iy[nb][:, None])
+    U, sig, _ = np.linalg.svd(B, full_matrices=False)
+    v = U[:, -1].conj()
+    m = np.asarray(m, dtype=np.complex128)
+    A = np.zeros((nc, nc), dtype=np.complex128)
+    C = np.zeros((nc, nc), dtype=np.complex128)
+    rows = np.arange(nc)
+
+    def shift(dx, dy):
+        ok = (ix + dx >= 0) & (ix + dx < nx) & (iy + dy >= 0) & (iy + dy < ny)
+        return ok, rows + dy * nx + dx
+
+    for (dxl, dyl), w in zip(offs, v):
+        okl, jl = shift(dxl, dyl)
+        A[rows[okl], jl[okl]] = w
+        for dx2, dy2 in offs:
+            ok2, j2 = shift(dx2, dy2)
+            ok = okl & ok2
+            same = dxl == dx2 and dyl == dy2
+            # L^(C)[l, j2] = [l == j2] + k^2 V^(C)(z_l - z_j2) m(z_j2)
+            lval = (1.0 if same else 0.0) + k * k * vgrid(dxl - dx2, dyl - dy2) * m[j2[ok]]
+            C[rows[ok], j2[ok]] += w * lval
+    return np.linalg.solve(C, A), float(sig[-1] / sig[0])
+
+
+def cartesian_inverse(op, prob, kh, kind="inverse"):
+    """The caller's S for the preconditioned form, on a grid of spacing kh / k.  kind "inverse":
+    the dense inverse of a first-order Cartesian discretization of L (off-diagonal h^2 G(z_i, z_j)
+    from the library's own Green's evaluation, the cell's own term integrated over the disk of the
+    cell's area, the medium's contrast at the grid nodes), inverted by host LAPACK.  kind
+    "sparsify": the sparsifying preconditioner S^(C) = (C^(C))^-1 A of the same discretization
+    (sparsifying_S), applied as a dense matrix.  Registers the grid with the operator and returns
+    (S^T on the device, grid size, seconds)."""
+    import numpy as np
+    import torch
+
+    import paper_2608_17615_amd as lsg
+    t0 = time.perf_counter()
+    k = prob.k
+    x0, y0, h, nx, ny = cartesian_grid(prob, kh)
     iy, ix = np.divmod(np.arange(nx * ny), nx)
+    if kind == "sparsify":
+        S, ratio = sparsifying_S(x0, y0, h, nx, ny, k, prob.m_at(x0 + ix * h, y0 + iy * h))
+        log(f"stencil: smallest / largest singular value {ratio:.2e}")
+        ST = torch.tensor(S.T.copy(), device="cuda")
+        del S
+        op.set_grid(x0, y0, h, nx, ny)
+        torch.cuda.synchronize()
+        return ST, nx * ny, time.perf_counter() - t0
     zx = torch.tensor(x0 + ix * h, device="cuda")
     zy = torch.tensor(y0 + iy * h, device="cuda")
     z2 = (k * k) * ((zx[:, None] - zx[None, :]) ** 2 + (zy[:, None] - zy[None, :]) ** 2)
     z2.fill_diagonal_(1.0)
     L = lsg.eval_green(z2)
     del z2
-    a = h / math.sqrt(math.pi)
     L.mul_(h * h)
-    L.diagonal().fill_((-1 + 0.5j * math.pi * a * k * complex(hankel1(1, k * a))) / k ** 2)
+    L.diagonal().fill_(cell_self_term(k, h))
     m = torch.tensor(np.asarray(prob.m_at(x0 + ix * h, y0 + iy * h), dtype=np.complex128), device="cuda")
     L.mul_((k * k) * m[None, :])
     L.diagonal().add_(1.0)
@@ -337,8 +411,8 @@ def run_batched(args, probs, label, B):
     if form in ("pc", "pcm"):
         if len(probs) != 1 or probs[0].m_at is None:
             raise SystemExit("--form pc needs one scatterer whose contrast is known off the nodes")
-        args._cartesian_S, nc, pre_s = cartesian_inverse(op, probs[0], args.kh)
-        pre = {"k_h": args.kh, "grid_nodes": nc, "build_s": pre_s}
+        args._cartesian_S, nc, pre_s = cartesian_inverse(op, probs[0], args.kh, args.precond)
+        pre = {"S": args.precond, "k_h": args.kh, "grid_nodes": nc, "build_s": pre_s}
         log(f"Cartesian S: {nc} grid nodes, built in {pre_s:.1f} s")
     if form == "bm" and len(probs) > 1:
         tune = op.autotune(B, precision="mixed")
@@ -398,8 +472,8 @@ def run_gradient(args, prob, label, B):
     if form in ("pc", "pcm"):
         if prob.m_at is None:
             raise SystemExit("--form pc needs a scatterer whose contrast is known off the nodes")
-        args._cartesian_S, nc, pre_s = cartesian_inverse(op, prob, args.kh)
-        pre = {"k_h": args.kh, "grid_nodes": nc, "build_s": pre_s}
+        args._cartesian_S, nc, pre_s = cartesian_inverse(op, prob, args.kh, args.precond)
+        pre = {"S": args.precond, "k_h": args.kh, "grid_nodes": nc, "build_s": pre_s}
         log(f"Cartesian S: {nc} grid nodes, built in {pre_s:.1f} s")
     # synthetic data: far field of the seeded contrast perturbation (input generation, untimed)
     m0 = torch.tensor(prob.m, device="cuda").to(torch.complex128)
@@ -499,6 +573,9 @@ def main():
                          "first-order Cartesian inverse as S (c3, c5); pcm: the same with relaxed mixed "
                          "precision")
     ap.add_argument("--kh", type=float, default=0.8, help="pc: k times the Cartesian grid spacing")
+    ap.add_argument("--precond", default="inverse", choices=["inverse", "sparsify"],
+                    help="pc: S is the dense inverse of the first-order Cartesian system (inverse) or the "
+                         "sparsifying preconditioner (C^(C))^-1 A of the same system (sparsify)")
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-8)

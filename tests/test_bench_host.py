@@ -40,3 +40,20 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_sparsifying_preconditioner_matches_the_oracle():
+    """The bench's host construction of S^(C) = (C^(C))^-1 A (library host Green's values, 25
+    offsets) equals the oracle's dense construction (SciPy Hankel values, the full product A L^(C)
+    and its 3 x 3 filter) on a 21 x 21 grid over a disk; S does not depend on the phase of the
+    singular vector, so the two are compared entry by entry."""
+    from oracle import sparsify as spf
+    from oracle.transfer import Grid
+    k, h = 8.0, 0.11
+    g = Grid(-1.1, -1.1, h, 21, 21)
+    zx, zy = g.nodes()
+    m = np.where(np.hypot(zx, zy) < 1.0, -1.0, 0.0)
+    S, ratio = bench.sparsifying_S(g.x0, g.y0, g.h, g.nx, g.ny, k, m)
+    So, _, _, _, ratio_o = spf.sparsifying_preconditioner(g, k, m, width=1)
+    assert abs(ratio - ratio_o) <= 1e-9 * ratio_o
+    assert np.abs(S - So).max() <= 1e-12 * np.abs(So).max()
