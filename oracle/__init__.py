@@ -15,6 +15,9 @@ Modules
   krylov    dense LU and GMRES without restart                  -- Section 6 setup
   mie       Fourier-Bessel series for one- and two-layer disks  -- Section 6.1
   farfield  far-field pattern, misfit and its adjoint gradient  -- Section 5, eq. dissipativity_identity
+  field     the field at exterior points                        -- eq. field_recovery
+  transfer  grid <-> node transfers and the preconditioner P    -- Section 4, eq. preconditioner_factored
+  sparsify  the sparsifying Cartesian preconditioner S^(C)      -- Section 4, eqs. sparsifying_min, LC_def
 
 Every function is pinned by a test in tests/test_oracle_*.py against something other
 than itself (closed forms, an addition-theorem evaluation, brute-force quadrature,
