@@ -47,6 +47,10 @@ def test_argument_validation_before_any_device_call():
     assert L.ls_transfer_setup(None, 0, None) == -1
     assert L.ls_quad_to_cart(None, 0, None, 1, None, 1, 1, None) == -1
     assert L.ls_precond_finish(None, 0, None, 1, None, None, 1, None, 1, None) == -1
+    assert L.ls_cart_to_quad(None, 0, None, 1, None, 1, 1, None) == -1
+    assert L.ls_transfer_colsums(None, 0, None) == -1
+    assert L.ls_solve_gmres_precond(None, None, None, 1, 1, None, 0, lsg._GridOp(), None, None, None, 1, None,
+                                    None) == -1
 
 
 def test_host_green_matches_mpmath():
