@@ -301,10 +301,11 @@ def sparsifying_S(x0, y0, h, nx, ny, k, m):
     sparsifying_min and LC_def), built on the host as a dense (nx ny)^2 array for the first-order
     Cartesian system L^(C) = I + k^2 V^(C) M^(C): V^(C) is h^2 G off the diagonal (the library's
     host Green's evaluation) and the cell's own term on it, m the contrast at the grid nodes.
-    The 3 x 3 stencil weights v are the smallest left singular vector of V^(C)(N(j0), N(j0)^c) at
-    the central node j0; A carries v on every row (an edge row keeps the neighbours that exist);
-    C^(C) is A L^(C) restricted to the 3 x 3 pattern, which needs V^(C) only at the 25 offsets
-    of at most two steps (the grid is uniform)."""
+    A row's weights are the smallest left singular vector of V^(C)(N(j), N(j)^c) over its 3 x 3
+    neighbourhood within the grid: the central node's serve every row with all 9 neighbours (the
+    grid is uniform), and each edge and corner row gets its own on its 6 or 4.  C^(C) is A L^(C)
+    restricted to the 3 x 3 pattern, which needs V^(C) only at the 25 offsets of at most two
+    steps."""
     import numpy as np
 
     import paper_2608_17615_amd as lsg
@@ -319,32 +320,42 @@ def sparsifying_S(x0, y0, h, nx, ny, k, m):
         return np.where(d2 > 0, out, vself)
 
     offs = [(dx, dy) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
-    j0 = (ny // 2) * nx + nx // 2
-    nb = np.array([j0 + dy * nx + dx for dx, dy in offs])
-    rest = np.setdiff1d(np.arange(nc), nb)
-    B = vgrid(ix[rest][None, :] - ix[nb][:, None], iy[rest][None, :] - iy[nb][:, None])
-    U, sig, _ = np.linalg.svd(B, full_matrices=False)
-    v = U[:, -1].conj()
-    m = np.asarray(m, dtype=np.complex128)
-    A = np.zeros((nc, nc), dtype=np.complex128)
-    C = np.zeros((nc, nc), dtype=np.complex128)
     rows = np.arange(nc)
 
     def shift(dx, dy):
         ok = (ix + dx >= 0) & (ix + dx < nx) & (iy + dy >= 0) & (iy + dy < ny)
         return ok, rows + dy * nx + dx
 
-    for (dxl, dyl), w in zip(offs, v):
+    def weights(j):
+        """Smallest left singular vector over row j's neighbours (-> 9 slots, 0 where missing)."""
+        have = [o for o in range(9) if 0 <= ix[j] + offs[o][0] < nx and 0 <= iy[j] + offs[o][1] < ny]
+        nb = np.array([j + offs[o][1] * nx + offs[o][0] for o in have])
+        rest = np.setdiff1d(rows, nb)
+        B = vgrid(ix[rest][None, :] - ix[nb][:, None], iy[rest][None, :] - iy[nb][:, None])
+        U, sig, _ = np.linalg.svd(B, full_matrices=False)
+        w = np.zeros(9, dtype=np.complex128)
+        w[have] = U[:, -1].conj()
+        return w, sig[-1] / sig[0]
+
+    v, ratio = weights((ny // 2) * nx + nx // 2)
+    W = np.tile(v, (nc, 1))
+    edge = np.nonzero((ix == 0) | (ix == nx - 1) | (iy == 0) | (iy == ny - 1))[0]
+    for j in edge:
+        W[j] = weights(j)[0]
+    m = np.asarray(m, dtype=np.complex128)
+    A = np.zeros((nc, nc), dtype=np.complex128)
+    C = np.zeros((nc, nc), dtype=np.complex128)
+    for o, (dxl, dyl) in enumerate(offs):
         okl, jl = shift(dxl, dyl)
-        A[rows[okl], jl[okl]] = w
+        A[rows[okl], jl[okl]] = W[okl, o]
         for dx2, dy2 in offs:
             ok2, j2 = shift(dx2, dy2)
             ok = okl & ok2
             same = dxl == dx2 and dyl == dy2
             # L^(C)[l, j2] = [l == j2] + k^2 V^(C)(z_l - z_j2) m(z_j2)
             lval = (1.0 if same else 0.0) + k * k * vgrid(dxl - dx2, dyl - dy2) * m[j2[ok]]
-            C[rows[ok], j2[ok]] += w * lval
-    return np.linalg.solve(C, A), float(sig[-1] / sig[0])
+            C[rows[ok], j2[ok]] += W[ok, o] * lval
+    return np.linalg.solve(C, A), float(ratio)
 
 
 def cartesian_inverse(op, prob, kh, kind="inverse"):

@@ -10,10 +10,12 @@ Readings (the paper's own choices are not available here):
     given.  This oracle uses the first-order rule: V_ij = h^2 G(z_i, z_j) for i != j, and on the
     diagonal the integral of G over the disk of the cell's area centred on the node,
     (-1 + (i pi/2) k a H1(k a)) / k^2 with a = h / sqrt(pi).
-  * Stencil: the 3 x 3 neighbours of the node (eq. cart_neighbors_LS with D the grid's box),
-    weights v from the smallest left singular vector of V(N(0), N(0)^c) at the grid's central
-    node (eq. sparsifying_min), used on every row by translation invariance; a row at the grid's
-    edge keeps the weights of the neighbours that exist.
+  * Stencil: the 3 x 3 neighbours of the node within the grid's box (eq. cart_neighbors_LS with D
+    the box), so 6 at an edge and 4 at a corner.  Each row's weights solve eq. sparsifying_min for
+    its own neighbourhood: the smallest left singular vector of V(N(j), N(j)^c).  Rows with all 9
+    neighbours share the weights of the grid's central node (the translation invariance the paper
+    invokes); every edge and corner row gets its own (truncating the central weights instead left
+    the dropped part of A L^(C) large in those rows and tripled the GMRES steps).
   * Filter: C^(C) keeps the entries of A L^(C) whose row and column nodes are at most `width`
     grid steps apart in each direction (the compact finite-difference pattern for width 1);
     width=None keeps everything (then S^(C) = (L^(C))^-1 exactly).
@@ -57,29 +59,40 @@ def neighbours(grid, j):
     return np.array(out)
 
 
-def stencil_weights(grid, V):
-    """v of eq. sparsifying_min at the central node j0: the unit row vector minimising
-    ||v V(N(j0), N(j0)^c)||, the left singular vector of the smallest singular value.
-    Returns (v, offsets (dx, dy) of its entries, smallest / largest singular value)."""
-    j0 = (grid.ny // 2) * grid.nx + grid.nx // 2
-    nb = neighbours(grid, j0)
-    assert nb.size == 9, "the grid needs at least 3 x 3 nodes"
+def row_weights(grid, V, j):
+    """Eq. sparsifying_min for row j: the unit vector v on N(j) minimising ||v V(N(j), N(j)^c)||,
+    the left singular vector of the smallest singular value.  Returns (N(j), v, smallest /
+    largest singular value)."""
+    nb = neighbours(grid, j)
     comp = np.setdiff1d(np.arange(grid.n), nb)
     U, s, _ = np.linalg.svd(V[np.ix_(nb, comp)])
-    v = U[:, -1].conj()
+    return nb, U[:, -1].conj(), s[-1] / s[0]
+
+
+def stencil_weights(grid, V):
+    """The weights of the grid's central node j0 and their offsets (dx, dy), with the smallest /
+    largest singular value."""
+    j0 = (grid.ny // 2) * grid.nx + grid.nx // 2
+    nb, v, ratio = row_weights(grid, V, j0)
+    assert nb.size == 9, "the grid needs at least 3 x 3 nodes"
     iy0, ix0 = divmod(j0, grid.nx)
     offs = [(int(j % grid.nx) - ix0, int(j // grid.nx) - iy0) for j in nb]
-    return v, offs, s[-1] / s[0]
+    return v, offs, ratio
 
 
-def stencil_matrix(grid, v, offs):
-    """A: row j holds v on node j's neighbours at the same offsets (dense (N_C, N_C))."""
+def stencil_matrix(grid, V):
+    """A (dense (N_C, N_C)): the central weights on every row with 9 neighbours, each edge and
+    corner row's own weights on its 6 or 4."""
+    v, offs, _ = stencil_weights(grid, V)
     A = np.zeros((grid.n, grid.n), dtype=np.complex128)
     for j in range(grid.n):
         iy, ix = divmod(j, grid.nx)
-        for (dx, dy), w in zip(offs, v):
-            if 0 <= ix + dx < grid.nx and 0 <= iy + dy < grid.ny:
+        if 0 < ix < grid.nx - 1 and 0 < iy < grid.ny - 1:
+            for (dx, dy), w in zip(offs, v):
                 A[j, (iy + dy) * grid.nx + ix + dx] = w
+        else:
+            nb, w, _ = row_weights(grid, V, j)
+            A[j, nb] = w
     return A
 
 
@@ -98,6 +111,6 @@ def sparsifying_preconditioner(grid, k, m, width=1):
     V = cartesian_volume(grid, k)
     L = np.eye(grid.n) + k * k * V * np.asarray(m)[None, :]
     v, offs, ratio = stencil_weights(grid, V)
-    A = stencil_matrix(grid, v, offs)
+    A = stencil_matrix(grid, V)
     C = filtered_product(grid, A, L, width)
     return np.linalg.solve(C, A), L, v, offs, ratio

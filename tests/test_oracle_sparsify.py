@@ -49,6 +49,22 @@ def test_stencil_weights_minimise_the_far_block():
     lap /= np.linalg.norm(lap)
     assert np.linalg.norm(lap @ B) > 10 * best
     assert ratio < 1e-3
+    # an edge row (6 neighbours) and a corner row (4) minimise over their own neighbourhoods, and
+    # beat the central weights truncated to them
+    A = spf.stencil_matrix(g, V)
+    for j in (g.nx // 2, 0):
+        nb = spf.neighbours(g, j)
+        Bj = V[np.ix_(nb, np.setdiff1d(np.arange(g.n), nb))]
+        w = A[j, nb]
+        own = np.linalg.norm(w @ Bj)
+        assert abs(np.linalg.norm(w) - 1) < 1e-14 and abs(own - np.linalg.svd(Bj, compute_uv=False)[-1]) < 1e-12 * own
+        Uj = rng.standard_normal((2000, nb.size)) + 1j * rng.standard_normal((2000, nb.size))
+        Uj /= np.linalg.norm(Uj, axis=1)[:, None]
+        assert np.all(np.linalg.norm(Uj @ Bj, axis=1) >= own * (1 - 1e-9))
+        iy, ix = divmod(j, g.nx)
+        trunc = np.array([v[o] for o, (dx, dy) in enumerate(offs)
+                          if 0 <= ix + dx < g.nx and 0 <= iy + dy < g.ny])
+        assert np.linalg.norm(trunc @ Bj) / np.linalg.norm(trunc) > 10 * own
 
 
 def test_unfiltered_product_gives_the_exact_inverse():
@@ -83,3 +99,45 @@ def test_sparsified_inverse_cuts_gmres_steps():
     y, it1, _ = krylov.gmres(lambda u: L @ (S @ u), b, tol=1e-8, maxit=400)
     assert np.linalg.norm(L @ (S @ y) - b) <= 1e-7 * np.linalg.norm(b)
     assert it0 > 60 and it1 < it0 / 2, (it0, it1)
+
+
+def test_sparsified_S_preconditions_the_nystrom_system():
+    """P = I + T_C^Q (S - I) T_Q^C with S = S^(C) on the Nystrom system of a small disk (k = 8,
+    N = 1 600, dense oracle matrices): about as few GMRES steps as with the exact inverse of the
+    same Cartesian system and a third of the plain count; the central weights truncated at the
+    grid's edge instead of each edge row's own take many more."""
+    from oracle import green, vdim
+    from oracle import transfer as tr
+    from workloads import problems as P
+    prob = P.disk_problem(4, 8.0, 2.0)
+    k = prob.k
+    V = green.far_matrix(prob.mesh.x, prob.mesh.y, prob.mesh.w, k) + vdim.correction_matrix(prob.mesh, k).toarray()
+    L = np.eye(prob.n_nodes) + k * k * V * prob.m[None, :]
+    b = prob.incident()
+    b = b[0] if b.ndim == 2 else b
+    h, pad = 0.8 / k, 0.02
+    x0, y0 = prob.mesh.x.min() - pad, prob.mesh.y.min() - pad
+    nx = int(np.ceil((prob.mesh.x.max() + pad - x0) / h)) + 1
+    ny = int(np.ceil((prob.mesh.y.max() + pad - y0) / h)) + 1
+    g = Grid(x0, y0, h, nx, ny)
+    T = tr.cart_to_quad(g, prob.mesh.x, prob.mesh.y)
+    zx, zy = g.nodes()
+    m = np.asarray(prob.m_at(zx, zy), dtype=np.complex128)
+    S, Lc, v, offs, _ = spf.sparsifying_preconditioner(g, k, m, width=1)
+
+    def steps(Smat):
+        return krylov.gmres(lambda u: L @ tr.precondition(T, u[None, :], lambda c: c @ Smat.T)[0], b,
+                            tol=1e-8, maxit=600)[1]
+
+    it_plain = krylov.gmres(lambda u: L @ u, b, tol=1e-8, maxit=600)[1]
+    it_s, it_inv = steps(S), steps(np.linalg.inv(Lc))
+    # the central weights truncated at the edge
+    At = np.zeros((g.n, g.n), dtype=np.complex128)
+    for j in range(g.n):
+        iy, ix = divmod(j, g.nx)
+        for (dx, dy), w in zip(offs, v):
+            if 0 <= ix + dx < g.nx and 0 <= iy + dy < g.ny:
+                At[j, (iy + dy) * g.nx + ix + dx] = w
+    it_t = steps(np.linalg.solve(spf.filtered_product(g, At, Lc, 1), At))
+    print(f"plain {it_plain}, S^(C) {it_s}, exact inverse {it_inv}, truncated edge weights {it_t}")
+    assert it_s <= it_inv + 3 and 3 * it_s <= it_plain and it_t >= it_s + 10
