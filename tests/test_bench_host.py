@@ -45,15 +45,16 @@ def test_more_than_one_gpu_is_refused():
 def test_sparsifying_preconditioner_matches_the_oracle():
     """The bench's host construction of S^(C) = (C^(C))^-1 A (library host Green's values, 25
     offsets) equals the oracle's dense construction (SciPy Hankel values, the full product A L^(C)
-    and its 3 x 3 filter) on a 21 x 21 grid over a disk; S does not depend on the phase of the
-    singular vector, so the two are compared entry by entry."""
+    and its 3 x 3 filter) on 21 x 21 and 23 x 17 grids over a disk; S does not depend on the
+    phase of each row's singular vector, so the two are compared entry by entry."""
     from oracle import sparsify as spf
     from oracle.transfer import Grid
     k, h = 8.0, 0.11
-    g = Grid(-1.1, -1.1, h, 21, 21)
-    zx, zy = g.nodes()
-    m = np.where(np.hypot(zx, zy) < 1.0, -1.0, 0.0)
-    S, ratio = bench.sparsifying_S(g.x0, g.y0, g.h, g.nx, g.ny, k, m)
-    So, _, _, _, ratio_o = spf.sparsifying_preconditioner(g, k, m, width=1)
-    assert abs(ratio - ratio_o) <= 1e-9 * ratio_o
-    assert np.abs(S - So).max() <= 1e-12 * np.abs(So).max()
+    for nx, ny in ((21, 21), (23, 17)):   # a non-square grid catches swapped indices
+        g = Grid(-1.1, -0.9, h, nx, ny)
+        zx, zy = g.nodes()
+        m = np.where(np.hypot(zx, zy) < 0.85, -1.0, 0.0)
+        S, ratio = bench.sparsifying_S(g.x0, g.y0, g.h, g.nx, g.ny, k, m)
+        So, _, _, _, ratio_o = spf.sparsifying_preconditioner(g, k, m, width=1)
+        assert abs(ratio - ratio_o) <= 1e-9 * ratio_o
+        assert np.abs(S - So).max() <= 1e-12 * np.abs(So).max()
