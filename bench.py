@@ -243,15 +243,25 @@ def solve_form(op, b, form, args, adjoint=False):
                 log(f"  column {c}: {its[-1]} iterations, relres {info['relres'][0]:.2e}, {info['seconds']:.2f} s")
         return torch.cat(xs), t.seconds, applies, 0, t, its, cols
     if form in ("pc", "pcm"):
-        ST = args._cartesian_S
-        if adjoint:
-            # the adjoint system takes P^H = I + T_C^Q (D^-1 S^H D - I) T_Q^C (D: ls_transfer_colsums)
-            if getattr(args, "_cartesian_S_adj", None) is None:
+        # the adjoint system takes P^H = I + T_C^Q (D^-1 S^H D - I) T_Q^C (D: ls_transfer_colsums)
+        S = args._cartesian_S
+        if isinstance(S, tuple):
+            # block LU appliers of S and S^H (BlockSparsifier)
+            if adjoint:
                 d = torch.tensor(op.transfer_colsums(), device="cuda")
-                args._cartesian_S_adj = (d[:, None] * ST.conj().T / d[None, :]).contiguous()
-            ST = args._cartesian_S_adj
+                apply = lambda v: S[1](v * d) / d
+            else:
+                apply = S[0]
+        else:
+            ST = S
+            if adjoint:
+                if getattr(args, "_cartesian_S_adj", None) is None:
+                    d = torch.tensor(op.transfer_colsums(), device="cuda")
+                    args._cartesian_S_adj = (d[:, None] * ST.conj().T / d[None, :]).contiguous()
+                ST = args._cartesian_S_adj
+            apply = lambda v: v @ ST
         with Timer(op) as t:
-            x, info = op.solve_precond(b, lambda v: v @ ST, tol=args.tol, maxit=args.maxit, restart=args.restart,
+            x, info = op.solve_precond(b, apply, tol=args.tol, maxit=args.maxit, restart=args.restart,
                                        adjoint=adjoint, precision="mixed" if form == "pcm" else "fp64",
                                        inner_tol=args.relax)
         its = [int(v) for v in info["iters"]]
@@ -296,16 +306,21 @@ def cell_self_term(k, h):
     return (-1 + 0.5j * math.pi * a * k * complex(hankel1(1, k * a))) / k ** 2
 
 
-def sparsifying_S(x0, y0, h, nx, ny, k, m):
-    """S^(C) = (C^(C))^-1 A of the sparsifying preconditioner (paper, Section 4, eqs.
-    sparsifying_min and LC_def), built on the host as a dense (nx ny)^2 array for the first-order
-    Cartesian system L^(C) = I + k^2 V^(C) M^(C): V^(C) is h^2 G off the diagonal (the library's
-    host Green's evaluation) and the cell's own term on it, m the contrast at the grid nodes.
-    A row's weights are the smallest left singular vector of V^(C)(N(j), N(j)^c) over its 3 x 3
-    neighbourhood within the grid: the central node's serve every row with all 9 neighbours (the
-    grid is uniform), and each edge and corner row gets its own on its 6 or 4.  C^(C) is A L^(C)
+STENCIL_OFFSETS = [(dx, dy) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+
+
+def sparsifying_stencil(x0, y0, h, nx, ny, k, m):
+    """The pieces of the sparsifying preconditioner (paper, Section 4, eqs. sparsifying_min and
+    LC_def) for the first-order Cartesian system L^(C) = I + k^2 V^(C) M^(C) on the grid
+    (x0 + ix h, y0 + iy h): V^(C) is h^2 G off the diagonal (the library's host Green's
+    evaluation) and the cell's own term on it, m the contrast at the grid nodes.  A row's weights
+    are the smallest left singular vector of V^(C)(N(j), N(j)^c) over its 3 x 3 neighbourhood
+    within the grid: the central node's serve every row with all 9 neighbours (the grid is
+    uniform), and each edge and corner row gets its own on its 6 or 4.  C^(C) is A L^(C)
     restricted to the 3 x 3 pattern, which needs V^(C) only at the 25 offsets of at most two
-    steps."""
+    steps.  Returns (W, E, ratio): W[j, o] = A[j, j + o] and E[j, o] = C^(C)[j, j + o] for the 9
+    offsets o of STENCIL_OFFSETS (0 where j + o is off the grid), and the central stencil's
+    smallest / largest singular value."""
     import numpy as np
 
     import paper_2608_17615_amd as lsg
@@ -319,7 +334,7 @@ def sparsifying_S(x0, y0, h, nx, ny, k, m):
         out = h * h * lsg.eval_green_host((k * h) ** 2 * np.where(d2 > 0, d2, 1.0))
         return np.where(d2 > 0, out, vself)
 
-    offs = [(dx, dy) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+    offs = STENCIL_OFFSETS
     rows = np.arange(nc)
 
     def shift(dx, dy):
@@ -339,23 +354,123 @@ def sparsifying_S(x0, y0, h, nx, ny, k, m):
 
     v, ratio = weights((ny // 2) * nx + nx // 2)
     W = np.tile(v, (nc, 1))
-    edge = np.nonzero((ix == 0) | (ix == nx - 1) | (iy == 0) | (iy == ny - 1))[0]
-    for j in edge:
+    for j in np.nonzero((ix == 0) | (ix == nx - 1) | (iy == 0) | (iy == ny - 1))[0]:
         W[j] = weights(j)[0]
     m = np.asarray(m, dtype=np.complex128)
-    A = np.zeros((nc, nc), dtype=np.complex128)
-    C = np.zeros((nc, nc), dtype=np.complex128)
+    E = np.zeros((nc, 9), dtype=np.complex128)
     for o, (dxl, dyl) in enumerate(offs):
-        okl, jl = shift(dxl, dyl)
-        A[rows[okl], jl[okl]] = W[okl, o]
-        for dx2, dy2 in offs:
+        okl, _ = shift(dxl, dyl)
+        W[~okl, o] = 0.0
+        for o2, (dx2, dy2) in enumerate(offs):
             ok2, j2 = shift(dx2, dy2)
             ok = okl & ok2
-            same = dxl == dx2 and dyl == dy2
+            same = o == o2
             # L^(C)[l, j2] = [l == j2] + k^2 V^(C)(z_l - z_j2) m(z_j2)
             lval = (1.0 if same else 0.0) + k * k * vgrid(dxl - dx2, dyl - dy2) * m[j2[ok]]
-            C[rows[ok], j2[ok]] += W[ok, o] * lval
-    return np.linalg.solve(C, A), float(ratio)
+            E[ok, o2] += W[ok, o] * lval
+    return W, E, float(ratio)
+
+
+def stencil_to_dense(X, nx, ny):
+    """The (nx ny)^2 matrix with X[j, o] at (j, j + o)."""
+    import numpy as np
+    nc = nx * ny
+    iy, ix = np.divmod(np.arange(nc), nx)
+    M = np.zeros((nc, nc), dtype=np.complex128)
+    for o, (dx, dy) in enumerate(STENCIL_OFFSETS):
+        ok = (ix + dx >= 0) & (ix + dx < nx) & (iy + dy >= 0) & (iy + dy < ny)
+        j = np.nonzero(ok)[0]
+        M[j, j + dy * nx + dx] = X[j, o]
+    return M
+
+
+def sparsifying_S(x0, y0, h, nx, ny, k, m):
+    """S^(C) = (C^(C))^-1 A as a dense (nx ny)^2 array (host LAPACK), with the central stencil's
+    singular-value ratio (sparsifying_stencil)."""
+    import numpy as np
+    W, E, ratio = sparsifying_stencil(x0, y0, h, nx, ny, k, m)
+    return np.linalg.solve(stencil_to_dense(E, nx, ny), stencil_to_dense(W, nx, ny)), ratio
+
+
+class BlockSparsifier:
+    """S^(C) = (C^(C))^-1 A (or its adjoint A^H (C^(C))^-H) applied without forming it.  With the
+    grid numbered row by row, C^(C) is block tridiagonal in blocks of one grid row (nx x nx):
+    block LU on the host at setup (Sigma_0 = D_0, Sigma_i = D_i - L_i Sigma_{i-1}^-1 U_{i-1}, no
+    pivoting across blocks), then per application two sweeps of ny small matrix products on the
+    device and one 9-point stencil for A.  Memory 3 ny nx^2 complex values instead of (nx ny)^2."""
+
+    def __init__(self, W, E, nx, ny, device, adjoint=False):
+        import numpy as np
+        import torch
+        self.nx, self.ny, self.adjoint = nx, ny, adjoint
+        Eb = E.reshape(ny, nx, 9)
+        ar = np.arange(nx)
+
+        def block(i, dy):
+            """The block of C^(C) at block row i, column block i + dy."""
+            out = np.zeros((nx, nx), dtype=np.complex128)
+            for o, (dx, ody) in enumerate(STENCIL_OFFSETS):
+                if ody != dy:
+                    continue
+                ok = (ar + dx >= 0) & (ar + dx < nx)
+                out[ar[ok], ar[ok] + dx] = Eb[i, ar[ok], o]
+            return out
+
+        D = [block(i, 0) for i in range(ny)]
+        Lo = [block(i, -1) for i in range(ny)]    # block (i, i - 1)
+        Up = [block(i, 1) for i in range(ny)]     # block (i, i + 1)
+        if adjoint:
+            # C^H: block (i, i) = D_i^H, (i, i - 1) = U_{i-1}^H, (i, i + 1) = L_{i+1}^H
+            D, Lo, Up = ([d.conj().T for d in D], [np.zeros((nx, nx))] + [Up[i - 1].conj().T for i in range(1, ny)],
+                         [Lo[i + 1].conj().T for i in range(ny - 1)] + [np.zeros((nx, nx))])
+        G, M = [np.linalg.inv(D[0])], [np.zeros((nx, nx), dtype=np.complex128)]
+        for i in range(1, ny):
+            Mi = Lo[i] @ G[i - 1]
+            M.append(Mi)
+            G.append(np.linalg.inv(D[i] - Mi @ Up[i - 1]))
+        # row-major right-hand sides (B, nx) multiply the transposes from the right
+        t = lambda xs: torch.tensor(np.stack([x.T for x in xs]), device=device)
+        self.Gt, self.Mt, self.Ut = t(G), t(M), t(Up)
+        Wg = W.reshape(ny, nx, 9)
+        self.W = torch.tensor(np.ascontiguousarray(np.moveaxis(Wg, 2, 0)), device=device)   # (9, ny, nx)
+
+    def _stencil(self, c):
+        """A c, or A^H c for the adjoint, on (B, ny, nx) grid arrays."""
+        import torch
+        nx, ny = self.nx, self.ny
+        out = torch.zeros_like(c)
+        if not self.adjoint:
+            cp = torch.nn.functional.pad(c, (1, 1, 1, 1))
+            for o, (dx, dy) in enumerate(STENCIL_OFFSETS):
+                out += self.W[o] * cp[:, 1 + dy:1 + dy + ny, 1 + dx:1 + dx + nx]
+        else:
+            # (A^H c)[l] = sum_o conj(W[l - o, o]) c[l - o]
+            for o, (dx, dy) in enumerate(STENCIL_OFFSETS):
+                t = torch.nn.functional.pad(self.W[o].conj() * c, (1, 1, 1, 1))
+                out += t[:, 1 - dy:1 - dy + ny, 1 - dx:1 - dx + nx]
+        return out
+
+    def _solve(self, y):
+        """(C^(C))^-1 y (or ^-H), y of shape (B, ny, nx)."""
+        import torch
+        z = [y[:, 0]]
+        for i in range(1, self.ny):
+            z.append(y[:, i] - z[-1] @ self.Mt[i])
+        x = [None] * self.ny
+        x[-1] = z[-1] @ self.Gt[-1]
+        for i in range(self.ny - 2, -1, -1):
+            x[i] = (z[i] - x[i + 1] @ self.Ut[i]) @ self.Gt[i]
+        return torch.stack(x, dim=1)
+
+    def __call__(self, v):
+        """S^(C) v (or S^(C)^H v) for row-major grid vectors v of shape (B, nx ny)."""
+        B = v.shape[0]
+        c = v.reshape(B, self.ny, self.nx)
+        if not self.adjoint:
+            out = self._solve(self._stencil(c))
+        else:
+            out = self._stencil(self._solve(c))
+        return out.reshape(B, self.nx * self.ny)
 
 
 def cartesian_inverse(op, prob, kh, kind="inverse"):
@@ -364,8 +479,9 @@ def cartesian_inverse(op, prob, kh, kind="inverse"):
     from the library's own Green's evaluation, the cell's own term integrated over the disk of the
     cell's area, the medium's contrast at the grid nodes), inverted by host LAPACK.  kind
     "sparsify": the sparsifying preconditioner S^(C) = (C^(C))^-1 A of the same discretization
-    (sparsifying_S), applied as a dense matrix.  Registers the grid with the operator and returns
-    (S^T on the device, grid size, seconds)."""
+    (sparsifying_S), applied as a dense matrix; "sparsify-lu": the same S applied through the block
+    LU of C^(C) (BlockSparsifier).  Registers the grid with the operator and returns (S^T on the
+    device, or the pair of appliers of S and S^H, grid size, seconds)."""
     import numpy as np
     import torch
 
@@ -382,6 +498,13 @@ def cartesian_inverse(op, prob, kh, kind="inverse"):
         op.set_grid(x0, y0, h, nx, ny)
         torch.cuda.synchronize()
         return ST, nx * ny, time.perf_counter() - t0
+    if kind == "sparsify-lu":
+        W, E, ratio = sparsifying_stencil(x0, y0, h, nx, ny, k, prob.m_at(x0 + ix * h, y0 + iy * h))
+        log(f"stencil: smallest / largest singular value {ratio:.2e}")
+        appliers = (BlockSparsifier(W, E, nx, ny, "cuda"), BlockSparsifier(W, E, nx, ny, "cuda", adjoint=True))
+        op.set_grid(x0, y0, h, nx, ny)
+        torch.cuda.synchronize()
+        return appliers, nx * ny, time.perf_counter() - t0
     zx = torch.tensor(x0 + ix * h, device="cuda")
     zy = torch.tensor(y0 + iy * h, device="cuda")
     z2 = (k * k) * ((zx[:, None] - zx[None, :]) ** 2 + (zy[:, None] - zy[None, :]) ** 2)
@@ -584,9 +707,10 @@ def main():
                          "first-order Cartesian inverse as S (c3, c5); pcm: the same with relaxed mixed "
                          "precision")
     ap.add_argument("--kh", type=float, default=0.8, help="pc: k times the Cartesian grid spacing")
-    ap.add_argument("--precond", default="inverse", choices=["inverse", "sparsify"],
-                    help="pc: S is the dense inverse of the first-order Cartesian system (inverse) or the "
-                         "sparsifying preconditioner (C^(C))^-1 A of the same system (sparsify)")
+    ap.add_argument("--precond", default="inverse", choices=["inverse", "sparsify", "sparsify-lu"],
+                    help="pc: S is the dense inverse of the first-order Cartesian system (inverse), the "
+                         "sparsifying preconditioner (C^(C))^-1 A of the same system as a dense matrix "
+                         "(sparsify), or the same applied through a block LU of C^(C) (sparsify-lu)")
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-8)
