@@ -1,31 +1,41 @@
 #!/usr/bin/env python3
 """Benchmark of the Lippmann-Schwinger Nystrom hot path on one MI355X.
 
-Default workload (c2): the two-material disk (inclusion |x| < 0.5 with n = 3, annulus
-0.5 < |x| < 1 with n = 1 + 0.5 exp(-|x|^2)), k = 20, O-grid/annulus mesh with 15 inner cells
-(N = 58 500 nodes), one plane wave along +x.  One step = one FP64 GMRES solve (no restart,
-x0 = 0) of L u = b to a relative residual of 1e-8, every operator application being the
-far-field Green's sum over all N(N-1) node pairs plus the sparse correction.
+Default workload (c3): the unit disk with n = 2, k = 40, O-grid mesh with 35 cells per side of
+the central square (N = 122 500 nodes), 64 plane waves at evenly spaced angles as one right-hand
+side block.  Form pcm: flexible GMRES (no restart within a pass, x0 = 0), right-preconditioned by
+the paper's P = I + T_C^Q (S - I) T_Q^C with the library's sparsifying S^(C) on a grid of
+k h = 0.5, in mixed-precision refinement passes: every Arnoldi application uses the FP32
+matrix-core Green's tiles (FP64 correction, Arnoldi and residuals), and each pass starts from the
+FP64 residual, until that meets the tolerance.  One step =
+one solve of all 64 waves to a relative residual of 1e-8 in every column; every operator
+application is the far-field Green's sum over all N(N-1) node pairs plus the sparse correction.
+After the timed steps, untimed reference solves of one column by the plain FP64 kernel (one
+right-hand side at a time; with and without the preconditioner) give the time to 1e-8 of the
+plain form, extrapolated to 64 columns, and the speedups.
 
 Other workloads (--workload, one JSON line each):
   c1  unit disk, n^2 = 2, k = 2 pi, N = 2 500, one plane wave (plain FP64);
-  c3  unit disk, n^2 = 2, k = 40, N = 122 500, 64 directions, forms p64 / b64 / bm;
-  c4  16 seeded scatterers of uneven size in one handle, 8 directions each, forms p64 / bm;
+  c2  two-material disk (inclusion |x| < 0.5 with n = 3, annulus with n = 1 + 0.5 exp(-|x|^2)),
+      k = 20, N = 58 500, one plane wave, plain FP64 GMRES (form p64);
+  c4  16 seeded scatterers of uneven size in one handle, 8 directions each, each with its own
+      preconditioner (form pcm by default);
   c5  two-material disk at k = 40, N = 114 660, 16 directions: far-field misfit and its contrast
-      gradient through the forward and adjoint solves, forms p64 / b64 / bm;
+      gradient through the forward and adjoint solves;
   field  the scattered field (eq. field_recovery) of 16 plane waves on the c3 mesh at the exterior
       points of a Cartesian grid over the enclosing square.
 Forms: p64 = FP64 VALU kernel, one right-hand side at a time (columns beyond --cols are
 extrapolated from the timed ones, and the line says so); b64 = all right-hand sides together on
-FP64 matrix-core tiles; bm = all together, FP32 matrix-core tiles inside FP64 GMRES (relaxed).
+FP64 matrix-core tiles; bm = all together, FP32 matrix-core tiles inside FP64 GMRES (relaxed);
+pc / pcm = b64 / bm with the library's sparsifying preconditioner.
 
 Reported: Green interactions per second over the timed work (value), the time to a 1e-8
 residual (ms_per_step), the dominant kernel's roofline position (average launch duration from
 HIP events the library records around each launch on the caller's stream), and the oracle's
 own throughput on a bounded sample of the same far sum on the host cores.
 
-Usage: python bench.py [--workload c2] [--form p64] [--steps K] [--warmup W] [--gpus 1]
-                       [--no-cpu-baseline]
+Usage: python bench.py [--workload c3] [--form pcm] [--steps K] [--warmup W] [--gpus 1]
+                       [--no-cpu-baseline] [--no-compare]
 """
 import argparse
 import json
@@ -112,7 +122,9 @@ def cpu_baseline(prob, rows_total=1024, workers=None):
     import numpy as np
 
     from workloads import problems as P
-    workers = workers or max(1, min(os.cpu_count() or 1, 16))
+    # the host cores this process may use, at most 16 (one GPU's share of the box)
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    workers = workers or max(1, min(avail, 16))
     n = prob.n_nodes
     rng = np.random.default_rng(0)
     rows = np.sort(rng.choice(n, min(rows_total, n), replace=False))
@@ -125,7 +137,8 @@ def cpu_baseline(prob, rows_total=1024, workers=None):
         done = sum(pool.map(_oracle_rows, [(prob.mesh.x, prob.mesh.y, prob.mesh.w, prob.k, f, c) for c in chunks]))
         dt = time.perf_counter() - t0
     gis = done * (n - 1) / dt / 1e9
-    return {"value": gis, "unit": "GI/s", "cores": workers, "kind": "oracle",
+    return {"value": gis, "unit": "GI/s", "cores": workers, "kind": "oracle", "host_cpu_count": os.cpu_count(),
+            "host_cpus_available": avail,
             "sample": f"punctured Green's far sum (SciPy AMOS H0), one right-hand side, for {done} seeded "
                       f"target rows x {n - 1} sources of the {prob.name} mesh ({done * (n - 1):.3g} "
                       f"interactions, {dt:.2f} s wall); the sparse correction rows (10 per subdomain and "
@@ -173,15 +186,6 @@ class Timer:
         self.prof = self.op.profile(reset=True)
         self.op.profile(False)
         self.far_avg_s = self.prof["far_ms"] / max(self.prof["far_launches"], 1) / 1e3
-
-
-def far_kernel_avg(op, x, precision, reps=5):
-    """Average far-kernel launch time of reps applications (the dominant kernel of a form)."""
-    op.apply(x, precision=precision)
-    with Timer(op) as t:
-        for _ in range(reps):
-            op.apply(x, precision=precision)
-    return t.far_avg_s
 
 
 # ---------------------------------------------------------------- c2 (default) and c1
@@ -243,27 +247,12 @@ def solve_form(op, b, form, args, adjoint=False):
                 log(f"  column {c}: {its[-1]} iterations, relres {info['relres'][0]:.2e}, {info['seconds']:.2f} s")
         return torch.cat(xs), t.seconds, applies, 0, t, its, cols
     if form in ("pc", "pcm"):
-        # the adjoint system takes P^H = I + T_C^Q (D^-1 S^H D - I) T_Q^C (D: ls_transfer_colsums)
-        S = args._cartesian_S
-        if isinstance(S, tuple):
-            # block LU appliers of S and S^H (BlockSparsifier)
-            if adjoint:
-                d = torch.tensor(op.transfer_colsums(), device="cuda")
-                apply = lambda v: S[1](v * d) / d
-            else:
-                apply = S[0]
-        else:
-            ST = S
-            if adjoint:
-                if getattr(args, "_cartesian_S_adj", None) is None:
-                    d = torch.tensor(op.transfer_colsums(), device="cuda")
-                    args._cartesian_S_adj = (d[:, None] * ST.conj().T / d[None, :]).contiguous()
-                ST = args._cartesian_S_adj
-            apply = lambda v: v @ ST
+        # right preconditioner P = I + T_C^Q (S - I) T_Q^C with the library's S^(C) on every
+        # scatterer (P^H for the adjoint system)
         with Timer(op) as t:
-            x, info = op.solve_precond(b, apply, tol=args.tol, maxit=args.maxit, restart=args.restart,
+            x, info = op.solve_precond(b, None, tol=args.tol, maxit=args.maxit, restart=args.restart,
                                        adjoint=adjoint, precision="mixed" if form == "pcm" else "fp64",
-                                       inner_tol=args.relax)
+                                       inner_tol=args.relax, scheme=args.scheme)
         its = [int(v) for v in info["iters"]]
         log(f"  preconditioned: max {max(its)} iterations, max relres {np.max(info['relres']):.2e}, applies "
             f"{info['n_apply_fp64']}+{info['n_apply_mixed']}, {info['seconds']:.2f} s")
@@ -275,7 +264,8 @@ def solve_form(op, b, form, args, adjoint=False):
         for c0 in range(0, B, batch):
             x, info = op.solve(b[c0:c0 + batch], tol=args.tol, maxit=args.maxit, precision=prec, adjoint=adjoint,
                                restart=args.restart, inner_maxit=args.inner if form == "bm" else 0,
-                               inner_tol=args.relax if form == "bm" else 0.0)
+                               inner_tol=args.relax if form == "bm" else 0.0,
+                               scheme=args.scheme if form == "bm" else "relaxed")
             xs.append(x)
             its += [int(v) for v in info["iters"]]
             a64 += int(info["n_apply_fp64"])
@@ -286,247 +276,78 @@ def solve_form(op, b, form, args, adjoint=False):
     return torch.cat(xs), t.seconds, a64, amx, t, its, B
 
 
-def cartesian_grid(prob, kh, pad=0.02):
-    """(x0, y0, h, nx, ny) of the Cartesian grid of spacing kh / k over the scatterer's nodes."""
-    import math
-    h = kh / prob.k
-    x, y = prob.mesh.x, prob.mesh.y
-    x0, y0 = x.min() - pad, y.min() - pad
-    nx = int(math.ceil((x.max() + pad - x0) / h)) + 1
-    ny = int(math.ceil((y.max() + pad - y0) / h)) + 1
-    return x0, y0, h, nx, ny
+# a scatterer gets the Cartesian preconditioner only when its quadrature nodes resolve the wave
+# inside it: k sqrt(max n) times the mean node spacing sqrt(area / N) at most this (about 8 nodes per
+# interior wavelength); on coarser meshes the Nystrom system is far from the continuous operator the
+# Cartesian system approximates, and the preconditioned iteration stagnates
+MAX_RESOLUTION = 0.75
 
 
-def cell_self_term(k, h):
-    """Integral of G over the disk of area h^2 centred on the node: (-1 + (i pi/2) k a H1(k a)) / k^2."""
-    import math
-
-    from scipy.special import hankel1
-    a = h / math.sqrt(math.pi)
-    return (-1 + 0.5j * math.pi * a * k * complex(hankel1(1, k * a))) / k ** 2
-
-
-STENCIL_OFFSETS = [(dx, dy) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
-
-
-def sparsifying_stencil(x0, y0, h, nx, ny, k, m):
-    """The pieces of the sparsifying preconditioner (paper, Section 4, eqs. sparsifying_min and
-    LC_def) for the first-order Cartesian system L^(C) = I + k^2 V^(C) M^(C) on the grid
-    (x0 + ix h, y0 + iy h): V^(C) is h^2 G off the diagonal (the library's host Green's
-    evaluation) and the cell's own term on it, m the contrast at the grid nodes.  A row's weights
-    are the smallest left singular vector of V^(C)(N(j), N(j)^c) over its 3 x 3 neighbourhood
-    within the grid: the central node's serve every row with all 9 neighbours (the grid is
-    uniform), and each edge and corner row gets its own on its 6 or 4.  C^(C) is A L^(C)
-    restricted to the 3 x 3 pattern, which needs V^(C) only at the 25 offsets of at most two
-    steps.  Returns (W, E, ratio): W[j, o] = A[j, j + o] and E[j, o] = C^(C)[j, j + o] for the 9
-    offsets o of STENCIL_OFFSETS (0 where j + o is off the grid), and the central stencil's
-    smallest / largest singular value."""
+def resolution(p):
+    """k sqrt(max n) x mean node spacing of a problem (n = 1 - m at the nodes)."""
     import numpy as np
-
-    import paper_2608_17615_amd as lsg
-    nc = nx * ny
-    iy, ix = np.divmod(np.arange(nc), nx)
-    vself = cell_self_term(k, h)
-
-    def vgrid(dx, dy):
-        """V^(C) between nodes dx, dy steps apart (arrays)."""
-        d2 = np.asarray(dx * dx + dy * dy, dtype=np.float64)
-        out = h * h * lsg.eval_green_host((k * h) ** 2 * np.where(d2 > 0, d2, 1.0))
-        return np.where(d2 > 0, out, vself)
-
-    offs = STENCIL_OFFSETS
-    rows = np.arange(nc)
-
-    def shift(dx, dy):
-        ok = (ix + dx >= 0) & (ix + dx < nx) & (iy + dy >= 0) & (iy + dy < ny)
-        return ok, rows + dy * nx + dx
-
-    def weights(j):
-        """Smallest left singular vector over row j's neighbours (-> 9 slots, 0 where missing)."""
-        have = [o for o in range(9) if 0 <= ix[j] + offs[o][0] < nx and 0 <= iy[j] + offs[o][1] < ny]
-        nb = np.array([j + offs[o][1] * nx + offs[o][0] for o in have])
-        rest = np.setdiff1d(rows, nb)
-        B = vgrid(ix[rest][None, :] - ix[nb][:, None], iy[rest][None, :] - iy[nb][:, None])
-        U, sig, _ = np.linalg.svd(B, full_matrices=False)
-        w = np.zeros(9, dtype=np.complex128)
-        w[have] = U[:, -1].conj()
-        return w, sig[-1] / sig[0]
-
-    v, ratio = weights((ny // 2) * nx + nx // 2)
-    W = np.tile(v, (nc, 1))
-    for j in np.nonzero((ix == 0) | (ix == nx - 1) | (iy == 0) | (iy == ny - 1))[0]:
-        W[j] = weights(j)[0]
-    m = np.asarray(m, dtype=np.complex128)
-    E = np.zeros((nc, 9), dtype=np.complex128)
-    for o, (dxl, dyl) in enumerate(offs):
-        okl, _ = shift(dxl, dyl)
-        W[~okl, o] = 0.0
-        for o2, (dx2, dy2) in enumerate(offs):
-            ok2, j2 = shift(dx2, dy2)
-            ok = okl & ok2
-            same = o == o2
-            # L^(C)[l, j2] = [l == j2] + k^2 V^(C)(z_l - z_j2) m(z_j2)
-            lval = (1.0 if same else 0.0) + k * k * vgrid(dxl - dx2, dyl - dy2) * m[j2[ok]]
-            E[ok, o2] += W[ok, o] * lval
-    return W, E, float(ratio)
+    n_max = float(np.max(np.real(1.0 - np.asarray(p.m))))
+    return p.k * np.sqrt(max(n_max, 1.0)) * np.sqrt(p.mesh.w.sum() / p.n_nodes)
 
 
-def stencil_to_dense(X, nx, ny):
-    """The (nx ny)^2 matrix with X[j, o] at (j, j + o)."""
-    import numpy as np
-    nc = nx * ny
-    iy, ix = np.divmod(np.arange(nc), nx)
-    M = np.zeros((nc, nc), dtype=np.complex128)
-    for o, (dx, dy) in enumerate(STENCIL_OFFSETS):
-        ok = (ix + dx >= 0) & (ix + dx < nx) & (iy + dy >= 0) & (iy + dy < ny)
-        j = np.nonzero(ok)[0]
-        M[j, j + dy * nx + dx] = X[j, o]
-    return M
-
-
-def sparsifying_S(x0, y0, h, nx, ny, k, m):
-    """S^(C) = (C^(C))^-1 A as a dense (nx ny)^2 array (host LAPACK), with the central stencil's
-    singular-value ratio (sparsifying_stencil)."""
-    import numpy as np
-    W, E, ratio = sparsifying_stencil(x0, y0, h, nx, ny, k, m)
-    return np.linalg.solve(stencil_to_dense(E, nx, ny), stencil_to_dense(W, nx, ny)), ratio
-
-
-class BlockSparsifier:
-    """S^(C) = (C^(C))^-1 A (or its adjoint A^H (C^(C))^-H) applied without forming it.  With the
-    grid numbered row by row, C^(C) is block tridiagonal in blocks of one grid row (nx x nx):
-    block LU on the host at setup (Sigma_0 = D_0, Sigma_i = D_i - L_i Sigma_{i-1}^-1 U_{i-1}, no
-    pivoting across blocks), then per application two sweeps of ny small matrix products on the
-    device and one 9-point stencil for A.  Memory 3 ny nx^2 complex values instead of (nx ny)^2."""
-
-    def __init__(self, W, E, nx, ny, device, adjoint=False):
-        import numpy as np
-        import torch
-        self.nx, self.ny, self.adjoint = nx, ny, adjoint
-        Eb = E.reshape(ny, nx, 9)
-        ar = np.arange(nx)
-
-        def block(i, dy):
-            """The block of C^(C) at block row i, column block i + dy."""
-            out = np.zeros((nx, nx), dtype=np.complex128)
-            for o, (dx, ody) in enumerate(STENCIL_OFFSETS):
-                if ody != dy:
-                    continue
-                ok = (ar + dx >= 0) & (ar + dx < nx)
-                out[ar[ok], ar[ok] + dx] = Eb[i, ar[ok], o]
-            return out
-
-        D = [block(i, 0) for i in range(ny)]
-        Lo = [block(i, -1) for i in range(ny)]    # block (i, i - 1)
-        Up = [block(i, 1) for i in range(ny)]     # block (i, i + 1)
-        if adjoint:
-            # C^H: block (i, i) = D_i^H, (i, i - 1) = U_{i-1}^H, (i, i + 1) = L_{i+1}^H
-            D, Lo, Up = ([d.conj().T for d in D], [np.zeros((nx, nx))] + [Up[i - 1].conj().T for i in range(1, ny)],
-                         [Lo[i + 1].conj().T for i in range(ny - 1)] + [np.zeros((nx, nx))])
-        G, M = [np.linalg.inv(D[0])], [np.zeros((nx, nx), dtype=np.complex128)]
-        for i in range(1, ny):
-            Mi = Lo[i] @ G[i - 1]
-            M.append(Mi)
-            G.append(np.linalg.inv(D[i] - Mi @ Up[i - 1]))
-        # row-major right-hand sides (B, nx) multiply the transposes from the right
-        t = lambda xs: torch.tensor(np.stack([x.T for x in xs]), device=device)
-        self.Gt, self.Mt, self.Ut = t(G), t(M), t(Up)
-        Wg = W.reshape(ny, nx, 9)
-        self.W = torch.tensor(np.ascontiguousarray(np.moveaxis(Wg, 2, 0)), device=device)   # (9, ny, nx)
-
-    def _stencil(self, c):
-        """A c, or A^H c for the adjoint, on (B, ny, nx) grid arrays."""
-        import torch
-        nx, ny = self.nx, self.ny
-        out = torch.zeros_like(c)
-        if not self.adjoint:
-            cp = torch.nn.functional.pad(c, (1, 1, 1, 1))
-            for o, (dx, dy) in enumerate(STENCIL_OFFSETS):
-                out += self.W[o] * cp[:, 1 + dy:1 + dy + ny, 1 + dx:1 + dx + nx]
-        else:
-            # (A^H c)[l] = sum_o conj(W[l - o, o]) c[l - o]
-            for o, (dx, dy) in enumerate(STENCIL_OFFSETS):
-                t = torch.nn.functional.pad(self.W[o].conj() * c, (1, 1, 1, 1))
-                out += t[:, 1 - dy:1 - dy + ny, 1 - dx:1 - dx + nx]
-        return out
-
-    def _solve(self, y):
-        """(C^(C))^-1 y (or ^-H), y of shape (B, ny, nx)."""
-        import torch
-        z = [y[:, 0]]
-        for i in range(1, self.ny):
-            z.append(y[:, i] - z[-1] @ self.Mt[i])
-        x = [None] * self.ny
-        x[-1] = z[-1] @ self.Gt[-1]
-        for i in range(self.ny - 2, -1, -1):
-            x[i] = (z[i] - x[i + 1] @ self.Ut[i]) @ self.Gt[i]
-        return torch.stack(x, dim=1)
-
-    def __call__(self, v):
-        """S^(C) v (or S^(C)^H v) for row-major grid vectors v of shape (B, nx ny)."""
-        B = v.shape[0]
-        c = v.reshape(B, self.ny, self.nx)
-        if not self.adjoint:
-            out = self._solve(self._stencil(c))
-        else:
-            out = self._stencil(self._solve(c))
-        return out.reshape(B, self.nx * self.ny)
-
-
-def cartesian_inverse(op, prob, kh, kind="inverse"):
-    """The caller's S for the preconditioned form, on a grid of spacing kh / k.  kind "inverse":
-    the dense inverse of a first-order Cartesian discretization of L (off-diagonal h^2 G(z_i, z_j)
-    from the library's own Green's evaluation, the cell's own term integrated over the disk of the
-    cell's area, the medium's contrast at the grid nodes), inverted by host LAPACK.  kind
-    "sparsify": the sparsifying preconditioner S^(C) = (C^(C))^-1 A of the same discretization
-    (sparsifying_S), applied as a dense matrix; "sparsify-lu": the same S applied through the block
-    LU of C^(C) (BlockSparsifier).  Registers the grid with the operator and returns (S^T on the
-    device, or the pair of appliers of S and S^H, grid size, seconds)."""
-    import numpy as np
+def setup_precond(op, probs, kh):
+    """The library's sparsifying preconditioner S^(C) (ls_sparsify_setup) for every scatterer whose
+    mesh resolves its interior wave, on a grid of spacing kh / k over it; returns a summary for the
+    bench line."""
     import torch
 
-    import paper_2608_17615_amd as lsg
+    from workloads import problems as P
     t0 = time.perf_counter()
-    k = prob.k
-    x0, y0, h, nx, ny = cartesian_grid(prob, kh)
-    iy, ix = np.divmod(np.arange(nx * ny), nx)
-    if kind == "sparsify":
-        S, ratio = sparsifying_S(x0, y0, h, nx, ny, k, prob.m_at(x0 + ix * h, y0 + iy * h))
-        log(f"stencil: smallest / largest singular value {ratio:.2e}")
-        ST = torch.tensor(S.T.copy(), device="cuda")
-        del S
-        op.set_grid(x0, y0, h, nx, ny)
-        torch.cuda.synchronize()
-        return ST, nx * ny, time.perf_counter() - t0
-    if kind == "sparsify-lu":
-        W, E, ratio = sparsifying_stencil(x0, y0, h, nx, ny, k, prob.m_at(x0 + ix * h, y0 + iy * h))
-        log(f"stencil: smallest / largest singular value {ratio:.2e}")
-        appliers = (BlockSparsifier(W, E, nx, ny, "cuda"), BlockSparsifier(W, E, nx, ny, "cuda", adjoint=True))
-        op.set_grid(x0, y0, h, nx, ny)
-        torch.cuda.synchronize()
-        return appliers, nx * ny, time.perf_counter() - t0
-    zx = torch.tensor(x0 + ix * h, device="cuda")
-    zy = torch.tensor(y0 + iy * h, device="cuda")
-    z2 = (k * k) * ((zx[:, None] - zx[None, :]) ** 2 + (zy[:, None] - zy[None, :]) ** 2)
-    z2.fill_diagonal_(1.0)
-    L = lsg.eval_green(z2)
-    del z2
-    L.mul_(h * h)
-    L.diagonal().fill_(cell_self_term(k, h))
-    m = torch.tensor(np.asarray(prob.m_at(x0 + ix * h, y0 + iy * h), dtype=np.complex128), device="cuda")
-    L.mul_((k * k) * m[None, :])
-    L.diagonal().add_(1.0)
-    Lh = L.cpu().numpy()
-    del L
-    torch.cuda.empty_cache()
-    ST = torch.tensor(np.linalg.inv(Lh).T.copy(), device="cuda")
-    op.set_grid(x0, y0, h, nx, ny)
+    nodes, lu_res, sv, skipped = 0, 0.0, [], []
+    for s, p in enumerate(probs):
+        if p.m_at is None:
+            raise SystemExit("the preconditioned forms need the contrast off the nodes")
+        if resolution(p) > MAX_RESOLUTION:
+            skipped.append(s)
+            continue
+        g = P.cartesian_grid(p, kh)
+        info = op.sparsify_setup(*g, P.grid_contrast(p, g), s=s)
+        nodes += g[3] * g[4]
+        lu_res = max(lu_res, info["lu_residual"])
+        sv.append(info["sv_ratio"])
     torch.cuda.synchronize()
-    return ST, nx * ny, time.perf_counter() - t0
+    out = {"S": "sparsifying (C^(C))^-1 A, first-order V^(C), block LU by grid rows (library)", "k_h": kh,
+           "grid_nodes": nodes, "build_s": time.perf_counter() - t0, "lu_residual_max": lu_res,
+           "stencil_sv_ratio_min": min(sv), "unpreconditioned_scatterers": skipped,
+           "max_resolution": MAX_RESOLUTION}
+    if skipped:
+        log(f"preconditioner: scatterers {skipped} left unpreconditioned (under-resolved interior wave)")
+    log(f"preconditioner: {nodes} grid nodes, built in {out['build_s']:.2f} s, LU residual {lu_res:.1e}")
+    return out
+
+
+def dominant_tiles(prof):
+    """The tile kernel (FP64 or FP32) with the larger share of far-sum time in a profile, with its
+    launches, milliseconds and pair-RHS interactions."""
+    ms32, n32, p32 = prof["far_ms_mixed"], prof["far_launches_mixed"], prof["pair_rhs_mixed"]
+    ms64, n64, p64 = prof["far_ms"] - ms32, prof["far_launches"] - n32, prof["pair_rhs"] - p32
+    if ms32 >= ms64:
+        return True, n32, ms32, p32
+    return False, n64, ms64, p64
+
+
+def reference_column(op, b, args, precond):
+    """Untimed reference: one column solved alone (the FP64 VALU kernel, one right-hand side at a
+    time), with or without the library's preconditioner; returns (seconds, iterations, GI/s)."""
+    with Timer(op) as t:
+        if precond:
+            _, info = op.solve_precond(b[:1], None, tol=args.tol, maxit=args.maxit, restart=args.restart)
+        else:
+            _, info = op.solve(b[:1], tol=args.tol, maxit=args.maxit, restart=args.restart)
+    it = int(info["iters"][0])
+    log(f"  reference column ({'preconditioned' if precond else 'plain'} P64): {it} iterations, "
+        f"relres {info['relres'][0]:.2e}, {t.seconds:.2f} s")
+    return t.seconds, it, t.prof["pair_rhs"] / t.seconds / 1e9
 
 
 def run_batched(args, probs, label, B):
-    """c3 / c4: solve L u = b for B plane waves per scatterer with one form."""
+    """c3 / c4: solve L u = b for B plane waves per scatterer with one form; a step is one solve
+    of the whole block."""
     import numpy as np
     import torch
 
@@ -543,48 +364,86 @@ def run_batched(args, probs, label, B):
     tune = None
     pre = None
     if form in ("pc", "pcm"):
-        if len(probs) != 1 or probs[0].m_at is None:
-            raise SystemExit("--form pc needs one scatterer whose contrast is known off the nodes")
-        args._cartesian_S, nc, pre_s = cartesian_inverse(op, probs[0], args.kh, args.precond)
-        pre = {"S": args.precond, "k_h": args.kh, "grid_nodes": nc, "build_s": pre_s}
-        log(f"Cartesian S: {nc} grid nodes, built in {pre_s:.1f} s")
-    if form == "bm" and len(probs) > 1:
+        pre = setup_precond(op, probs, args.kh)
+    if form in ("bm", "pcm") and len(probs) > 1:
         tune = op.autotune(B, precision="mixed")
         log(f"autotune: {tune}")
-    x, secs, a64, amx, t, its, cols = solve_form(op, b, form, args)
+    steps = 1 if form == "p64" else args.steps
+    warm = 0 if form == "p64" else args.warmup
+    for w in range(warm):
+        solve_form(op, b, form, args)
+        log(f"warmup {w} done")
+    runs = []
+    for st in range(steps):
+        runs.append(solve_form(op, b, form, args))
+        log(f"step {st}: {runs[-1][1]:.3f} s")
+    x, _, a64, amx, t, its, cols = runs[-1]
+    secs = sum(r[1] for r in runs)
+    pair_rhs = sum(r[4].prof["pair_rhs"] for r in runs)
     pairs = sum(p.n_nodes * (p.n_nodes - 1) for p in probs)
     frac = z_fractions([(p.mesh, p.k) for p in probs])
     # interactions the far sums evaluated (the library leaves out scatterers whose systems have
     # all finished, so this is not applications x pairs for several scatterers)
-    value = t.prof["pair_rhs"] / secs / 1e9
+    value = pair_rhs / secs / 1e9
     if form == "p64":
         # every column is its own solve: scale the timed columns to all B
-        total_s = secs * B / cols
+        step_s = secs * B / cols
         roof = roofline_valu(flops_per_pair(frac, 1), pairs, t.far_avg_s)
         dtype = "f64"
+        kern = {"kernel": "far_fp64_kernel", "launches": t.prof["far_launches"], "ms_avg": t.far_avg_s * 1e3}
     else:
-        total_s = secs
-        single = form == "bm"
-        roof = roofline_mfma(pairs * B, far_kernel_avg(op, b, "mixed" if single else "fp64"), single)
+        step_s = secs / steps
+        prof = {k: sum(r[4].prof[k] for r in runs) for k in runs[-1][4].prof}
+        single, nl, ms, pr = dominant_tiles(prof)
+        roof = roofline_mfma(pr, ms / 1e3, single)
         dtype = "f32-mfma+f64" if form in ("bm", "pcm") else "f64"
-    # true FP64 residual of the returned solution
+        kern = {"kernel": "far_tile_kernel<float>" if single else "far_tile_kernel<double>",
+                "launches": nl, "ms_avg": ms / max(nl, 1), "share_of_step": ms / 1e3 / secs}
+        if len(probs) > 1:
+            kern["kernel"] = "far_tile_persistent<float>" if single else "far_tile_persistent<double>"
+    # true FP64 residual of the returned solution, per column and per (scatterer, column) system
     r = b[:x.shape[0]] - op.apply(x)
     relres = (torch.linalg.norm(r, dim=1) / torch.linalg.norm(b[:x.shape[0]], dim=1)).cpu().numpy()
+    per_scat = None
+    if len(probs) > 1:
+        per_scat = []
+        for s_, p in enumerate(probs):
+            o0, o1 = op.offsets[s_], op.offsets[s_] + p.n_nodes
+            rs = (torch.linalg.norm(r[:, o0:o1], dim=1) / torch.linalg.norm(b[:x.shape[0], o0:o1], dim=1)).max()
+            per_scat.append({"name": p.name, "N": p.n_nodes, "k": p.k, "resolution": resolution(p),
+                             "relres_max": float(rs.item())})
+        conv = sum(1 for q in per_scat if q["relres_max"] <= args.tol * 1.01)
+        log(f"  scatterers converged to {args.tol:g}: {conv} of {len(probs)}")
     check = None
-    if form == "bm":
+    if form in ("bm", "pcm"):
         # untimed: distance of the mixed-precision solution's first column from an FP64 solve of it
-        x64, _ = op.solve(b[:1], tol=args.tol, maxit=args.maxit, restart=args.restart)
+        if form == "pcm":
+            x64, _ = op.solve_precond(b[:1], None, tol=args.tol, maxit=args.maxit)
+        else:
+            x64, _ = op.solve(b[:1], tol=args.tol, maxit=args.maxit, restart=args.restart)
         check = float(((x[:1] - x64).abs().max() / x64.abs().max()).item())
         log(f"first column against FP64 GMRES: {check:.2e}")
+    compare = None
+    if args.compare and form != "p64" and len(probs) == 1:
+        p_s, p_it, p_gis = reference_column(op, b, args, False)
+        compare = {"p64_plain_column_s": p_s, "p64_plain_iterations": p_it, "p64_plain_gis": p_gis,
+                   "p64_plain_time_to_tol_s": p_s * B, "extrapolated": True}
+        if pre is not None:
+            c_s, c_it, c_gis = reference_column(op, b, args, True)
+            compare.update({"p64_precond_column_s": c_s, "p64_precond_iterations": c_it,
+                            "p64_precond_time_to_tol_s": c_s * B})
+            compare["speedup_vs_p64_precond"] = c_s * B / step_s
+        compare["speedup_vs_p64_plain"] = p_s * B / step_s
     cfg = {"workload": label, "form": form, "n_nodes": n, "scatterers": len(probs), "nrhs": B, "tol": args.tol,
-           "restart": args.restart, "inner": args.inner, "relax": args.relax, "batch": args.batch or B,
-           "columns_timed": cols,
-           "time_to_tol_s": total_s, "extrapolated": cols < B,
+           "step": "one solve of every right-hand side to the tolerance (true FP64 residual)",
+           "restart": args.restart, "inner": args.inner, "relax": args.relax, "scheme": args.scheme, "batch": args.batch or B,
+           "columns_timed": cols, "time_to_tol_s": step_s, "extrapolated": cols < B,
            "iterations_max": int(max(its)), "iterations_mean": float(np.mean(its)),
            "applies_fp64": a64, "applies_mixed": amx, "final_fp64_relres_max": float(relres.max()),
-           "setup_s": setup_s, "far_kernel_ms_avg": t.far_avg_s * 1e3, "z_range_fractions": frac,
-           "autotune": tune, "error_vs_fp64_column0": check, "preconditioner": pre}
-    return line(value, total_s * 1e3, 1, 0, dtype, cfg, roof, None), x
+           "setup_s": setup_s, "dominant_kernel": kern, "z_range_fractions": frac,
+           "autotune": tune, "error_vs_fp64_column0": check, "preconditioner": pre, "compare": compare,
+           "per_scatterer": per_scat}
+    return line(value, step_s * 1e3, steps, warm, dtype, cfg, roof, None), x
 
 
 def run_gradient(args, prob, label, B):
@@ -602,13 +461,7 @@ def run_gradient(args, prob, label, B):
     n = op.n
     b = torch.tensor(prob.incident(), device="cuda")
     thetas = P.receivers(128)
-    pre = None
-    if form in ("pc", "pcm"):
-        if prob.m_at is None:
-            raise SystemExit("--form pc needs a scatterer whose contrast is known off the nodes")
-        args._cartesian_S, nc, pre_s = cartesian_inverse(op, prob, args.kh, args.precond)
-        pre = {"S": args.precond, "k_h": args.kh, "grid_nodes": nc, "build_s": pre_s}
-        log(f"Cartesian S: {nc} grid nodes, built in {pre_s:.1f} s")
+    pre = setup_precond(op, [prob], args.kh) if form in ("pc", "pcm") else None
     # synthetic data: far field of the seeded contrast perturbation (input generation, untimed)
     m0 = torch.tensor(prob.m, device="cuda").to(torch.complex128)
     dm = torch.tensor(P.contrast_perturbation(prob.mesh), device="cuda").to(torch.complex128)
@@ -636,8 +489,9 @@ def run_gradient(args, prob, label, B):
         dtype = "f64"
     else:
         total_s = secs
-        single = form == "bm"
-        roof = roofline_mfma(pairs * B, far_kernel_avg(op, b, "mixed" if single else "fp64"), single)
+        prof = {k: fwd[4].prof[k] + adj[4].prof[k] for k in fwd[4].prof}
+        single, nl, ms, pr = dominant_tiles(prof)
+        roof = roofline_mfma(pr, ms / 1e3, single)
         dtype = "f32-mfma+f64" if form in ("bm", "pcm") else "f64"
     check = None
     if form == "bm":
@@ -700,18 +554,15 @@ def run_field(args, prob, label, B):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "field"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5", "field"])
     ap.add_argument("--grid", type=int, default=256, help="field: points per side of the Cartesian grid")
     ap.add_argument("--form", default=None, choices=["p64", "b64", "bm", "pc", "pcm"],
-                    help="pc: FP64 GMRES right-preconditioned by P = I + T_C^Q (S - I) T_Q^C with a dense "
-                         "first-order Cartesian inverse as S (c3, c5); pcm: the same with relaxed mixed "
-                         "precision")
-    ap.add_argument("--kh", type=float, default=0.8, help="pc: k times the Cartesian grid spacing")
-    ap.add_argument("--precond", default="inverse", choices=["inverse", "sparsify", "sparsify-lu"],
-                    help="pc: S is the dense inverse of the first-order Cartesian system (inverse), the "
-                         "sparsifying preconditioner (C^(C))^-1 A of the same system as a dense matrix "
-                         "(sparsify), or the same applied through a block LU of C^(C) (sparsify-lu)")
-    ap.add_argument("--steps", type=int, default=3)
+                    help="p64: FP64 VALU kernel, one right-hand side at a time; b64: FP64 matrix-core tiles; "
+                         "bm: FP32 matrix-core tiles in relaxed FP64 GMRES; pc: FP64 GMRES right-preconditioned "
+                         "by P = I + T_C^Q (S - I) T_Q^C with the library's sparsifying S^(C); pcm: pc with "
+                         "mixed precision (default for c3, c4, c5)")
+    ap.add_argument("--kh", type=float, default=0.5, help="pc, pcm: k times the Cartesian grid spacing")
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=2000)
@@ -720,13 +571,16 @@ def main():
     ap.add_argument("--batch", type=int, default=0, help="b64/bm: right-hand sides per solve (0 = all)")
     ap.add_argument("--inner", type=int, default=0,
                     help="bm: > 0 selects flexible GMRES with this many inner mixed-precision steps")
-    ap.add_argument("--relax", type=float, default=0.0,
-                    help="bm: accuracy granted to the mixed operator (relaxed GMRES) or inner tolerance "
-                         "(flexible); 0 = the library default")
+    ap.add_argument("--relax", type=float, default=None,
+                    help="bm, pcm: accuracy granted to the mixed operator (relaxed GMRES) or inner tolerance "
+                         "(flexible); 0 = the library default (default: 1e-6 for pcm, the library's for bm)")
+    ap.add_argument("--scheme", default=None, choices=["relaxed", "passes"],
+                    help="bm, pcm: relaxed GMRES (FP64 applications until the residual allows the mixed "
+                         "operator) or mixed-precision refinement passes (default: passes for pcm, relaxed "
+                         "for bm)")
+    ap.add_argument("--no-compare", dest="compare", action="store_false",
+                    help="c3: skip the untimed one-column P64 reference solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
-                    help="first run one elementwise kernel that reads and writes BYTES each "
-                         "(calibrates a profiler's HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); a multi-GPU layout (target rows, or "
@@ -747,8 +601,12 @@ def main():
         probs, label = [P.config5()], "two-material disk, k = 40, 16 plane waves, 128 receivers"
     else:
         probs, label = [P.config3(B=16)], "unit disk, n^2 = 2, k = 40, N = 122500"
-    form = args.form or ("p64" if wl in ("c1", "c2", "field") else "bm")
+    form = args.form or ("p64" if wl in ("c1", "c2", "field") else "pcm")
     args.form = form
+    if args.scheme is None:
+        args.scheme = "passes" if form == "pcm" else "relaxed"
+    if args.relax is None:
+        args.relax = 0.0
     if wl in ("c1", "c2") and form != "p64":
         ap.error("c1 and c2 are plain FP64 single-wave solves (form p64)")
 
@@ -758,16 +616,6 @@ def main():
         log(f"cpu baseline: oracle far sum on a row sample of {big.name}")
         cpu = cpu_baseline(big)
         log(f"cpu baseline: {cpu['value']:.4f} GI/s on {cpu['cores']} processes")
-
-    import torch
-    if args.copy_probe:
-        src = torch.ones(args.copy_probe // 8, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        torch.mul(src, 1.0, out=dst)
-        torch.cuda.synchronize()
-        log(f"copy probe: read and wrote {src.numel() * 8} bytes")
-        del src, dst
 
     if wl == "field":
         out = run_field(args, probs[0], label, 16)

@@ -122,7 +122,10 @@ typedef struct {
   int32_t adjoint;     /* solve L^H x = b instead */
   int32_t x0_given;    /* use x as the initial guess */
   int32_t inner_maxit; /* LS_MIXED: > 0 selects flexible GMRES with this many inner steps */
-  double inner_tol;    /* LS_MIXED: inner tolerance (flexible) or granted operator accuracy (relaxed) */
+  double inner_tol;    /* LS_MIXED: inner tolerance (flexible), granted operator accuracy (relaxed) or
+                        * residual reduction per pass (mixed_scheme 1) */
+  int32_t mixed_scheme;/* LS_MIXED: 0 = relaxed or flexible as below, 1 = refinement passes */
+  int32_t pad_;
   /* LS_MIXED solves keep the Krylov basis, orthogonalisation and residuals in FP64.
    *   inner_maxit > 0: flexible GMRES; each outer direction is preconditioned by up to
    *                    inner_maxit steps of GMRES with the mixed operator (to inner_tol,
@@ -133,6 +136,11 @@ typedef struct {
    *                    3e-5 for tol 1e-8): the mixed operator's error is below 1e-6 at N ~ 1e5,
    *                    but switching earlier (inner_tol 1e-5 or 3e-5) slowed the k = 40 disk
    *                    solve from 1 069 to 1 471-1 560 steps.
+   *   mixed_scheme = 1: refinement passes; every Arnoldi application uses the mixed operator,
+   *                    each pass is a GMRES cycle from the FP64 residual that stops once its
+   *                    estimate has fallen by the factor inner_tol (default 1e-5) or below
+   *                    0.3 tol, and passes repeat until the FP64 residual meets tol (one FP64
+   *                    application per pass).  inner_maxit is ignored.
    * With several scatterers in the handle, every (column, scatterer) pair is an independent
    * system with its own Krylov space and convergence test; iters reports the most steps any
    * scatterer of the column took, relres the residual over the whole column. */
@@ -252,17 +260,64 @@ ls_status ls_precond_finish(ls_handle h, int32_t s, const double *x, int64_t ld,
 typedef ls_status (*ls_grid_op)(const double *c, double *sc, int32_t nrhs, int64_t ldc, void *user,
                                 hipStream_t stream);
 
-/* GMRES with the right preconditioner P = I + T_C^Q (S - I) T_Q^C of scatterer s (eq.
- * preconditioner_factored; ls_transfer_setup first): flexible GMRES with z_j = P v_j, so S may be
- * inexact or change between calls; the other scatterers' segments are not preconditioned.  c and sc
- * are the caller's grid workspaces [nrhs][ldc] (device, ldc >= nx ny): the library writes T_Q^C v_j
- * into c and calls S(c, sc, ...) once per step.  With o->prec = LS_MIXED the operator
- * applications switch to the mixed precision once the residual allows it, as in relaxed GMRES
- * (o->inner_tol is the granted accuracy, default 1e-4), followed by FP64 refinement; o->inner_maxit
- * is ignored.  Everything else is as for ls_solve_gmres. */
+/* GMRES with the right preconditioner P = I + T_C^Q (S - I) T_Q^C (eq. preconditioner_factored):
+ * flexible GMRES with z_j = P v_j, so S may be inexact or change between calls.  Two forms:
+ *   s >= 0, S given: the caller's S on scatterer s (ls_transfer_setup first); the other
+ *     scatterers' segments are not preconditioned.  c and sc are the caller's grid workspaces
+ *     [nrhs][ldc] (device, ldc >= nx ny): the library writes T_Q^C v_j into c and calls
+ *     S(c, sc, ...) once per step.  For an adjoint solve the caller's S must be the one for L^H.
+ *   s = -1, S = NULL (c, sc, ldc, user ignored): the library's sparsifying S^(C) on every
+ *     scatterer that has one (ls_sparsify_setup), each (column, scatterer) system preconditioned
+ *     by its own scatterer's P; scatterers without one are not preconditioned.  Adjoint solves
+ *     (o->adjoint) take P^H = I + T_C^Q (D^-1 S^H D - I) T_Q^C (D of eq. D_def), the
+ *     preconditioner of L^H that corresponds to P.  The grid workspaces are the library's.
+ * With o->prec = LS_MIXED the operator applications switch to the mixed precision once the
+ * residual allows it, as in relaxed GMRES (o->inner_tol is the granted accuracy, default 1e-4),
+ * followed by FP64 refinement; o->inner_maxit is ignored.  Everything else is as for
+ * ls_solve_gmres. */
 ls_status ls_solve_gmres_precond(ls_handle h, const double *b, double *x, int32_t nrhs, int64_t ld,
                                  const ls_solve_opts *o, int32_t s, ls_grid_op S, void *user, double *c, double *sc,
                                  int64_t ldc, ls_solve_info *info, hipStream_t stream);
+
+/* The sparsifying Cartesian preconditioner S^(C) = (C^(C))^-1 A of Section 4 (subsection
+ * "Sparsifying preconditioner": eqs. LS_eq_on_cartesian_points, cart_neighbors_LS,
+ * sparsifying_min, LC_def, S_minus_I) for scatterer s on the grid g, built by the library.
+ *   Cartesian system: L^(C) = I + k^2 V^(C) M^(C), M^(C) = diag(m(z_j)) with m_grid the contrast
+ *     m = 1 - n at the grid nodes (host, interleaved complex, nx ny values in grid order, 0 outside
+ *     the scatterer), k the scatterer's wavenumber.  V^(C) is the first-order rule: h^2 G(z_i, z_j)
+ *     off the diagonal, (-1 + (i pi/2) k a H1(k a)) / k^2 with a = h / sqrt(pi) on it (the
+ *     paper's Duan-Rokhlin corrections are cited there, not given).
+ *   A (eq. sparsifying_min): row j's weights on its 3 x 3 neighbourhood N(j) within the grid are
+ *     the conjugate of the left singular vector of the smallest singular value of
+ *     V^(C)(N(j), N(j)^c); rows with all 9 neighbours share the central node's weights, each edge
+ *     and corner row has its own.  A row's weights are unique up to a unit factor, which S^(C)
+ *     does not depend on.
+ *   C^(C) (eq. LC_def): A L^(C) kept on the 3 x 3 pattern; factored by block LU with grid rows as
+ *     blocks (no pivoting across blocks, partial pivoting inside; O(ny nx^3) host work, ny nx^2
+ *     complex values twice on the device).
+ * ls_sparsify_setup also sets the transfer grid of s (as ls_transfer_setup, replacing an earlier
+ * grid and preconditioner).  Needs 3 <= nx <= 1536, ny >= 3.  Synchronous; LS_ERR_BREAKDOWN if a
+ * diagonal block of the LU is singular.  info (host, may be NULL) receives the build time, the
+ * central stencil's smallest / largest singular value, ||C x - y|| / ||y|| for a seeded y solved
+ * through the factors, and the device bytes held. */
+typedef struct {
+  double build_seconds;
+  double sv_ratio;
+  double lu_residual;
+  int64_t device_bytes;
+} ls_sparsify_info;
+ls_status ls_sparsify_setup(ls_handle h, int32_t s, const ls_grid *g, const double *m_grid, ls_sparsify_info *info);
+/* sc = S^(C) c (adjoint = 0) or sc = (S^(C))^H c (adjoint != 0) for nrhs grid vectors [nrhs][ldc]
+ * (device, c and sc distinct, ldc >= nx ny), asynchronous on stream.  The adjoint form may
+ * allocate a grid workspace on its first use with a larger nrhs. */
+ls_status ls_sparsify_apply(ls_handle h, int32_t s, const double *c, int64_t ldc, double *sc, int32_t nrhs,
+                            int32_t adjoint, hipStream_t stream);
+/* Host-only construction of A and C^(C) for the grid g (origin unused), wavenumber k and grid
+ * contrast m_grid, as ls_sparsify_setup builds them: W[9 j + o] = A[j, j + off(o)] and
+ * E[9 j + o] = C^(C)[j, j + off(o)] (interleaved complex, 9 nx ny values each; 0 where j + off(o)
+ * is off the grid), off(o) = (o mod 3 - 1) + (o div 3 - 1) nx.  Needs no GPU. */
+ls_status ls_sparsify_stencil_host(const ls_grid *g, double k, const double *m_grid, double *W, double *E,
+                                   double *sv_ratio);
 
 /* Introspection. */
 int64_t ls_num_nodes(ls_handle h);                       /* total nodes */
@@ -289,6 +344,9 @@ typedef struct {
   double apply_ms;
   double pair_rhs;      /* Green's interactions evaluated: sum over applications of
                          * N_s (N_s - 1) x right-hand sides over the scatterers computed */
+  int64_t far_launches_mixed;  /* the part of the three figures above due to FP32 tiles */
+  double far_ms_mixed;
+  double pair_rhs_mixed;
 } ls_profile;
 ls_status ls_profile_enable(ls_handle h, int32_t on);
 ls_status ls_profile_query(ls_handle h, ls_profile *out, int32_t reset);

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "libls.so")
 LS_OK, LS_NOT_CONVERGED, LS_ERR_ARG = 0, 1, -1
 FP64, MIXED = 0, 1
 _PREC = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}
+_SCHEME = {"relaxed": 0, "passes": 1}
 CIRCLE, ELLIPSE = 0, 1
 
 _lib = None
@@ -47,7 +48,9 @@ class _Scatterer(ctypes.Structure):
 
 class _Profile(ctypes.Structure):
     _fields_ = [("far_launches", ctypes.c_int64), ("far_ms", ctypes.c_double), ("apply_calls", ctypes.c_int64),
-                ("apply_ms", ctypes.c_double), ("pair_rhs", ctypes.c_double)]
+                ("apply_ms", ctypes.c_double), ("pair_rhs", ctypes.c_double),
+                ("far_launches_mixed", ctypes.c_int64), ("far_ms_mixed", ctypes.c_double),
+                ("pair_rhs_mixed", ctypes.c_double)]
 
 
 class _TuneResult(ctypes.Structure):
@@ -63,7 +66,8 @@ class _Options(ctypes.Structure):
 class _SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("adjoint", ctypes.c_int32), ("x0_given", ctypes.c_int32),
-                ("inner_maxit", ctypes.c_int32), ("inner_tol", ctypes.c_double)]
+                ("inner_maxit", ctypes.c_int32), ("inner_tol", ctypes.c_double),
+                ("mixed_scheme", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class _SolveInfo(ctypes.Structure):
@@ -105,6 +109,9 @@ def lib():
         L.ls_cart_to_quad.argtypes = [vp, i32, vp, i64, vp, i64, i32, vp]
         L.ls_precond_finish.argtypes = [vp, i32, vp, i64, vp, vp, i64, vp, i32, vp]
         L.ls_solve_gmres_precond.argtypes = [vp, vp, vp, i32, i64, vp, i32, _GridOp, vp, vp, vp, i64, vp, vp]
+        L.ls_sparsify_setup.argtypes = [vp, i32, vp, vp, vp]
+        L.ls_sparsify_apply.argtypes = [vp, i32, vp, i64, vp, i32, i32, vp]
+        L.ls_sparsify_stencil_host.argtypes = [vp, dbl, vp, vp, vp, vp]
         L.ls_autotune.argtypes = [vp, i32, i32, vp, vp]
         L.ls_set_tile_shape.argtypes = [vp, i32, i32, i32]
         L.ls_profile_enable.argtypes = [vp, i32]
@@ -138,6 +145,11 @@ _GridOp = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, cty
 class _Grid(ctypes.Structure):
     _fields_ = [("x0", ctypes.c_double), ("y0", ctypes.c_double), ("h", ctypes.c_double),
                 ("nx", ctypes.c_int32), ("ny", ctypes.c_int32)]
+
+
+class _SparsifyInfo(ctypes.Structure):
+    _fields_ = [("build_seconds", ctypes.c_double), ("sv_ratio", ctypes.c_double),
+                ("lu_residual", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
 
 
 @dataclass
@@ -242,8 +254,10 @@ class Operator:
         return self.apply(x, precision, adjoint=True, out=out)
 
     def solve(self, b, tol=1e-8, maxit=1000, precision="fp64", adjoint=False, x0=None, inner_tol=0.0,
-              inner_maxit=0, restart=0):
-        """Solve L x = b (or L^H x = b) by GMRES (restart = 0: none); returns (x, info dict)."""
+              inner_maxit=0, restart=0, scheme="relaxed"):
+        """Solve L x = b (or L^H x = b) by GMRES (restart = 0: none); returns (x, info dict).
+        precision="mixed": scheme "relaxed" (or flexible with inner_maxit > 0) or "passes"
+        (mixed-precision refinement passes), see ls_solve_opts."""
         import torch
         b2 = self._cols(b)
         if x0 is not None:
@@ -254,7 +268,7 @@ class Operator:
         iters = np.zeros(B, dtype=np.int32)
         relres = np.zeros(B, dtype=np.float64)
         o = _SolveOpts(float(tol), int(maxit), int(restart), _PREC[precision], int(bool(adjoint)), int(x0 is not None),
-                       int(inner_maxit), float(inner_tol))
+                       int(inner_maxit), float(inner_tol), _SCHEME[scheme], 0)
         info = _SolveInfo(iters.ctypes.data, relres.ctypes.data, 0, 0, 0.0, 0)
         st = _check(lib().ls_solve_gmres(self._h, b2.data_ptr(), x.data_ptr(), B, self.n, ctypes.byref(o),
                                          ctypes.byref(info), _stream()), self._h)
@@ -372,14 +386,57 @@ class Operator:
                                        y.data_ptr(), x2.shape[0], _stream()), self._h)
         return y.reshape(x.shape)
 
-    def solve_precond(self, b, S, s=0, tol=1e-8, maxit=1000, restart=0, adjoint=False, precision="fp64",
-                      inner_tol=0.0):
-        """GMRES preconditioned on the right by P = I + T_C^Q (S - I) T_Q^C of scatterer s
-        (set_grid first); S is a callable on (B, nx ny) CUDA tensors.  precision="mixed" relaxes the
-        operator applications to the FP32 tiles late in the iteration.  Returns (x, info)."""
+    def sparsify_setup(self, x0, y0, h, nx, ny, m_grid, s=0):
+        """Build the library's sparsifying preconditioner S^(C) of scatterer s on the grid
+        (x0 + ix h, y0 + iy h) with the contrast m_grid (nx ny values in grid order, 0 outside the
+        scatterer); also sets the transfer grid.  Returns the build info (see ls_sparsify_setup)."""
+        g = _Grid(float(x0), float(y0), float(h), int(nx), int(ny))
+        m = np.ascontiguousarray(np.asarray(m_grid, dtype=np.complex128).ravel())
+        if m.size != int(nx) * int(ny):
+            raise ValueError("m_grid must have nx ny entries")
+        info = _SparsifyInfo()
+        _check(lib().ls_sparsify_setup(self._h, s, ctypes.byref(g), m.ctypes.data, ctypes.byref(info)), self._h)
+        self._grids = getattr(self, "_grids", {})
+        self._grids[s] = int(nx) * int(ny)
+        self._sparsified = getattr(self, "_sparsified", set()) | {s}
+        return {"build_seconds": info.build_seconds, "sv_ratio": info.sv_ratio, "lu_residual": info.lu_residual,
+                "device_bytes": info.device_bytes}
+
+    def sparsify_apply(self, c, s=0, adjoint=False):
+        """S^(C) c (or its adjoint) for grid vectors c of shape (B, nx ny) (complex128 CUDA)."""
+        import torch
+        c = c.to(torch.complex128).contiguous()
+        if c.dim() == 1:
+            c = c[None, :]
+        if c.shape[1] != self._grid_n(s):
+            raise ValueError("grid vectors must have nx ny entries")
+        out = torch.empty_like(c)
+        _check(lib().ls_sparsify_apply(self._h, s, c.data_ptr(), c.shape[1], out.data_ptr(), c.shape[0],
+                                       int(bool(adjoint)), _stream()), self._h)
+        return out
+
+    def solve_precond(self, b, S=None, s=0, tol=1e-8, maxit=1000, restart=0, adjoint=False, precision="fp64",
+                      inner_tol=0.0, scheme="relaxed"):
+        """GMRES preconditioned on the right by P = I + T_C^Q (S - I) T_Q^C.  S=None: the library's
+        sparsifying S^(C) on every scatterer that has one (sparsify_setup; s is ignored).  Otherwise S
+        is a callable on (B, nx ny) CUDA tensors for scatterer s (set_grid first).  precision="mixed"
+        relaxes the operator applications to the FP32 tiles late in the iteration.  Returns (x, info)."""
         import torch
         b2 = self._cols(b)
         B = b2.shape[0]
+        if S is None:
+            x = torch.zeros_like(b2)
+            iters = np.zeros(B, dtype=np.int32)
+            relres = np.zeros(B, dtype=np.float64)
+            o = _SolveOpts(float(tol), int(maxit), int(restart), _PREC[precision], int(bool(adjoint)), 0, 0,
+                           float(inner_tol), _SCHEME[scheme], 0)
+            info = _SolveInfo(iters.ctypes.data, relres.ctypes.data, 0, 0, 0.0, 0)
+            st = _check(lib().ls_solve_gmres_precond(self._h, b2.data_ptr(), x.data_ptr(), B, self.n, ctypes.byref(o),
+                                                     -1, _GridOp(), None, None, None, 0, ctypes.byref(info),
+                                                     _stream()), self._h)
+            return x.reshape(b.shape), {"converged": st == LS_OK, "iters": iters, "relres": relres,
+                                        "n_apply_fp64": info.n_apply_fp64, "n_apply_mixed": info.n_apply_mixed,
+                                        "seconds": info.seconds, "n_reorth": info.n_reorth}
         nc = self._grid_n(s)
         c = torch.empty((B, nc), dtype=torch.complex128, device=b2.device)
         sc = torch.empty_like(c)
@@ -401,7 +458,7 @@ class Operator:
         iters = np.zeros(B, dtype=np.int32)
         relres = np.zeros(B, dtype=np.float64)
         o = _SolveOpts(float(tol), int(maxit), int(restart), _PREC[precision], int(bool(adjoint)), 0, 0,
-                       float(inner_tol))
+                       float(inner_tol), _SCHEME[scheme], 0)
         info = _SolveInfo(iters.ctypes.data, relres.ctypes.data, 0, 0, 0.0, 0)
         st = lib().ls_solve_gmres_precond(self._h, b2.data_ptr(), x.data_ptr(), B, self.n, ctypes.byref(o), s, fn,
                                           None, c.data_ptr(), sc.data_ptr(), nc, ctypes.byref(info), _stream())
@@ -464,7 +521,8 @@ class Operator:
         p = _Profile()
         _check(lib().ls_profile_query(self._h, ctypes.byref(p), int(bool(reset))), self._h)
         return {"far_launches": p.far_launches, "far_ms": p.far_ms, "apply_calls": p.apply_calls,
-                "apply_ms": p.apply_ms, "pair_rhs": p.pair_rhs}
+                "apply_ms": p.apply_ms, "pair_rhs": p.pair_rhs, "far_launches_mixed": p.far_launches_mixed,
+                "far_ms_mixed": p.far_ms_mixed, "pair_rhs_mixed": p.pair_rhs_mixed}
 
     def correction_nnz(self, s=0):
         return int(lib().ls_correction_nnz(self._h, s))
@@ -479,6 +537,23 @@ class Operator:
         val = np.zeros(max(nnz, 1), dtype=np.complex128)
         _check(L.ls_export_correction(self._h, s, rowptr.ctypes.data, col.ctypes.data, val.ctypes.data), self._h)
         return rowptr, col[:nnz], val[:nnz]
+
+
+def sparsify_stencil_host(h, nx, ny, k, m_grid):
+    """The library's host construction of the sparsifying preconditioner's stencils on an nx x ny
+    grid of spacing h: (W, E, sv_ratio) with W[j, o] = A[j, j + off(o)], E[j, o] = C^(C)[j, j + off(o)]
+    (complex (nx ny, 9)), off(o) = (o % 3 - 1) + (o // 3 - 1) nx.  Needs no GPU."""
+    g = _Grid(0.0, 0.0, float(h), int(nx), int(ny))
+    m = np.ascontiguousarray(np.asarray(m_grid, dtype=np.complex128).ravel())
+    nc = int(nx) * int(ny)
+    if m.size != nc:
+        raise ValueError("m_grid must have nx ny entries")
+    W = np.empty((nc, 9), dtype=np.complex128)
+    E = np.empty((nc, 9), dtype=np.complex128)
+    r = ctypes.c_double()
+    _check(lib().ls_sparsify_stencil_host(ctypes.byref(g), float(k), m.ctypes.data, W.ctypes.data, E.ctypes.data,
+                                          ctypes.byref(r)))
+    return W, E, r.value
 
 
 def eval_green(z2, single=False):

@@ -13,7 +13,7 @@ OUT = os.path.join(HERE, "libls.so")
 BUILD = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.hip", "apply.hip", "mfma.hip", "setup.hip", "krylov.hip", "farfield.hip", "transfer.hip"]
+SOURCES = ["api.hip", "apply.hip", "mfma.hip", "setup.hip", "krylov.hip", "farfield.hip", "transfer.hip", "sparsify.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall", "-Wno-unused-function",
          # keep the compiler from emitting packed FP32 ops (hipcc's host pass warns it does not know
          # the feature; that warning is harmless)

@@ -216,6 +216,7 @@ void ls_destroy(ls_handle h) {
   for (void *p : h->owned) (void)hipFree(p);
   if (h->ws_apply.ptr) (void)hipFree(h->ws_apply.ptr);
   if (h->ws_ff.ptr) (void)hipFree(h->ws_ff.ptr);
+  if (h->ws_grid.ptr) (void)hipFree(h->ws_grid.ptr);
   if (h->batch_tables) (void)hipFree(h->batch_tables);
   lsk::free_solve_ws(h);
   for (hipEvent_t e : h->ev_far) (void)hipEventDestroy(e);
@@ -366,8 +367,11 @@ ls_status apply_op(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, 
   hipEvent_t a0 = nullptr, a1 = nullptr;
   if (h->prof) {
     for (size_t si = 0; si < h->sc.size(); ++si)
-      if (h->scat_skip.empty() || !h->scat_skip[si])
-        h->prof_pairs += (double)h->sc[si].n * (double)(h->sc[si].n - 1) * nrhs;
+      if (h->scat_skip.empty() || !h->scat_skip[si]) {
+        const double pr = (double)h->sc[si].n * (double)(h->sc[si].n - 1) * nrhs;
+        h->prof_pairs += pr;
+        if (single) h->prof_pairs_mixed += pr;
+      }
     HIPCHK(h, hipEventCreate(&a0));
     HIPCHK(h, hipEventCreate(&a1));
     HIPCHK(h, hipEventRecord(a0, stream));
@@ -379,6 +383,7 @@ ls_status apply_op(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, 
       HIPCHK(h, hipEventCreate(&f1));
       h->ev_far.push_back(f0);
       h->ev_far.push_back(f1);
+      h->ev_far_mixed.push_back(single ? 1 : 0);
     }
     HIPCHK(h, lsk::launch_apply_batch(h, x, y, nrhs, ld, mode, single, bmt, bsplit, h->ws_apply.ptr, stream, f0, f1));
   }
@@ -392,6 +397,7 @@ ls_status apply_op(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, 
       HIPCHK(h, hipEventCreate(&f1));
       h->ev_far.push_back(f0);
       h->ev_far.push_back(f1);
+      h->ev_far_mixed.push_back(single ? 1 : 0);
     }
     if (tiles)
       HIPCHK(h, lsk::launch_apply_tile(sc, x, y, nrhs, ld, mode, single, nsplit, h->ws_apply.ptr, stream, f0, f1));
@@ -453,12 +459,20 @@ ls_status ls_solve_gmres_precond(ls_handle h, const double *b, double *x, int32_
   if (o->maxit < 1) return fail(h, LS_ERR_ARG, "maxit must be >= 1");
   if (o->restart < 0) return fail(h, LS_ERR_ARG, "restart < 0");
   if (o->prec != LS_FP64 && o->prec != LS_MIXED) return fail(h, LS_ERR_ARG, "bad precision");
+  lsk::PrecondCb pc;
+  if (s == -1 && !S) {
+    // the library's sparsifying preconditioner on every scatterer that has one
+    bool any = false;
+    for (const Scat &q : h->sc) any = any || q.sp != nullptr;
+    if (!any) return fail(h, LS_ERR_ARG, "no scatterer has a preconditioner (ls_sparsify_setup)");
+    pc.s = -1;
+    return lsk::solve_gmres(h, b, x, nrhs, ld, *o, info, stream, &pc);
+  }
   if (s < 0 || s >= (int32_t)h->sc.size()) return fail(h, LS_ERR_ARG, "bad scatterer index");
   const Scat &sct = h->sc[s];
   if (!sct.tr) return fail(h, LS_ERR_ARG, "no grid for this scatterer (ls_transfer_setup)");
   if (!S || !c || !sc) return fail(h, LS_ERR_ARG, "null preconditioner argument");
   if (ldc < (int64_t)sct.tr->nx * sct.tr->ny) return fail(h, LS_ERR_ARG, "ldc < number of grid nodes");
-  lsk::PrecondCb pc;
   pc.s = s;
   pc.S = S;
   pc.user = user;
@@ -503,11 +517,18 @@ ls_status ls_profile_query(ls_handle h, ls_profile *out, int32_t reset) {
   out->apply_calls = (int64_t)h->ev_apply.size() / 2;
   out->far_ms = out->apply_ms = 0.0;
   out->pair_rhs = h->prof_pairs;
+  out->far_launches_mixed = 0;
+  out->far_ms_mixed = 0.0;
+  out->pair_rhs_mixed = h->prof_pairs_mixed;
   for (size_t i = 0; i + 1 < h->ev_far.size(); i += 2) {
     float ms = 0.f;
     HIPCHK(h, hipEventSynchronize(h->ev_far[i + 1]));
     HIPCHK(h, hipEventElapsedTime(&ms, h->ev_far[i], h->ev_far[i + 1]));
     out->far_ms += ms;
+    if (h->ev_far_mixed[i / 2]) {
+      out->far_ms_mixed += ms;
+      ++out->far_launches_mixed;
+    }
   }
   for (size_t i = 0; i + 1 < h->ev_apply.size(); i += 2) {
     float ms = 0.f;
@@ -519,8 +540,10 @@ ls_status ls_profile_query(ls_handle h, ls_profile *out, int32_t reset) {
     for (hipEvent_t e : h->ev_far) (void)hipEventDestroy(e);
     for (hipEvent_t e : h->ev_apply) (void)hipEventDestroy(e);
     h->ev_far.clear();
+    h->ev_far_mixed.clear();
     h->ev_apply.clear();
     h->prof_pairs = 0.0;
+    h->prof_pairs_mixed = 0.0;
   }
   return LS_OK;
 }
@@ -613,6 +636,7 @@ ls_status ls_field(ls_handle h, int32_t s, const double *tx, const double *ty, i
     (void)hipEventCreate(&f1);
     h->ev_far.push_back(f0);
     h->ev_far.push_back(f1);
+    h->ev_far_mixed.push_back(0);
     h->prof_pairs += (double)sc.n * (double)nt * nrhs;
   }
   if (e == hipSuccess)

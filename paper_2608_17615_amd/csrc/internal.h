@@ -36,6 +36,19 @@ struct TransferData {
   std::vector<double> colsum;       // D: column sums of T_C^Q per grid node (1 where zero), host
 };
 
+// The sparsifying Cartesian preconditioner S^(C) = (C^(C))^-1 A of one scatterer on its transfer
+// grid (sparsify.hip): the stencil weights W of A and the entries E of C^(C) as [9][nx ny]
+// (slot o = (dy + 1) 3 + (dx + 1)), the inverse diagonal blocks G_i of the block LU of C^(C)
+// (grid rows as blocks) column-major (Gc) and row-major (Gr), and D, D^-1 of the transfer grid.
+struct SparsifyData {
+  int32_t nx = 0, ny = 0;
+  double2 *W = nullptr, *E = nullptr, *Gc = nullptr, *Gr = nullptr;
+  double *d = nullptr, *dinv = nullptr;
+  double sv_ratio = 0, lu_residual = 0;
+  int64_t bytes = 0;
+  std::vector<void *> bufs;         // the allocations above
+};
+
 // One scatterer, all device arrays in the internal (sorted) node order.
 struct Scat {
   int64_t n = 0, off = 0;     // nodes, offset in the concatenated caller vectors
@@ -52,6 +65,7 @@ struct Scat {
   std::vector<int32_t> perm_host;   // same as perm, on the host
   std::shared_ptr<GeomData> geom;
   std::shared_ptr<TransferData> tr; // set by ls_transfer_setup
+  std::shared_ptr<SparsifyData> sp; // set by ls_sparsify_setup (dropped by a new transfer grid)
 };
 
 // One scatterer of a batched launch and one unit of its far-sum work.
@@ -84,12 +98,14 @@ struct ls_ctx {
   std::vector<lsk::Scat> sc;
   bool prof = false;
   std::vector<hipEvent_t> ev_far, ev_apply;   // start/stop pairs, in launch order
+  std::vector<char> ev_far_mixed;              // per far-sum launch: FP32 tiles
   double prof_pairs = 0.0;                     // interactions evaluated while profiling
+  double prof_pairs_mixed = 0.0;               // of which by FP32 tiles
   int64_t n_total = 0;
   int device = 0;
   ls_options opt{};
   std::string err;
-  lsk::Workspace ws_apply, ws_solve, ws_ff;
+  lsk::Workspace ws_apply, ws_solve, ws_ff, ws_grid;
   lsk::TileTune tune[2];                 // [single]
   void *batch_tables = nullptr;          // device BatchDesc[] + WorkItem[] + counter
   size_t batch_bytes = 0;
@@ -106,7 +122,8 @@ namespace lsk {
 // Forward: y = L x;  Adjoint: y = L^H x;  AdjointPotential: y = V^H x = W conj(G~) x + C^H x.
 enum class Mode { Forward, Adjoint, AdjointPotential };
 
-// krylov.hip: the right preconditioner P = I + T_C^Q (S - I) T_Q^C of scatterer s with the caller's S
+// krylov.hip: the right preconditioner P = I + T_C^Q (S - I) T_Q^C, either with the caller's S on
+// scatterer s (s >= 0), or (s < 0) with the library's sparsifying S on every scatterer that has one
 struct PrecondCb {
   int s = 0;
   ls_grid_op S = nullptr;
@@ -168,6 +185,10 @@ int field_source_split(int64_t n, int64_t nt, int nrhs);
 // the caller's business); x, y [nrhs][ld] caller order, c, sc [nrhs][ldc]
 hipError_t launch_quad_to_cart(const Scat &s, const double2 *x, int64_t ld, double2 *c, int64_t ldc, int nrhs,
                                hipStream_t st);
+// sparsify.hip: sc = S c (adjoint: sc = S^H c, or D^-1 S^H D c with dscale; tmp [nrhs][ldt] is then
+// needed); c and sc must not alias
+hipError_t launch_sparsify(const SparsifyData &sp, const double2 *c, int64_t ldc, double2 *sc, int64_t ldo,
+                           double2 *tmp, int64_t ldt, int nrhs, bool adjoint, bool dscale, hipStream_t st);
 hipError_t launch_precond_finish(const Scat &s, const double2 *x, int64_t ld, const double2 *c, const double2 *sc,
                                  int64_t ldc, double2 *y, int nrhs, hipStream_t st);
 size_t field_workspace_bytes(int64_t n, int nrhs, int64_t nt, int nsplit);

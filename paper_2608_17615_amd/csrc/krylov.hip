@@ -252,6 +252,8 @@ struct SolveWs {
   size_t meta_bytes = 0;
   void *vecs = nullptr;      // r, t, inner workspaces
   size_t vec_bytes = 0;
+  void *grid = nullptr;      // grid vectors of the library's preconditioner (c, S c, temporary)
+  size_t grid_bytes = 0;
 };
 
 hipError_t ensure_chunks(Basis &B, int nvec, int64_t n, int nrhs) {
@@ -424,6 +426,10 @@ struct CoreOpts {
   double relax_eps;      // > 0: FP64 applies while the residual estimate exceeds tol / relax_eps, mixed after
   int progress;          // > 0: print a progress line every this many steps
   const PrecondCb *pc = nullptr;   // flexible: z_j = P v_j instead of an inner solve
+  bool all_mixed = false;          // every Arnoldi application in the mixed precision (the residual
+                                   // at the start of a cycle stays FP64)
+  double pass_reduce = 0.0;        // > 0: a cycle stops once its residual estimate is below
+                                   // max(0.3 tol, pass_reduce x the largest starting residual)
 };
 
 struct CoreResult {
@@ -522,7 +528,7 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
     if (first_cycle && !o.x0_given) {
       HIPTRY(hipMemcpyAsync(r, b, vb, hipMemcpyDeviceToDevice, st));
     } else {
-      const ls_precision pr = (o.flexible || o.relax_eps > 0) ? LS_FP64 : o.matvec;
+      const ls_precision pr = (o.flexible || o.relax_eps > 0 || o.all_mixed) ? LS_FP64 : o.matvec;
       for (int q = 0; q < nsys; ++q) act[q] = res.done[q] ? 0 : 1;
       set_skip(act);
       ls_status s2 = apply_op(h, (const double *)x, (double *)t, nrhs, n, o.mode, pr, st);
@@ -545,6 +551,16 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
       all = all && res.done[q];
     }
     if (all) break;
+    // the Arnoldi iteration's own target: tol, or for a refinement pass the reduction it is
+    // asked for (its estimate follows the mixed-precision operator, so the pass stops where the
+    // FP64 residual can still follow it)
+    double tol_it = o.tol;
+    if (o.pass_reduce > 0) {
+      double w = 0.0;
+      for (int q = 0; q < nsys; ++q)
+        if (act[q]) w = std::max(w, est[q]);
+      tol_it = std::max(0.3 * o.tol, o.pass_reduce * w);
+    }
     HIPTRY(G.set_active(act));
     scale_kernel<<<gt, kBlock, 0, st>>>(nseg, G.tiles, G.active, G.beta, r, n, tbl[0], n);
     HIPTRY(hipGetLastError());
@@ -566,14 +582,38 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
         HIPTRY(ensure_chunks(ws->Z, j + 1, n, nrhs));
         double2 *zj = ws->Z.vec(j, n, nrhs);
         const PrecondCb &pc = *o.pc;
-        const Scat &scp = h->sc[pc.s];
         HIPTRY(hipMemcpyAsync(zj, vj, sizeof(double2) * (size_t)n * nrhs, hipMemcpyDeviceToDevice, st));
-        HIPTRY(launch_quad_to_cart(scp, vj, n, pc.c, pc.ldc, nrhs, st));
-        const ls_status sst = pc.S((const double *)pc.c, (double *)pc.sc, nrhs, pc.ldc, pc.user, st);
-        if (sst < 0) return setup_fail(h, sst, "the preconditioner's S failed");
-        HIPTRY(launch_precond_finish(scp, vj, n, pc.c, pc.sc, pc.ldc, zj, nrhs, st));
+        if (pc.s >= 0) {
+          const Scat &scp = h->sc[pc.s];
+          HIPTRY(launch_quad_to_cart(scp, vj, n, pc.c, pc.ldc, nrhs, st));
+          const ls_status sst = pc.S((const double *)pc.c, (double *)pc.sc, nrhs, pc.ldc, pc.user, st);
+          if (sst < 0) return setup_fail(h, sst, "the preconditioner's S failed");
+          HIPTRY(launch_precond_finish(scp, vj, n, pc.c, pc.sc, pc.ldc, zj, nrhs, st));
+        } else {
+          // the library's S^(C) per scatterer (P^H with D^-1 S^H D for adjoint solves); scatterers
+          // none of whose systems is active keep z = v
+          size_t need = 0;
+          for (const Scat &scp : h->sc)
+            if (scp.sp) need = std::max(need, 3 * sizeof(double2) * (size_t)scp.sp->nx * scp.sp->ny * nrhs);
+          if (need > ws->grid_bytes) {
+            HIPTRY(hipStreamSynchronize(st));
+            HIPTRY(ensure(ws->grid, ws->grid_bytes, need));
+          }
+          for (int si = 0; si < nseg; ++si) {
+            const Scat &scp = h->sc[si];
+            if (!scp.sp) continue;
+            bool live = false;
+            for (int c = 0; c < nrhs && !live; ++c) live = act[c * nseg + si] != 0;
+            if (!live) continue;
+            const int64_t nc = (int64_t)scp.sp->nx * scp.sp->ny;
+            double2 *gc = (double2 *)ws->grid, *gs = gc + (size_t)nc * nrhs, *gt = gs + (size_t)nc * nrhs;
+            HIPTRY(launch_quad_to_cart(scp, vj, n, gc, nc, nrhs, st));
+            HIPTRY(launch_sparsify(*scp.sp, gc, nc, gs, nc, gt, nc, nrhs, o.mode == Mode::Adjoint, true, st));
+            HIPTRY(launch_precond_finish(scp, vj, n, gc, gs, nc, zj, nrhs, st));
+          }
+        }
         // relaxed: the mixed-precision operator once the residual allows it (as below)
-        ls_precision pj = LS_FP64;
+        ls_precision pj = o.all_mixed ? LS_MIXED : LS_FP64;
         if (o.relax_eps > 0) {
           double worst = 0.0;
           for (int q = 0; q < nsys; ++q)
@@ -618,7 +658,7 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
         // relaxed inexact Arnoldi: an application error of relative size eps perturbs the
         // residual by about eps times the current residual, so once the largest active residual
         // estimate is below tol / eps the cheaper mixed-precision operator is accurate enough
-        ls_precision pj = o.matvec;
+        ls_precision pj = o.all_mixed ? LS_MIXED : o.matvec;
         if (o.relax_eps > 0) {
           double worst = 0.0;
           for (int q = 0; q < nsys; ++q)
@@ -680,7 +720,7 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
         mc[q] = j + 1;
         res.iters[q]++;
         est[q] = bnorm[q] > 0 ? std::abs(gc[j + 1]) / bnorm[q] : 0.0;
-        if (est[q] <= o.tol || betah[q] == 0.0) {
+        if (est[q] <= tol_it || betah[q] == 0.0) {
           act[q] = 0;
           res.done[q] = 1;
           changed = true;
@@ -780,11 +820,44 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
   // perturbed by the mixed applications, still meets tol without a (Krylov-space-losing) restart
   CoreOpts co{relax > 0 ? 0.3 * o.tol : o.tol, o.maxit, o.restart, mode, LS_FP64, flexible,
               o.inner_tol > 0 ? o.inner_tol : 1e-12, o.inner_maxit, o.x0_given != 0, relax, progress, pc};
+  // LS_MIXED with mixed_scheme = 1: refinement passes, each a GMRES cycle from the FP64 residual
+  // whose applications are all mixed-precision, stopped once its estimate has fallen by inner_tol
+  // (default 1e-5) or below 0.3 tol; the passes repeat until the FP64 residual meets tol
+  const bool passes = mixed && o.mixed_scheme == 1;
+  if (passes) {
+    co.tol = o.tol;
+    co.relax_eps = 0.0;
+    co.all_mixed = true;
+    co.matvec = LS_MIXED;
+    co.flexible = pc != nullptr;
+    co.pass_reduce = o.inner_tol > 0 ? o.inner_tol : 1e-5;
+  }
   CoreResult res;
   ls_status status = gmres_core(h, ws, wi, bb, xs, nrhs, co, res, st);
   if (status < 0) return status;
   const int nsys = (int)res.iters.size();
-  for (int pass = 0; pass < 3 && relax > 0; ++pass) {
+  for (int pass = 0; pass < 30 && passes; ++pass) {
+    int used = 0;
+    for (int q = 0; q < nsys; ++q) used = std::max(used, res.iters[q]);
+    if (used >= o.maxit) break;
+    CoreOpts ro = co;
+    ro.x0_given = true;
+    ro.maxit = o.maxit - used;
+    CoreResult rr;
+    status = gmres_core(h, ws, wi, bb, xs, nrhs, ro, rr, st);
+    if (status < 0) return status;
+    int more = 0;
+    for (int q = 0; q < nsys; ++q) {
+      res.iters[q] += rr.iters[q];
+      res.done[q] = rr.done[q];
+      more += rr.iters[q];
+    }
+    res.n_fp64 += rr.n_fp64;
+    res.n_mixed += rr.n_mixed;
+    res.n_reorth += rr.n_reorth;
+    if (more == 0) break;   // every system met tol on its FP64 residual
+  }
+  for (int pass = 0; pass < 3 && relax > 0 && !passes; ++pass) {
     // refinement from the FP64 residual for systems the relaxed iteration left above tol
     int used = 0;
     for (int q = 0; q < nsys; ++q) used = std::max(used, res.iters[q]);
@@ -846,6 +919,8 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
       const double rr = b2 > 0 ? std::sqrt(r2 / b2) : 0.0;
       if (info && info->relres) info->relres[c] = rr;
       if (info && info->iters) info->iters[c] = it;
+      // refinement passes end on estimates only when maxit cut them short: check the FP64 residual
+      if (passes && rr > o.tol) done = false;
       if (!done) status = LS_NOT_CONVERGED;
     }
   }
@@ -889,6 +964,7 @@ void free_solve_ws(ls_ctx *h) {
     if (ws->part) (void)hipFree(ws->part);
     if (ws->meta) (void)hipFree(ws->meta);
     if (ws->vecs) (void)hipFree(ws->vecs);
+    if (ws->grid) (void)hipFree(ws->grid);
   }
   delete[] all;
   h->ws_solve.ptr = nullptr;

@@ -226,12 +226,17 @@ ls_status ls_transfer_setup(ls_handle h, int32_t s, const ls_grid *g) {
       !up((void **)&t->col, col.data(), sizeof(int32_t) * col.size()) ||
       !up((void **)&t->val, val.data(), sizeof(double) * val.size()))
     return lsk::tfail(h, LS_ERR_ALLOC, "transfer tables");
-  if (sc.tr) {
+  if (sc.tr || sc.sp) {
     (void)hipDeviceSynchronize();
-    for (void *p : sc.tr->bufs) {
+    // the old grid's tables, and a sparsifying preconditioner built on that grid
+    std::vector<void *> old;
+    if (sc.tr) old = sc.tr->bufs;
+    if (sc.sp) old.insert(old.end(), sc.sp->bufs.begin(), sc.sp->bufs.end());
+    for (void *p : old) {
       h->owned.erase(std::remove(h->owned.begin(), h->owned.end(), p), h->owned.end());
       (void)hipFree(p);
     }
+    sc.sp.reset();
   }
   sc.tr = t;
   return LS_OK;

@@ -1,5 +1,6 @@
 """Host-side logic of bench.py: the flop model by argument range, the z-distribution sampler and
-the one-GPU contract (no GPU needed)."""
+the one-GPU contract (no GPU needed).  The preconditioner the bench uses is the library's (its
+host construction is checked against the oracle in test_sparsify_host.py)."""
 import os
 import subprocess
 import sys
@@ -40,42 +41,3 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
-
-
-def test_sparsifying_preconditioner_matches_the_oracle():
-    """The bench's host construction of S^(C) = (C^(C))^-1 A (library host Green's values, 25
-    offsets) equals the oracle's dense construction (SciPy Hankel values, the full product A L^(C)
-    and its 3 x 3 filter) on 21 x 21 and 23 x 17 grids over a disk; S does not depend on the
-    phase of each row's singular vector, so the two are compared entry by entry."""
-    from oracle import sparsify as spf
-    from oracle.transfer import Grid
-    k, h = 8.0, 0.11
-    for nx, ny in ((21, 21), (23, 17)):   # a non-square grid catches swapped indices
-        g = Grid(-1.1, -0.9, h, nx, ny)
-        zx, zy = g.nodes()
-        m = np.where(np.hypot(zx, zy) < 0.85, -1.0, 0.0)
-        S, ratio = bench.sparsifying_S(g.x0, g.y0, g.h, g.nx, g.ny, k, m)
-        So, _, _, _, ratio_o = spf.sparsifying_preconditioner(g, k, m, width=1)
-        assert abs(ratio - ratio_o) <= 1e-9 * ratio_o
-        assert np.abs(S - So).max() <= 1e-12 * np.abs(So).max()
-
-
-def test_block_lu_applier_matches_the_dense_sparsifying_S():
-    """BlockSparsifier (block LU of C^(C) by grid rows, 9-point stencil for A) applies S^(C) and
-    S^(C)^H as the dense (C^(C))^-1 A does, run with torch on the CPU; edge and corner rows carry
-    their own weights, so a non-square grid checks the block bookkeeping."""
-    import torch
-    k, h = 8.0, 0.11
-    rng = np.random.default_rng(11)
-    for nx, ny in ((21, 21), (23, 17)):
-        zx = -1.1 + h * np.tile(np.arange(nx), ny)
-        zy = -0.9 + h * np.repeat(np.arange(ny), nx)
-        m = np.where(np.hypot(zx, zy) < 0.85, -1.0 + 0.3j, 0.0)
-        W, E, _ = bench.sparsifying_stencil(-1.1, -0.9, h, nx, ny, k, m)
-        S = np.linalg.solve(bench.stencil_to_dense(E, nx, ny), bench.stencil_to_dense(W, nx, ny))
-        v = rng.standard_normal((3, nx * ny)) + 1j * rng.standard_normal((3, nx * ny))
-        fwd = bench.BlockSparsifier(W, E, nx, ny, "cpu")(torch.tensor(v)).numpy()
-        adj = bench.BlockSparsifier(W, E, nx, ny, "cpu", adjoint=True)(torch.tensor(v)).numpy()
-        ref, refh = v @ S.T, v @ S.conj()
-        assert np.abs(fwd - ref).max() <= 1e-12 * np.abs(ref).max()
-        assert np.abs(adj - refh).max() <= 1e-12 * np.abs(refh).max()

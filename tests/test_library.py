@@ -65,14 +65,24 @@ def test_host_green_matches_mpmath():
     assert np.all(err <= 4.5e-16 * np.maximum(1.0, z)), err.max()
 
 
-def test_workspace_and_options_structs_match_header():
-    assert ctypes.sizeof(lsg._Curve) == 48
-    assert ctypes.sizeof(lsg._Scatterer) == 80
-    assert ctypes.sizeof(lsg._SolveOpts) == 40
-    assert ctypes.sizeof(lsg._Options) == 24
-    assert ctypes.sizeof(lsg._Profile) == 40
-    assert ctypes.sizeof(lsg._SolveInfo) == 48
-    assert ctypes.sizeof(lsg._Grid) == 32
+def test_workspace_and_options_structs_match_header(tmp_path):
+    """The binding's ctypes structures have the sizes a C compiler gives the header's structs."""
+    import shutil
+    import subprocess
+    mine = [lsg._Curve, lsg._Scatterer, lsg._SolveOpts, lsg._Options, lsg._Profile, lsg._SolveInfo, lsg._Grid,
+            lsg._SparsifyInfo]
+    names = ["ls_curve", "ls_scatterer", "ls_solve_opts", "ls_options", "ls_profile", "ls_solve_info", "ls_grid",
+             "ls_sparsify_info"]
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include "ls.h"\nint main(void) {\n' +
+                   "".join(f'  printf("%zu\\n", sizeof({n}));\n' for n in names) + "  return 0;\n}\n")
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "include"),
+                    str(src), "-o", str(exe)], check=True)
+    want = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert [ctypes.sizeof(c) for c in mine] == want
 
 
 def _table(name):

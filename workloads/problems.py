@@ -111,8 +111,9 @@ def config4(seed=4, count=16, B=8, n_min=5e3, n_max=8e4):
         n_target = np.exp(rng.uniform(np.log(n_min), np.log(n_max)))
         n = max(1, int(round(np.sqrt(n_target / 100.0))))
         msh = _mesh.ogrid_disk(n, a) if is_disk else _mesh.ellipse(n, a, b)
+        m_at = lambda x, y, a=a, b=b, idx=idx: np.where((x / a) ** 2 + (y / b) ** 2 < 1.0, 1.0 - idx, 0.0)
         out.append(Problem(msh, k, contrast_from_index(msh, [const(idx)]),
-                           f'{"disk" if is_disk else "ellipse"}-{s}', even_directions(B)))
+                           f'{"disk" if is_disk else "ellipse"}-{s}', even_directions(B), m_at))
     return out
 
 
@@ -145,3 +146,21 @@ def random_vectors(N, B=1, seed=0):
 
 def receivers(R=128):
     return 2 * np.pi * np.arange(R) / R
+
+
+def cartesian_grid(prob, kh, pad=0.02):
+    """A uniform Cartesian grid of spacing kh / k covering the scatterer's nodes with a margin pad:
+    (x0, y0, h, nx, ny), node (ix, iy) at (x0 + ix h, y0 + iy h)."""
+    h = kh / prob.k
+    x, y = prob.mesh.x, prob.mesh.y
+    x0, y0 = x.min() - pad, y.min() - pad
+    nx = int(np.ceil((x.max() + pad - x0) / h)) + 1
+    ny = int(np.ceil((y.max() + pad - y0) / h)) + 1
+    return float(x0), float(y0), float(h), nx, ny
+
+
+def grid_contrast(prob, grid):
+    """The contrast m = 1 - n at the nodes of grid (x0, y0, h, nx, ny), in grid order (0 outside)."""
+    x0, y0, h, nx, ny = grid
+    iy, ix = np.divmod(np.arange(nx * ny), nx)
+    return np.asarray(prob.m_at(x0 + ix * h, y0 + iy * h), dtype=np.complex128)
