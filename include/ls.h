@@ -106,13 +106,26 @@ ls_status ls_setup_from_csr(const ls_scatterer *s, const int64_t *rowptr, const 
                             const double *val, const ls_options *opt, ls_handle *out);
 
 /* y = L x for nrhs columns (x, y: device, complex, leading dimension ld >= total nodes).
- * Asynchronous on stream.  May allocate workspace on first use of a larger nrhs. */
+ * Asynchronous on stream.  Allocates nothing: the handle's workspace must already hold what nrhs
+ * columns in precision p need (ls_reserve), else LS_ERR_ARG and nothing is enqueued.  With several
+ * scatterers on the matrix cores the call copies its launch tables to the device and waits for
+ * that copy when nrhs or p differ from the previous such application. */
 ls_status ls_apply(ls_handle h, const double *x, double *y, int32_t nrhs, int64_t ld,
                    ls_precision p, hipStream_t stream);
 
-/* y = L^H x = x + k^2 conj(m) (W conj(G~) x + C^H x)  (exact adjoint of ls_apply in FP64). */
+/* y = L^H x = x + k^2 conj(m) (W conj(G~) x + C^H x)  (exact adjoint of ls_apply in FP64); the
+ * workspace rules of ls_apply apply. */
 ls_status ls_apply_adjoint(ls_handle h, const double *x, double *y, int32_t nrhs, int64_t ld,
                            ls_precision p, hipStream_t stream);
+
+/* Grow the handle's application workspace (and, with several scatterers, its launch tables) to
+ * what ls_apply / ls_apply_adjoint need for nrhs columns in precision p; a no-op when it is large
+ * enough.  Synchronous (waits for the device before replacing a workspace). */
+ls_status ls_reserve(ls_handle h, int32_t nrhs, ls_precision p);
+
+/* Number of device allocations the library has made in this process (all handles), for checking
+ * that a sequence of calls allocated nothing. */
+int64_t ls_device_allocations(void);
 
 typedef struct {
   double tol;          /* relative residual ||b - L x||_2 / ||b||_2 per column */

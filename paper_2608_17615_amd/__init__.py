@@ -87,6 +87,9 @@ def lib():
         L.ls_setup_from_csr.argtypes = [vp, vp, vp, vp, vp, vp]
         L.ls_apply.argtypes = [vp, vp, vp, i32, i64, i32, vp]
         L.ls_apply_adjoint.argtypes = [vp, vp, vp, i32, i64, i32, vp]
+        L.ls_reserve.argtypes = [vp, i32, i32]
+        L.ls_device_allocations.argtypes = []
+        L.ls_device_allocations.restype = i64
         L.ls_solve_gmres.argtypes = [vp, vp, vp, i32, i64, vp, vp, vp]
         L.ls_grad_contrast.argtypes = [vp, vp, vp, vp, i32, i64, vp, vp]
         L.ls_num_nodes.argtypes = [vp]
@@ -246,9 +249,21 @@ class Operator:
         if out is not None and not (out.is_contiguous() and out.shape == x2.shape and out.dtype == x2.dtype):
             raise ValueError("out must be a contiguous tensor shaped like x")
         y = torch.empty_like(x2) if out is None else out
+        self.reserve(x2.shape[0], precision)
         fn = lib().ls_apply_adjoint if adjoint else lib().ls_apply
         _check(fn(self._h, x2.data_ptr(), y.data_ptr(), x2.shape[0], self.n, _PREC[precision], _stream()), self._h)
         return y.reshape(x.shape)
+
+    def reserve(self, nrhs, precision="fp64"):
+        """Grow the application workspace for nrhs columns (ls_reserve); apply() calls it itself."""
+        _check(lib().ls_reserve(self._h, int(nrhs), _PREC[precision]), self._h)
+
+    def apply_raw(self, x, out, precision="fp64", adjoint=False):
+        """ls_apply (or ls_apply_adjoint) alone, without reserving: fails if the workspace is too small."""
+        x2, y = self._cols(x), out
+        fn = lib().ls_apply_adjoint if adjoint else lib().ls_apply
+        _check(fn(self._h, x2.data_ptr(), y.data_ptr(), x2.shape[0], self.n, _PREC[precision], _stream()), self._h)
+        return y
 
     def apply_adjoint(self, x, precision="fp64", out=None):
         return self.apply(x, precision, adjoint=True, out=out)
@@ -563,6 +578,11 @@ def eval_green(z2, single=False):
     g = torch.empty(z2.shape, dtype=torch.complex128, device=z2.device)
     _check(lib().ls_eval_green(z2.data_ptr(), g.data_ptr(), z2.numel(), int(bool(single)), _stream()))
     return g
+
+
+def device_allocations():
+    """Device allocations the library has made in this process (ls_device_allocations)."""
+    return int(lib().ls_device_allocations())
 
 
 def eval_green_host(z2):

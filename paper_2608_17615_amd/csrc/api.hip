@@ -1,6 +1,8 @@
 // C ABI entry points: argument validation, internal node ordering, device uploads, dispatch.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <numeric>
@@ -33,7 +35,7 @@ template <class T>
 ls_status upload(ls_ctx *h, T **dst, const T *src, size_t count) {
   *dst = nullptr;
   void *p = nullptr;
-  if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess)
+  if (lsk::dmalloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess)
     return fail(h, LS_ERR_ALLOC, "hipMalloc failed");
   h->owned.push_back(p);
   *dst = (T *)p;
@@ -316,6 +318,7 @@ ls_status ls_setup_from_csr(const ls_scatterer *s, const int64_t *rowptr, const 
     }
   }
   if ((st = lsk::upload_correction(h, sc, rp, ci, cv)) != LS_OK) {
+    g_err = h->err;
     ls_destroy(h);
     return st;
   }
@@ -327,33 +330,58 @@ ls_status ls_setup_from_csr(const ls_scatterer *s, const int64_t *rowptr, const 
 
 namespace lsk {
 
-// Operator application without argument checks (callers validate).
-ls_status apply_op(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, Mode mode, ls_precision p,
-                   hipStream_t stream) {
-  // path: FP32 tiles (mixed), FP64 tiles (batched FP64 on the matrix cores) or the FP64 VALU sum
-  const bool single = p == LS_MIXED;
-  const bool tiles = single || h->opt.fp64_matrix == 2 || (h->opt.fp64_matrix == 0 && nrhs >= 16);
-  const int tpl = h->opt.targets_per_lane == 2 ? 2 : 1;
-  const int chunk = h->opt.rhs_chunk > 0 ? h->opt.rhs_chunk : 1;
-  auto splits = [&](const Scat &sc) {
-    if (h->opt.source_split > 0) return h->opt.source_split;
-    return tiles ? lsk::tile_source_split(sc.n, nrhs, single)
-                 : lsk::auto_source_split(sc.n, nrhs, std::max(1, nrhs / chunk), tpl);
-  };
-  // several scatterers on the matrix cores: one persistent launch over all of them
-  const bool batch = tiles && h->sc.size() > 1;
-  const lsk::TileTune &tt = h->tune[single ? 1 : 0];
-  const int bmt =
-      h->opt.mixed_tile > 0 ? h->opt.mixed_tile : (tt.mt > 0 ? tt.mt : lsk::tile_mt(nrhs, single));
-  const int bsplit = tt.split_len > 0 ? tt.split_len : lsk::batch_default_split_len(h, single);
-  size_t need = 0;
-  if (batch) need = lsk::batch_workspace_bytes(h, nrhs, single, bsplit);
+namespace {
+std::atomic<int64_t> g_device_allocations{0};
+
+}  // namespace
+
+void count_device_allocation() { g_device_allocations.fetch_add(1, std::memory_order_relaxed); }
+
+// How an application of nrhs columns in precision p runs: FP32 tiles (mixed), FP64 tiles
+// (batched FP64 on the matrix cores) or the FP64 VALU sum, one persistent launch over several
+// scatterers on the matrix cores, and the workspace it needs.
+struct ApplyPlan {
+  bool single, tiles, batch;
+  int tpl, chunk, bmt, bsplit;
+  size_t need;
+};
+
+int plan_splits(const ls_ctx *h, const ApplyPlan &pl, const Scat &sc, int nrhs) {
+  if (h->opt.source_split > 0) return h->opt.source_split;
+  return pl.tiles ? lsk::tile_source_split(sc.n, nrhs, pl.single)
+                  : lsk::auto_source_split(sc.n, nrhs, std::max(1, nrhs / pl.chunk), pl.tpl);
+}
+
+ApplyPlan apply_plan(const ls_ctx *h, int nrhs, ls_precision p) {
+  ApplyPlan pl;
+  pl.single = p == LS_MIXED;
+  pl.tiles = pl.single || h->opt.fp64_matrix == 2 || (h->opt.fp64_matrix == 0 && nrhs >= 16);
+  pl.tpl = h->opt.targets_per_lane == 2 ? 2 : 1;
+  pl.chunk = h->opt.rhs_chunk > 0 ? h->opt.rhs_chunk : 1;
+  pl.batch = pl.tiles && h->sc.size() > 1;
+  const lsk::TileTune &tt = h->tune[pl.single ? 1 : 0];
+  pl.bmt = h->opt.mixed_tile > 0 ? h->opt.mixed_tile : (tt.mt > 0 ? tt.mt : lsk::tile_mt(nrhs, pl.single));
+  pl.bsplit = tt.split_len > 0 ? tt.split_len : lsk::batch_default_split_len(h, pl.single);
+  pl.need = 0;
+  if (pl.batch) pl.need = lsk::batch_workspace_bytes(h, nrhs, pl.single, pl.bsplit);
   else
     for (const Scat &sc : h->sc) {
-      const int nsplit = splits(sc);
-      need = std::max(need, tiles ? lsk::tile_workspace_bytes(sc.n, nrhs, nsplit)
-                                  : lsk::apply_workspace_bytes(sc.n, nrhs, nsplit));
+      const int nsplit = plan_splits(h, pl, sc, nrhs);
+      pl.need = std::max(pl.need, pl.tiles ? lsk::tile_workspace_bytes(sc.n, nrhs, nsplit)
+                                           : lsk::apply_workspace_bytes(sc.n, nrhs, nsplit));
     }
+  return pl;
+}
+
+// Operator application without argument checks (callers validate).
+ls_status apply_op(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, Mode mode, ls_precision p,
+                   hipStream_t stream, bool may_grow) {
+  const ApplyPlan pl = apply_plan(h, nrhs, p);
+  const bool single = pl.single, tiles = pl.tiles, batch = pl.batch;
+  const int tpl = pl.tpl, chunk = pl.chunk, bmt = pl.bmt, bsplit = pl.bsplit;
+  const size_t need = pl.need;
+  if (need > h->ws_apply.bytes && !may_grow)
+    return fail(h, LS_ERR_ARG, "the workspace is smaller than this application needs: call ls_reserve first");
   if (need > h->ws_apply.bytes) {
     if (h->ws_apply.ptr) {
       HIPCHK(h, hipStreamSynchronize(stream));
@@ -361,7 +389,7 @@ ls_status apply_op(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, 
       h->ws_apply.ptr = nullptr;
       h->ws_apply.bytes = 0;
     }
-    if (hipMalloc(&h->ws_apply.ptr, need) != hipSuccess) return fail(h, LS_ERR_ALLOC, "workspace allocation failed");
+    if (lsk::dmalloc(&h->ws_apply.ptr, need) != hipSuccess) return fail(h, LS_ERR_ALLOC, "workspace allocation failed");
     h->ws_apply.bytes = need;
   }
   hipEvent_t a0 = nullptr, a1 = nullptr;
@@ -385,12 +413,16 @@ ls_status apply_op(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, 
       h->ev_far.push_back(f1);
       h->ev_far_mixed.push_back(single ? 1 : 0);
     }
-    HIPCHK(h, lsk::launch_apply_batch(h, x, y, nrhs, ld, mode, single, bmt, bsplit, h->ws_apply.ptr, stream, f0, f1));
+    const hipError_t eb = lsk::launch_apply_batch(h, x, y, nrhs, ld, mode, single, bmt, bsplit, h->ws_apply.ptr,
+                                                  stream, f0, f1, false, may_grow);
+    if (eb == hipErrorOutOfMemory && !may_grow)
+      return fail(h, LS_ERR_ARG, "the batch tables are smaller than this application needs: call ls_reserve first");
+    HIPCHK(h, eb);
   }
   for (size_t si = 0; si < h->sc.size() && !batch; ++si) {
     if (!h->scat_skip.empty() && h->scat_skip[si]) continue;
     const Scat &sc = h->sc[si];
-    const int nsplit = splits(sc);
+    const int nsplit = plan_splits(h, pl, sc, nrhs);
     hipEvent_t f0 = nullptr, f1 = nullptr;
     if (h->prof) {
       HIPCHK(h, hipEventCreate(&f0));
@@ -426,8 +458,29 @@ static ls_status apply_common(ls_handle h, const double *x, double *y, int32_t n
   if (x == y) return fail(h, LS_ERR_ARG, "x and y must not alias");
   if (ld < h->n_total) return fail(h, LS_ERR_ARG, "ld < number of nodes");
   if (p != LS_FP64 && p != LS_MIXED) return fail(h, LS_ERR_ARG, "bad precision");
-  return lsk::apply_op(h, x, y, nrhs, ld, mode, p, stream);
+  return lsk::apply_op(h, x, y, nrhs, ld, mode, p, stream, false);
 }
+
+ls_status ls_reserve(ls_handle h, int32_t nrhs, ls_precision p) {
+  if (!h) return fail(nullptr, LS_ERR_ARG, "null handle");
+  if (nrhs < 0 || nrhs > 65535) return fail(h, LS_ERR_ARG, "bad nrhs");
+  if (p != LS_FP64 && p != LS_MIXED) return fail(h, LS_ERR_ARG, "bad precision");
+  if (nrhs == 0) return LS_OK;
+  const lsk::ApplyPlan pl = lsk::apply_plan(h, nrhs, p);
+  if (pl.need > h->ws_apply.bytes) {
+    HIPCHK(h, hipDeviceSynchronize());   // an earlier application may still use the old workspace
+    if (h->ws_apply.ptr) HIPCHK(h, hipFree(h->ws_apply.ptr));
+    h->ws_apply.ptr = nullptr;
+    h->ws_apply.bytes = 0;
+    if (lsk::dmalloc(&h->ws_apply.ptr, pl.need) != hipSuccess) return fail(h, LS_ERR_ALLOC, "workspace allocation failed");
+    h->ws_apply.bytes = pl.need;
+    h->batch_key = -1;
+  }
+  if (pl.batch) HIPCHK(h, lsk::reserve_batch_tables(h, nrhs, pl.single, pl.bmt, pl.bsplit));
+  return LS_OK;
+}
+
+int64_t ls_device_allocations(void) { return lsk::g_device_allocations.load(); }
 
 ls_status ls_solve_gmres(ls_handle h, const double *b, double *x, int32_t nrhs, int64_t ld, const ls_solve_opts *o,
                          ls_solve_info *info, hipStream_t stream) {
@@ -556,7 +609,7 @@ static ls_status ensure_ws(ls_ctx *h, lsk::Workspace &w, size_t need, hipStream_
     w.ptr = nullptr;
     w.bytes = 0;
   }
-  if (hipMalloc(&w.ptr, need) != hipSuccess) return fail(h, LS_ERR_ALLOC, "workspace allocation failed");
+  if (lsk::dmalloc(&w.ptr, need) != hipSuccess) return fail(h, LS_ERR_ALLOC, "workspace allocation failed");
   w.bytes = need;
   return LS_OK;
 }
@@ -618,7 +671,7 @@ ls_status ls_field(ls_handle h, int32_t s, const double *tx, const double *ty, i
                b_cv = al(sizeof(double) * cv.size()), b_t = al(sizeof(double) * 2 * nt);
   const size_t need = b_rp + b_ci + b_cv + b_t + lsk::field_workspace_bytes(sc.n, nrhs, nt, nsplit);
   void *ws = nullptr;
-  if (hipMalloc(&ws, need) != hipSuccess) return fail(h, LS_ERR_ALLOC, "field workspace");
+  if (lsk::dmalloc(&ws, need) != hipSuccess) return fail(h, LS_ERR_ALLOC, "field workspace");
   char *p = (char *)ws;
   int64_t *drp = (int64_t *)p;
   int32_t *dci = (int32_t *)(p + b_rp);

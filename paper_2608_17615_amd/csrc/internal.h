@@ -92,6 +92,15 @@ struct Workspace {
   size_t bytes = 0;
 };
 
+// Every device allocation of the library goes through dmalloc, which counts them (process-wide;
+// ls_device_allocations reports the count).
+void count_device_allocation();
+template <class T>
+hipError_t dmalloc(T **p, size_t bytes) {
+  count_device_allocation();
+  return hipMalloc((void **)p, bytes);
+}
+
 }  // namespace lsk
 
 struct ls_ctx {
@@ -149,14 +158,17 @@ hipError_t launch_apply_tile(const Scat &s, const double *x, double *y, int nrhs
 size_t batch_workspace_bytes(const ls_ctx *h, int nrhs, bool single, int split_len);
 hipError_t launch_apply_batch(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, Mode mode, bool single,
                               int mt, int split_len, void *ws, hipStream_t st, hipEvent_t far_start,
-                              hipEvent_t far_stop, bool far_only = false);
+                              hipEvent_t far_stop, bool far_only = false, bool may_alloc = true);
+// device tables of the persistent launch for nrhs right-hand sides and every scatterer
+hipError_t reserve_batch_tables(ls_ctx *h, int nrhs, bool single, int mt, int split_len);
 int batch_default_split_len(const ls_ctx *h, bool single);
 hipError_t launch_eval_green(const double *z2, double *g, int64_t n, int single, hipStream_t st);
 void eval_green_host(const double *z2, double *g, int64_t n);
 
-// api.hip
+// api.hip: with may_grow false the application fails (LS_ERR_ARG) instead of enlarging the
+// handle's workspace
 ls_status apply_op(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, Mode mode, ls_precision p,
-                   hipStream_t st);
+                   hipStream_t st, bool may_grow = true);
 ls_status setup_fail(ls_ctx *h, ls_status st, const char *msg);
 // krylov.hip
 ls_status solve_gmres(ls_ctx *h, const double *b, double *x, int nrhs, int64_t ld, const ls_solve_opts &o,

@@ -266,7 +266,7 @@ hipError_t ensure_chunks(Basis &B, int nvec, int64_t n, int nrhs) {
   const int need = (nvec + Basis::kChunk - 1) / Basis::kChunk;
   while ((int)B.chunks.size() < need) {
     void *p = nullptr;
-    hipError_t e = hipMalloc(&p, cb);
+    hipError_t e = lsk::dmalloc(&p, cb);
     if (e != hipSuccess) return e;
     B.chunks.push_back(p);
   }
@@ -278,7 +278,7 @@ hipError_t ensure(void *&p, size_t &have, size_t need) {
   if (p) (void)hipFree(p);
   p = nullptr;
   have = 0;
-  hipError_t e = hipMalloc(&p, need);
+  hipError_t e = lsk::dmalloc(&p, need);
   if (e == hipSuccess) have = need;
   return e;
 }

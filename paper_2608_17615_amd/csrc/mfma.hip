@@ -330,9 +330,38 @@ size_t batch_workspace_bytes(const ls_ctx *h, int nrhs, bool single, int split_l
   return batch_layout(h, nrhs, single, split_len, nullptr);
 }
 
+// bytes of the descriptor and work-item tables of the persistent launch when no scatterer is left out
+static size_t batch_table_bytes(const ls_ctx *h, int nrhs, int mt, int split_len) {
+  const int ldx = tile_ldx(nrhs);
+  const int nt = nt_of(ldx);
+  size_t items = 0;
+  for (const Scat &sc : h->sc) {
+    const int64_t nsplit = (sc.n + split_len - 1) / split_len;
+    const int64_t tblocks = (sc.n + 64 * mt - 1) / (64 * mt);
+    items += (size_t)(tblocks * nsplit * (ldx / (16 * nt)));
+  }
+  return sizeof(BatchDesc) * h->sc.size() + sizeof(WorkItem) * items + 512;
+}
+
+hipError_t reserve_batch_tables(ls_ctx *h, int nrhs, bool single, int mt, int split_len) {
+  (void)single;
+  const size_t tb = batch_table_bytes(h, nrhs, mt, split_len);
+  if (tb <= h->batch_bytes) return hipSuccess;
+  hipError_t e = hipDeviceSynchronize();   // an earlier launch may still read the old tables
+  if (e != hipSuccess) return e;
+  if (h->batch_tables) (void)hipFree(h->batch_tables);
+  h->batch_tables = nullptr;
+  h->batch_bytes = 0;
+  e = lsk::dmalloc(&h->batch_tables, tb);
+  if (e != hipSuccess) return e;
+  h->batch_bytes = tb;
+  h->batch_key = -1;
+  return hipSuccess;
+}
+
 hipError_t launch_apply_batch(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, Mode mode, bool single,
                               int mt, int split_len, void *ws, hipStream_t st, hipEvent_t far_start,
-                              hipEvent_t far_stop, bool far_only) {
+                              hipEvent_t far_stop, bool far_only, bool may_alloc) {
   const int ldx = tile_ldx(nrhs);
   const int nt = nt_of(ldx);
   const int ns = (int)h->sc.size();
@@ -369,10 +398,11 @@ hipError_t launch_apply_batch(ls_ctx *h, const double *x, double *y, int nrhs, i
   const size_t tb = sizeof(BatchDesc) * ns + sizeof(WorkItem) * items.size() + 512;
   hipError_t e = hipSuccess;
   if (tb > h->batch_bytes) {
+    if (!may_alloc) return hipErrorOutOfMemory;
     if (h->batch_tables) (void)hipFree(h->batch_tables);
     h->batch_tables = nullptr;
     h->batch_bytes = 0;
-    e = hipMalloc(&h->batch_tables, tb);
+    e = lsk::dmalloc(&h->batch_tables, tb);
     if (e != hipSuccess) return e;
     h->batch_bytes = tb;
     h->batch_key = -1;

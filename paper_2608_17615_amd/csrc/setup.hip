@@ -457,9 +457,9 @@ ls_status correction_rows(ls_ctx *h, const Scat &sc, int64_t nt, const double *t
       if (dout) (void)hipFree(dout);
       if (dtgt) (void)hipFree(dtgt);
     };
-    if (hipMalloc(&dframe, sizeof(double4) * nt) != hipSuccess ||
-        hipMalloc(&dout, sizeof(double2) * NA * nt * (size_t)nsplit) != hipSuccess ||
-        (!nodes && hipMalloc(&dtgt, sizeof(double) * 2 * nt) != hipSuccess)) {
+    if (lsk::dmalloc(&dframe, sizeof(double4) * nt) != hipSuccess ||
+        lsk::dmalloc(&dout, sizeof(double2) * NA * nt * (size_t)nsplit) != hipSuccess ||
+        (!nodes && lsk::dmalloc(&dtgt, sizeof(double) * 2 * nt) != hipSuccess)) {
       release();
       return setup_fail(h, LS_ERR_ALLOC, "monomial sums");
     }

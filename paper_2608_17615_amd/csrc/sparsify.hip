@@ -680,7 +680,7 @@ ls_status ls_sparsify_setup(ls_handle h, int32_t s, const ls_grid *g, const doub
   std::vector<double> d(sc.tr->colsum), dinv(nc);
   for (int64_t j = 0; j < nc; ++j) dinv[j] = 1.0 / d[j];
   auto up = [&](void **dst, const void *src, size_t bytes) -> bool {
-    if (hipMalloc(dst, std::max<size_t>(bytes, 16)) != hipSuccess) return false;
+    if (lsk::dmalloc(dst, std::max<size_t>(bytes, 16)) != hipSuccess) return false;
     sp->bufs.push_back(*dst);
     h->owned.push_back(*dst);
     sp->bytes += (int64_t)bytes;
@@ -733,7 +733,7 @@ ls_status ls_sparsify_apply(ls_handle h, int32_t s, const double *c, int64_t ldc
         h->ws_grid.ptr = nullptr;
         h->ws_grid.bytes = 0;
       }
-      if (hipMalloc(&h->ws_grid.ptr, need) != hipSuccess) return sfail(h, LS_ERR_ALLOC, "grid workspace");
+      if (lsk::dmalloc(&h->ws_grid.ptr, need) != hipSuccess) return sfail(h, LS_ERR_ALLOC, "grid workspace");
       h->ws_grid.bytes = need;
     }
     tmp = (double2 *)h->ws_grid.ptr;

@@ -216,7 +216,7 @@ ls_status ls_transfer_setup(ls_handle h, int32_t s, const ls_grid *g) {
   t->ny = g->ny;
   t->colsum = std::move(colsum);
   auto up = [&](void **dst, const void *src, size_t bytes) -> bool {
-    if (hipMalloc(dst, std::max<size_t>(bytes, 16)) != hipSuccess) return false;
+    if (lsk::dmalloc(dst, std::max<size_t>(bytes, 16)) != hipSuccess) return false;
     t->bufs.push_back(*dst);
     h->owned.push_back(*dst);
     return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
