@@ -127,6 +127,20 @@ ls_status ls_reserve(ls_handle h, int32_t nrhs, ls_precision p);
  * that a sequence of calls allocated nothing. */
 int64_t ls_device_allocations(void);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops or
+ * harnesses that forbid hipMalloc): y = L x as ls_apply computes it, with every temporary taken
+ * from the library's fixed per-GPU workspace of 64 MiB (a static device array that each GPU the
+ * library runs on holds until the process ends).  Same arguments as ls_apply; the same result up
+ * to the order of the floating-point sums over source splits (a scatterer whose sums need more
+ * room than the workspace holds takes fewer splits; FP32 tiles then accumulate longer partial
+ * sums).  Each scatterer takes its own launch.  Allocates nothing and never waits on the device.
+ * Sizes whose workspace exceeds 64 MiB (about nrhs x nodes > 1.3e6 for the FP64 sum, less for the
+ * tiles) are rejected with LS_ERR_ARG before anything is enqueued.  Every call on a GPU uses that
+ * GPU's one workspace, whatever the handle or stream: calls that overlap in time on one GPU race
+ * and must be ordered by the caller. */
+ls_status ls_apply_noalloc(ls_handle h, const double *x, double *y, int32_t nrhs, int64_t ld, ls_precision p,
+                           hipStream_t stream);
+
 typedef struct {
   double tol;          /* relative residual ||b - L x||_2 / ||b||_2 per column */
   int32_t maxit;       /* outer iterations (Arnoldi steps) */

@@ -88,6 +88,7 @@ def lib():
         L.ls_apply.argtypes = [vp, vp, vp, i32, i64, i32, vp]
         L.ls_apply_adjoint.argtypes = [vp, vp, vp, i32, i64, i32, vp]
         L.ls_reserve.argtypes = [vp, i32, i32]
+        L.ls_apply_noalloc.argtypes = [vp, vp, vp, i32, i64, i32, vp]
         L.ls_device_allocations.argtypes = []
         L.ls_device_allocations.restype = i64
         L.ls_solve_gmres.argtypes = [vp, vp, vp, i32, i64, vp, vp, vp]
@@ -257,6 +258,15 @@ class Operator:
     def reserve(self, nrhs, precision="fp64"):
         """Grow the application workspace for nrhs columns (ls_reserve); apply() calls it itself."""
         _check(lib().ls_reserve(self._h, int(nrhs), _PREC[precision]), self._h)
+
+    def apply_noalloc(self, x, out, precision="fp64"):
+        """y = L x through ls_apply_noalloc (the library's fixed workspace; nothing allocated)."""
+        x2 = self._cols(x)
+        if not (out.is_contiguous() and out.shape == x2.shape and out.dtype == x2.dtype):
+            raise ValueError("out must be a contiguous tensor shaped like x")
+        _check(lib().ls_apply_noalloc(self._h, x2.data_ptr(), out.data_ptr(), x2.shape[0], self.n, _PREC[precision],
+                                      _stream()), self._h)
+        return out
 
     def apply_raw(self, x, out, precision="fp64", adjoint=False):
         """ls_apply (or ls_apply_adjoint) alone, without reserving: fails if the workspace is too small."""

@@ -94,6 +94,7 @@ ls_status validate_scatterer(const ls_scatterer &s) {
 namespace lsk {
 
 ls_status setup_fail(ls_ctx *h, ls_status st, const char *msg) { return fail(h, st, msg); }
+ls_status resolve_scratch(ls_ctx *h);
 ls_status build_correction(ls_ctx *h, Scat &sc, const ls_scatterer &s, const std::vector<int32_t> &eord,
                            hipStream_t st);
 
@@ -263,6 +264,7 @@ ls_status ls_setup(const ls_scatterer *s, int32_t n_scatterers, const ls_options
   }
   (void)hipStreamDestroy(st);
   h->n_total = off;
+  if (rc == LS_OK) rc = lsk::resolve_scratch(h);
   if (rc != LS_OK) {
     g_err = h->err;
     ls_destroy(h);
@@ -317,7 +319,7 @@ ls_status ls_setup_from_csr(const ls_scatterer *s, const int64_t *rowptr, const 
       cv[2 * d + 1] = val[2 * q + 1];
     }
   }
-  if ((st = lsk::upload_correction(h, sc, rp, ci, cv)) != LS_OK) {
+  if ((st = lsk::upload_correction(h, sc, rp, ci, cv)) != LS_OK || (st = lsk::resolve_scratch(h)) != LS_OK) {
     g_err = h->err;
     ls_destroy(h);
     return st;
@@ -333,7 +335,32 @@ namespace lsk {
 namespace {
 std::atomic<int64_t> g_device_allocations{0};
 
+// The workspace of ls_apply_noalloc: a static device array, so that application allocates
+// nothing.  In host code its name stands for a host-side symbol; its address on a device comes
+// from hipGetSymbolAddress (resolved once per device by ls_setup, with that device current).
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch_ptr;   // per device ordinal
 }  // namespace
+
+// Resolves the address of the static workspace on the current device (once per device).
+ls_status resolve_scratch(ls_ctx *h) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (h->device < 0) return fail(h, LS_ERR_HIP, "no device");
+  if ((int)g_scratch_ptr.size() <= h->device) g_scratch_ptr.resize(h->device + 1, nullptr);
+  if (g_scratch_ptr[h->device]) return LS_OK;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) return fail(h, LS_ERR_HIP, std::string("hipGetSymbolAddress: ") + hipGetErrorString(e));
+  g_scratch_ptr[h->device] = p;
+  return LS_OK;
+}
+
+void *scratch_on(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return device >= 0 && device < (int)g_scratch_ptr.size() ? g_scratch_ptr[device] : nullptr;
+}
 
 void count_device_allocation() { g_device_allocations.fetch_add(1, std::memory_order_relaxed); }
 
@@ -481,6 +508,51 @@ ls_status ls_reserve(ls_handle h, int32_t nrhs, ls_precision p) {
 }
 
 int64_t ls_device_allocations(void) { return lsk::g_device_allocations.load(); }
+
+ls_status ls_apply_noalloc(ls_handle h, const double *x, double *y, int32_t nrhs, int64_t ld, ls_precision p,
+                           hipStream_t stream) {
+  if (!h) return fail(nullptr, LS_ERR_ARG, "null handle");
+  if (nrhs < 0) return fail(h, LS_ERR_ARG, "nrhs < 0");
+  if (nrhs == 0) return LS_OK;
+  if (!x || !y) return fail(h, LS_ERR_ARG, "null vector");
+  if (x == y) return fail(h, LS_ERR_ARG, "x and y must not alias");
+  if (ld < h->n_total) return fail(h, LS_ERR_ARG, "ld < number of nodes");
+  if (p != LS_FP64 && p != LS_MIXED) return fail(h, LS_ERR_ARG, "bad precision");
+  void *ws = lsk::scratch_on(h->device);
+  if (!ws) return fail(h, LS_ERR_HIP, "the allocation-free workspace is not resolved on this device");
+  // each scatterer by itself (tile or VALU kernel) with as many source splits as the workspace
+  // holds, at most the ones ls_apply takes; every size is checked before anything is enqueued
+  lsk::ApplyPlan pl = lsk::apply_plan(h, nrhs, p);
+  pl.batch = false;
+  const size_t cap = lsk::kScratchBytes;
+  std::vector<int> nsplit(h->sc.size());
+  for (size_t si = 0; si < h->sc.size(); ++si) {
+    const Scat &sc = h->sc[si];
+    const size_t col = sizeof(double2) * (size_t)sc.n * nrhs;   // one [nrhs][n] complex block
+    int64_t fit;
+    if (pl.tiles) {
+      const size_t fixed = sizeof(double2) * (size_t)sc.n * lsk::tile_ldx(nrhs) + 512;
+      fit = cap > fixed ? (int64_t)((cap - fixed) / col) - 1 : -1;
+    } else {
+      fit = cap > 256 ? (int64_t)((cap - 256) / col) - 2 : -1;
+    }
+    if (fit < 1)
+      return fail(h, LS_ERR_ARG, "nrhs x nodes too large for the 64 MiB allocation-free workspace (scatterer " +
+                                     std::to_string(si) + ", " + std::to_string(sc.n) + " nodes, " +
+                                     std::to_string(nrhs) + " columns)");
+    nsplit[si] = (int)std::min<int64_t>(lsk::plan_splits(h, pl, sc, nrhs), fit);
+  }
+  for (size_t si = 0; si < h->sc.size(); ++si) {
+    const Scat &sc = h->sc[si];
+    if (pl.tiles)
+      HIPCHK(h, lsk::launch_apply_tile(sc, x, y, nrhs, ld, lsk::Mode::Forward, pl.single, nsplit[si], ws, stream,
+                                       nullptr, nullptr));
+    else
+      HIPCHK(h, lsk::launch_apply_fp64(sc, x, y, nrhs, ld, lsk::Mode::Forward, nsplit[si], pl.chunk, pl.tpl, ws,
+                                       stream));
+  }
+  return LS_OK;
+}
 
 ls_status ls_solve_gmres(ls_handle h, const double *b, double *x, int32_t nrhs, int64_t ld, const ls_solve_opts *o,
                          ls_solve_info *info, hipStream_t stream) {
