@@ -190,8 +190,14 @@ ls_status ls_solve_gmres(ls_handle h, const double *b, double *x, int32_t nrhs, 
                          const ls_solve_opts *o, ls_solve_info *info, hipStream_t stream);
 
 /* grad_j (real, device, total nodes) = sum_d Re[conj(a_jd - k^2 (V^H lam_d)_j) u_jd]:
- * the gradient of a far-field misfit with respect to real nodal contrast values, given the
- * forward fields u, the adjoint states lam (L^H lam = conj(m) a) and a = A^H r. */
+ * the gradient of a far-field misfit J = 1/2 sum_d ||A u_d - data_d||^2 with respect to real
+ * nodal contrast values m_j, given the forward fields u (L u_d = b_d), the adjoint states lam
+ * (L^H lam_d = conj(m) a_d) and a_d = A^H (A u_d - data_d), A the far-field map of ls_farfield.
+ * It differentiates the Nystrom system L = I + k^2 V M of Section 3 (eqs. linear_system,
+ * linear_system_matrix) through its exact adjoint, with the far-field pattern of the energy
+ * balance of Section 5 (subsection on the energy balance, eq. dissipativity_identity); the paper
+ * names inverse problems as the application this serves (Conclusion), without a gradient of its
+ * own.  nrhs columns with leading dimension ld (device); grad is written, not accumulated. */
 ls_status ls_grad_contrast(ls_handle h, const double *u, const double *lam, const double *a,
                            int32_t nrhs, int64_t ld, double *grad, hipStream_t stream);
 

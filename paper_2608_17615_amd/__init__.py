@@ -610,16 +610,22 @@ def _autograd():
         """J(m) = 1/2 sum_{d,r} |u_inf,d(theta_r) - data_{d,r}|^2 with L(m) u_d = b_d.
 
         forward: set the contrast, solve, far field and misfit; only the converged fields u and the
-        far-field residual are kept (no Krylov vectors).  backward: a = A^H res, adjoint solve
+        far-field residual are kept (no Krylov vectors).  A forward or adjoint solve that misses
+        tol within maxit raises LSError (status LS_NOT_CONVERGED) instead of returning a misfit or
+        gradient of an unconverged field.  backward: a = A^H res, adjoint solve
         L^H lam = conj(m) a, grad_j = sum_d Re[conj(a_jd - k^2 (V^H lam_d)_j) u_jd].
         """
 
         @staticmethod
-        def forward(ctx, m, op, b, data, thetas, tol, maxit, precision):
+        def forward(ctx, m, op, b, data, thetas, tol, maxit, precision, adjoint_maxit):
             op.set_contrast(m)
             u, info = op.solve(b, tol=tol, maxit=maxit, precision=precision)
+            if not info["converged"]:
+                raise LSError(LS_NOT_CONVERGED, f"forward solve missed tol {tol:g} in {maxit} steps "
+                                                f"(largest relative residual {float(np.max(info['relres'])):.2e})")
             _, res, J = op.farfield(u, thetas, data)
-            ctx.op, ctx.thetas, ctx.tol, ctx.maxit, ctx.precision = op, thetas, tol, maxit, precision
+            ctx.op, ctx.thetas, ctx.tol, ctx.precision = op, thetas, tol, precision
+            ctx.maxit = adjoint_maxit if adjoint_maxit is not None else maxit
             ctx.solve_info = info
             ctx.save_for_backward(m, u, res)
             return torch.tensor(J, dtype=torch.float64, device=m.device)
@@ -630,13 +636,17 @@ def _autograd():
             op = ctx.op
             op.set_contrast(m)
             a, rhs = op.farfield_adjoint(res, ctx.thetas)
-            lam, _ = op.solve(rhs, tol=ctx.tol, maxit=ctx.maxit, precision=ctx.precision, adjoint=True)
+            lam, info = op.solve(rhs, tol=ctx.tol, maxit=ctx.maxit, precision=ctx.precision, adjoint=True)
+            if not info["converged"]:
+                raise LSError(LS_NOT_CONVERGED, f"adjoint solve missed tol {ctx.tol:g} in {ctx.maxit} steps "
+                                                f"(largest relative residual {float(np.max(info['relres'])):.2e})")
             g = op.grad_contrast(u, lam, a)
-            return gJ * g, None, None, None, None, None, None, None
+            return gJ * g, None, None, None, None, None, None, None, None
 
     return FarFieldMisfit
 
 
-def farfield_misfit(m, op, b, data, thetas, tol=1e-10, maxit=2000, precision="fp64"):
-    """Differentiable far-field misfit J(m) (real contrast m as a float64 CUDA tensor)."""
-    return _autograd().apply(m, op, b, data, thetas, tol, maxit, precision)
+def farfield_misfit(m, op, b, data, thetas, tol=1e-10, maxit=2000, precision="fp64", adjoint_maxit=None):
+    """Differentiable far-field misfit J(m) (real contrast m as a float64 CUDA tensor); the adjoint
+    solve of the backward pass takes adjoint_maxit steps at most (default: maxit)."""
+    return _autograd().apply(m, op, b, data, thetas, tol, maxit, precision, adjoint_maxit)

@@ -11,10 +11,10 @@
 //   * E_l[P](x) = -Phi(x) [x in Omega_l] + oint_{dOmega_l} (G d_nu Phi - Phi d_nu G) ds by Green's
 //     third identity with the polynomial particular solution Phi = P/k^2 - Delta P / k^4
 //     ((Delta + k^2) Phi = P for cubic P), integrated with adaptive 16-point Gauss-Legendre
-//     panels on the exact curves: host threads, libm J0/Y0/J1/Y1.
+//     panels on the exact curves: host threads, libm J0/Y0/J1/Y1 in long double.
 //   * The punctured monomial sums (N^2 x 10 work) run on the GPU: one target per lane with its
 //     own frame (c, 1/s), sources of subdomain l walked uniformly per wavefront, G from the same
-//     in-register evaluation as the operator's far sum.
+//     in-register evaluation as the operator's far sum, compensated (TwoSum) accumulation.
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -77,9 +77,18 @@ __global__ __launch_bounds__(kBlock) void poly_sums_kernel(int n, const double *
   const double4 fr = frame[ii];   // (cx, cy, 1/s, unused)
   const int s0 = q0 + blockIdx.y * split_len;
   const int s1 = min(q1, s0 + split_len);
-  double ar[NA], ai[NA];
+  // compensated accumulation (TwoSum: the rounding error of every addition is kept in cr, ci),
+  // since the sums of far-away, large monomial values cancel against the exact potentials
+  double ar[NA], ai[NA], cr[NA], ci[NA];
 #pragma unroll
-  for (int a = 0; a < NA; ++a) ar[a] = ai[a] = 0.0;
+  for (int a = 0; a < NA; ++a) ar[a] = ai[a] = cr[a] = ci[a] = 0.0;
+  auto two_sum = [](double &s, double &c, double t) {
+#pragma clang fp contract(off)
+    const double u = s + t;
+    const double bp = u - s;
+    c += (s - (u - bp)) + (t - bp);
+    s = u;
+  };
   for (int q = s0; q < s1; ++q) {
     const double2 p = pos[q];
     const double wq = w[q];
@@ -95,14 +104,16 @@ __global__ __launch_bounds__(kBlock) void poly_sums_kernel(int n, const double *
     const double P[NA] = {1.0, u, v, u2, uv, v2, u2 * u, u2 * v, u * v2, v2 * v};
 #pragma unroll
     for (int a = 0; a < NA; ++a) {
-      ar[a] = std::fma(gr, P[a], ar[a]);
-      ai[a] = std::fma(gi, P[a], ai[a]);
+      // the product is rounded on its own (no contraction into the sum)
+      const double tr = __builtin_fma(gr, P[a], 0.0), ti = __builtin_fma(gi, P[a], 0.0);
+      two_sum(ar[a], cr[a], tr);
+      two_sum(ai[a], ci[a], ti);
     }
   }
   if (i < n) {
     double2 *o = out + ((int64_t)blockIdx.y * n + i) * NA;
 #pragma unroll
-    for (int a = 0; a < NA; ++a) o[a] = make_double2(ar[a], ai[a]);
+    for (int a = 0; a < NA; ++a) o[a] = make_double2(ar[a] + cr[a], ai[a] + ci[a]);
   }
 }
 
@@ -206,7 +217,10 @@ void poly_potential(const std::vector<CurveH> &curves, bool inside, double x1, d
         const double rx = py1 - x1, ry = py2 - x2;
         const double rho = std::hypot(rx, ry);
         const double z = k * rho;
-        const double J0 = ::j0(z), Y0 = ::y0(z), J1 = ::j1(z), Y1 = ::y1(z);
+        // extended-precision Bessel values (x87 long double), rounded once: their absolute error
+        // multiplies the large polynomial densities of far-away panels
+        const long double zl = (long double)z;
+        const double J0 = (double)::j0l(zl), Y0 = (double)::y0l(zl), J1 = (double)::j1l(zl), Y1 = (double)::y1l(zl);
         // G = (i/4)(J0 + i Y0);  d_nu G = -(i k / 4)(J1 + i Y1) (y - x).nu / rho
         const double Gr = -0.25 * Y0 * ds, Gi = 0.25 * J0 * ds;
         const double f = (rx * nx + ry * ny) / rho * k * 0.25 * ds;

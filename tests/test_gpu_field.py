@@ -1,6 +1,8 @@
 """Field recovery at exterior points (ls_field) against the oracle's field recovery, on smooth
-nodal fields (the exact interior field, plane waves), where the native and the oracle's
-correction rows agree to ~1e-11 in action."""
+nodal fields (the exact interior field, plane waves).  The field rows carry the correction's
+cancellation (the interpolant extended over the subdomain), so the bar is 1e-12 or five times the
+oracle's own conditioning floor for the same points (tests/oracle_floor.py), whichever is larger (the
+factor is argued in tests/test_gpu_setup.py)."""
 import numpy as np
 import pytest
 import torch
@@ -8,6 +10,7 @@ import torch
 import paper_2608_17615_amd as lsg
 from oracle import field as ofield
 from oracle import mie
+from tests import oracle_floor as of
 from tests.gpu_cases import relmax
 from workloads import problems as P
 
@@ -29,10 +32,10 @@ def test_disk_exact_interior_field():
     ue, _ = mie.disk(prob.k, 2.0, 1.0, prob.mesh.x, prob.mesh.y)
     tx, ty = ring_points([1.05, 1.2, 1.5, 2.0, 3.0], 13)
     got = _op(prob).field(torch.tensor(ue[None, :], device="cuda"), tx, ty).cpu().numpy()
-    ref = ofield.scattered_field(prob.mesh, prob.k, prob.m, ue, tx, ty)
+    fl, ref = of.floor(lambda: ofield.scattered_field(prob.mesh, prob.k, prob.m, ue, tx, ty))
     e = relmax(got, ref)
-    print(f"disk N={prob.n_nodes}: field rel err {e:.2e}", flush=True)
-    assert e <= 1e-10
+    print(f"disk N={prob.n_nodes}: field rel err {e:.2e}, oracle floor {fl:.2e}", flush=True)
+    assert e <= max(1e-12, 5 * fl)
 
 
 def test_two_material_several_waves():
@@ -40,10 +43,10 @@ def test_two_material_several_waves():
     u = prob.incident()
     tx, ty = ring_points([1.1, 1.7, 2.5], 11, phase=0.3)
     got = _op(prob).field(torch.tensor(u, device="cuda"), tx, ty).cpu().numpy()
-    ref = ofield.scattered_field(prob.mesh, prob.k, prob.m, u, tx, ty)
+    fl, ref = of.floor(lambda: ofield.scattered_field(prob.mesh, prob.k, prob.m, u, tx, ty))
     e = relmax(got, ref)
-    print(f"two-material N={prob.n_nodes}, B=3: field rel err {e:.2e}", flush=True)
-    assert e <= 1e-10
+    print(f"two-material N={prob.n_nodes}, B=3: field rel err {e:.2e}, oracle floor {fl:.2e}", flush=True)
+    assert e <= max(1e-12, 5 * fl)
 
 
 def test_scatterer_of_a_batch_handle_and_errors():
@@ -70,7 +73,7 @@ def test_full_size_disk_field():
     u = prob.incident()
     tx, ty = ring_points([1.05, 1.5, 3.0], 8)
     got = _op(prob).field(torch.tensor(u, device="cuda"), tx, ty).cpu().numpy()
-    ref = ofield.scattered_field(prob.mesh, prob.k, prob.m, u, tx, ty)
+    fl, ref = of.floor(lambda: ofield.scattered_field(prob.mesh, prob.k, prob.m, u, tx, ty))
     e = relmax(got, ref)
-    print(f"disk N={prob.n_nodes}, B=4: field rel err {e:.2e}", flush=True)
-    assert e <= 1e-10
+    print(f"disk N={prob.n_nodes}, B=4: field rel err {e:.2e}, oracle floor {fl:.2e}", flush=True)
+    assert e <= max(1e-12, 5 * fl)

@@ -1,10 +1,11 @@
 """Full-size parity at the benchmark workloads, in the launch configurations bench.py times.
 
 The GPU operator is built by the library's own setup (so the sparse correction is the native
-one), applied to the workloads' plane waves (smooth inputs, on which the native and the oracle's
-correction agree to ~1e-11), and sampled rows are compared with the oracle, which computes each
-sampled row one by one: its punctured far sum with SciPy's H0 plus its own correction row.
-Properties that hold at any size (the adjoint identity) are checked on the full vectors."""
+one), applied to the workloads' plane waves, and sampled rows are compared with the oracle, which
+computes each sampled row one by one: its punctured far sum with SciPy's H0 plus its own
+correction row.  The FP64 bar is 1e-12 or five times the oracle's own conditioning floor for the
+same rows (tests/oracle_floor.py; the reasoning is in tests/test_gpu_setup.py), whichever is larger.  Properties that hold at any size (the
+adjoint identity) are checked on the full vectors."""
 import numpy as np
 import pytest
 import torch
@@ -12,6 +13,7 @@ import torch
 import paper_2608_17615_amd as lsg
 from oracle import green as ogreen
 from oracle import vdim
+from tests import oracle_floor as of
 from tests.gpu_cases import relmax
 from workloads import problems as P
 
@@ -45,10 +47,12 @@ def test_c3_batched_tiles_sampled_rows():
     y64 = op.apply(xt).cpu().numpy()
     ym = op.apply(xt, precision="mixed").cpu().numpy()
     rows = sample(prob.n_nodes, 16, 11)
-    ref = oracle_rows(prob, x, rows)
+    fl, ref = of.floor(lambda: oracle_rows(prob, x, rows))
     e64, em = relmax(y64[:, rows], ref), relmax(ym[:, rows], ref)
-    print(f"C3 N={prob.n_nodes} B=64: FP64 tiles {e64:.2e}, FP32 tiles {em:.2e} ({rows.size} rows)", flush=True)
-    assert e64 <= 1e-11
+    bar = max(1e-12, 5 * fl)
+    print(f"C3 N={prob.n_nodes} B=64: FP64 tiles {e64:.2e} (oracle floor {fl:.2e}, bar {bar:.1e}), "
+          f"FP32 tiles {em:.2e} ({rows.size} rows)", flush=True)
+    assert e64 <= bar
     assert em <= 3e-5
 
 
@@ -66,11 +70,13 @@ def test_c4_persistent_batch_sampled_rows():
     for s, p in enumerate(probs):
         o = op64.offsets[s]
         rows = sample(p.n_nodes, 3, 20 + s)
-        ref = oracle_rows(p, x[:, o:o + p.n_nodes], rows)
-        worst64 = max(worst64, relmax(y64[:, o + rows], ref))
+        fl, ref = of.floor(lambda: oracle_rows(p, x[:, o:o + p.n_nodes], rows))
+        e64 = relmax(y64[:, o + rows], ref)
+        worst64 = max(worst64, e64 / max(1e-12, 5 * fl))
         worstm = max(worstm, relmax(ym[:, o + rows], ref))
-    print(f"C4 16 scatterers, N = {op64.n}: FP64 tiles {worst64:.2e}, FP32 tiles {worstm:.2e}", flush=True)
-    assert worst64 <= 1e-11
+    print(f"C4 16 scatterers, N = {op64.n}: FP64 tiles at most {worst64:.2f} of the bar max(1e-12, 5 x oracle "
+          f"floor), FP32 tiles {worstm:.2e}", flush=True)
+    assert worst64 <= 1.0
     assert worstm <= 3e-5
 
 
@@ -83,13 +89,15 @@ def test_c5_forward_rows_and_adjoint_identity():
     xt = torch.tensor(x, device="cuda")
     y = op.apply(xt).cpu().numpy()
     rows = sample(prob.n_nodes, 16, 12)
-    e = relmax(y[:, rows], oracle_rows(prob, x, rows))
+    fl, ref = of.floor(lambda: oracle_rows(prob, x, rows))
+    e = relmax(y[:, rows], ref)
     yv = torch.tensor(P.random_vectors(prob.n_nodes, 16, 13), device="cuda")
     Lx = op.apply(xt)
     LHy = op.apply_adjoint(yv)
     lhs = torch.sum(Lx.conj() * yv).item()
     rhs = torch.sum(xt.conj() * LHy).item()
     ident = abs(lhs - rhs) / (torch.linalg.norm(Lx).item() * torch.linalg.norm(yv).item())
-    print(f"C5 N={prob.n_nodes} B=16: forward rows {e:.2e}, adjoint identity {ident:.1e}", flush=True)
-    assert e <= 1e-11
+    print(f"C5 N={prob.n_nodes} B=16: forward rows {e:.2e} (oracle floor {fl:.2e}), adjoint identity {ident:.1e}",
+          flush=True)
+    assert e <= max(1e-12, 5 * fl)
     assert ident <= 1e-13
