@@ -88,7 +88,7 @@ typedef struct {
   int32_t targets_per_lane; /* targets per lane in the FP64 far sum (0 = automatic; 1 or 2) */
   int32_t mixed_tile;       /* mixed-precision tile variant (0 = automatic / autotuned cache) */
   int32_t n_threads_host;   /* host threads for setup (0 = all) */
-  int32_t fp64_matrix;      /* FP64 batched sum on the matrix cores: 0 = when nrhs >= 16, 1 = never, 2 = always */
+  int32_t fp64_matrix;      /* FP64 batched sum on the matrix cores: 0 = when nrhs >= 4, 1 = never, 2 = always */
 } ls_options;
 
 typedef struct ls_ctx *ls_handle;

@@ -435,6 +435,10 @@ struct CoreOpts {
 struct CoreResult {
   std::vector<int> iters;   // per system
   std::vector<char> done;   // per system
+  // the call ended at a cycle's start because every system met tol on its FP64 residual: the
+  // residual and right-hand-side norms of that check (x has not changed since)
+  bool start_done = false;
+  std::vector<double> rn0, bn0;
   int64_t n_fp64 = 0, n_mixed = 0;
   int64_t n_reorth = 0;     // system-steps that took a second Gram-Schmidt pass
 };
@@ -524,6 +528,7 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
   const dim3 gv(blocks_of(n), nrhs);
   const dim3 gt = G.tile_grid();
   while (total_it < maxit) {
+    const bool first_of_call = first_cycle;
     // r = b - L x (FP64), skipped while x = 0
     if (first_cycle && !o.x0_given) {
       HIPTRY(hipMemcpyAsync(r, b, vb, hipMemcpyDeviceToDevice, st));
@@ -550,7 +555,14 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
       act[q] = res.done[q] ? 0 : 1;
       all = all && res.done[q];
     }
-    if (all) break;
+    if (all) {
+      // the residual was taken with the FP64 operator unless this is the unapplied x = 0 start
+      res.start_done = !(first_of_call && !o.x0_given) && (o.flexible || o.relax_eps > 0 || o.all_mixed ||
+                                                           o.matvec == LS_FP64);
+      res.rn0 = rnorm;
+      res.bn0 = bnorm;
+      break;
+    }
     // the Arnoldi iteration's own target: tol, or for a refinement pass the reduction it is
     // asked for (its estimate follows the mixed-precision operator, so the pass stops where the
     // FP64 residual can still follow it)
@@ -836,6 +848,9 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
   ls_status status = gmres_core(h, ws, wi, bb, xs, nrhs, co, res, st);
   if (status < 0) return status;
   const int nsys = (int)res.iters.size();
+  // the last GMRES call's closing residual check, when it found every system done
+  bool have_final = res.start_done;
+  std::vector<double> rn_final = res.rn0, bn_final = res.bn0;
   for (int pass = 0; pass < 30 && passes; ++pass) {
     int used = 0;
     for (int q = 0; q < nsys; ++q) used = std::max(used, res.iters[q]);
@@ -855,6 +870,9 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
     res.n_fp64 += rr.n_fp64;
     res.n_mixed += rr.n_mixed;
     res.n_reorth += rr.n_reorth;
+    have_final = rr.start_done;
+    rn_final = rr.rn0;
+    bn_final = rr.bn0;
     if (more == 0) break;   // every system met tol on its FP64 residual
   }
   for (int pass = 0; pass < 3 && relax > 0 && !passes; ++pass) {
@@ -878,26 +896,36 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
     res.n_fp64 += rr.n_fp64;
     res.n_mixed += rr.n_mixed;
     res.n_reorth += rr.n_reorth;
+    have_final = rr.start_done;
+    rn_final = rr.rn0;
+    bn_final = rr.bn0;
     if (more == 0) break;   // every system met tol on its FP64 residual
   }
-  // true residuals with the FP64 apply
-  ls_status s2 = apply_op(h, (const double *)xs, (double *)t, nrhs, n, mode, LS_FP64, st);
-  if (s2 != LS_OK) return s2;
-  ++res.n_fp64;
   {
     Gmres G{h, st, n, nrhs, mode, ws};
     HIPTRY(G.init(1));
     const int nseg = G.nseg;
-    const dim3 gv(blocks_of(n), nrhs);
-    axpy_kernel<<<gv, kBlock, 0, st>>>(n, bb, n, -1.0, t, n, r, n);
-    const std::vector<int> all(nsys, 1);
-    HIPTRY(G.set_active(all));
     std::vector<double> rn(nsys), bn(nsys);
-    for (int pass = 0; pass < 2; ++pass) {
-      HIPTRY(G.set_slot(pass == 0 ? r : bb));
-      HIPTRY(G.norms());
-      HIPTRY(hipMemcpyAsync((pass == 0 ? rn : bn).data(), G.beta, sizeof(double) * nsys, hipMemcpyDeviceToHost, st));
-      HIPTRY(hipStreamSynchronize(st));
+    if (have_final) {
+      // the last GMRES call closed on the FP64 residual of the current x: nothing to recompute
+      rn = rn_final;
+      bn = bn_final;
+    } else {
+      // true residuals with the FP64 apply
+      ls_status s2 = apply_op(h, (const double *)xs, (double *)t, nrhs, n, mode, LS_FP64, st);
+      if (s2 != LS_OK) return s2;
+      ++res.n_fp64;
+      const dim3 gv(blocks_of(n), nrhs);
+      axpy_kernel<<<gv, kBlock, 0, st>>>(n, bb, n, -1.0, t, n, r, n);
+      const std::vector<int> all(nsys, 1);
+      HIPTRY(G.set_active(all));
+      for (int pass = 0; pass < 2; ++pass) {
+        HIPTRY(G.set_slot(pass == 0 ? r : bb));
+        HIPTRY(G.norms());
+        HIPTRY(hipMemcpyAsync((pass == 0 ? rn : bn).data(), G.beta, sizeof(double) * nsys, hipMemcpyDeviceToHost,
+                              st));
+        HIPTRY(hipStreamSynchronize(st));
+      }
     }
     HIPTRY(hipMemcpy2DAsync(x_out, ld * sizeof(double2), xs, n * sizeof(double2), n * sizeof(double2), nrhs,
                             hipMemcpyDeviceToDevice, st));
