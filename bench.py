@@ -5,7 +5,7 @@ Default workload (c3): the unit disk with n = 2, k = 40, O-grid mesh with 35 cel
 the central square (N = 122 500 nodes), 64 plane waves at evenly spaced angles as one right-hand
 side block.  Form pcm: flexible GMRES (no restart within a pass, x0 = 0), right-preconditioned by
 the paper's P = I + T_C^Q (S - I) T_Q^C with the library's sparsifying S^(C) on a grid of
-k h = 0.5, in mixed-precision refinement passes: every Arnoldi application uses the FP32
+k h = 0.3 (273 x 273 nodes), in mixed-precision refinement passes: every Arnoldi application uses the FP32
 matrix-core Green's tiles (FP64 correction, Arnoldi and residuals), and each pass starts from the
 FP64 residual, until that meets the tolerance.  One step =
 one solve of all 64 waves to a relative residual of 1e-8 in every column; every operator
@@ -283,6 +283,10 @@ def solve_form(op, b, form, args, adjoint=False):
 MAX_RESOLUTION = 0.75
 
 
+# grid spacing of the Cartesian preconditioner at least this many mean node spacings
+MIN_CELL = 1.5
+
+
 def resolution(p):
     """k sqrt(max n) x mean node spacing of a problem (n = 1 - m at the nodes)."""
     import numpy as np
@@ -294,6 +298,7 @@ def setup_precond(op, probs, kh):
     """The library's sparsifying preconditioner S^(C) (ls_sparsify_setup) for every scatterer whose
     mesh resolves its interior wave, on a grid of spacing kh / k over it; returns a summary for the
     bench line."""
+    import numpy as np
     import torch
 
     from workloads import problems as P
@@ -305,7 +310,9 @@ def setup_precond(op, probs, kh):
         if resolution(p) > MAX_RESOLUTION:
             skipped.append(s)
             continue
-        g = P.cartesian_grid(p, kh)
+        # at least MIN_CELL node spacings per grid cell, so that T_Q^C sees nodes in most cells
+        spacing = float(np.sqrt(p.mesh.w.sum() / p.n_nodes))
+        g = P.cartesian_grid(p, max(kh, MIN_CELL * spacing * p.k))
         info = op.sparsify_setup(*g, P.grid_contrast(p, g), s=s)
         nodes += g[3] * g[4]
         lu_res = max(lu_res, info["lu_residual"])
@@ -314,7 +321,7 @@ def setup_precond(op, probs, kh):
     out = {"S": "sparsifying (C^(C))^-1 A, first-order V^(C), block LU by grid rows (library)", "k_h": kh,
            "grid_nodes": nodes, "build_s": time.perf_counter() - t0, "lu_residual_max": lu_res,
            "stencil_sv_ratio_min": min(sv), "unpreconditioned_scatterers": skipped,
-           "max_resolution": MAX_RESOLUTION}
+           "max_resolution": MAX_RESOLUTION, "min_cell_node_spacings": MIN_CELL}
     if skipped:
         log(f"preconditioner: scatterers {skipped} left unpreconditioned (under-resolved interior wave)")
     log(f"preconditioner: {nodes} grid nodes, built in {out['build_s']:.2f} s, LU residual {lu_res:.1e}")
@@ -561,7 +568,8 @@ def main():
                          "bm: FP32 matrix-core tiles in relaxed FP64 GMRES; pc: FP64 GMRES right-preconditioned "
                          "by P = I + T_C^Q (S - I) T_Q^C with the library's sparsifying S^(C); pcm: pc with "
                          "mixed precision (default for c3, c4, c5)")
-    ap.add_argument("--kh", type=float, default=0.5, help="pc, pcm: k times the Cartesian grid spacing")
+    ap.add_argument("--kh", type=float, default=0.3,
+                    help="pc, pcm: k times the Cartesian grid spacing (at least 1.5 mean node spacings)")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-8)

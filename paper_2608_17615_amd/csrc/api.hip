@@ -1,4 +1,6 @@
 // C ABI entry points: argument validation, internal node ordering, device uploads, dispatch.
+#include <sched.h>
+
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -7,6 +9,7 @@
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "internal.h"
@@ -363,6 +366,15 @@ void *scratch_on(int device) {
 }
 
 void count_device_allocation() { g_device_allocations.fetch_add(1, std::memory_order_relaxed); }
+
+int host_threads(const ls_options &opt) {
+  if (opt.n_threads_host > 0) return opt.n_threads_host;
+  cpu_set_t set;
+  int n = 0;
+  if (sched_getaffinity(0, sizeof(set), &set) == 0) n = CPU_COUNT(&set);
+  if (n <= 0) n = (int)std::thread::hardware_concurrency();
+  return std::max(1, std::min(n, 16));
+}
 
 // How an application of nrhs columns in precision p runs: FP32 tiles (mixed), FP64 tiles
 // (batched FP64 on the matrix cores) or the FP64 VALU sum, one persistent launch over several

@@ -92,6 +92,10 @@ struct Workspace {
   size_t bytes = 0;
 };
 
+// Host threads for setup work: opt.n_threads_host when set, else the CPUs this process may run on
+// (its affinity mask), at most 16.
+int host_threads(const ls_options &opt);
+
 // Every device allocation of the library goes through dmalloc, which counts them (process-wide;
 // ls_device_allocations reports the count).
 void count_device_allocation();

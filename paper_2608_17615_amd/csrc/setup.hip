@@ -391,7 +391,7 @@ ls_status correction_rows(ls_ctx *h, const Scat &sc, int64_t nt, const double *t
                           std::vector<double> &cv) {
   const GeomData &g = *sc.geom;
   const int nsub = g.nsub;
-  int threads = h->opt.n_threads_host > 0 ? h->opt.n_threads_host : (int)std::thread::hardware_concurrency();
+  int threads = host_threads(h->opt);
   threads = std::max(1, std::min(threads, 64));
   // interpolation element for each (target, subdomain): the node's own element, else the
   // nearest centroid (uniform bucket grid per subdomain; ties to the smaller caller index)

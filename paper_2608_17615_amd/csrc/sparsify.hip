@@ -26,7 +26,9 @@
 // (one workgroup per right-hand side, the grid rows in order, one dense block product per row
 // and direction).  S^H c = A^H (C^-H c) uses the same factors (C^H = U~^H L~^H).
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <functional>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -252,42 +254,6 @@ void parallel_for(int n, int threads, const std::function<void(int)> &f) {
   for (auto &th : pool) th.join();
 }
 
-// In-place inverse of the n x n row-major matrix a by Gauss-Jordan elimination with partial
-// pivoting.  Returns false for a singular matrix.
-bool invert(std::vector<cplx> &a, int n) {
-  std::vector<int> piv(n);
-  for (int c = 0; c < n; ++c) {
-    int p = c;
-    double best = std::abs(a[(size_t)c * n + c]);
-    for (int r = c + 1; r < n; ++r)
-      if (std::abs(a[(size_t)r * n + c]) > best) {
-        best = std::abs(a[(size_t)r * n + c]);
-        p = r;
-      }
-    if (!(best > 0)) return false;
-    piv[c] = p;
-    if (p != c)
-      for (int q = 0; q < n; ++q) std::swap(a[(size_t)c * n + q], a[(size_t)p * n + q]);
-    cplx *rc = &a[(size_t)c * n];
-    const cplx inv = 1.0 / rc[c];
-    rc[c] = 1.0;
-    for (int q = 0; q < n; ++q) rc[q] *= inv;
-    for (int r = 0; r < n; ++r) {
-      if (r == c) continue;
-      cplx *rr = &a[(size_t)r * n];
-      const cplx f = rr[c];
-      if (f == cplx(0)) continue;
-      rr[c] = 0.0;
-      for (int q = 0; q < n; ++q) rr[q] -= f * rc[q];
-    }
-  }
-  // undo the row interchanges as column interchanges, last first
-  for (int c = n - 1; c >= 0; --c)
-    if (piv[c] != c)
-      for (int r = 0; r < n; ++r) std::swap(a[(size_t)r * n + c], a[(size_t)r * n + piv[c]]);
-  return true;
-}
-
 // Entry of the tridiagonal block (i, i + dy) of C^(C) at (r, r + dx).
 inline cplx eblk(const std::vector<cplx> &E, int nx, int i, int r, int dx, int dy) {
   return E[((size_t)i * nx + r) * 9 + slot(dx, dy)];
@@ -295,43 +261,122 @@ inline cplx eblk(const std::vector<cplx> &E, int nx, int i, int r, int dx, int d
 
 }  // namespace
 
-// Block LU of C^(C): G[i] = Sigma_i^-1 (row-major, nx x nx each).  Returns false if a block is
-// singular.
-bool sparsify_factor(int nx, int ny, const std::vector<cplx> &E, std::vector<std::vector<cplx>> &G) {
-  G.assign(ny, {});
-  const size_t n2 = (size_t)nx * nx;
-  std::vector<cplx> T(n2);
-  for (int i = 0; i < ny; ++i) {
-    std::vector<cplx> S(n2, cplx(0));
-    for (int r = 0; r < nx; ++r)
-      for (int dx = -1; dx <= 1; ++dx)
-        if (r + dx >= 0 && r + dx < nx) S[(size_t)r * nx + r + dx] = eblk(E, nx, i, r, dx, 0);
-    if (i > 0) {
-      // T = G_{i-1} U_{i-1}, U_{i-1}[q][q + dx] = C[(i-1, q), (i, q + dx)]
-      const std::vector<cplx> &Gp = G[i - 1];
-      for (int r = 0; r < nx; ++r)
-        for (int c = 0; c < nx; ++c) {
-          cplx acc = 0;
-          for (int dx = -1; dx <= 1; ++dx) {
-            const int q = c - dx;
-            if (q >= 0 && q < nx) acc += Gp[(size_t)r * nx + q] * eblk(E, nx, i - 1, q, dx, 1);
-          }
-          T[(size_t)r * nx + c] = acc;
-        }
-      // S -= L_i T, L_i[r][r + dx] = C[(i, r), (i-1, r + dx)]
-      for (int r = 0; r < nx; ++r)
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int q = r + dx;
-          if (q < 0 || q >= nx) continue;
-          const cplx l = eblk(E, nx, i, r, dx, -1);
-          if (l == cplx(0)) continue;
-          for (int c = 0; c < nx; ++c) S[(size_t)r * nx + c] -= l * T[(size_t)q * nx + c];
-        }
+// A reusable barrier for the factorization's worker threads (spinning: the waits are a few
+// microseconds, one per pivot).
+struct SpinBarrier {
+  explicit SpinBarrier(int n) : n_(n) {}
+  void wait() {
+    const int g = gen_.load(std::memory_order_acquire);
+    if (count_.fetch_add(1, std::memory_order_acq_rel) + 1 == n_) {
+      count_.store(0, std::memory_order_relaxed);
+      gen_.fetch_add(1, std::memory_order_acq_rel);
+    } else {
+      while (gen_.load(std::memory_order_acquire) == g) std::this_thread::yield();
     }
-    if (!invert(S, nx)) return false;
-    G[i] = std::move(S);
   }
-  return true;
+  int n_;
+  std::atomic<int> count_{0}, gen_{0};
+};
+
+// Block LU of C^(C): G[i] = Sigma_i^-1 (row-major, nx x nx each), with `threads` host threads
+// sharing each block's work by rows (the blocks themselves are sequential).  Gauss-Jordan with
+// partial pivoting inside a block.  Returns false if a block is singular.
+bool sparsify_factor(int nx, int ny, const std::vector<cplx> &E, std::vector<std::vector<cplx>> &G, int threads) {
+  const size_t n2 = (size_t)nx * nx;
+  G.assign(ny, std::vector<cplx>(n2));
+  threads = std::max(1, std::min(threads, std::max(1, nx / 8)));
+  std::vector<cplx> S(n2), T(n2);
+  std::vector<int> piv(nx);
+  std::atomic<bool> singular{false};
+  SpinBarrier bar(threads);
+  auto work = [&](int tid) {
+    const int r0 = (int)((int64_t)nx * tid / threads), r1 = (int)((int64_t)nx * (tid + 1) / threads);
+    for (int i = 0; i < ny; ++i) {
+      // S = D_i - L_i G_{i-1} U_{i-1}, rows [r0, r1)
+      for (int r = r0; r < r1; ++r) {
+        cplx *sr = &S[(size_t)r * nx];
+        std::fill(sr, sr + nx, cplx(0));
+        for (int dx = -1; dx <= 1; ++dx)
+          if (r + dx >= 0 && r + dx < nx) sr[r + dx] = eblk(E, nx, i, r, dx, 0);
+      }
+      if (i > 0) {
+        // T = G_{i-1} U_{i-1}, U_{i-1}[q][q + dx] = C[(i-1, q), (i, q + dx)]
+        const std::vector<cplx> &Gp = G[i - 1];
+        for (int r = r0; r < r1; ++r)
+          for (int c = 0; c < nx; ++c) {
+            cplx acc = 0;
+            for (int dx = -1; dx <= 1; ++dx) {
+              const int q = c - dx;
+              if (q >= 0 && q < nx) acc += Gp[(size_t)r * nx + q] * eblk(E, nx, i - 1, q, dx, 1);
+            }
+            T[(size_t)r * nx + c] = acc;
+          }
+        bar.wait();
+        // S -= L_i T, L_i[r][r + dx] = C[(i, r), (i-1, r + dx)]
+        for (int r = r0; r < r1; ++r)
+          for (int dx = -1; dx <= 1; ++dx) {
+            const int q = r + dx;
+            if (q < 0 || q >= nx) continue;
+            const cplx l = eblk(E, nx, i, r, dx, -1);
+            if (l == cplx(0)) continue;
+            cplx *sr = &S[(size_t)r * nx];
+            const cplx *tq = &T[(size_t)q * nx];
+            for (int c = 0; c < nx; ++c) sr[c] -= l * tq[c];
+          }
+      }
+      bar.wait();
+      // Gauss-Jordan: thread 0 picks and normalises the pivot row, every thread eliminates the
+      // column from its own rows
+      for (int c = 0; c < nx; ++c) {
+        if (tid == 0) {
+          int p = c;
+          double best = std::abs(S[(size_t)c * nx + c]);
+          for (int r = c + 1; r < nx; ++r)
+            if (std::abs(S[(size_t)r * nx + c]) > best) {
+              best = std::abs(S[(size_t)r * nx + c]);
+              p = r;
+            }
+          if (!(best > 0)) {
+            singular = true;
+          } else {
+            piv[c] = p;
+            if (p != c)
+              for (int q = 0; q < nx; ++q) std::swap(S[(size_t)c * nx + q], S[(size_t)p * nx + q]);
+            cplx *rc = &S[(size_t)c * nx];
+            const cplx inv = 1.0 / rc[c];
+            rc[c] = 1.0;
+            for (int q = 0; q < nx; ++q) rc[q] *= inv;
+          }
+        }
+        bar.wait();
+        if (singular) return;
+        const cplx *rc = &S[(size_t)c * nx];
+        for (int r = r0; r < r1; ++r) {
+          if (r == c) continue;
+          cplx *rr = &S[(size_t)r * nx];
+          const cplx f = rr[c];
+          if (f == cplx(0)) continue;
+          rr[c] = 0.0;
+          for (int q = 0; q < nx; ++q) rr[q] -= f * rc[q];
+        }
+        bar.wait();
+      }
+      // undo the row interchanges as column interchanges (last first), row by row, into G_i
+      std::vector<cplx> &Gi = G[i];
+      for (int r = r0; r < r1; ++r) {
+        cplx *sr = &S[(size_t)r * nx];
+        for (int c = nx - 1; c >= 0; --c)
+          if (piv[c] != c) std::swap(sr[c], sr[piv[c]]);
+        std::copy(sr, sr + nx, &Gi[(size_t)r * nx]);
+      }
+      bar.wait();
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < threads; ++t) pool.emplace_back(work, t);
+  work(0);
+  for (auto &th : pool) th.join();
+  return !singular;
 }
 
 // x = C^-1 y through the factors on the host (the sweeps the device kernel performs).
@@ -607,7 +652,7 @@ ls_status ls_sparsify_stencil_host(const ls_grid *g, double k, const double *m_g
     return lsk::setup_fail(nullptr, LS_ERR_ARG, "bad argument");
   std::vector<cplx> w, e;
   lsk::sparsify_stencil(g->nx, g->ny, g->h, k, (const cplx *)m_grid,
-                        (int)std::max(1u, std::thread::hardware_concurrency()), w, e, sv_ratio);
+                        lsk::host_threads(ls_options{}), w, e, sv_ratio);
   std::memcpy(W, w.data(), sizeof(cplx) * w.size());
   std::memcpy(E, e.data(), sizeof(cplx) * e.size());
   return LS_OK;
@@ -626,13 +671,13 @@ ls_status ls_sparsify_setup(ls_handle h, int32_t s, const ls_grid *g, const doub
   if (st != LS_OK) return st;
   Scat &sc = h->sc[s];
   const int nx = g->nx, ny = g->ny;
-  const int threads = h->opt.n_threads_host > 0 ? h->opt.n_threads_host
-                                                : (int)std::max(1u, std::thread::hardware_concurrency());
+  const int threads = lsk::host_threads(h->opt);
   std::vector<cplx> W, E;
   double ratio = 0;
   lsk::sparsify_stencil(nx, ny, g->h, sc.k, (const cplx *)m_grid, threads, W, E, &ratio);
   std::vector<std::vector<cplx>> G;
-  if (!lsk::sparsify_factor(nx, ny, E, G)) return sfail(h, LS_ERR_BREAKDOWN, "singular block in the LU of C^(C)");
+  if (!lsk::sparsify_factor(nx, ny, E, G, threads))
+    return sfail(h, LS_ERR_BREAKDOWN, "singular block in the LU of C^(C)");
   // residual of a seeded right-hand side solved through the factors, C x applied by the stencil
   double lu_res = 0;
   {
