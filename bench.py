@@ -59,7 +59,18 @@ METRIC = "Green interactions/s + time to 1e-8 residual, batched/mixed vs FP64 pl
 FLOPS_RANGE = {"small": 72, "mid1": 106, "mid2": 92, "far": 79}
 FLOPS_PER_RHS = 8
 Z_BOUNDS = (2.0, 5.0, 12.0)
-PEAK_FP64_TFLOPS = 78.6       # vector and matrix: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
+# The split-FP16 tile kernel (far_tile_h_kernel), counted the same way on its loop body: per pair,
+# coordinates and k^2 r^2 in FP64 (6), z^(-1/2) and the tail (z, the FP64 Newton step for z, the
+# phase in turns, sine, cosine, modulus: 18), the modulus-phase polynomials (far z >= 8: 15, z in
+# [1, 8): 38), or the FP64 small-argument series for z < 1 (69 after the coordinates); plus 4 for
+# the hi/lo splits of Re G, Im G and Re G + Im G.  The contraction runs on the matrix cores.
+FLOPS_H16_RANGE = {"small": 75, "mid": 62, "far": 39}
+FLOPS_H16_SPLIT = 4
+Z_BOUNDS_H16 = (1.0, 8.0)
+# VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz, for FP64 and for unpacked FP32 (the
+# build turns the packed FP32 instructions off, so FP32 work issues at the FP64 rate)
+PEAK_FP64_TFLOPS = 78.6
+PEAK_VALU_TFLOPS = 78.6
 PEAK_FP32_MFMA_TFLOPS = 157.3
 # HBM bytes per far-kernel launch in the default workload, from two rocprofv3 counter passes
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors that make a 1 GiB copy read 1 GiB and write
@@ -70,37 +81,59 @@ FAR_TRAFFIC_SOURCES = ("apply.hip", "hankel.h", "hankel_tables.h")
 FAR_TRAFFIC_DIGEST = "57aa3428bd671f22"
 
 
-def far_traffic():
+# The same for the split-FP16 tile kernel at the default workload (unit disk, N = 122 500, 64
+# plane waves): FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 per launch, averaged over the 17 launches of one
+# solve (profiles/far_tile_h_disk_N122500_B64_counters.md); most of it is the 34 source splits'
+# partial sums (34 x 64 x 122 500 x 16 B written, read back by the epilogue).
+H16_TRAFFIC_BYTES = 3_392_566_000 + 4_503_041_000
+H16_TRAFFIC_SOURCES = ("mfma.hip", "hankel.h", "hankel_tables.h")
+H16_TRAFFIC_DIGEST = "f8c54ea7cb08b28e"
+
+
+def _digest(files):
     import hashlib
     h = hashlib.sha256()
-    for f in FAR_TRAFFIC_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, "paper_2608_17615_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    return FAR_TRAFFIC_BYTES if h.hexdigest()[:16] == FAR_TRAFFIC_DIGEST else None
+    return h.hexdigest()[:16]
+
+
+def far_traffic():
+    return FAR_TRAFFIC_BYTES if _digest(FAR_TRAFFIC_SOURCES) == FAR_TRAFFIC_DIGEST else None
+
+
+def h16_traffic():
+    return H16_TRAFFIC_BYTES if _digest(H16_TRAFFIC_SOURCES) == H16_TRAFFIC_DIGEST else None
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def z_fractions(meshes_k, rows=256, seed=0):
-    """Fractions of node pairs in the far kernel's argument ranges (seeded row sample),
+def z_fractions(meshes_k, rows=256, seed=0, bounds=Z_BOUNDS, names=("small", "mid1", "mid2", "far")):
+    """Fractions of node pairs in a far kernel's argument ranges (seeded row sample),
     weighted by each scatterer's pair count."""
     import numpy as np
     rng = np.random.default_rng(seed)
-    acc = np.zeros(4)
+    acc = np.zeros(len(bounds) + 1)
     for mesh, k in meshes_k:
         n = mesh.x.size
         sel = rng.choice(n, min(rows, n), replace=False)
-        cnt = np.zeros(4)
+        cnt = np.zeros(len(bounds) + 1)
         for r in sel:
             z = np.hypot(mesh.x - mesh.x[r], mesh.y - mesh.y[r]) * k
             z[r] = -1.0
             z = z[z >= 0]
-            cnt += np.histogram(z, bins=[0.0, *Z_BOUNDS, np.inf])[0]
+            cnt += np.histogram(z, bins=[0.0, *bounds, np.inf])[0]
         acc += cnt / cnt.sum() * float(n) * (n - 1)
     f = acc / acc.sum()
-    return dict(zip(("small", "mid1", "mid2", "far"), (float(v) for v in f)))
+    return dict(zip(names, (float(v) for v in f)))
+
+
+def flops_per_pair_h16(meshes_k):
+    f = z_fractions(meshes_k, bounds=Z_BOUNDS_H16, names=("small", "mid", "far"))
+    return sum(f[r] * FLOPS_H16_RANGE[r] for r in FLOPS_H16_RANGE) + FLOPS_H16_SPLIT, f
 
 
 def flops_per_pair(frac, nrhs=1):
@@ -162,6 +195,18 @@ def roofline_mfma(pair_rhs, far_s, single):
     achieved = FLOPS_PER_RHS * pair_rhs / far_s / 1e12
     return {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
             "traffic": None}
+
+
+def roofline_h16(pair_rhs, nrhs, far_s, meshes_k):
+    """The split-FP16 tiles are bound by the Green's evaluation on the VALU (one per pair and
+    64-column group; the contraction overlaps on the matrix cores): VALU flops per pair counted on
+    the kernel's assembly, weighted by the pairs' z ranges, against the VALU peak."""
+    fpp, frac = flops_per_pair_h16(meshes_k)
+    groups = -(-nrhs // 64)
+    pairs = pair_rhs / nrhs * groups
+    achieved = fpp * pairs / far_s / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_VALU_TFLOPS, "traffic": h16_traffic() if nrhs == 64 else None}, fpp, frac
 
 
 class Timer:
@@ -329,13 +374,31 @@ def setup_precond(op, probs, kh):
 
 
 def dominant_tiles(prof):
-    """The tile kernel (FP64 or FP32) with the larger share of far-sum time in a profile, with its
-    launches, milliseconds and pair-RHS interactions."""
-    ms32, n32, p32 = prof["far_ms_mixed"], prof["far_launches_mixed"], prof["pair_rhs_mixed"]
-    ms64, n64, p64 = prof["far_ms"] - ms32, prof["far_launches"] - n32, prof["pair_rhs"] - p32
-    if ms32 >= ms64:
-        return True, n32, ms32, p32
-    return False, n64, ms64, p64
+    """The tile kernel family ("h16" split-FP16, "f32" or "f64") with the largest share of far-sum
+    time in a profile, with its launches, milliseconds and pair-RHS interactions."""
+    ms16, n16, p16 = prof["far_ms_h16"], prof["far_launches_h16"], prof["pair_rhs_h16"]
+    ms32, n32, p32 = (prof["far_ms_mixed"] - ms16, prof["far_launches_mixed"] - n16,
+                      prof["pair_rhs_mixed"] - p16)
+    ms64, n64, p64 = (prof["far_ms"] - prof["far_ms_mixed"], prof["far_launches"] - prof["far_launches_mixed"],
+                      prof["pair_rhs"] - prof["pair_rhs_mixed"])
+    return max([("h16", n16, ms16, p16), ("f32", n32, ms32, p32), ("f64", n64, ms64, p64)], key=lambda t: t[2])
+
+
+TILE_KERNEL = {"h16": "far_tile_h_kernel", "f32": "far_tile_kernel<float>", "f64": "far_tile_kernel<double>"}
+
+
+def tiles_roofline(prof, nrhs, meshes_k):
+    """roofline entry and kernel record of the dominant tile kernel of a profile"""
+    kind, nl, ms, pr = dominant_tiles(prof)
+    extra = {}
+    if kind == "h16":
+        roof, fpp, zf = roofline_h16(pr, nrhs, ms / 1e3, meshes_k)
+        extra = {"valu_flops_per_pair": fpp, "z_ranges": zf,
+                 "matrix_core_tflops": FLOPS_PER_RHS * pr / (ms / 1e3) / 1e12}
+    else:
+        roof = roofline_mfma(pr, ms / 1e3, kind == "f32")
+    kern = {"kernel": TILE_KERNEL[kind], "launches": nl, "ms_avg": ms / max(nl, 1), **extra}
+    return kind, roof, kern, ms
 
 
 def reference_column(op, b, args, precond):
@@ -401,13 +464,11 @@ def run_batched(args, probs, label, B):
     else:
         step_s = secs / steps
         prof = {k: sum(r[4].prof[k] for r in runs) for k in runs[-1][4].prof}
-        single, nl, ms, pr = dominant_tiles(prof)
-        roof = roofline_mfma(pr, ms / 1e3, single)
-        dtype = "f32-mfma+f64" if form in ("bm", "pcm") else "f64"
-        kern = {"kernel": "far_tile_kernel<float>" if single else "far_tile_kernel<double>",
-                "launches": nl, "ms_avg": ms / max(nl, 1), "share_of_step": ms / 1e3 / secs}
-        if len(probs) > 1:
-            kern["kernel"] = "far_tile_persistent<float>" if single else "far_tile_persistent<double>"
+        kind, roof, kern, ms = tiles_roofline(prof, B, [(p.mesh, p.k) for p in probs])
+        dtype = {"h16": "f16x2-mfma+f64", "f32": "f32-mfma+f64", "f64": "f64"}[kind]
+        kern["share_of_step"] = ms / 1e3 / secs
+        if len(probs) > 1 and kind != "h16":
+            kern["kernel"] = kern["kernel"].replace("far_tile_kernel", "far_tile_persistent")
     # true FP64 residual of the returned solution, per column and per (scatterer, column) system
     r = b[:x.shape[0]] - op.apply(x)
     relres = (torch.linalg.norm(r, dim=1) / torch.linalg.norm(b[:x.shape[0]], dim=1)).cpu().numpy()
@@ -497,9 +558,8 @@ def run_gradient(args, prob, label, B):
     else:
         total_s = secs
         prof = {k: fwd[4].prof[k] + adj[4].prof[k] for k in fwd[4].prof}
-        single, nl, ms, pr = dominant_tiles(prof)
-        roof = roofline_mfma(pr, ms / 1e3, single)
-        dtype = "f32-mfma+f64" if form in ("bm", "pcm") else "f64"
+        kind, roof, _, _ = tiles_roofline(prof, B, [(prob.mesh, prob.k)])
+        dtype = {"h16": "f16x2-mfma+f64", "f32": "f32-mfma+f64", "f64": "f64"}[kind]
     check = None
     if form == "bm":
         # untimed: the same misfit and gradient through FP64 solves (batched FP64 tiles)

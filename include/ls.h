@@ -89,6 +89,11 @@ typedef struct {
   int32_t mixed_tile;       /* mixed-precision tile variant (0 = automatic / autotuned cache) */
   int32_t n_threads_host;   /* host threads for setup (0 = all) */
   int32_t fp64_matrix;      /* FP64 batched sum on the matrix cores: 0 = when nrhs >= 4, 1 = never, 2 = always */
+  int32_t mixed_fp16;       /* LS_MIXED tiles on split FP16 (each operand a sum of two FP16 numbers, three FP16
+                             * matrix-core products with FP32 accumulation per real product, one launch per
+                             * scatterer) instead of FP32: 0 = for single-scatterer handles when nrhs rounds up
+                             * to a multiple of 64, 1 = always, 2 = never */
+  int32_t pad_;
 } ls_options;
 
 typedef struct ls_ctx *ls_handle;
@@ -377,9 +382,12 @@ typedef struct {
   double apply_ms;
   double pair_rhs;      /* Green's interactions evaluated: sum over applications of
                          * N_s (N_s - 1) x right-hand sides over the scatterers computed */
-  int64_t far_launches_mixed;  /* the part of the three figures above due to FP32 tiles */
+  int64_t far_launches_mixed;  /* the part of the three figures above in mixed precision */
   double far_ms_mixed;
   double pair_rhs_mixed;
+  int64_t far_launches_h16;    /* the part of the mixed figures due to split-FP16 tiles */
+  double far_ms_h16;
+  double pair_rhs_h16;
 } ls_profile;
 ls_status ls_profile_enable(ls_handle h, int32_t on);
 ls_status ls_profile_query(ls_handle h, ls_profile *out, int32_t reset);

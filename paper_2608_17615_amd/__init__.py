@@ -50,7 +50,8 @@ class _Profile(ctypes.Structure):
     _fields_ = [("far_launches", ctypes.c_int64), ("far_ms", ctypes.c_double), ("apply_calls", ctypes.c_int64),
                 ("apply_ms", ctypes.c_double), ("pair_rhs", ctypes.c_double),
                 ("far_launches_mixed", ctypes.c_int64), ("far_ms_mixed", ctypes.c_double),
-                ("pair_rhs_mixed", ctypes.c_double)]
+                ("pair_rhs_mixed", ctypes.c_double), ("far_launches_h16", ctypes.c_int64),
+                ("far_ms_h16", ctypes.c_double), ("pair_rhs_h16", ctypes.c_double)]
 
 
 class _TuneResult(ctypes.Structure):
@@ -60,7 +61,8 @@ class _TuneResult(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("source_split", ctypes.c_int32), ("rhs_chunk", ctypes.c_int32),
                 ("targets_per_lane", ctypes.c_int32), ("mixed_tile", ctypes.c_int32),
-                ("n_threads_host", ctypes.c_int32), ("fp64_matrix", ctypes.c_int32)]
+                ("n_threads_host", ctypes.c_int32), ("fp64_matrix", ctypes.c_int32),
+                ("mixed_fp16", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class _SolveOpts(ctypes.Structure):
@@ -194,8 +196,9 @@ class Scatterer:
         return s, keep
 
 
-def _options(source_split=0, rhs_chunk=0, targets_per_lane=0, mixed_tile=0, n_threads_host=0, fp64_matrix=0):
-    return _Options(source_split, rhs_chunk, targets_per_lane, mixed_tile, n_threads_host, fp64_matrix)
+def _options(source_split=0, rhs_chunk=0, targets_per_lane=0, mixed_tile=0, n_threads_host=0, fp64_matrix=0,
+             mixed_fp16=0):
+    return _Options(source_split, rhs_chunk, targets_per_lane, mixed_tile, n_threads_host, fp64_matrix, mixed_fp16, 0)
 
 
 class Operator:
@@ -547,7 +550,9 @@ class Operator:
         _check(lib().ls_profile_query(self._h, ctypes.byref(p), int(bool(reset))), self._h)
         return {"far_launches": p.far_launches, "far_ms": p.far_ms, "apply_calls": p.apply_calls,
                 "apply_ms": p.apply_ms, "pair_rhs": p.pair_rhs, "far_launches_mixed": p.far_launches_mixed,
-                "far_ms_mixed": p.far_ms_mixed, "pair_rhs_mixed": p.pair_rhs_mixed}
+                "far_ms_mixed": p.far_ms_mixed, "pair_rhs_mixed": p.pair_rhs_mixed,
+                "far_launches_h16": p.far_launches_h16, "far_ms_h16": p.far_ms_h16,
+                "pair_rhs_h16": p.pair_rhs_h16}
 
     def correction_nnz(self, s=0):
         return int(lib().ls_correction_nnz(self._h, s))

@@ -380,7 +380,7 @@ int host_threads(const ls_options &opt) {
 // (batched FP64 on the matrix cores) or the FP64 VALU sum, one persistent launch over several
 // scatterers on the matrix cores, and the workspace it needs.
 struct ApplyPlan {
-  bool single, tiles, batch;
+  bool single, tiles, batch, h16;
   int tpl, chunk, bmt, bsplit;
   size_t need;
 };
@@ -399,7 +399,11 @@ ApplyPlan apply_plan(const ls_ctx *h, int nrhs, ls_precision p) {
   pl.tiles = pl.single || h->opt.fp64_matrix == 2 || (h->opt.fp64_matrix == 0 && nrhs >= 4);
   pl.tpl = h->opt.targets_per_lane == 2 ? 2 : 1;
   pl.chunk = h->opt.rhs_chunk > 0 ? h->opt.rhs_chunk : 1;
-  pl.batch = pl.tiles && h->sc.size() > 1;
+  // mixed precision on split FP16 (one launch per scatterer) where a wave holds a 64-column group,
+  // unless the option asks otherwise (1: always, 2: never)
+  pl.h16 = pl.single && (h->opt.mixed_fp16 == 1 ||
+                         (h->opt.mixed_fp16 == 0 && h->sc.size() == 1 && lsk::tile_ldx(nrhs) % 64 == 0));
+  pl.batch = pl.tiles && h->sc.size() > 1 && !pl.h16;
   const lsk::TileTune &tt = h->tune[pl.single ? 1 : 0];
   pl.bmt = h->opt.mixed_tile > 0 ? h->opt.mixed_tile : (tt.mt > 0 ? tt.mt : lsk::tile_mt(nrhs, pl.single));
   pl.bsplit = tt.split_len > 0 ? tt.split_len : lsk::batch_default_split_len(h, pl.single);
@@ -408,8 +412,9 @@ ApplyPlan apply_plan(const ls_ctx *h, int nrhs, ls_precision p) {
   else
     for (const Scat &sc : h->sc) {
       const int nsplit = plan_splits(h, pl, sc, nrhs);
-      pl.need = std::max(pl.need, pl.tiles ? lsk::tile_workspace_bytes(sc.n, nrhs, nsplit)
-                                           : lsk::apply_workspace_bytes(sc.n, nrhs, nsplit));
+      pl.need = std::max(pl.need, pl.h16     ? lsk::tile_h_workspace_bytes(sc.n, nrhs, nsplit)
+                                  : pl.tiles ? lsk::tile_workspace_bytes(sc.n, nrhs, nsplit)
+                                             : lsk::apply_workspace_bytes(sc.n, nrhs, nsplit));
     }
   return pl;
 }
@@ -440,6 +445,7 @@ ls_status apply_op(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, 
         const double pr = (double)h->sc[si].n * (double)(h->sc[si].n - 1) * nrhs;
         h->prof_pairs += pr;
         if (single) h->prof_pairs_mixed += pr;
+        if (pl.h16) h->prof_pairs_h16 += pr;
       }
     HIPCHK(h, hipEventCreate(&a0));
     HIPCHK(h, hipEventCreate(&a1));
@@ -470,9 +476,11 @@ ls_status apply_op(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, 
       HIPCHK(h, hipEventCreate(&f1));
       h->ev_far.push_back(f0);
       h->ev_far.push_back(f1);
-      h->ev_far_mixed.push_back(single ? 1 : 0);
+      h->ev_far_mixed.push_back(pl.h16 ? 2 : (single ? 1 : 0));
     }
-    if (tiles)
+    if (pl.h16)
+      HIPCHK(h, lsk::launch_apply_tile_h(sc, x, y, nrhs, ld, mode, nsplit, h->ws_apply.ptr, stream, f0, f1));
+    else if (tiles)
       HIPCHK(h, lsk::launch_apply_tile(sc, x, y, nrhs, ld, mode, single, nsplit, h->ws_apply.ptr, stream, f0, f1));
     else
       HIPCHK(h, lsk::launch_apply_fp64(sc, x, y, nrhs, ld, mode, nsplit, chunk, tpl, h->ws_apply.ptr, stream, f0,
@@ -544,7 +552,10 @@ ls_status ls_apply_noalloc(ls_handle h, const double *x, double *y, int32_t nrhs
     const Scat &sc = h->sc[si];
     const size_t col = sizeof(double2) * (size_t)sc.n * nrhs;   // one [nrhs][n] complex block
     int64_t fit;
-    if (pl.tiles) {
+    if (pl.h16) {
+      const size_t fixed = 2 * 6 * (size_t)((sc.n + 31) / 32 * 32) * lsk::tile_ldx(nrhs) + 16 * (size_t)lsk::tile_ldx(nrhs) + 1024;
+      fit = cap > fixed ? (int64_t)((cap - fixed) / col) - 1 : -1;
+    } else if (pl.tiles) {
       const size_t fixed = sizeof(double2) * (size_t)sc.n * lsk::tile_ldx(nrhs) + 512;
       fit = cap > fixed ? (int64_t)((cap - fixed) / col) - 1 : -1;
     } else {
@@ -558,7 +569,10 @@ ls_status ls_apply_noalloc(ls_handle h, const double *x, double *y, int32_t nrhs
   }
   for (size_t si = 0; si < h->sc.size(); ++si) {
     const Scat &sc = h->sc[si];
-    if (pl.tiles)
+    if (pl.h16)
+      HIPCHK(h, lsk::launch_apply_tile_h(sc, x, y, nrhs, ld, lsk::Mode::Forward, nsplit[si], ws, stream, nullptr,
+                                         nullptr));
+    else if (pl.tiles)
       HIPCHK(h, lsk::launch_apply_tile(sc, x, y, nrhs, ld, lsk::Mode::Forward, pl.single, nsplit[si], ws, stream,
                                        nullptr, nullptr));
     else
@@ -659,6 +673,9 @@ ls_status ls_profile_query(ls_handle h, ls_profile *out, int32_t reset) {
   out->far_launches_mixed = 0;
   out->far_ms_mixed = 0.0;
   out->pair_rhs_mixed = h->prof_pairs_mixed;
+  out->far_launches_h16 = 0;
+  out->far_ms_h16 = 0.0;
+  out->pair_rhs_h16 = h->prof_pairs_h16;
   for (size_t i = 0; i + 1 < h->ev_far.size(); i += 2) {
     float ms = 0.f;
     HIPCHK(h, hipEventSynchronize(h->ev_far[i + 1]));
@@ -667,6 +684,10 @@ ls_status ls_profile_query(ls_handle h, ls_profile *out, int32_t reset) {
     if (h->ev_far_mixed[i / 2]) {
       out->far_ms_mixed += ms;
       ++out->far_launches_mixed;
+    }
+    if (h->ev_far_mixed[i / 2] == 2) {
+      out->far_ms_h16 += ms;
+      ++out->far_launches_h16;
     }
   }
   for (size_t i = 0; i + 1 < h->ev_apply.size(); i += 2) {
@@ -683,6 +704,7 @@ ls_status ls_profile_query(ls_handle h, ls_profile *out, int32_t reset) {
     h->ev_apply.clear();
     h->prof_pairs = 0.0;
     h->prof_pairs_mixed = 0.0;
+    h->prof_pairs_h16 = 0.0;
   }
   return LS_OK;
 }

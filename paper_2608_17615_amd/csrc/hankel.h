@@ -330,11 +330,33 @@ __host__ __device__ __forceinline__ float hornerf(const Arr &c, float x) {
   return r;
 }
 
-template <class Tab>
+// A polynomial's coefficients times a constant factor, rounded to FP32 at compile time.
+template <int N>
+struct F32Poly {
+  float c[N];
+  __host__ __device__ constexpr float operator[](int i) const { return c[i]; }
+};
+template <int N>
+constexpr F32Poly<N> f32_scaled(const float (&a)[N], double f) {
+  F32Poly<N> r{};
+  for (int i = 0; i < N; ++i) r.c[i] = (float)((double)a[i] * f);
+  return r;
+}
+// H16: return 256 G instead of G/K (the split-FP16 tiles' scale), by modulus polynomials that carry
+// the factor 256 K; the extra rounding of the coefficients is 2^-24 relative.
+constexpr double H16_GSCALE = 256.0 * G_SCALE;
+constexpr F32Poly<4> F32_FAR_MOD_H16 = f32_scaled(F32_FAR_MOD, H16_GSCALE);
+constexpr F32Poly<11> F32_MID_MOD_H16 = f32_scaled(F32_MID_MOD, H16_GSCALE);
+
+template <bool H16 = false, class Tab>
 __host__ __device__ __forceinline__ void green32_unit(double A, float &gre, float &gim, const Tab &T) {
   if (A < 1.0) {
     double r, i;
     green_small(A, r, i, T);
+    if (H16) {
+      r *= H16_GSCALE;
+      i *= H16_GSCALE;
+    }
     gre = (float)r;
     gim = (float)i;
     return;
@@ -349,11 +371,17 @@ __host__ __device__ __forceinline__ void green32_unit(double A, float &gre, floa
   float mod, ph;
   if (a >= F32_ZF * F32_ZF) {
     const float t2 = t * t;
-    mod = hornerf(F32_FAR_MOD, t2);
+    if constexpr (H16)
+      mod = hornerf(F32_FAR_MOD_H16, t2);
+    else
+      mod = hornerf(F32_FAR_MOD, t2);
     ph = std::fma(t, hornerf(F32_FAR_PH, t2), -0.785398163f);
   } else {
     const float x = (t - F32_MID_TA) * F32_MID_SCALE;
-    mod = hornerf(F32_MID_MOD, x);
+    if constexpr (H16)
+      mod = hornerf(F32_MID_MOD_H16, x);
+    else
+      mod = hornerf(F32_MID_MOD, x);
     ph = hornerf(F32_MID_PH, x);
   }
   const float m4 = mod * s;

@@ -111,9 +111,10 @@ struct ls_ctx {
   std::vector<lsk::Scat> sc;
   bool prof = false;
   std::vector<hipEvent_t> ev_far, ev_apply;   // start/stop pairs, in launch order
-  std::vector<char> ev_far_mixed;              // per far-sum launch: FP32 tiles
+  std::vector<char> ev_far_mixed;              // per far-sum launch: 0 FP64, 1 FP32 tiles, 2 split-FP16 tiles
   double prof_pairs = 0.0;                     // interactions evaluated while profiling
-  double prof_pairs_mixed = 0.0;               // of which by FP32 tiles
+  double prof_pairs_mixed = 0.0;               // of which in mixed precision
+  double prof_pairs_h16 = 0.0;                 // of which by split-FP16 tiles
   int64_t n_total = 0;
   int device = 0;
   ls_options opt{};
@@ -159,6 +160,10 @@ size_t tile_workspace_bytes(int64_t n, int nrhs, int nsplit);
 int tile_source_split(int64_t n, int nrhs, bool single);
 hipError_t launch_apply_tile(const Scat &s, const double *x, double *y, int nrhs, int64_t ld, Mode mode, bool single,
                              int nsplit, void *ws, hipStream_t st, hipEvent_t far_start, hipEvent_t far_stop);
+// split-FP16 tiles (LS_MIXED with opt.mixed_fp16, one scatterer per launch)
+size_t tile_h_workspace_bytes(int64_t n, int nrhs, int nsplit);
+hipError_t launch_apply_tile_h(const Scat &s, const double *x, double *y, int nrhs, int64_t ld, Mode mode, int nsplit,
+                               void *ws, hipStream_t st, hipEvent_t far_start, hipEvent_t far_stop);
 size_t batch_workspace_bytes(const ls_ctx *h, int nrhs, bool single, int split_len);
 hipError_t launch_apply_batch(ls_ctx *h, const double *x, double *y, int nrhs, int64_t ld, Mode mode, bool single,
                               int mt, int split_len, void *ws, hipStream_t st, hipEvent_t far_start,

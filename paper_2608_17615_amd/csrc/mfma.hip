@@ -289,6 +289,264 @@ void launch_persistent_nt(const BatchDesc *desc, const WorkItem *items, int n_it
 
 int nt_of(int ldx) { return (ldx / 16) % 4 == 0 ? 4 : ((ldx / 16) % 2 == 0 ? 2 : 1); }
 
+// ---------------------------------------------------------------------------------------------
+// Split-FP16 tiles (mixed precision on the FP16 matrix cores).  Each real operand v is carried as
+// v_hi + v_lo, two FP16 numbers (v_hi = fp16(v), v_lo = fp16(v - v_hi): about 22 significant bits),
+// and a real product as A_hi B_hi + A_hi B_lo + A_lo B_hi, three v_mfma_f32_16x16x32_f16 with FP32
+// accumulation (the dropped A_lo B_lo is below 2^-22 of the product).  With Gauss's three real
+// products per complex tile that is nine MFMAs per (M-tile, N-tile) and 32 sources.  FP16's range
+// needs scales: the Green's values enter as 256 G (|G| < 0.8), the densities of right-hand side b
+// as s_b 2^(13 - e_b) with 2^e_b <= max |Re s_b|, |Im s_b| < 2^(e_b + 1), so every hi part is far
+// inside FP16's range and a lo part is normal for values above 2^-9 of the column's largest.  The
+// partial sums are brought back to G/K units in FP64 per column (colinv).
+//   Layout of the split densities: six planes (Re hi, Re lo, Im hi, Im lo, (Re + Im) hi, (Re + Im) lo),
+//   each [source / 8][ldx][8] halves, sources padded with zeros to a multiple of 32: the eight
+//   sources of one lane's MFMA operand are one 16-byte load.
+//   Operand layout of the 16x16x32 MFMA: lane l supplies row l % 16 of A and column l % 16 of B at
+//   eight contraction indices that depend on l / 16 only (the same eight for A and B), here the
+//   sources s + 8 (l / 16) + j, j < 8.  Results are D[4 (l / 16) + r][l % 16], as for the FP32 tiles.
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+constexpr int kHPlanes = 6;
+
+__host__ __device__ inline int64_t h_npad(int64_t n) { return (n + 31) / 32 * 32; }
+
+__device__ __forceinline__ double2 density(int64_t i, int b, const int32_t *__restrict__ perm,
+                                           const double *__restrict__ w, const double2 *__restrict__ m,
+                                           const double2 *__restrict__ x, int64_t ld, int64_t off, bool fwd,
+                                           double2 *fv) {
+  const double2 xv = x[(int64_t)b * ld + off + perm[i]];
+  if (!fwd) {
+    *fv = xv;
+    return xv;
+  }
+  const double2 mi = m[i];
+  *fv = make_double2(mi.x * xv.x - mi.y * xv.y, mi.x * xv.y + mi.y * xv.x);
+  return make_double2(w[i] * fv->x, w[i] * fv->y);
+}
+
+__global__ void zero_u32_kernel(unsigned *p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// cmax[b] = max over the nodes of max(|Re s_b|, |Im s_b|) as the bits of a non-negative float
+// (rounded up, so that the scale below never overflows); grid (ceil(n / kBlock), nrhs)
+__global__ __launch_bounds__(kBlock) void colmax_kernel(int64_t n, const int32_t *__restrict__ perm,
+                                                        const double *__restrict__ w, const double2 *__restrict__ m,
+                                                        const double2 *__restrict__ x, int64_t ld, int64_t off,
+                                                        int fwd, unsigned *__restrict__ cmax) {
+  __shared__ float red[kBlock / 64];
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int b = blockIdx.y;
+  float v = 0.f;
+  if (i < n) {
+    double2 fv;
+    const double2 sv = density(i, b, perm, w, m, x, ld, off, fwd != 0, &fv);
+    const double a = fmax(fabs(sv.x), fabs(sv.y));
+    v = __double2float_ru(a);
+  }
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float r = red[0];
+    for (int k = 1; k < kBlock / 64; ++k) r = fmaxf(r, red[k]);
+    atomicMax(cmax + b, __float_as_uint(r));
+  }
+}
+
+__device__ __forceinline__ void split16(double v, _Float16 &hi, _Float16 &lo) {
+  hi = (_Float16)(float)v;
+  lo = (_Float16)(float)(v - (double)(float)hi);
+}
+
+// the same for an FP32 value: v - hi is exact in FP32 (hi is v rounded to 11 bits)
+__device__ __forceinline__ void split16f(float v, _Float16 &hi, _Float16 &lo) {
+  hi = (_Float16)v;
+  lo = (_Float16)(v - (float)hi);
+}
+
+// the split densities (planes Xh), the FP64 f[b][i] for the sparse correction, and colinv[b] =
+// 1 / (256 K cs_b) with cs_b the column's scale; grid over npad * ldx
+__global__ __launch_bounds__(kBlock) void prologue_h_kernel(int64_t n, int nrhs, int ldx,
+                                                            const int32_t *__restrict__ perm,
+                                                            const double *__restrict__ w,
+                                                            const double2 *__restrict__ m,
+                                                            const double2 *__restrict__ x, int64_t ld, int64_t off,
+                                                            int fwd, const unsigned *__restrict__ cmax,
+                                                            _Float16 *__restrict__ Xh, double2 *__restrict__ f,
+                                                            double *__restrict__ colinv) {
+  const int64_t npad = h_npad(n);
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= npad * ldx) return;
+  const int64_t i = t / ldx;
+  const int b = (int)(t - i * ldx);
+  const size_t plane = (size_t)npad * ldx;
+  const size_t idx = ((size_t)(i >> 3) * ldx + b) * 8 + (i & 7);
+  double sr = 0.0, si = 0.0, cs = 1.0;
+  if (b < nrhs) {
+    const float mx = __uint_as_float(cmax[b]);
+    cs = mx > 0.f ? ldexp(1.0, 13 - ilogbf(mx)) : 1.0;
+    if (i == 0) colinv[b] = 1.0 / (cs * 256.0 * G_SCALE);
+    if (i < n) {
+      double2 fv;
+      const double2 sv = density(i, b, perm, w, m, x, ld, off, fwd != 0, &fv);
+      f[(int64_t)b * n + i] = fv;
+      sr = sv.x * cs;
+      si = sv.y * cs;
+    }
+  }
+  _Float16 h, l;
+  split16(sr, h, l);
+  Xh[idx] = h;
+  Xh[plane + idx] = l;
+  split16(si, h, l);
+  Xh[2 * plane + idx] = h;
+  Xh[3 * plane + idx] = l;
+  split16(sr + si, h, l);
+  Xh[4 * plane + idx] = h;
+  Xh[5 * plane + idx] = l;
+}
+
+__device__ __forceinline__ v4f mma16(v8h a, v8h b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+union H8 {
+  v8h v;
+  h2 p[4];
+};
+
+// hi and lo parts of two FP32 values at once (one packed conversion each way)
+__device__ __forceinline__ void split16x2(f2 v, h2 &hi, h2 &lo) {
+  hi = __builtin_convertvector(v, h2);
+  const f2 back = __builtin_convertvector(hi, f2);
+  lo = __builtin_convertvector(v - back, h2);
+}
+
+constexpr int kHChunk = kBlock;   // source positions staged in LDS per pass of a block
+
+// grid: (ceil(n / (4 * 16 * MT)), source splits, ldx / (16 * NT)); split_len a multiple of 32.
+// The four waves of a block take different targets and the same sources, whose positions pass
+// through LDS kHChunk at a time.
+template <int MT, int NT, bool CONJ>
+__global__ __launch_bounds__(kBlock) void far_tile_h_kernel(int n, const double2 *__restrict__ pos,
+                                                            const _Float16 *__restrict__ Xh, int ldx, int nrhs,
+                                                            double k2, int split_len,
+                                                            const double *__restrict__ colinv,
+                                                            double2 *__restrict__ part) {
+  __shared__ double2 spos[kHChunk];
+  const int lane = threadIdx.x & 63;
+  const int kq = lane >> 4, col = lane & 15;
+  const int t0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 * MT;
+  const int b0 = blockIdx.z * 16 * NT;
+  const int s0 = blockIdx.y * split_len;
+  const int s1 = min(n, s0 + split_len);
+  const size_t plane = (size_t)h_npad(n) * ldx;
+  int tm[MT];
+  double xt[MT], yt[MT];
+#pragma unroll
+  for (int mi = 0; mi < MT; ++mi) {
+    tm[mi] = t0 + 16 * mi + col;
+    const double2 p = pos[tm[mi] < n ? tm[mi] : n - 1];
+    xt[mi] = p.x;
+    yt[mi] = p.y;
+  }
+  v4f p0[MT][NT], p1[MT][NT], p2[MT][NT];
+#pragma unroll
+  for (int mi = 0; mi < MT; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < NT; ++ni) {
+      p0[mi][ni] = v4f{0, 0, 0, 0};
+      p1[mi][ni] = v4f{0, 0, 0, 0};
+      p2[mi][ni] = v4f{0, 0, 0, 0};
+    }
+  for (int c0 = s0; c0 < s1; c0 += kHChunk) {
+    __syncthreads();   // every wave is done with the previous chunk
+    {
+      const int src = c0 + (int)threadIdx.x;
+      spos[threadIdx.x] = pos[src < n ? src : n - 1];
+    }
+    __syncthreads();
+    const int c1 = min(s1, c0 + kHChunk);
+    for (int s = c0; s < c1; s += 32) {
+      // 256 G for this lane's eight sources s + 8 kq + j and each of its M-tiles
+      float gr[MT][8], gi[MT][8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const double2 p = spos[s - c0 + 8 * kq + j];
+#pragma unroll
+        for (int mi = 0; mi < MT; ++mi) {
+          const double dx = xt[mi] - p.x, dy = yt[mi] - p.y;
+          lsk::green32_unit<true>(k2 * std::fma(dx, dx, dy * dy), gr[mi][j], gi[mi][j], mtab());
+          if (CONJ) gi[mi][j] = -gi[mi][j];
+        }
+      }
+      // the wave's targets t0 .. t0 + 16 MT - 1 meet these sources (the diagonal pair, G undefined
+      // there) or the step runs past the split's last source: zero those pairs
+      if ((s < t0 + 16 * MT && t0 < s + 32) || s + 32 > c1) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int src = s + 8 * kq + j;
+#pragma unroll
+          for (int mi = 0; mi < MT; ++mi)
+            if (src >= c1 || src == tm[mi]) {
+              gr[mi][j] = 0.f;
+              gi[mi][j] = 0.f;
+            }
+        }
+      }
+      H8 ar_h[MT], ar_l[MT], ai_h[MT], ai_l[MT], a2_h[MT], a2_l[MT];
+#pragma unroll
+      for (int mi = 0; mi < MT; ++mi)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const f2 vr = {gr[mi][2 * q], gr[mi][2 * q + 1]}, vi = {gi[mi][2 * q], gi[mi][2 * q + 1]};
+          split16x2(vr, ar_h[mi].p[q], ar_l[mi].p[q]);
+          split16x2(vi, ai_h[mi].p[q], ai_l[mi].p[q]);
+          split16x2(vr + vi, a2_h[mi].p[q], a2_l[mi].p[q]);
+        }
+#pragma unroll
+      for (int ni = 0; ni < NT; ++ni) {
+        const size_t bi = ((size_t)(s / 8 + kq) * ldx + b0 + 16 * ni + col) * 8;
+        const v8h br_h = *(const v8h *)(Xh + bi), br_l = *(const v8h *)(Xh + plane + bi);
+        const v8h bi_h = *(const v8h *)(Xh + 2 * plane + bi), bi_l = *(const v8h *)(Xh + 3 * plane + bi);
+        const v8h b2_h = *(const v8h *)(Xh + 4 * plane + bi), b2_l = *(const v8h *)(Xh + 5 * plane + bi);
+#pragma unroll
+        for (int mi = 0; mi < MT; ++mi) {
+          p0[mi][ni] = mma16(ar_h[mi].v, br_h, p0[mi][ni]);
+          p0[mi][ni] = mma16(ar_h[mi].v, br_l, p0[mi][ni]);
+          p0[mi][ni] = mma16(ar_l[mi].v, br_h, p0[mi][ni]);
+          p1[mi][ni] = mma16(ai_h[mi].v, bi_h, p1[mi][ni]);
+          p1[mi][ni] = mma16(ai_h[mi].v, bi_l, p1[mi][ni]);
+          p1[mi][ni] = mma16(ai_l[mi].v, bi_h, p1[mi][ni]);
+          p2[mi][ni] = mma16(a2_h[mi].v, b2_h, p2[mi][ni]);
+          p2[mi][ni] = mma16(a2_h[mi].v, b2_l, p2[mi][ni]);
+          p2[mi][ni] = mma16(a2_l[mi].v, b2_h, p2[mi][ni]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int mi = 0; mi < MT; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < NT; ++ni) {
+      const int b = b0 + 16 * ni + col;
+      const double ci = b < nrhs ? colinv[b] : 0.0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int t = t0 + 16 * mi + 4 * kq + r;
+        if (t < n && b < nrhs) {
+          const double a = (double)p0[mi][ni][r], c = (double)p1[mi][ni][r];
+          part[((int64_t)blockIdx.y * nrhs + b) * n + t] =
+              make_double2((a - c) * ci, ((double)p2[mi][ni][r] - a - c) * ci);
+        }
+      }
+    }
+}
+
 }  // namespace
 
 int tile_ldx(int nrhs) { return (nrhs + 15) / 16 * 16; }
@@ -493,6 +751,73 @@ int tile_source_split(int64_t n, int nrhs, bool single) {
   if (s > 128) s = 128;
   if (s > n) s = n;
   return (int)s;
+}
+
+size_t tile_h_workspace_bytes(int64_t n, int nrhs, int nsplit) {
+  // six FP16 planes [npad][ldx], column maxima and scales, f [nrhs][n], part [nsplit][nrhs][n]
+  const size_t ldx = (size_t)tile_ldx(nrhs);
+  return 2 * kHPlanes * (size_t)h_npad(n) * ldx + 256 + 16 * ldx + 256 +
+         sizeof(double2) * (size_t)n * nrhs * (1 + (size_t)nsplit) + 512;
+}
+
+hipError_t launch_apply_tile_h(const Scat &s, const double *x, double *y, int nrhs, int64_t ld, Mode mode, int nsplit,
+                               void *ws, hipStream_t st, hipEvent_t far_start, hipEvent_t far_stop) {
+  const int64_t n = s.n, npad = h_npad(n);
+  const int ldx = tile_ldx(nrhs);
+  auto al = [](char *q) { return (char *)(((uintptr_t)q + 255) & ~(uintptr_t)255); };
+  char *p = (char *)ws;
+  _Float16 *Xh = (_Float16 *)p;
+  p = al(p + 2 * kHPlanes * (size_t)npad * ldx);
+  unsigned *cmax = (unsigned *)p;
+  double *colinv = (double *)(p + 8 * (size_t)ldx);
+  p = al(p + 16 * (size_t)ldx);
+  double2 *f = (double2 *)p;
+  double2 *part = f + n * nrhs;
+  const double2 *xc = (const double2 *)x;
+  const int fwd = mode == Mode::Forward ? 1 : 0;
+  zero_u32_kernel<<<(nrhs + 255) / 256, 256, 0, st>>>(cmax, nrhs);
+  colmax_kernel<<<dim3((unsigned)((n + kBlock - 1) / kBlock), (unsigned)nrhs), kBlock, 0, st>>>(
+      n, s.perm, s.w, s.m, xc, ld, s.off, fwd, cmax);
+  prologue_h_kernel<<<(unsigned)((npad * ldx + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+      n, nrhs, ldx, s.perm, s.w, s.m, xc, ld, s.off, fwd, cmax, Xh, f, colinv);
+  // a multiple of 32 sources per split
+  const int split_len = (int)(((n + nsplit - 1) / nsplit + 31) / 32 * 32);
+  const int used = (int)((n + split_len - 1) / split_len);
+  if (far_start) (void)hipEventRecord(far_start, st);
+  // the kernel is bound by the Green's evaluation on the VALU, so a wave takes as many right-hand
+  // sides as its registers hold: two M-tiles and four N-tiles (221 VGPRs) at 64 columns.  Measured at
+  // N = 122 500, B = 64, k = 40: 36.5 ms (MT 2, NT 4), 40.9 (MT 1, NT 4), 49.0 (MT 2, NT 2); the FP32
+  // tiles take 62.7 ms
+  constexpr int MT = 2, NT = 2;
+  const dim3 grid((unsigned)((n + 64 * MT - 1) / (64 * MT)), (unsigned)used, (unsigned)(ldx / 32 > 0 ? ldx / 32 : 1));
+  if (ldx % 64 == 0) {
+    const dim3 g4((unsigned)((n + 64 * MT - 1) / (64 * MT)), (unsigned)used, (unsigned)(ldx / 64));
+    if (fwd)
+      far_tile_h_kernel<MT, 4, false><<<g4, kBlock, 0, st>>>((int)n, s.pos, Xh, ldx, nrhs, s.k * s.k, split_len,
+                                                              colinv, part);
+    else
+      far_tile_h_kernel<MT, 4, true><<<g4, kBlock, 0, st>>>((int)n, s.pos, Xh, ldx, nrhs, s.k * s.k, split_len,
+                                                             colinv, part);
+  } else if (ldx % 32 != 0) {
+    // an odd number of 16-column groups: one N-tile per wave
+    const dim3 g1((unsigned)((n + 64 * MT - 1) / (64 * MT)), (unsigned)used, (unsigned)(ldx / 16));
+    if (fwd)
+      far_tile_h_kernel<MT, 1, false><<<g1, kBlock, 0, st>>>((int)n, s.pos, Xh, ldx, nrhs, s.k * s.k, split_len,
+                                                              colinv, part);
+    else
+      far_tile_h_kernel<MT, 1, true><<<g1, kBlock, 0, st>>>((int)n, s.pos, Xh, ldx, nrhs, s.k * s.k, split_len,
+                                                             colinv, part);
+  } else if (fwd) {
+    far_tile_h_kernel<MT, NT, false><<<grid, kBlock, 0, st>>>((int)n, s.pos, Xh, ldx, nrhs, s.k * s.k, split_len,
+                                                               colinv, part);
+  } else {
+    far_tile_h_kernel<MT, NT, true><<<grid, kBlock, 0, st>>>((int)n, s.pos, Xh, ldx, nrhs, s.k * s.k, split_len,
+                                                              colinv, part);
+  }
+  if (far_stop) (void)hipEventRecord(far_stop, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_epilogue(s, part, used, f, x, y, nrhs, ld, mode, st);
 }
 
 hipError_t launch_apply_tile(const Scat &s, const double *x, double *y, int nrhs, int64_t ld, Mode mode, bool single,

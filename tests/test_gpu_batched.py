@@ -46,3 +46,29 @@ def test_mixed_tiles_error(name, B):
     ea = relmax(ya, _cols(c, "LHx", B))
     print(f"{name} B={B}: mixed apply {e:.2e} adjoint {ea:.2e}", flush=True)
     assert e <= 1e-6 and ea <= 1e-6
+
+
+@pytest.mark.parametrize("name", ["disk2500", "twomat1040", "ellipse900"])
+@pytest.mark.parametrize("B", [5, 16, 20, 48, 64, 100])
+def test_split_fp16_tiles_error(name, B):
+    """Split-FP16 matrix-core tiles (each operand a sum of two FP16 numbers, three FP16 products with
+    FP32 accumulation): forward and adjoint within the FP32 tiles' bar of the oracle's L x, for
+    every tile shape (one, two and four 16-column tiles per wave, ragged column counts)."""
+    p, c, op = _op(name, mixed_fp16=1)
+    x = torch.tensor(_cols(c, "x", B), device="cuda")
+    y = op.apply(x, precision="mixed").cpu().numpy()
+    e = relmax(y, _cols(c, "Lx", B))
+    ea = relmax(op.apply_adjoint(x, precision="mixed").cpu().numpy(), _cols(c, "LHx", B))
+    print(f"{name} B={B}: split-FP16 apply {e:.2e} adjoint {ea:.2e}", flush=True)
+    assert e <= 1e-6 and ea <= 1e-6
+
+
+def test_split_fp16_is_the_default_at_64_columns():
+    """A single-scatterer handle takes the split-FP16 tiles by default at 64 columns and the FP32
+    tiles at 16: the default equals the forced variant bit for bit."""
+    p, c, op = _op("disk2500")
+    _, _, h16 = _op("disk2500", mixed_fp16=1)
+    _, _, f32 = _op("disk2500", mixed_fp16=2)
+    for B, same in ((64, h16), (16, f32)):
+        x = torch.tensor(_cols(c, "x", B), device="cuda")
+        assert torch.equal(op.apply(x, precision="mixed"), same.apply(x, precision="mixed"))

@@ -29,13 +29,15 @@ def test_apply_matches_oracle_dense(name, kh):
     x0, y0, h, nx, ny = g
     S, _, _, _, ratio = osp.sparsifying_preconditioner(tr.Grid(x0, y0, h, nx, ny), p.k, m)
     rng = np.random.default_rng(2)
-    c = rng.standard_normal((5, nx * ny)) + 1j * rng.standard_normal((5, nx * ny))
-    ct = torch.tensor(c, device="cuda")
-    e_f = relmax(op.sparsify_apply(ct).cpu().numpy(), c @ S.T)
-    e_a = relmax(op.sparsify_apply(ct, adjoint=True).cpu().numpy(), c @ S.conj())
-    print(f"{name} grid {nx}x{ny}: S {e_f:.2e}, S^H {e_a:.2e}, LU residual {info['lu_residual']:.1e}, "
-          f"sv ratio {info['sv_ratio']:.2e} (oracle {ratio:.2e})", flush=True)
-    assert e_f <= 1e-12 and e_a <= 1e-12
+    c = rng.standard_normal((20, nx * ny)) + 1j * rng.standard_normal((20, nx * ny))
+    # 1, 5 and 20 right-hand sides: one column group of the cooperative sweeps, and 16 + 4
+    for nb in (1, 5, 20):
+        ct = torch.tensor(c[:nb], device="cuda")
+        e_f = relmax(op.sparsify_apply(ct).cpu().numpy(), c[:nb] @ S.T)
+        e_a = relmax(op.sparsify_apply(ct, adjoint=True).cpu().numpy(), c[:nb] @ S.conj())
+        print(f"{name} grid {nx}x{ny}, {nb} vectors: S {e_f:.2e}, S^H {e_a:.2e}, LU residual "
+              f"{info['lu_residual']:.1e}, sv ratio {info['sv_ratio']:.2e} (oracle {ratio:.2e})", flush=True)
+        assert e_f <= 1e-12 and e_a <= 1e-12
     assert info["lu_residual"] <= 1e-12
     assert abs(info["sv_ratio"] - ratio) <= 1e-9 * ratio
 
@@ -121,3 +123,42 @@ def test_errors_and_regrid_drops_the_preconditioner():
     op.set_grid(*g)                                   # a new transfer grid drops S^(C)
     with pytest.raises(lsg.LSError):
         op.sparsify_apply(torch.zeros((1, g[3] * g[4]), dtype=torch.complex128, device="cuda"))
+
+
+def _apply9(E, z, nx, ny):
+    """(sum_o E[j, o] z[j + off(o)])_j for grid vectors z of shape (B, nx ny)."""
+    out = np.zeros_like(z)
+    zz = z.reshape(z.shape[0], ny, nx)
+    for o in range(9):
+        dx, dy = o % 3 - 1, o // 3 - 1
+        sh = np.zeros_like(zz)
+        ys, xs = slice(max(0, -dy), ny - max(0, dy)), slice(max(0, -dx), nx - max(0, dx))
+        yd, xd = slice(max(0, dy), ny - max(0, -dy)), slice(max(0, dx), nx - max(0, -dx))
+        sh[:, ys, xs] = zz[:, yd, xd]           # sh[iy, ix] = z[iy + dy, ix + dx] where on the grid
+        out += E[:, o].reshape(1, ny, nx).reshape(1, -1) * sh.reshape(z.shape[0], -1)
+    return out
+
+
+def test_full_size_grid_sweeps_invert_c_and_adjoint_identity():
+    """The grid of the unit disk at k = 40 and k h = 0.3 (273 x 273 nodes) with 64 vectors, the
+    launch the benchmark's preconditioned solve makes: C^(C) (S c) = A c through the stencils the
+    library builds (a property of the block LU at any size), and <S c, d> = <c, S^H d>."""
+    p = P.disk_problem(4, 40.0, 2.0)
+    op = _op(p)
+    g = P.cartesian_grid(p, 0.3)
+    x0, y0, h, nx, ny = g
+    m = P.grid_contrast(p, g)
+    info = op.sparsify_setup(*g, m)
+    W, E, _ = lsg.sparsify_stencil_host(h, nx, ny, p.k, m)
+    rng = np.random.default_rng(5)
+    c = rng.standard_normal((64, nx * ny)) + 1j * rng.standard_normal((64, nx * ny))
+    d = rng.standard_normal((64, nx * ny)) + 1j * rng.standard_normal((64, nx * ny))
+    sc = op.sparsify_apply(torch.tensor(c, device="cuda")).cpu().numpy()
+    shd = op.sparsify_apply(torch.tensor(d, device="cuda"), adjoint=True).cpu().numpy()
+    ac = _apply9(W, c, nx, ny)
+    res = np.abs(_apply9(E, sc, nx, ny) - ac).max() / np.abs(ac).max()
+    ident = abs(np.vdot(sc, d) - np.vdot(c, shd)) / (np.linalg.norm(sc) * np.linalg.norm(d))
+    print(f"grid {nx}x{ny}, 64 vectors: C (S c) vs A c {res:.2e} (LU residual {info['lu_residual']:.1e}), "
+          f"adjoint identity {ident:.1e}", flush=True)
+    assert res <= 1e-11
+    assert ident <= 1e-13
