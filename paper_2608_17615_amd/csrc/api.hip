@@ -12,6 +12,7 @@
 #include <thread>
 #include <vector>
 
+#include "host.h"
 #include "internal.h"
 
 using lsk::Scat;

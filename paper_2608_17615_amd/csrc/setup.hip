@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "hankel.h"
+#include "host.h"
 #include "internal.h"
 
 namespace lsk {
@@ -378,24 +379,19 @@ ls_status build_geometry(ls_ctx *h, Scat &sc, const ls_scatterer &s, const std::
   return LS_OK;
 }
 
-namespace {
-
-// Correction rows (10 entries per subdomain) for nt targets, in CSR form on the host.
+// Host stage of the correction rows for nt targets: the interpolation element tau of every
+// (target, subdomain) and the exact polynomial potentials E[P_a] there (Er, Ei: [nt][nsub][10]).
 //   nodes = true : the targets are the scatterer's own nodes (internal order); a node's own
 //                  element serves its own subdomain, it lies inside that subdomain, and the
 //                  monomial sums leave out the node itself;
 //   nodes = false: external targets (tx, ty), all outside the scatterer: the nearest element
 //                  serves every subdomain and nothing is left out.
-ls_status correction_rows(ls_ctx *h, const Scat &sc, int64_t nt, const double *tx, const double *ty, bool nodes,
-                          hipStream_t st, std::vector<int64_t> &rp, std::vector<int32_t> &ci,
-                          std::vector<double> &cv) {
-  const GeomData &g = *sc.geom;
+void correction_potentials(const GeomData &g, int threads, int64_t nt, const double *tx, const double *ty,
+                           bool nodes, std::vector<int32_t> &tau, std::vector<double> &Er, std::vector<double> &Ei) {
   const int nsub = g.nsub;
-  int threads = host_threads(h->opt);
-  threads = std::max(1, std::min(threads, 64));
   // interpolation element for each (target, subdomain): the node's own element, else the
   // nearest centroid (uniform bucket grid per subdomain; ties to the smaller caller index)
-  std::vector<int32_t> tau((size_t)nt * nsub);
+  tau.assign((size_t)nt * nsub, 0);
   for (int l = 0; l < nsub; ++l) {
     const auto &E = g.sub_elems[l];
     double bx0 = 1e300, bx1 = -1e300, by0 = 1e300, by1 = -1e300;
@@ -450,7 +446,8 @@ ls_status correction_rows(ls_ctx *h, const Scat &sc, int64_t nt, const double *t
   }
   // exact polynomial potentials (host threads)
   GaussLegendre gl;
-  std::vector<double> Er((size_t)nt * nsub * NA), Ei((size_t)nt * nsub * NA);
+  Er.assign((size_t)nt * nsub * NA, 0.0);
+  Ei.assign((size_t)nt * nsub * NA, 0.0);
   const double k = g.k;
   parallel_for(nt * nsub, threads, [&](int64_t jl) {
     const int64_t j = jl / nsub;
@@ -461,6 +458,55 @@ ls_status correction_rows(ls_ctx *h, const Scat &sc, int64_t nt, const double *t
     poly_potential(g.curves[l], inside, xj, yj, g.ecx[e], g.ecy[e], g.esc[e], k, gl, &Er[(size_t)jl * NA],
                    &Ei[(size_t)jl * NA]);
   });
+}
+
+// Host stage closing the correction rows: per (target, subdomain) the solve V^T r = E - S with
+// the interpolation element's factors, S the punctured monomial sums ([nt][nsub][10] complex).
+void correction_solve(const GeomData &g, int threads, int64_t nt, const std::vector<int32_t> &tau,
+                      const std::vector<double> &Er, const std::vector<double> &Ei, const std::vector<double> &S,
+                      std::vector<int64_t> &rp, std::vector<int32_t> &ci, std::vector<double> &cv) {
+  const int nsub = g.nsub;
+  rp.resize(nt + 1);
+  for (int64_t j = 0; j <= nt; ++j) rp[j] = j * NA * nsub;
+  ci.resize((size_t)nt * NA * nsub);
+  cv.resize((size_t)nt * NA * nsub * 2);
+  parallel_for(nt, threads, [&](int64_t j) {
+    for (int l = 0; l < nsub; ++l) {
+      const size_t jl = (size_t)j * nsub + l;
+      const int32_t e = tau[jl];
+      double dr[NA], di[NA];
+      for (int a = 0; a < NA; ++a) {
+        dr[a] = Er[jl * NA + a] - S[(jl * NA + a) * 2];
+        di[a] = Ei[jl * NA + a] - S[(jl * NA + a) * 2 + 1];
+      }
+      lu10_solve(&g.LU[(size_t)e * NA * NA], &g.piv[(size_t)e * NA], dr);
+      lu10_solve(&g.LU[(size_t)e * NA * NA], &g.piv[(size_t)e * NA], di);
+      for (int i = 0; i < NA; ++i) {
+        const size_t d = (size_t)rp[j] + (size_t)l * NA + i;
+        ci[d] = 10 * e + i;
+        cv[2 * d] = dr[i];
+        cv[2 * d + 1] = di[i];
+      }
+    }
+  });
+}
+
+namespace {
+
+// Correction rows (10 entries per subdomain) for nt targets, in CSR form on the host: the host
+// potentials, the punctured monomial sums on the GPU, and the solves with the interpolation
+// matrices (nodes as for correction_potentials).
+ls_status correction_rows(ls_ctx *h, const Scat &sc, int64_t nt, const double *tx, const double *ty, bool nodes,
+                          hipStream_t st, std::vector<int64_t> &rp, std::vector<int32_t> &ci,
+                          std::vector<double> &cv) {
+  const GeomData &g = *sc.geom;
+  const int nsub = g.nsub;
+  int threads = host_threads(h->opt);
+  threads = std::max(1, std::min(threads, 64));
+  std::vector<int32_t> tau;
+  std::vector<double> Er, Ei;
+  correction_potentials(g, threads, nt, tx, ty, nodes, tau, Er, Ei);
+  const double k = g.k;
   // monomial sums on the GPU
   std::vector<double> S((size_t)nt * nsub * NA * 2);
   {
@@ -527,30 +573,7 @@ ls_status correction_rows(ls_ctx *h, const Scat &sc, int64_t nt, const double *t
     release();
     if (err != hipSuccess) return setup_fail(h, LS_ERR_HIP, hipGetErrorString(err));
   }
-  // rows: V^T r = E - S per (target, subdomain)
-  rp.resize(nt + 1);
-  for (int64_t j = 0; j <= nt; ++j) rp[j] = j * NA * nsub;
-  ci.resize((size_t)nt * NA * nsub);
-  cv.resize((size_t)nt * NA * nsub * 2);
-  parallel_for(nt, threads, [&](int64_t j) {
-    for (int l = 0; l < nsub; ++l) {
-      const size_t jl = (size_t)j * nsub + l;
-      const int32_t e = tau[jl];
-      double dr[NA], di[NA];
-      for (int a = 0; a < NA; ++a) {
-        dr[a] = Er[jl * NA + a] - S[(jl * NA + a) * 2];
-        di[a] = Ei[jl * NA + a] - S[(jl * NA + a) * 2 + 1];
-      }
-      lu10_solve(&g.LU[(size_t)e * NA * NA], &g.piv[(size_t)e * NA], dr);
-      lu10_solve(&g.LU[(size_t)e * NA * NA], &g.piv[(size_t)e * NA], di);
-      for (int i = 0; i < NA; ++i) {
-        const size_t d = (size_t)rp[j] + (size_t)l * NA + i;
-        ci[d] = 10 * e + i;
-        cv[2 * d] = dr[i];
-        cv[2 * d + 1] = di[i];
-      }
-    }
-  });
+  correction_solve(g, threads, nt, tau, Er, Ei, S, rp, ci, cv);
   return LS_OK;
 }
 

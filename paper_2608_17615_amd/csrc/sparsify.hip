@@ -36,6 +36,7 @@
 #include <thread>
 #include <vector>
 
+#include "host.h"
 #include "internal.h"
 
 namespace lsk {
