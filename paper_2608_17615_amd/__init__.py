@@ -62,7 +62,7 @@ class _Options(ctypes.Structure):
     _fields_ = [("source_split", ctypes.c_int32), ("rhs_chunk", ctypes.c_int32),
                 ("targets_per_lane", ctypes.c_int32), ("mixed_tile", ctypes.c_int32),
                 ("n_threads_host", ctypes.c_int32), ("fp64_matrix", ctypes.c_int32),
-                ("mixed_fp16", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("mixed_fp16", ctypes.c_int32), ("mixed_near", ctypes.c_int32)]
 
 
 class _SolveOpts(ctypes.Structure):
@@ -102,6 +102,8 @@ def lib():
         L.ls_scatterer_offset.restype = i64
         L.ls_correction_nnz.argtypes = [vp, i32]
         L.ls_correction_nnz.restype = i64
+        L.ls_near_pairs.argtypes = [vp, i32]
+        L.ls_near_pairs.restype = i64
         L.ls_export_correction.argtypes = [vp, i32, vp, vp, vp]
         L.ls_eval_green.argtypes = [vp, vp, i64, i32, vp]
         L.ls_eval_green_host.argtypes = [vp, vp, i64]
@@ -197,8 +199,9 @@ class Scatterer:
 
 
 def _options(source_split=0, rhs_chunk=0, targets_per_lane=0, mixed_tile=0, n_threads_host=0, fp64_matrix=0,
-             mixed_fp16=0):
-    return _Options(source_split, rhs_chunk, targets_per_lane, mixed_tile, n_threads_host, fp64_matrix, mixed_fp16, 0)
+             mixed_fp16=0, mixed_near=0):
+    return _Options(source_split, rhs_chunk, targets_per_lane, mixed_tile, n_threads_host, fp64_matrix, mixed_fp16,
+                    mixed_near)
 
 
 class Operator:
@@ -556,6 +559,10 @@ class Operator:
 
     def correction_nnz(self, s=0):
         return int(lib().ls_correction_nnz(self._h, s))
+
+    def near_pairs(self, s=0):
+        """Pairs with z < 1 that mixed applications take in FP64 (0: in the mixed tiles)."""
+        return int(lib().ls_near_pairs(self._h, s))
 
     def export_correction(self, s=0):
         """Scatterer s's correction C as (rowptr, col, val) in the caller's node order."""

@@ -156,6 +156,7 @@ ls_status upload_nodes(ls_ctx *h, Scat &sc, const ls_scatterer &s, const std::ve
       pos[2 * i] = px[i];
       pos[2 * i + 1] = py[i];
     }
+  sc.w_host = w;
   ls_status st;
   if ((st = upload(h, &sc.px, px.data(), n)) != LS_OK) return st;
   if ((st = upload(h, &sc.py, py.data(), n)) != LS_OK) return st;
@@ -167,6 +168,140 @@ ls_status upload_nodes(ls_ctx *h, Scat &sc, const ls_scatterer &s, const std::ve
 }
 
 // Upload C (internal order, CSR) and build/upload C^H.
+// The mixed-precision applications' correction of scatterer sc: every row of C followed by the
+// far sum's pairs with z = k |y_j - y_n| < 1 (n != j), G(y_j, y_n) w_n, in FP64, and C^H's rows
+// followed by w_j conj G(y_j, y_n).  The pairs are classified with the far kernels' own A =
+// k^2 fma(dx, dx, dy dy) < 1 test, so that the mixed tiles leave out exactly these; G is the
+// kernels' FP64 evaluation.  Skipped (near_ok false) when they exceed kNearPerNode per node.
+ls_status upload_mixed_correction(ls_ctx *h, Scat &sc, const std::vector<int64_t> &rp, const std::vector<int32_t> &ci,
+                                  const std::vector<double> &cv, const std::vector<int64_t> &rpH,
+                                  const std::vector<int32_t> &ciH, const std::vector<double> &cvH) {
+#pragma clang fp contract(off)
+  sc.near_ok = false;
+  if (h->opt.mixed_near != 1) return LS_OK;
+  const int64_t n = sc.n;
+  const double *px = geom_x(sc), *py = geom_y(sc);
+  if (!px || !py || (int64_t)sc.w_host.size() != n || n < 2) return LS_OK;
+  const double k = sc.k, k2 = k * k;
+  // buckets of side 1 / k (slightly more): a pair with z < 1 lies in neighbouring buckets
+  double x0 = px[0], x1 = px[0], y0 = py[0], y1 = py[0];
+  for (int64_t i = 1; i < n; ++i) {
+    x0 = std::min(x0, px[i]);
+    x1 = std::max(x1, px[i]);
+    y0 = std::min(y0, py[i]);
+    y1 = std::max(y1, py[i]);
+  }
+  const double cell = 1.0001 / k;
+  const int64_t gx = std::min<int64_t>((int64_t)((x1 - x0) / cell) + 1, 1 << 15);
+  const int64_t gy = std::min<int64_t>((int64_t)((y1 - y0) / cell) + 1, 1 << 15);
+  if ((double)gx * (double)gy > 16.0 * (double)n + 1e6) return LS_OK;   // sparse buckets: few near pairs anyway
+  auto bucket_of = [&](double x, double y, int64_t &bx, int64_t &by) {
+    bx = std::min(gx - 1, std::max<int64_t>(0, (int64_t)std::floor((x - x0) / cell)));
+    by = std::min(gy - 1, std::max<int64_t>(0, (int64_t)std::floor((y - y0) / cell)));
+  };
+  std::vector<int64_t> bstart(gx * gy + 1, 0);
+  std::vector<int32_t> border(n);
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t bx, by;
+    bucket_of(px[i], py[i], bx, by);
+    ++bstart[by * gx + bx + 1];
+  }
+  for (int64_t b = 0; b < gx * gy; ++b) bstart[b + 1] += bstart[b];
+  {
+    std::vector<int64_t> fill(bstart.begin(), bstart.end() - 1);
+    for (int64_t i = 0; i < n; ++i) {
+      int64_t bx, by;
+      bucket_of(px[i], py[i], bx, by);
+      border[fill[by * gx + bx]++] = (int32_t)i;
+    }
+  }
+  const int threads = std::max(1, std::min(host_threads(h->opt), 64));
+  auto par = [&](auto f) {
+    std::vector<std::thread> pool;
+    std::atomic<int64_t> next(0);
+    for (int t = 0; t < threads; ++t)
+      pool.emplace_back([&]() {
+        for (;;) {
+          const int64_t b = next.fetch_add(256);
+          if (b >= n) break;
+          for (int64_t j = b; j < std::min(n, b + 256); ++j) f(j);
+        }
+      });
+    for (auto &th : pool) th.join();
+  };
+  // near sources of target j, in bucket order, with their A
+  auto scan = [&](int64_t j, auto emit) {
+    int64_t bx, by;
+    bucket_of(px[j], py[j], bx, by);
+    for (int64_t yb = std::max<int64_t>(0, by - 1); yb <= std::min(gy - 1, by + 1); ++yb)
+      for (int64_t xb = std::max<int64_t>(0, bx - 1); xb <= std::min(gx - 1, bx + 1); ++xb)
+        for (int64_t q = bstart[yb * gx + xb]; q < bstart[yb * gx + xb + 1]; ++q) {
+          const int32_t s = border[q];
+          if (s == j) continue;
+          const double dx = px[j] - px[s], dy = py[j] - py[s];
+          const double A = k2 * std::fma(dx, dx, dy * dy);
+          if (A < 1.0) emit(s, A);
+        }
+  };
+  std::vector<int64_t> cnt(n + 1, 0);
+  par([&](int64_t j) {
+    int64_t c = 0;
+    scan(j, [&](int32_t, double) { ++c; });
+    cnt[j + 1] = c;
+  });
+  for (int64_t j = 0; j < n; ++j) cnt[j + 1] += cnt[j];
+  const int64_t nnear = cnt[n];
+  if (nnear > Scat::kNearPerNode * n) return LS_OK;
+  const int64_t nnz = rp[n], nnzM = nnz + nnear;
+  std::vector<int64_t> rpM(n + 1), rpMH(n + 1);
+  for (int64_t j = 0; j <= n; ++j) {
+    rpM[j] = rp[j] + cnt[j];
+    rpMH[j] = rpH[j] + cnt[j];
+  }
+  std::vector<int32_t> ciM(nnzM), ciMH(nnzM);
+  std::vector<double> cvM(2 * nnzM), cvMH(2 * nnzM);
+  const std::vector<double> &w = sc.w_host;
+  par([&](int64_t j) {
+    int64_t d = rpM[j], dh = rpMH[j];
+    for (int64_t q = rp[j]; q < rp[j + 1]; ++q, ++d) {
+      ciM[d] = ci[q];
+      cvM[2 * d] = cv[2 * q];
+      cvM[2 * d + 1] = cv[2 * q + 1];
+    }
+    for (int64_t q = rpH[j]; q < rpH[j + 1]; ++q, ++dh) {
+      ciMH[dh] = ciH[q];
+      cvMH[2 * dh] = cvH[2 * q];
+      cvMH[2 * dh + 1] = cvH[2 * q + 1];
+    }
+    std::vector<int32_t> src;
+    std::vector<double> z2;
+    scan(j, [&](int32_t s, double A) {
+      src.push_back(s);
+      z2.push_back(A);
+    });
+    std::vector<double> g(2 * src.size());
+    eval_green_host(z2.data(), g.data(), (int64_t)src.size());
+    for (size_t e = 0; e < src.size(); ++e, ++d, ++dh) {
+      ciM[d] = src[e];
+      cvM[2 * d] = g[2 * e] * w[src[e]];
+      cvM[2 * d + 1] = g[2 * e + 1] * w[src[e]];
+      ciMH[dh] = src[e];
+      cvMH[2 * dh] = w[j] * g[2 * e];
+      cvMH[2 * dh + 1] = -(w[j] * g[2 * e + 1]);
+    }
+  });
+  ls_status st;
+  if ((st = upload(h, &sc.rpM, rpM.data(), n + 1)) != LS_OK) return st;
+  if ((st = upload(h, &sc.ciM, ciM.data(), nnzM)) != LS_OK) return st;
+  if ((st = upload(h, (double **)&sc.cvM, cvM.data(), 2 * nnzM)) != LS_OK) return st;
+  if ((st = upload(h, &sc.rpMH, rpMH.data(), n + 1)) != LS_OK) return st;
+  if ((st = upload(h, &sc.ciMH, ciMH.data(), nnzM)) != LS_OK) return st;
+  if ((st = upload(h, (double **)&sc.cvMH, cvMH.data(), 2 * nnzM)) != LS_OK) return st;
+  sc.nnzM = nnzM;
+  sc.near_ok = true;
+  return LS_OK;
+}
+
 ls_status upload_correction(ls_ctx *h, Scat &sc, const std::vector<int64_t> &rp, const std::vector<int32_t> &ci,
                             const std::vector<double> &cv) {
   const int64_t n = sc.n, nnz = rp[n];
@@ -191,7 +326,7 @@ ls_status upload_correction(ls_ctx *h, Scat &sc, const std::vector<int64_t> &rp,
   if ((st = upload(h, &sc.rpH, rpH.data(), n + 1)) != LS_OK) return st;
   if ((st = upload(h, &sc.ciH, ciH.data(), nnz)) != LS_OK) return st;
   if ((st = upload(h, (double **)&sc.cvH, cvH.data(), 2 * nnz)) != LS_OK) return st;
-  return LS_OK;
+  return upload_mixed_correction(h, sc, rp, ci, cv, rpH, ciH, cvH);
 }
 
 }  // namespace lsk
@@ -893,6 +1028,12 @@ int64_t ls_scatterer_offset(ls_handle h, int32_t s) {
 }
 int64_t ls_correction_nnz(ls_handle h, int32_t s) {
   return (h && s >= 0 && s < (int32_t)h->sc.size()) ? h->sc[s].nnz : -1;
+}
+
+int64_t ls_near_pairs(ls_handle h, int32_t s) {
+  if (!h || s < 0 || s >= (int32_t)h->sc.size()) return -1;
+  const lsk::Scat &sc = h->sc[s];
+  return sc.near_ok ? sc.nnzM - sc.nnz : 0;
 }
 
 ls_status ls_export_correction(ls_handle h, int32_t s, int64_t *rowptr, int32_t *col, double *val) {

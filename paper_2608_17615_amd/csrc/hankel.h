@@ -348,9 +348,16 @@ constexpr double H16_GSCALE = 256.0 * G_SCALE;
 constexpr F32Poly<4> F32_FAR_MOD_H16 = f32_scaled(F32_FAR_MOD, H16_GSCALE);
 constexpr F32Poly<11> F32_MID_MOD_H16 = f32_scaled(F32_MID_MOD, H16_GSCALE);
 
+// excl_small: pairs with z < 1 give 0 (the caller adds them in FP64 through a sparse near part)
 template <bool H16 = false, class Tab>
-__host__ __device__ __forceinline__ void green32_unit(double A, float &gre, float &gim, const Tab &T) {
+__host__ __device__ __forceinline__ void green32_unit(double A, float &gre, float &gim, const Tab &T,
+                                                      bool excl_small = false) {
   if (A < 1.0) {
+    if (excl_small) {
+      gre = 0.f;
+      gim = 0.f;
+      return;
+    }
     double r, i;
     green_small(A, r, i, T);
     if (H16) {

@@ -55,7 +55,7 @@ struct Tile<double> {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
-  static __device__ __forceinline__ void green(double A, double &gr, double &gi, const PhaseLds &sct) {
+  static __device__ __forceinline__ void green(double A, double &gr, double &gi, const PhaseLds &sct, bool) {
     lsk::green_unit<true>(A, gr, gi, mtab(), sct);
   }
   static __device__ __forceinline__ cplx_t make(double a, double b) { return make_double2(a, b); }
@@ -69,8 +69,8 @@ struct Tile<float> {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
-  static __device__ __forceinline__ void green(double A, float &gr, float &gi, const PhaseLds &) {
-    lsk::green32_unit(A, gr, gi, mtab());
+  static __device__ __forceinline__ void green(double A, float &gr, float &gi, const PhaseLds &, bool excl) {
+    lsk::green32_unit(A, gr, gi, mtab(), excl);
   }
   static __device__ __forceinline__ cplx_t make(double a, double b) { return make_float2((float)a, (float)b); }
 };
@@ -111,7 +111,7 @@ template <class T, int MT, int NT, bool CONJ>
 __device__ __forceinline__ void tile_body(int n, const double2 *__restrict__ pos,
                                           const typename Tile<T>::cplx_t *__restrict__ X, int ldx, int nrhs,
                                           double k2, int s0, int s1, int t0, int b0, int split,
-                                          double2 *__restrict__ part, const PhaseLds &sct) {
+                                          double2 *__restrict__ part, const PhaseLds &sct, bool excl) {
   typedef Tile<T> TL;
   typedef typename TL::acc_t acc_t;
   const int lane = threadIdx.x & 63;
@@ -146,7 +146,7 @@ __device__ __forceinline__ void tile_body(int n, const double2 *__restrict__ pos
     for (int mi = 0; mi < MT; ++mi) {
       const double dx = xt[mi] - p.x, dy = yt[mi] - p.y;
       const double A = k2 * std::fma(dx, dx, dy * dy);
-      TL::green(A, gr[mi], gi[mi], sct);
+      TL::green(A, gr[mi], gi[mi], sct, excl);
       const bool zero = !ok || src == tm[mi];
       gr[mi] = zero ? (T)0 : gr[mi];
       gi[mi] = zero ? (T)0 : gi[mi];
@@ -190,7 +190,7 @@ template <class T, int MT, int NT, bool CONJ>
 __global__ __launch_bounds__(kBlock) void far_tile_kernel(int n, const double2 *__restrict__ pos,
                                                           const typename Tile<T>::cplx_t *__restrict__ X, int ldx,
                                                           int nrhs, double k2, int split_len,
-                                                          double2 *__restrict__ part) {
+                                                          double2 *__restrict__ part, int excl) {
   // the FP64 Green's values take e^{i theta} from a table in LDS (hankel.h, phase_tail_table)
   __shared__ double2 sct_lds[kFP64<T> ? SINCOS_N : 1];
   PhaseLds sct{sct_lds, 0.0};
@@ -198,7 +198,8 @@ __global__ __launch_bounds__(kBlock) void far_tile_kernel(int n, const double2 *
   const int wave = threadIdx.x >> 6;
   const int s0 = blockIdx.y * split_len;
   tile_body<T, MT, NT, CONJ>(n, pos, X, ldx, nrhs, k2, s0, min(n, s0 + split_len),
-                             (blockIdx.x * 4 + wave) * 16 * MT, blockIdx.z * 16 * NT, blockIdx.y, part, sct);
+                             (blockIdx.x * 4 + wave) * 16 * MT, blockIdx.z * 16 * NT, blockIdx.y, part, sct,
+                             excl != 0);
 }
 
 // Uneven batch of scatterers in one launch: each workgroup repeatedly takes the next work item
@@ -225,7 +226,7 @@ __global__ __launch_bounds__(kBlock) void far_tile_persistent(const BatchDesc *_
     const int s0 = wi.split * d.split_len;
     tile_body<T, MT, NT, CONJ>(d.n, d.pos, (const typename Tile<T>::cplx_t *)d.X, ldx, nrhs, d.k2, s0,
                                min(d.n, s0 + d.split_len), (wi.tblock * 4 + wave) * 16 * MT, wi.bgroup * 16 * NT,
-                               wi.split, d.part, sct);
+                               wi.split, d.part, sct, d.excl != 0);
   }
 }
 
@@ -234,12 +235,14 @@ void launch_tile(const Scat &s, const void *X, int ldx, int nrhs, int split_len,
                  bool conj, hipStream_t st) {
   dim3 grid((unsigned)((s.n + 64 * MT - 1) / (64 * MT)), (unsigned)nsplit, (unsigned)(ldx / (16 * NT)));
   typedef typename Tile<T>::cplx_t C;
+  // the FP32 tiles leave the pairs with z < 1 to the FP64 near part of the mixed correction
+  const int excl = (!kFP64<T> && s.near_ok) ? 1 : 0;
   if (conj)
     far_tile_kernel<T, MT, NT, true><<<grid, kBlock, 0, st>>>((int)s.n, s.pos, (const C *)X, ldx, nrhs, s.k * s.k,
-                                                             split_len, part);
+                                                             split_len, part, excl);
   else
     far_tile_kernel<T, MT, NT, false><<<grid, kBlock, 0, st>>>((int)s.n, s.pos, (const C *)X, ldx, nrhs, s.k * s.k,
-                                                              split_len, part);
+                                                              split_len, part, excl);
 }
 
 template <class T, int MT>
@@ -436,7 +439,7 @@ __global__ __launch_bounds__(kBlock) void far_tile_h_kernel(int n, const double2
                                                             const _Float16 *__restrict__ Xh, int ldx, int nrhs,
                                                             double k2, int split_len,
                                                             const double *__restrict__ colinv,
-                                                            double2 *__restrict__ part) {
+                                                            double2 *__restrict__ part, int excl) {
   __shared__ double2 spos[kHChunk];
   const int lane = threadIdx.x & 63;
   const int kq = lane >> 4, col = lane & 15;
@@ -480,7 +483,7 @@ __global__ __launch_bounds__(kBlock) void far_tile_h_kernel(int n, const double2
 #pragma unroll
         for (int mi = 0; mi < MT; ++mi) {
           const double dx = xt[mi] - p.x, dy = yt[mi] - p.y;
-          lsk::green32_unit<true>(k2 * std::fma(dx, dx, dy * dy), gr[mi][j], gi[mi][j], mtab());
+          lsk::green32_unit<true>(k2 * std::fma(dx, dx, dy * dy), gr[mi][j], gi[mi][j], mtab(), excl != 0);
           if (CONJ) gi[mi][j] = -gi[mi][j];
         }
       }
@@ -639,7 +642,8 @@ hipError_t launch_apply_batch(ls_ctx *h, const double *x, double *y, int nrhs, i
   for (int i = 0; i < ns; ++i) {
     const Scat &sc = h->sc[i];
     const int nsplit = (int)((sc.n + split_len - 1) / split_len);
-    desc[i] = BatchDesc{(int)sc.n, split_len, sc.k * sc.k, sc.pos, base + offs[3 * i], (double2 *)(base + offs[3 * i + 2])};
+    desc[i] = BatchDesc{(int)sc.n, split_len, (single && sc.near_ok) ? 1 : 0, sc.k * sc.k, sc.pos, base + offs[3 * i],
+                        (double2 *)(base + offs[3 * i + 2])};
     if (skip(i)) continue;
     const int tblocks = (int)((sc.n + 64 * mt - 1) / (64 * mt));
     for (int tb = 0; tb < tblocks; ++tb)
@@ -720,7 +724,8 @@ hipError_t launch_apply_batch(ls_ctx *h, const double *x, double *y, int nrhs, i
     if (skip(i)) continue;
     const Scat &sc = h->sc[i];
     const int nsplit = (int)((sc.n + split_len - 1) / split_len);
-    e = launch_epilogue(sc, desc[i].part, nsplit, (const double2 *)(base + offs[3 * i + 1]), x, y, nrhs, ld, mode, st);
+    e = launch_epilogue(sc, desc[i].part, nsplit, (const double2 *)(base + offs[3 * i + 1]), x, y, nrhs, ld, mode,
+                        st, single);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -783,6 +788,7 @@ hipError_t launch_apply_tile_h(const Scat &s, const double *x, double *y, int nr
   // a multiple of 32 sources per split
   const int split_len = (int)(((n + nsplit - 1) / nsplit + 31) / 32 * 32);
   const int used = (int)((n + split_len - 1) / split_len);
+  const int excl = s.near_ok ? 1 : 0;   // z < 1 pairs in FP64 through the mixed correction
   if (far_start) (void)hipEventRecord(far_start, st);
   // the kernel is bound by the Green's evaluation on the VALU, so a wave takes as many right-hand
   // sides as its registers hold: two M-tiles and four N-tiles (221 VGPRs) at 64 columns.  Measured at
@@ -794,30 +800,30 @@ hipError_t launch_apply_tile_h(const Scat &s, const double *x, double *y, int nr
     const dim3 g4((unsigned)((n + 64 * MT - 1) / (64 * MT)), (unsigned)used, (unsigned)(ldx / 64));
     if (fwd)
       far_tile_h_kernel<MT, 4, false><<<g4, kBlock, 0, st>>>((int)n, s.pos, Xh, ldx, nrhs, s.k * s.k, split_len,
-                                                              colinv, part);
+                                                              colinv, part, excl);
     else
       far_tile_h_kernel<MT, 4, true><<<g4, kBlock, 0, st>>>((int)n, s.pos, Xh, ldx, nrhs, s.k * s.k, split_len,
-                                                             colinv, part);
+                                                             colinv, part, excl);
   } else if (ldx % 32 != 0) {
     // an odd number of 16-column groups: one N-tile per wave
     const dim3 g1((unsigned)((n + 64 * MT - 1) / (64 * MT)), (unsigned)used, (unsigned)(ldx / 16));
     if (fwd)
       far_tile_h_kernel<MT, 1, false><<<g1, kBlock, 0, st>>>((int)n, s.pos, Xh, ldx, nrhs, s.k * s.k, split_len,
-                                                              colinv, part);
+                                                              colinv, part, excl);
     else
       far_tile_h_kernel<MT, 1, true><<<g1, kBlock, 0, st>>>((int)n, s.pos, Xh, ldx, nrhs, s.k * s.k, split_len,
-                                                             colinv, part);
+                                                             colinv, part, excl);
   } else if (fwd) {
     far_tile_h_kernel<MT, NT, false><<<grid, kBlock, 0, st>>>((int)n, s.pos, Xh, ldx, nrhs, s.k * s.k, split_len,
-                                                               colinv, part);
+                                                               colinv, part, excl);
   } else {
     far_tile_h_kernel<MT, NT, true><<<grid, kBlock, 0, st>>>((int)n, s.pos, Xh, ldx, nrhs, s.k * s.k, split_len,
-                                                              colinv, part);
+                                                              colinv, part, excl);
   }
   if (far_stop) (void)hipEventRecord(far_stop, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_epilogue(s, part, used, f, x, y, nrhs, ld, mode, st);
+  return launch_epilogue(s, part, used, f, x, y, nrhs, ld, mode, st, true);
 }
 
 hipError_t launch_apply_tile(const Scat &s, const double *x, double *y, int nrhs, int64_t ld, Mode mode, bool single,
@@ -860,7 +866,7 @@ hipError_t launch_apply_tile(const Scat &s, const double *x, double *y, int nrhs
   if (far_stop) (void)hipEventRecord(far_stop, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_epilogue(s, part, nsplit, f, x, y, nrhs, ld, mode, st);
+  return launch_epilogue(s, part, nsplit, f, x, y, nrhs, ld, mode, st, single);
 }
 
 }  // namespace lsk

@@ -72,3 +72,30 @@ def test_split_fp16_is_the_default_at_64_columns():
     for B, same in ((64, h16), (16, f32)):
         x = torch.tensor(_cols(c, "x", B), device="cuda")
         assert torch.equal(op.apply(x, precision="mixed"), same.apply(x, precision="mixed"))
+
+
+@pytest.mark.parametrize("fp16", [2, 1])
+@pytest.mark.parametrize("name", ["disk2500", "twomat1040", "absorb900"])
+def test_near_pairs_taken_in_fp64(name, fp16):
+    """Mixed applications leave the far sum's pairs with z = k |y_j - y_n| < 1 (the logarithmic
+    part of G) out of the FP32 / split-FP16 tiles and add them in FP64 through a near part kept
+    with the correction: the number of such pairs against a count from the node positions, and
+    forward and adjoint against the oracle's L x, with the near part and without it."""
+    p, c, op = _op(name, mixed_fp16=fp16, mixed_near=1)
+    _, _, keep = _op(name, mixed_fp16=fp16)
+    x, y, k = p.mesh.x, p.mesh.y, p.k
+    z2 = k * k * ((x[:, None] - x[None, :]) ** 2 + (y[:, None] - y[None, :]) ** 2)
+    count = int((z2 < 1.0).sum()) - x.size
+    assert abs(op.near_pairs() - count) <= max(2, count // 10000) and keep.near_pairs() == 0
+    B = 20
+    xt = torch.tensor(_cols(c, "x", B), device="cuda")
+    res = {}
+    for tag, o in (("near in FP64", op), ("near in the tiles", keep)):
+        e = relmax(o.apply(xt, precision="mixed").cpu().numpy(), _cols(c, "Lx", B))
+        ea = relmax(o.apply_adjoint(xt, precision="mixed").cpu().numpy(), _cols(c, "LHx", B))
+        res[tag] = (e, ea)
+    kind = "split-FP16" if fp16 == 1 else "FP32"
+    print(f"{name} {kind}, {count} near pairs: " + ", ".join(f"{t}: apply {e:.2e} adjoint {ea:.2e}"
+                                                          for t, (e, ea) in res.items()), flush=True)
+    e, ea = res["near in FP64"]
+    assert e <= 1e-6 and ea <= 1e-6

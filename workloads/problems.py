@@ -97,9 +97,12 @@ def config3(n=35, B=64):
     return disk_problem(n, 40.0, 2.0, directions=even_directions(B), name=f'disk-N{100*n*n}-k40-B{B}')
 
 
-def config4(seed=4, count=16, B=8, n_min=5e3, n_max=8e4):
+def config4(seed=4, count=16, B=8, n_min=5e3, n_max=8e4, resolve=0.5):
     """16 seeded scatterers (disk or ellipse, semi-axes U[0.5,1.5], one constant index
-    U[0.5,3], k U[5,40], node count log-uniform in [5e3, 8e4]), 8 directions each."""
+    U[0.5,3], k U[5,40], node count log-uniform in [5e3, 8e4]), 8 directions each.  With
+    resolve, a draw whose mesh would not resolve its interior wave (k sqrt(n) times the node
+    spacing sqrt(area / N) above resolve) gets the smallest mesh that does, within n_max nodes;
+    the random draws are the same either way."""
     rng = np.random.default_rng(seed)
     out = []
     for s in range(count):
@@ -110,6 +113,10 @@ def config4(seed=4, count=16, B=8, n_min=5e3, n_max=8e4):
         k = rng.uniform(5.0, 40.0)
         n_target = np.exp(rng.uniform(np.log(n_min), np.log(n_max)))
         n = max(1, int(round(np.sqrt(n_target / 100.0))))
+        if resolve:
+            # N = 100 n^2 nodes over the area pi a b
+            need = int(np.ceil(k * np.sqrt(idx) * np.sqrt(np.pi * a * b / 100.0) / resolve))
+            n = max(n, min(need, int(np.sqrt(n_max / 100.0))))
         msh = _mesh.ogrid_disk(n, a) if is_disk else _mesh.ellipse(n, a, b)
         m_at = lambda x, y, a=a, b=b, idx=idx: np.where((x / a) ** 2 + (y / b) ** 2 < 1.0, 1.0 - idx, 0.0)
         out.append(Problem(msh, k, contrast_from_index(msh, [const(idx)]),
