@@ -94,10 +94,11 @@ typedef struct {
                              * scatterer) instead of FP32: 0 = for single-scatterer handles when nrhs rounds up
                              * to a multiple of 64, 1 = always, 2 = never */
   int32_t mixed_near;       /* LS_MIXED applications and the far sum's pairs with z = k |y_j - y_n| < 1 (the
-                             * logarithmic part of G): 0 = in the mixed tiles like every other pair (their G
-                             * from the FP64 series, rounded to the tile precision), 1 = left out of the mixed
-                             * tiles and added in FP64 through a sparse near part kept with the correction
-                             * (unless they exceed 512 per node on average) */
+                             * logarithmic part of G): 0 = left out of the mixed tiles and added by an FP64
+                             * near launch (FP64 Green's values and contraction over per-tile source lists
+                             * built at setup), unless they exceed 512 per node on average; 1 = in the mixed
+                             * tiles like every other pair (G from the FP64 series, rounded to the tile
+                             * precision) */
 } ls_options;
 
 typedef struct ls_ctx *ls_handle;
@@ -366,9 +367,9 @@ int64_t ls_num_nodes(ls_handle h);                       /* total nodes */
 int32_t ls_num_scatterers(ls_handle h);
 int64_t ls_scatterer_offset(ls_handle h, int32_t s);     /* first node of scatterer s */
 int64_t ls_correction_nnz(ls_handle h, int32_t s);
-/* Pairs (j, n) with z = k |y_j - y_n| < 1 of scatterer s that mixed-precision applications take in
- * FP64 through the near part of their correction (0: the mixed tiles keep them; ls_options.mixed_near
- * = 1 asks for the near part); -1 for a bad argument. */
+/* Ordered pairs (j, n), n != j, with z = k |y_j - y_n| < 1 of scatterer s that mixed-precision
+ * applications take in FP64 (0: the mixed tiles keep them, see ls_options.mixed_near); -1 for a bad
+ * argument. */
 int64_t ls_near_pairs(ls_handle h, int32_t s);
 /* Copy scatterer s's correction back in the caller's node order (host buffers of sizes
  * n_nodes+1, nnz, 2*nnz). */

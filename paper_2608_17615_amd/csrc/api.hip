@@ -168,20 +168,21 @@ ls_status upload_nodes(ls_ctx *h, Scat &sc, const ls_scatterer &s, const std::ve
 }
 
 // Upload C (internal order, CSR) and build/upload C^H.
-// The mixed-precision applications' correction of scatterer sc: every row of C followed by the
-// far sum's pairs with z = k |y_j - y_n| < 1 (n != j), G(y_j, y_n) w_n, in FP64, and C^H's rows
-// followed by w_j conj G(y_j, y_n).  The pairs are classified with the far kernels' own A =
-// k^2 fma(dx, dx, dy dy) < 1 test, so that the mixed tiles leave out exactly these; G is the
-// kernels' FP64 evaluation.  Skipped (near_ok false) when they exceed kNearPerNode per node.
-ls_status upload_mixed_correction(ls_ctx *h, Scat &sc, const std::vector<int64_t> &rp, const std::vector<int32_t> &ci,
-                                  const std::vector<double> &cv, const std::vector<int64_t> &rpH,
-                                  const std::vector<int32_t> &ciH, const std::vector<double> &cvH) {
+// Source intervals of the FP64 near launch of scatterer sc (mixed-precision applications): for
+// every tile of 16 consecutive targets (internal order), 4-aligned index intervals [begin, end)
+// that hold every source n != j with z = k |y_j - y_n| < 1 of its targets j.  The pairs are
+// classified with the far kernels' own A = k^2 fma(dx, dx, dy dy) < 1 test (the near launch and
+// the mixed tiles apply the same test to the same FP64 positions, so each pair is taken exactly
+// once).  Sources of one tile closer than 16 in the node order share an interval.  Skipped
+// (near_ok false) when the options keep the pairs in the tiles or they exceed kNearPerNode per node.
+ls_status build_near_lists(ls_ctx *h, Scat &sc) {
 #pragma clang fp contract(off)
   sc.near_ok = false;
-  if (h->opt.mixed_near != 1) return LS_OK;
+  sc.near_pairs = 0;
+  if (h->opt.mixed_near == 1) return LS_OK;
   const int64_t n = sc.n;
   const double *px = geom_x(sc), *py = geom_y(sc);
-  if (!px || !py || (int64_t)sc.w_host.size() != n || n < 2) return LS_OK;
+  if (!px || !py || n < 2) return LS_OK;
   const double k = sc.k, k2 = k * k;
   // buckets of side 1 / k (slightly more): a pair with z < 1 lies in neighbouring buckets
   double x0 = px[0], x1 = px[0], y0 = py[0], y1 = py[0];
@@ -192,9 +193,9 @@ ls_status upload_mixed_correction(ls_ctx *h, Scat &sc, const std::vector<int64_t
     y1 = std::max(y1, py[i]);
   }
   const double cell = 1.0001 / k;
-  const int64_t gx = std::min<int64_t>((int64_t)((x1 - x0) / cell) + 1, 1 << 15);
-  const int64_t gy = std::min<int64_t>((int64_t)((y1 - y0) / cell) + 1, 1 << 15);
-  if ((double)gx * (double)gy > 16.0 * (double)n + 1e6) return LS_OK;   // sparse buckets: few near pairs anyway
+  const double gxd = std::floor((x1 - x0) / cell) + 1, gyd = std::floor((y1 - y0) / cell) + 1;
+  if (gxd * gyd > 16.0 * (double)n + 1e6) return LS_OK;   // a mesh coarse against 1 / k: hardly any pair
+  const int64_t gx = (int64_t)gxd, gy = (int64_t)gyd;
   auto bucket_of = [&](double x, double y, int64_t &bx, int64_t &by) {
     bx = std::min(gx - 1, std::max<int64_t>(0, (int64_t)std::floor((x - x0) / cell)));
     by = std::min(gy - 1, std::max<int64_t>(0, (int64_t)std::floor((y - y0) / cell)));
@@ -215,89 +216,66 @@ ls_status upload_mixed_correction(ls_ctx *h, Scat &sc, const std::vector<int64_t
       border[fill[by * gx + bx]++] = (int32_t)i;
     }
   }
+  const int32_t ntiles = (int32_t)((n + 15) / 16);
+  std::vector<std::vector<int2>> tiv(ntiles);
+  std::vector<int64_t> tpairs(ntiles, 0);
   const int threads = std::max(1, std::min(host_threads(h->opt), 64));
-  auto par = [&](auto f) {
-    std::vector<std::thread> pool;
-    std::atomic<int64_t> next(0);
-    for (int t = 0; t < threads; ++t)
-      pool.emplace_back([&]() {
-        for (;;) {
-          const int64_t b = next.fetch_add(256);
-          if (b >= n) break;
-          for (int64_t j = b; j < std::min(n, b + 256); ++j) f(j);
+  std::vector<std::thread> pool;
+  std::atomic<int32_t> next(0);
+  for (int th = 0; th < threads; ++th)
+    pool.emplace_back([&]() {
+      std::vector<int32_t> src;
+      for (;;) {
+        const int32_t t = next.fetch_add(16);
+        if (t >= ntiles) break;
+        for (int32_t tile = t; tile < std::min(ntiles, t + 16); ++tile) {
+          src.clear();
+          for (int64_t j = 16 * (int64_t)tile; j < std::min(n, 16 * (int64_t)tile + 16); ++j) {
+            int64_t bx, by;
+            bucket_of(px[j], py[j], bx, by);
+            for (int64_t yb = std::max<int64_t>(0, by - 1); yb <= std::min(gy - 1, by + 1); ++yb)
+              for (int64_t xb = std::max<int64_t>(0, bx - 1); xb <= std::min(gx - 1, bx + 1); ++xb)
+                for (int64_t q = bstart[yb * gx + xb]; q < bstart[yb * gx + xb + 1]; ++q) {
+                  const int32_t c = border[q];
+                  if (c == j) continue;
+                  const double dx = px[j] - px[c], dy = py[j] - py[c];
+                  if (k2 * std::fma(dx, dx, dy * dy) < 1.0) {
+                    src.push_back(c);
+                    ++tpairs[tile];
+                  }
+                }
+          }
+          std::sort(src.begin(), src.end());
+          src.erase(std::unique(src.begin(), src.end()), src.end());
+          for (size_t e = 0; e < src.size();) {
+            int64_t b = src[e] / 4 * 4, end = src[e] + 1;
+            size_t f = e + 1;
+            while (f < src.size() && src[f] < end + 16) end = src[f++] + 1;
+            tiv[tile].push_back(make_int2((int)b, (int)std::min<int64_t>(n, (end + 3) / 4 * 4)));
+            e = f;
+          }
         }
-      });
-    for (auto &th : pool) th.join();
-  };
-  // near sources of target j, in bucket order, with their A
-  auto scan = [&](int64_t j, auto emit) {
-    int64_t bx, by;
-    bucket_of(px[j], py[j], bx, by);
-    for (int64_t yb = std::max<int64_t>(0, by - 1); yb <= std::min(gy - 1, by + 1); ++yb)
-      for (int64_t xb = std::max<int64_t>(0, bx - 1); xb <= std::min(gx - 1, bx + 1); ++xb)
-        for (int64_t q = bstart[yb * gx + xb]; q < bstart[yb * gx + xb + 1]; ++q) {
-          const int32_t s = border[q];
-          if (s == j) continue;
-          const double dx = px[j] - px[s], dy = py[j] - py[s];
-          const double A = k2 * std::fma(dx, dx, dy * dy);
-          if (A < 1.0) emit(s, A);
-        }
-  };
-  std::vector<int64_t> cnt(n + 1, 0);
-  par([&](int64_t j) {
-    int64_t c = 0;
-    scan(j, [&](int32_t, double) { ++c; });
-    cnt[j + 1] = c;
-  });
-  for (int64_t j = 0; j < n; ++j) cnt[j + 1] += cnt[j];
-  const int64_t nnear = cnt[n];
-  if (nnear > Scat::kNearPerNode * n) return LS_OK;
-  const int64_t nnz = rp[n], nnzM = nnz + nnear;
-  std::vector<int64_t> rpM(n + 1), rpMH(n + 1);
-  for (int64_t j = 0; j <= n; ++j) {
-    rpM[j] = rp[j] + cnt[j];
-    rpMH[j] = rpH[j] + cnt[j];
-  }
-  std::vector<int32_t> ciM(nnzM), ciMH(nnzM);
-  std::vector<double> cvM(2 * nnzM), cvMH(2 * nnzM);
-  const std::vector<double> &w = sc.w_host;
-  par([&](int64_t j) {
-    int64_t d = rpM[j], dh = rpMH[j];
-    for (int64_t q = rp[j]; q < rp[j + 1]; ++q, ++d) {
-      ciM[d] = ci[q];
-      cvM[2 * d] = cv[2 * q];
-      cvM[2 * d + 1] = cv[2 * q + 1];
-    }
-    for (int64_t q = rpH[j]; q < rpH[j + 1]; ++q, ++dh) {
-      ciMH[dh] = ciH[q];
-      cvMH[2 * dh] = cvH[2 * q];
-      cvMH[2 * dh + 1] = cvH[2 * q + 1];
-    }
-    std::vector<int32_t> src;
-    std::vector<double> z2;
-    scan(j, [&](int32_t s, double A) {
-      src.push_back(s);
-      z2.push_back(A);
+      }
     });
-    std::vector<double> g(2 * src.size());
-    eval_green_host(z2.data(), g.data(), (int64_t)src.size());
-    for (size_t e = 0; e < src.size(); ++e, ++d, ++dh) {
-      ciM[d] = src[e];
-      cvM[2 * d] = g[2 * e] * w[src[e]];
-      cvM[2 * d + 1] = g[2 * e + 1] * w[src[e]];
-      ciMH[dh] = src[e];
-      cvMH[2 * dh] = w[j] * g[2 * e];
-      cvMH[2 * dh + 1] = -(w[j] * g[2 * e + 1]);
-    }
-  });
+  for (auto &t : pool) t.join();
+  int64_t pairs = 0, niv = 0;
+  for (int32_t t = 0; t < ntiles; ++t) {
+    pairs += tpairs[t];
+    niv += (int64_t)tiv[t].size();
+  }
+  if (pairs > Scat::kNearPerNode * n) return LS_OK;
+  std::vector<int32_t> rp(ntiles + 1, 0);
+  std::vector<int2> iv;
+  iv.reserve(niv);
+  for (int32_t t = 0; t < ntiles; ++t) {
+    iv.insert(iv.end(), tiv[t].begin(), tiv[t].end());
+    rp[t + 1] = (int32_t)iv.size();
+  }
   ls_status st;
-  if ((st = upload(h, &sc.rpM, rpM.data(), n + 1)) != LS_OK) return st;
-  if ((st = upload(h, &sc.ciM, ciM.data(), nnzM)) != LS_OK) return st;
-  if ((st = upload(h, (double **)&sc.cvM, cvM.data(), 2 * nnzM)) != LS_OK) return st;
-  if ((st = upload(h, &sc.rpMH, rpMH.data(), n + 1)) != LS_OK) return st;
-  if ((st = upload(h, &sc.ciMH, ciMH.data(), nnzM)) != LS_OK) return st;
-  if ((st = upload(h, (double **)&sc.cvMH, cvMH.data(), 2 * nnzM)) != LS_OK) return st;
-  sc.nnzM = nnzM;
+  if ((st = upload(h, &sc.near_rp, rp.data(), rp.size())) != LS_OK) return st;
+  if ((st = upload(h, &sc.near_iv, iv.empty() ? nullptr : iv.data(), iv.size())) != LS_OK) return st;
+  sc.near_ntiles = ntiles;
+  sc.near_pairs = pairs;
   sc.near_ok = true;
   return LS_OK;
 }
@@ -326,7 +304,7 @@ ls_status upload_correction(ls_ctx *h, Scat &sc, const std::vector<int64_t> &rp,
   if ((st = upload(h, &sc.rpH, rpH.data(), n + 1)) != LS_OK) return st;
   if ((st = upload(h, &sc.ciH, ciH.data(), nnz)) != LS_OK) return st;
   if ((st = upload(h, (double **)&sc.cvH, cvH.data(), 2 * nnz)) != LS_OK) return st;
-  return upload_mixed_correction(h, sc, rp, ci, cv, rpH, ciH, cvH);
+  return build_near_lists(h, sc);
 }
 
 }  // namespace lsk
@@ -548,8 +526,10 @@ ApplyPlan apply_plan(const ls_ctx *h, int nrhs, ls_precision p) {
   else
     for (const Scat &sc : h->sc) {
       const int nsplit = plan_splits(h, pl, sc, nrhs);
-      pl.need = std::max(pl.need, pl.h16     ? lsk::tile_h_workspace_bytes(sc.n, nrhs, nsplit)
-                                  : pl.tiles ? lsk::tile_workspace_bytes(sc.n, nrhs, nsplit)
+      // the mixed tiles' partial sums have one more split for the FP64 near launch
+      const int near = (pl.single && sc.near_ok) ? 1 : 0;
+      pl.need = std::max(pl.need, pl.h16     ? lsk::tile_h_workspace_bytes(sc.n, nrhs, nsplit + near)
+                                  : pl.tiles ? lsk::tile_workspace_bytes(sc.n, nrhs, nsplit + near)
                                              : lsk::apply_workspace_bytes(sc.n, nrhs, nsplit));
     }
   return pl;
@@ -687,13 +667,15 @@ ls_status ls_apply_noalloc(ls_handle h, const double *x, double *y, int32_t nrhs
   for (size_t si = 0; si < h->sc.size(); ++si) {
     const Scat &sc = h->sc[si];
     const size_t col = sizeof(double2) * (size_t)sc.n * nrhs;   // one [nrhs][n] complex block
+    // blocks besides the far splits: f, and the FP64 near launch's split of mixed applications
+    const int64_t extra = 1 + ((pl.single && sc.near_ok) ? 1 : 0);
     int64_t fit;
     if (pl.h16) {
       const size_t fixed = 2 * 6 * (size_t)((sc.n + 31) / 32 * 32) * lsk::tile_ldx(nrhs) + 16 * (size_t)lsk::tile_ldx(nrhs) + 1024;
-      fit = cap > fixed ? (int64_t)((cap - fixed) / col) - 1 : -1;
+      fit = cap > fixed ? (int64_t)((cap - fixed) / col) - extra : -1;
     } else if (pl.tiles) {
       const size_t fixed = sizeof(double2) * (size_t)sc.n * lsk::tile_ldx(nrhs) + 512;
-      fit = cap > fixed ? (int64_t)((cap - fixed) / col) - 1 : -1;
+      fit = cap > fixed ? (int64_t)((cap - fixed) / col) - extra : -1;
     } else {
       fit = cap > 256 ? (int64_t)((cap - 256) / col) - 2 : -1;
     }
@@ -1033,7 +1015,7 @@ int64_t ls_correction_nnz(ls_handle h, int32_t s) {
 int64_t ls_near_pairs(ls_handle h, int32_t s) {
   if (!h || s < 0 || s >= (int32_t)h->sc.size()) return -1;
   const lsk::Scat &sc = h->sc[s];
-  return sc.near_ok ? sc.nnzM - sc.nnz : 0;
+  return sc.near_ok ? sc.near_pairs : 0;
 }
 
 ls_status ls_export_correction(ls_handle h, int32_t s, int64_t *rowptr, int32_t *col, double *val) {

@@ -340,16 +340,15 @@ hipError_t launch_apply_fp64(const Scat &s, const double *x, double *y, int nrhs
 }
 
 hipError_t launch_epilogue(const Scat &s, const double2 *part, int nsplit, const double2 *f, const double *x,
-                           double *y, int nrhs, int64_t ld, Mode mode, hipStream_t st, bool mixed) {
+                           double *y, int nrhs, int64_t ld, Mode mode, hipStream_t st) {
   const int64_t n = s.n;
   const double2 *xc = (const double2 *)x;
   double2 *yc = (double2 *)y;
   dim3 ge((unsigned)((n + kBlock - 1) / kBlock), (unsigned)nrhs);
   const double k2 = s.k * s.k;
-  const bool near = mixed && s.near_ok;
-  const int64_t *rp = near ? s.rpM : s.rp, *rpH = near ? s.rpMH : s.rpH;
-  const int32_t *ci = near ? s.ciM : s.ci, *ciH = near ? s.ciMH : s.ciH;
-  const double2 *cv = near ? s.cvM : s.cv, *cvH = near ? s.cvMH : s.cvH;
+  const int64_t *rp = s.rp, *rpH = s.rpH;
+  const int32_t *ci = s.ci, *ciH = s.ciH;
+  const double2 *cv = s.cv, *cvH = s.cvH;
   if (mode == Mode::Forward)
     epilogue_kernel<Mode::Forward><<<ge, kBlock, 0, st>>>(n, nrhs, nsplit, part, f, rp, ci, cv, s.w, s.m, s.perm,
                                                          xc, yc, ld, s.off, k2);

@@ -62,18 +62,18 @@ struct Scat {
   int64_t *rp = nullptr, *rpH = nullptr;
   int32_t *ci = nullptr, *ciH = nullptr;
   double2 *cv = nullptr, *cvH = nullptr;
-  // The mixed-precision applications' correction: C plus the pairs with z = k |y_j - y_n| < 1 of
-  // the far sum (G(y_j, y_n) w_n, n != j) in FP64, which the mixed tiles then leave out; and its
-  // adjoint (C^H plus w_j conj G(y_j, y_n)); built when the options ask for it (mixed_near = 1)
-  // unless the near pairs would exceed kNearPerNode per node on average (a scatterer small against
-  // the wavelength).  Without it (near_ok false) the mixed tiles keep every pair and the mixed
-  // applications use C.
+  // Mixed-precision applications and the far sum's pairs with z = k |y_j - y_n| < 1: unless the
+  // options keep them in the mixed tiles, the tiles leave them out and an FP64 near launch adds
+  // them, one wave per tile of 16 targets over the source intervals near_iv[near_rp[t] ..
+  // near_rp[t + 1]) that hold every such source of the tile (intervals of 4-aligned [begin, end)).
+  // near_ok is false without the lists, also when the pairs would exceed kNearPerNode per node on
+  // average (a scatterer small against the wavelength).
   static constexpr int64_t kNearPerNode = 512;
   bool near_ok = false;
-  int64_t nnzM = 0;
-  int64_t *rpM = nullptr, *rpMH = nullptr;
-  int32_t *ciM = nullptr, *ciMH = nullptr;
-  double2 *cvM = nullptr, *cvMH = nullptr;
+  int64_t near_pairs = 0;
+  int32_t near_ntiles = 0;
+  int32_t *near_rp = nullptr;
+  int2 *near_iv = nullptr;
   std::vector<int32_t> perm_host;   // same as perm, on the host
   std::vector<double> w_host;       // the quadrature weights, internal order, on the host
   std::shared_ptr<GeomData> geom;
@@ -164,10 +164,8 @@ hipError_t launch_apply_fp64(const Scat &s, const double *x, double *y, int nrhs
                              Mode mode, int source_split, int rhs_chunk, int tpl, void *ws, hipStream_t st,
                              hipEvent_t far_start = nullptr, hipEvent_t far_stop = nullptr);
 size_t apply_workspace_bytes(int64_t n, int nrhs, int source_split);
-// mixed: the application's far sum left out the pairs with z < 1 when s.near_ok (the mixed tiles):
-// use the mixed correction
 hipError_t launch_epilogue(const Scat &s, const double2 *part, int nsplit, const double2 *f, const double *x,
-                           double *y, int nrhs, int64_t ld, Mode mode, hipStream_t st, bool mixed = false);
+                           double *y, int nrhs, int64_t ld, Mode mode, hipStream_t st);
 // mfma.hip: batched right-hand sides on the matrix cores (single = FP32 tiles)
 int tile_ldx(int nrhs);
 int tile_mt(int nrhs, bool single);

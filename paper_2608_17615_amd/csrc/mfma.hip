@@ -245,6 +245,72 @@ void launch_tile(const Scat &s, const void *X, int ldx, int nrhs, int split_len,
                                                               split_len, part, excl);
 }
 
+// The pairs with z < 1 of a mixed-precision application, in FP64 (the mixed tiles leave them out):
+// one wave per tile of 16 targets, over the tile's source intervals, keeping the pairs whose A =
+// k^2 r^2 falls below 1 (the same test on the same positions as the tiles' exclusion).  G/K is the
+// FP64 tiles' own evaluation and the densities come from f (w f forward, f adjoint); the result,
+// one split of partial sums in G/K units, goes to part[b * n + t] for the epilogue.
+// grid: (ceil(ntiles / 4), ldx / (16 NT))
+template <int NT, bool CONJ>
+__global__ __launch_bounds__(kBlock) void near_tile_kernel(int n, int ntiles, const double2 *__restrict__ pos,
+                                                           const double *__restrict__ w,
+                                                           const double2 *__restrict__ f, int nrhs, double k2,
+                                                           const int32_t *__restrict__ tile_rp,
+                                                           const int2 *__restrict__ iv, double2 *__restrict__ part) {
+  __shared__ double2 sct_lds[SINCOS_N];
+  const PhaseLds sct = load_sincos(sct_lds, m_sincos);
+  const int lane = threadIdx.x & 63, kk = lane >> 4, col = lane & 15;
+  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (tile >= ntiles) return;
+  const int t0 = tile * 16, tm = t0 + col;
+  const int b0 = blockIdx.y * 16 * NT;
+  const double2 pt = pos[tm < n ? tm : n - 1];
+  v4d p0[NT], p1[NT], p2[NT];
+#pragma unroll
+  for (int ni = 0; ni < NT; ++ni) {
+    p0[ni] = v4d{0, 0, 0, 0};
+    p1[ni] = v4d{0, 0, 0, 0};
+    p2[ni] = v4d{0, 0, 0, 0};
+  }
+  for (int q = tile_rp[tile]; q < tile_rp[tile + 1]; ++q) {
+    const int2 r = iv[q];
+    for (int s = r.x; s < r.y; s += 4) {
+      const int src = s + kk;
+      const bool ok = src < r.y;
+      const int sc = ok ? src : r.x;
+      const double2 p = pos[sc];
+      const double dx = pt.x - p.x, dy = pt.y - p.y;
+      const double A = k2 * std::fma(dx, dx, dy * dy);
+      double gr = 0.0, gi = 0.0;
+      if (ok && A < 1.0 && src != tm) lsk::green_unit<true>(A, gr, gi, mtab(), sct);
+      if (CONJ) gi = -gi;
+      const double g2 = gr + gi;
+      const double ws = CONJ ? 1.0 : w[sc];
+#pragma unroll
+      for (int ni = 0; ni < NT; ++ni) {
+        const int b = b0 + 16 * ni + col;
+        double2 xv = make_double2(0.0, 0.0);
+        if (ok && b < nrhs) xv = f[(int64_t)b * n + sc];
+        const double xr = ws * xv.x, xi = ws * xv.y;
+        p0[ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(gr, xr, p0[ni], 0, 0, 0);
+        p1[ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(gi, xi, p1[ni], 0, 0, 0);
+        p2[ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(g2, xr + xi, p2[ni], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int ni = 0; ni < NT; ++ni)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int t = t0 + kk + 4 * rr;
+      const int b = b0 + 16 * ni + col;
+      if (t < n && b < nrhs) {
+        const double a = p0[ni][rr], c = p1[ni][rr];
+        part[(int64_t)b * n + t] = make_double2(a - c, p2[ni][rr] - a - c);
+      }
+    }
+}
+
 template <class T, int MT>
 void launch_tile_nt(const Scat &s, const void *X, int ldx, int nrhs, int split_len, int nsplit, double2 *part,
                     bool conj, hipStream_t st) {
@@ -291,6 +357,28 @@ void launch_persistent_nt(const BatchDesc *desc, const WorkItem *items, int n_it
 }
 
 int nt_of(int ldx) { return (ldx / 16) % 4 == 0 ? 4 : ((ldx / 16) % 2 == 0 ? 2 : 1); }
+
+// the FP64 near launch of a mixed-precision application into the partial-sum slot `slot`
+// ([nrhs][n]); nothing when the scatterer has no near lists
+hipError_t launch_near(const Scat &s, const double2 *f, int nrhs, bool conj, double2 *slot, hipStream_t st) {
+  if (!s.near_ok) return hipSuccess;
+  const int ldx = tile_ldx(nrhs), nt = nt_of(ldx);
+  const dim3 grid((unsigned)((s.near_ntiles + 3) / 4), (unsigned)(ldx / (16 * nt)));
+  const int n = (int)s.n;
+  const double k2 = s.k * s.k;
+#define LSK_NEAR(NT, CJ)                                                                                          \
+  near_tile_kernel<NT, CJ><<<grid, kBlock, 0, st>>>(n, s.near_ntiles, s.pos, s.w, f, nrhs, k2, s.near_rp, s.near_iv, \
+                                                    slot)
+  if (nt == 4) {
+    if (conj) LSK_NEAR(4, true); else LSK_NEAR(4, false);
+  } else if (nt == 2) {
+    if (conj) LSK_NEAR(2, true); else LSK_NEAR(2, false);
+  } else {
+    if (conj) LSK_NEAR(1, true); else LSK_NEAR(1, false);
+  }
+#undef LSK_NEAR
+  return hipGetLastError();
+}
 
 // ---------------------------------------------------------------------------------------------
 // Split-FP16 tiles (mixed precision on the FP16 matrix cores).  Each real operand v is carried as
@@ -576,7 +664,8 @@ static size_t batch_layout(const ls_ctx *h, int nrhs, bool single, int split_len
   size_t o = 0;
   auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
   for (const Scat &sc : h->sc) {
-    const int64_t nsplit = (sc.n + split_len - 1) / split_len;
+    // the mixed tiles' splits and, with near lists, the FP64 near launch's one
+    const int64_t nsplit = (sc.n + split_len - 1) / split_len + ((single && sc.near_ok) ? 1 : 0);
     if (offs) offs->push_back(o);
     o = al(o + (single ? sizeof(float2) : sizeof(double2)) * (size_t)sc.n * ldx);
     if (offs) offs->push_back(o);
@@ -723,9 +812,14 @@ hipError_t launch_apply_batch(ls_ctx *h, const double *x, double *y, int nrhs, i
   for (int i = 0; i < ns; ++i) {
     if (skip(i)) continue;
     const Scat &sc = h->sc[i];
-    const int nsplit = (int)((sc.n + split_len - 1) / split_len);
-    e = launch_epilogue(sc, desc[i].part, nsplit, (const double2 *)(base + offs[3 * i + 1]), x, y, nrhs, ld, mode,
-                        st, single);
+    int nsplit = (int)((sc.n + split_len - 1) / split_len);
+    const double2 *f = (const double2 *)(base + offs[3 * i + 1]);
+    if (single && sc.near_ok) {
+      e = launch_near(sc, f, nrhs, !fwd, desc[i].part + (size_t)nsplit * nrhs * sc.n, st);
+      if (e != hipSuccess) return e;
+      ++nsplit;
+    }
+    e = launch_epilogue(sc, desc[i].part, nsplit, f, x, y, nrhs, ld, mode, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -823,7 +917,9 @@ hipError_t launch_apply_tile_h(const Scat &s, const double *x, double *y, int nr
   if (far_stop) (void)hipEventRecord(far_stop, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_epilogue(s, part, used, f, x, y, nrhs, ld, mode, st, true);
+  e = launch_near(s, f, nrhs, !fwd, part + (size_t)used * nrhs * n, st);
+  if (e != hipSuccess) return e;
+  return launch_epilogue(s, part, used + (s.near_ok ? 1 : 0), f, x, y, nrhs, ld, mode, st);
 }
 
 hipError_t launch_apply_tile(const Scat &s, const double *x, double *y, int nrhs, int64_t ld, Mode mode, bool single,
@@ -866,7 +962,12 @@ hipError_t launch_apply_tile(const Scat &s, const double *x, double *y, int nrhs
   if (far_stop) (void)hipEventRecord(far_stop, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_epilogue(s, part, nsplit, f, x, y, nrhs, ld, mode, st, single);
+  if (single && s.near_ok) {
+    e = launch_near(s, f, nrhs, !fwd, part + (size_t)nsplit * nrhs * n, st);
+    if (e != hipSuccess) return e;
+    ++nsplit;
+  }
+  return launch_epilogue(s, part, nsplit, f, x, y, nrhs, ld, mode, st);
 }
 
 }  // namespace lsk

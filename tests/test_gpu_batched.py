@@ -78,11 +78,11 @@ def test_split_fp16_is_the_default_at_64_columns():
 @pytest.mark.parametrize("name", ["disk2500", "twomat1040", "absorb900"])
 def test_near_pairs_taken_in_fp64(name, fp16):
     """Mixed applications leave the far sum's pairs with z = k |y_j - y_n| < 1 (the logarithmic
-    part of G) out of the FP32 / split-FP16 tiles and add them in FP64 through a near part kept
-    with the correction: the number of such pairs against a count from the node positions, and
-    forward and adjoint against the oracle's L x, with the near part and without it."""
-    p, c, op = _op(name, mixed_fp16=fp16, mixed_near=1)
-    _, _, keep = _op(name, mixed_fp16=fp16)
+    part of G) out of the FP32 / split-FP16 tiles and add them with an FP64 near launch: the
+    number of such pairs against a count from the node positions, and forward and adjoint against
+    the oracle's L x, with the near launch and with the pairs kept in the tiles."""
+    p, c, op = _op(name, mixed_fp16=fp16)
+    _, _, keep = _op(name, mixed_fp16=fp16, mixed_near=1)
     x, y, k = p.mesh.x, p.mesh.y, p.k
     z2 = k * k * ((x[:, None] - x[None, :]) ** 2 + (y[:, None] - y[None, :]) ** 2)
     count = int((z2 < 1.0).sum()) - x.size
