@@ -72,13 +72,13 @@ Z_BOUNDS_H16 = (1.0, 8.0)
 PEAK_FP64_TFLOPS = 78.6
 PEAK_VALU_TFLOPS = 78.6
 PEAK_FP32_MFMA_TFLOPS = 157.3
-# HBM bytes per far-kernel launch in the default workload, from two rocprofv3 counter passes
-# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors that make a 1 GiB copy read 1 GiB and write
-# 1 GiB; profiles/far_fp64_two_material_N58500_hbm_counters.md), valid for the kernel sources
-# with this digest only: after any change to them the field is reported as null.
-FAR_TRAFFIC_BYTES = 37_694_000 + 134_784_000
+# HBM bytes per launch of the single right-hand-side far sum at the two-material workload (N =
+# 58 500), from two rocprofv3 counter passes (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors that
+# make a 1 GiB copy read 1 GiB and write 1 GiB; profiles/far_fp64_sym_two_material_N58500_counters.md),
+# valid for the kernel sources with this digest only: after any change to them the field is null.
+FAR_TRAFFIC_BYTES = 71_467_000 + 214_344_000
 FAR_TRAFFIC_SOURCES = ("apply.hip", "hankel.h", "hankel_tables.h")
-FAR_TRAFFIC_DIGEST = "57aa3428bd671f22"
+FAR_TRAFFIC_DIGEST = "4222d59bc846cd48"
 
 
 # The same for the split-FP16 tile kernel at the default workload (unit disk, N = 122 500, 64
@@ -260,16 +260,29 @@ def run_plain(args, prob, label):
     pairs = n * (n - 1)
     frac = z_fractions([(prob.mesh, prob.k)])
     fpp = flops_per_pair(frac, 1)
+    # the single right-hand-side sum evaluates each unordered pair once (blocks of 256 on the
+    # diagonal in both orders) and does two complex multiply-adds per evaluation: executed flops
+    # per launch, against which the roofline is taken; the survey's count per ordered pair is the
+    # effective rate
+    blk = 256
+    nb = -(-n // blk)
+    evals = n * (n - 1) // 2 + nb * blk * (blk - 1) // 2
+    executed = (fpp + FLOPS_PER_RHS) * evals
     cfg = {"workload": f"{label}, N={n}, one plane wave, FP64 GMRES (no restart) to relative residual "
                        f"{args.tol:g}",
            "n_nodes": n, "k": prob.k, "nrhs": 1, "tol": args.tol, "iterations": int(infos[-1]["iters"][0]),
            "applies_per_solve": n_apply // args.steps, "final_relres": float(infos[-1]["relres"][0]),
            "setup_s": setup_s, "far_kernel_ms_avg": t.far_avg_s * 1e3,
            "apply_ms_avg": t.prof["apply_ms"] / max(t.prof["apply_calls"], 1),
-           "flops_per_pair": fpp, "z_range_fractions": frac}
-    traffic = far_traffic() if args.workload == "c2" else None
+           "flops_per_pair": fpp, "z_range_fractions": frac,
+           "hankel_evaluations_per_ordered_pair": evals / pairs,
+           "executed_flops_per_launch": executed,
+           "effective_tflops_ordered_pair_count": fpp * pairs / t.far_avg_s / 1e12}
+    roof = {"bound": "alu", "achieved": executed / t.far_avg_s / 1e12, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": executed / t.far_avg_s / 1e12 / PEAK_FP64_TFLOPS,
+            "traffic": far_traffic() if args.workload == "c2" else None}
     return line(n_apply * pairs / t.seconds / 1e9, t.seconds / args.steps * 1e3, args.steps, args.warmup, "f64", cfg,
-                roofline_valu(fpp, pairs, t.far_avg_s, traffic), None)
+                roof, None)
 
 
 # ---------------------------------------------------------------- batched forms (c3, c4, c5)

@@ -501,8 +501,10 @@ struct ApplyPlan {
 
 int plan_splits(const ls_ctx *h, const ApplyPlan &pl, const Scat &sc, int nrhs) {
   if (h->opt.source_split > 0) return h->opt.source_split;
-  return pl.tiles ? lsk::tile_source_split(sc.n, nrhs, pl.single)
-                  : lsk::auto_source_split(sc.n, nrhs, std::max(1, nrhs / pl.chunk), pl.tpl);
+  if (pl.tiles) return lsk::tile_source_split(sc.n, nrhs, pl.single);
+  // one right-hand side, one target per lane: the sum over unordered pairs, one split per block
+  if (nrhs == 1 && pl.tpl == 1) return lsk::fp64_sym_splits(sc.n);
+  return lsk::auto_source_split(sc.n, nrhs, std::max(1, nrhs / pl.chunk), pl.tpl);
 }
 
 ApplyPlan apply_plan(const ls_ctx *h, int nrhs, ls_precision p) {

@@ -143,6 +143,106 @@ __global__ __launch_bounds__(kBlock) void far_fp64_kernel(int n, const double *_
     }
 }
 
+// The punctured far sum of one right-hand side with every unordered pair evaluated once (G is
+// symmetric in its two points).  Workgroup (T, S), S >= T, takes the kBlock targets of block T
+// against the kBlock sources of block S:
+//   S > T : each lane adds G(t, j) d_j into its target t, and the wave's sum over its 64 targets
+//           of G(t, j) d_t into source j (a butterfly across the lanes, the four waves through
+//           LDS), so that the pair also serves row j;
+//   S == T: every pair of the block in both orders, the self pair left out.
+// Slot S of row i holds its sum over block S's sources: workgroup (blk(i), S) writes it for
+// S >= blk(i), the transposed sums of workgroup (S, blk(i)) for S < blk(i), so every slot of every
+// row is written exactly once and the epilogue adds the nb slots.
+// grid: nb (nb + 1) / 2 workgroups in the order (0, 0), (0, 1), ..., (0, nb - 1), (1, 1), ...
+template <bool CONJ>
+__global__ __launch_bounds__(kBlock) void far_fp64_sym_kernel(int n, int nb, const double *__restrict__ px,
+                                                             const double *__restrict__ py,
+                                                             const double2 *__restrict__ pos,
+                                                             const double2 *__restrict__ sd, double k2,
+                                                             double2 *__restrict__ part) {
+  __shared__ double2 sct_lds[SINCOS_N];
+  __shared__ double2 red[kBlock / 64][kBlock];
+  const PhaseLds sct = load_sincos(sct_lds, d_sincos);
+  // (T, S) of this workgroup: T rows of nb, nb - 1, ... pairs precede row T
+  const int64_t idx = blockIdx.x;
+  const double b2 = 2.0 * nb + 1.0;
+  int T = (int)((b2 - std::sqrt(b2 * b2 - 8.0 * (double)idx)) * 0.5);
+  auto first = [&](int r) { return (int64_t)r * (2 * (int64_t)nb - r + 1) / 2; };
+  while (T > 0 && first(T) > idx) --T;
+  while (T + 1 < nb && first(T + 1) <= idx) ++T;
+  const int S = T + (int)(idx - first(T));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int t = T * kBlock + threadIdx.x;
+  const int ti = t < n ? t : n - 1;
+  const double xt = px[ti], yt = py[ti];
+  const double2 dt = t < n ? sd[t] : make_double2(0.0, 0.0);
+  const int s0 = S * kBlock, s1 = min(n, s0 + kBlock);
+  double ar[1][1] = {{0.0}}, ai[1][1] = {{0.0}};
+  if (S == T) {
+    const int it[1] = {t};
+    const double xa[1] = {xt}, ya[1] = {yt};
+    for (int j = s0; j < s1; ++j)
+      far_source<1, 1, CONJ, true>(j, it, xa, ya, k2, pos, sd + j, sct, ar, ai);
+  } else {
+    // eight sources at a time: G d_t of each lane for the eight, then a reduce-scatter across the
+    // lanes (lane bits 5, 4, 3 halve the set: 8 -> 4 -> 2 -> 1 values, then bits 2..0 add up), so
+    // that lanes 8u .. 8u + 7 end with source u's wave sum; five exchanges per source
+    const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8;
+    for (int j0 = s0; j0 < s1; j0 += 8) {
+      double vr[8], vi[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        vr[u] = vi[u] = 0.0;
+        const int j = j0 + u;
+        if (j < s1) {
+          const double2 p = pos[j];
+          const double dx = xt - p.x, dy = yt - p.y;
+          const double A = k2 * std::fma(dx, dx, dy * dy);
+          double gr, gi;
+          green_unit<true>(A, gr, gi, hankel_table(), sct);
+          if (CONJ) gi = -gi;
+          const double2 sv = sd[j];
+          ar[0][0] = std::fma(gr, sv.x, std::fma(-gi, sv.y, ar[0][0]));
+          ai[0][0] = std::fma(gr, sv.y, std::fma(gi, sv.x, ai[0][0]));
+          vr[u] = std::fma(gr, dt.x, -gi * dt.y);
+          vi[u] = std::fma(gr, dt.y, gi * dt.x);
+        }
+      }
+      double r4[4], i4[4], r2[2], i2[2];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        r4[q] = (h5 ? vr[4 + q] : vr[q]) + __shfl_xor(h5 ? vr[q] : vr[4 + q], 32);
+        i4[q] = (h5 ? vi[4 + q] : vi[q]) + __shfl_xor(h5 ? vi[q] : vi[4 + q], 32);
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        r2[q] = (h4 ? r4[2 + q] : r4[q]) + __shfl_xor(h4 ? r4[q] : r4[2 + q], 16);
+        i2[q] = (h4 ? i4[2 + q] : i4[q]) + __shfl_xor(h4 ? i4[q] : i4[2 + q], 16);
+      }
+      double r1 = (h3 ? r2[1] : r2[0]) + __shfl_xor(h3 ? r2[0] : r2[1], 8);
+      double i1 = (h3 ? i2[1] : i2[0]) + __shfl_xor(h3 ? i2[0] : i2[1], 8);
+#pragma unroll
+      for (int off = 4; off > 0; off >>= 1) {
+        r1 += __shfl_xor(r1, off);
+        i1 += __shfl_xor(i1, off);
+      }
+      const int u = (h5 ? 4 : 0) + (h4 ? 2 : 0) + (h3 ? 1 : 0);
+      if ((lane & 7) == 0 && j0 + u < s1) red[wave][j0 + u - s0] = make_double2(r1, i1);
+    }
+  }
+  if (t < n) part[(int64_t)S * n + t] = make_double2(ar[0][0], ai[0][0]);
+  if (S != T) {
+    __syncthreads();
+    const int j = s0 + threadIdx.x;
+    if (j < s1) {
+      double2 v = red[0][threadIdx.x];
+#pragma unroll
+      for (int w = 1; w < kBlock / 64; ++w) v = make_double2(v.x + red[w][threadIdx.x].x, v.y + red[w][threadIdx.x].y);
+      part[(int64_t)T * n + j] = v;
+    }
+  }
+}
+
 template <Mode M>
 __global__ __launch_bounds__(kBlock) void epilogue_kernel(
     int64_t n, int nrhs, int nsplit, const double2 *__restrict__ part, const double2 *__restrict__ f,
@@ -293,6 +393,8 @@ int auto_source_split(int64_t n, int nrhs, int launches_per_split, int tpl) {
   return (int)s;
 }
 
+int fp64_sym_splits(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+
 size_t apply_workspace_bytes(int64_t n, int nrhs, int nsplit) {
   // sd [n][nrhs], f [nrhs][n], part [nsplit][nrhs][n]  (double2 each)
   return sizeof(double2) * (size_t)n * nrhs * (2 + (size_t)nsplit) + 256;
@@ -314,6 +416,20 @@ hipError_t launch_apply_fp64(const Scat &s, const double *x, double *y, int nrhs
     prologue_kernel<Mode::Adjoint><<<gp, kBlock, 0, st>>>(n, nrhs, s.perm, s.w, s.m, xc, ld, s.off, sd, f);
   const int split_len = (int)((n + nsplit - 1) / nsplit);
   const bool conj = mode != Mode::Forward;
+  if (nrhs == 1 && tpl == 1 && nsplit == fp64_sym_splits(n)) {
+    // one right-hand side: each unordered pair once, one slot per source block
+    const int nb = nsplit;
+    const unsigned wg = (unsigned)((int64_t)nb * (nb + 1) / 2);
+    if (far_start) (void)hipEventRecord(far_start, st);
+    if (conj)
+      far_fp64_sym_kernel<true><<<wg, kBlock, 0, st>>>((int)n, nb, s.px, s.py, pos, sd, s.k * s.k, part);
+    else
+      far_fp64_sym_kernel<false><<<wg, kBlock, 0, st>>>((int)n, nb, s.px, s.py, pos, sd, s.k * s.k, part);
+    if (far_stop) (void)hipEventRecord(far_stop, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_epilogue(s, part, nsplit, f, x, y, nrhs, ld, mode, st);
+  }
   // RHS per pass: the largest of 16, 8, 4, 1 that is <= rhs_chunk and divides nrhs
   int bc = 1;
   for (int c : {16, 8, 4})

@@ -164,6 +164,10 @@ hipError_t launch_apply_fp64(const Scat &s, const double *x, double *y, int nrhs
                              Mode mode, int source_split, int rhs_chunk, int tpl, void *ws, hipStream_t st,
                              hipEvent_t far_start = nullptr, hipEvent_t far_stop = nullptr);
 size_t apply_workspace_bytes(int64_t n, int nrhs, int source_split);
+// source splits of the single right-hand-side sum that evaluates each unordered pair once (one per
+// block of 256 sources); launch_apply_fp64 takes that kernel for nrhs = 1, one target per lane and
+// exactly this many splits
+int fp64_sym_splits(int64_t n);
 hipError_t launch_epilogue(const Scat &s, const double2 *part, int nsplit, const double2 *f, const double *x,
                            double *y, int nrhs, int64_t ld, Mode mode, hipStream_t st);
 // mfma.hip: batched right-hand sides on the matrix cores (single = FP32 tiles)
