@@ -83,7 +83,9 @@ typedef struct {
 } ls_scatterer;
 
 typedef struct {
-  int32_t source_split;     /* far-sum source chunks per launch (0 = automatic) */
+  int32_t source_split;     /* far-sum source chunks per launch (0 = automatic); for one right-hand side and
+                             * one target per lane, ceil(N / 256) chunks select the sum that evaluates each
+                             * unordered pair once (automatic from N ~ 16 000 on) */
   int32_t rhs_chunk;        /* RHS per pass of the batched FP64 kernel (0 = automatic; 1, 4, 8, 16) */
   int32_t targets_per_lane; /* targets per lane in the FP64 far sum (0 = automatic; 1 or 2) */
   int32_t mixed_tile;       /* mixed-precision tile variant (0 = automatic / autotuned cache) */

@@ -502,8 +502,14 @@ struct ApplyPlan {
 int plan_splits(const ls_ctx *h, const ApplyPlan &pl, const Scat &sc, int nrhs) {
   if (h->opt.source_split > 0) return h->opt.source_split;
   if (pl.tiles) return lsk::tile_source_split(sc.n, nrhs, pl.single);
-  // one right-hand side, one target per lane: the sum over unordered pairs, one split per block
-  if (nrhs == 1 && pl.tpl == 1) return lsk::fp64_sym_splits(sc.n);
+  // one right-hand side, one target per lane: the sum over unordered pairs, one split per block,
+  // once its nb (nb + 1) / 2 workgroups fill the chip several times over (N above ~16 000; at
+  // N = 2 500 its 55 workgroups left most of the chip idle: 12.7 ms per solve of the unit disk at
+  // k = 2 pi against 8.7 ms with the ordered-pair sum's source splits)
+  if (nrhs == 1 && pl.tpl == 1) {
+    const int64_t nb = lsk::fp64_sym_splits(sc.n);
+    if (nb * (nb + 1) / 2 >= 2048) return (int)nb;
+  }
   return lsk::auto_source_split(sc.n, nrhs, std::max(1, nrhs / pl.chunk), pl.tpl);
 }
 
