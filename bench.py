@@ -687,9 +687,12 @@ def main():
     if args.maxit is None:
         args.maxit = 1500 if wl == "c4" else 2000
     if args.scheme is None:
-        # refinement passes stop only when every system meets its pass target, which a stagnating
-        # scatterer of the uneven batch never does: c4 takes the relaxed scheme
-        args.scheme = "passes" if form == "pcm" and wl != "c4" else "relaxed"
+        # refinement passes (every Arnoldi application mixed) pay where the mixed tiles are much
+        # faster than the FP64 ones (c3: split-FP16 at 64 columns, 1.07 s against 1.43 s relaxed);
+        # at 16 columns (c5) the FP32 tiles are only twice as fast and the passes' extra steps cost
+        # more than they save (3.41 s against 2.33 s relaxed); c4's slowest scatterers need
+        # hundreds of steps, which the relaxed scheme keeps in one Krylov space
+        args.scheme = "passes" if form == "pcm" and wl == "c3" else "relaxed"
     if args.relax is None:
         args.relax = 0.0
     if wl in ("c1", "c2") and form != "p64":
