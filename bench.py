@@ -61,11 +61,12 @@ FLOPS_PER_RHS = 8
 Z_BOUNDS = (2.0, 5.0, 12.0)
 # The split-FP16 tile kernel (far_tile_h_kernel), counted the same way on its loop body: per pair,
 # coordinates and k^2 r^2 in FP64 (6), z^(-1/2) and the tail (z, the FP64 Newton step for z, the
-# phase in turns, sine, cosine, modulus: 18), the modulus-phase polynomials (far z >= 8: 15, z in
-# [1, 8): 38), or the FP64 small-argument series for z < 1 (69 after the coordinates); plus 4 for
-# the hi/lo splits of Re G, Im G and Re G + Im G.  The contraction runs on the matrix cores.
-FLOPS_H16_RANGE = {"small": 75, "mid": 62, "far": 39}
-FLOPS_H16_SPLIT = 4
+# phase in turns from polynomials that return turns, sine, cosine, modulus: 17), the modulus-phase
+# polynomials (far z >= 8: 15, z in [1, 8): 38), or the FP64 small-argument series for z < 1 (69
+# after the coordinates); plus 2 for the hi/lo splits of Re G and Im G.  The contraction runs on
+# the matrix cores.
+FLOPS_H16_RANGE = {"small": 75, "mid": 61, "far": 38}
+FLOPS_H16_SPLIT = 2
 Z_BOUNDS_H16 = (1.0, 8.0)
 # VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz, for FP64 and for unpacked FP32 (the
 # build turns the packed FP32 instructions off, so FP32 work issues at the FP64 rate)

@@ -347,6 +347,11 @@ constexpr F32Poly<N> f32_scaled(const float (&a)[N], double f) {
 constexpr double H16_GSCALE = 256.0 * G_SCALE;
 constexpr F32Poly<4> F32_FAR_MOD_H16 = f32_scaled(F32_FAR_MOD, H16_GSCALE);
 constexpr F32Poly<11> F32_MID_MOD_H16 = f32_scaled(F32_MID_MOD, H16_GSCALE);
+// The phase polynomials in turns (radians / 2 pi), so that the phase joins the FP64 number of turns
+// without a multiplication; the far form's constant -pi/4 is -1/8 turn.
+constexpr double F32_INV_2PI = 0.15915494309189535;
+constexpr F32Poly<4> F32_FAR_PH_TURNS = f32_scaled(F32_FAR_PH, F32_INV_2PI);
+constexpr F32Poly<9> F32_MID_PH_TURNS = f32_scaled(F32_MID_PH, F32_INV_2PI);
 
 // excl_small: pairs with z < 1 give 0 (the caller adds them in FP64 through a sparse near part)
 template <bool H16 = false, class Tab>
@@ -375,21 +380,21 @@ __host__ __device__ __forceinline__ void green32_unit(double A, float &gre, floa
   const float s = 1.0f / std::sqrt(std::sqrt(a));
 #endif
   const float t = s * s, z = a * t;
-  float mod, ph;
+  float mod, ph;   // ph in turns
   if (a >= F32_ZF * F32_ZF) {
     const float t2 = t * t;
     if constexpr (H16)
       mod = hornerf(F32_FAR_MOD_H16, t2);
     else
       mod = hornerf(F32_FAR_MOD, t2);
-    ph = std::fma(t, hornerf(F32_FAR_PH, t2), -0.785398163f);
+    ph = std::fma(t, hornerf(F32_FAR_PH_TURNS, t2), -0.125f);
   } else {
     const float x = (t - F32_MID_TA) * F32_MID_SCALE;
     if constexpr (H16)
       mod = hornerf(F32_MID_MOD_H16, x);
     else
       mod = hornerf(F32_MID_MOD, x);
-    ph = hornerf(F32_MID_PH, x);
+    ph = hornerf(F32_MID_PH_TURNS, x);
   }
   const float m4 = mod * s;
   // Phase in FP64: z in FP32 carries a relative error ~2^-24, i.e. ~z 2^-24 radians of phase.
@@ -397,7 +402,7 @@ __host__ __device__ __forceinline__ void green32_unit(double A, float &gre, floa
   // turns (z + ph)/(2 pi) is reduced in FP64; only the fraction goes to the FP32 sine/cosine.
   const double zd = (double)z;
   const double z64 = std::fma(std::fma(-zd, zd, A), (double)(0.5f * t), zd);
-  const double rev = std::fma(z64, 0.15915494309189535, (double)(ph * 0.159154943f));   // turns
+  const double rev = std::fma(z64, F32_INV_2PI, (double)ph);   // turns
 #ifdef __HIP_DEVICE_COMPILE__
   const float f = (float)__builtin_amdgcn_fract(rev);
   const float sn = __builtin_amdgcn_sinf(f), cs = __builtin_amdgcn_cosf(f);

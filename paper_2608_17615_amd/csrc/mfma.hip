@@ -384,20 +384,24 @@ hipError_t launch_near(const Scat &s, const double2 *f, int nrhs, bool conj, dou
 // Split-FP16 tiles (mixed precision on the FP16 matrix cores).  Each real operand v is carried as
 // v_hi + v_lo, two FP16 numbers (v_hi = fp16(v), v_lo = fp16(v - v_hi): about 22 significant bits),
 // and a real product as A_hi B_hi + A_hi B_lo + A_lo B_hi, three v_mfma_f32_16x16x32_f16 with FP32
-// accumulation (the dropped A_lo B_lo is below 2^-22 of the product).  With Gauss's three real
-// products per complex tile that is nine MFMAs per (M-tile, N-tile) and 32 sources.  FP16's range
+// accumulation (the dropped A_lo B_lo is below 2^-22 of the product).  A complex tile takes the four
+// real products, accumulated straight into Re (Re G Re X - Im G Im X, the second with the FP16 sign
+// bits of Im G flipped) and Im (Re G Im X + Im G Re X): twelve MFMAs per (M-tile, N-tile) and 32
+// sources.  Gauss's three products need nine, but also a third accumulator, the split of Re G + Im G
+// and two more density planes; at 64 columns the four-product form holds the wave in 162 VGPRs (three
+// waves per SIMD instead of two) and the launch at N = 122 500 took 29.1 ms against 33.0.  FP16's range
 // needs scales: the Green's values enter as 256 G (|G| < 0.8), the densities of right-hand side b
 // as s_b 2^(13 - e_b) with 2^e_b <= max |Re s_b|, |Im s_b| < 2^(e_b + 1), so every hi part is far
 // inside FP16's range and a lo part is normal for values above 2^-9 of the column's largest.  The
 // partial sums are brought back to G/K units in FP64 per column (colinv).
-//   Layout of the split densities: six planes (Re hi, Re lo, Im hi, Im lo, (Re + Im) hi, (Re + Im) lo),
-//   each [source / 8][ldx][8] halves, sources padded with zeros to a multiple of 32: the eight
+//   Layout of the split densities: four planes (Re hi, Re lo, Im hi, Im lo), each
+//   [source / 8][ldx][8] halves, sources padded with zeros to a multiple of 32: the eight
 //   sources of one lane's MFMA operand are one 16-byte load.
 //   Operand layout of the 16x16x32 MFMA: lane l supplies row l % 16 of A and column l % 16 of B at
 //   eight contraction indices that depend on l / 16 only (the same eight for A and B), here the
 //   sources s + 8 (l / 16) + j, j < 8.  Results are D[4 (l / 16) + r][l % 16], as for the FP32 tiles.
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
-constexpr int kHPlanes = 6;
+constexpr int kHPlanes = 4;
 
 __host__ __device__ inline int64_t h_npad(int64_t n) { return (n + 31) / 32 * 32; }
 
@@ -494,9 +498,6 @@ __global__ __launch_bounds__(kBlock) void prologue_h_kernel(int64_t n, int nrhs,
   split16(si, h, l);
   Xh[2 * plane + idx] = h;
   Xh[3 * plane + idx] = l;
-  split16(sr + si, h, l);
-  Xh[4 * plane + idx] = h;
-  Xh[5 * plane + idx] = l;
 }
 
 __device__ __forceinline__ v4f mma16(v8h a, v8h b, v4f c) {
@@ -510,11 +511,19 @@ union H8 {
   h2 p[4];
 };
 
-// hi and lo parts of two FP32 values at once (one packed conversion each way)
+// hi and lo parts of two FP32 values: hi by one packed conversion, each lo = v - hi by one
+// mixed-precision FMA that reads hi as FP16 and rounds the (exact) FP32 difference to FP16 into
+// its half of the register.  Two instructions fewer per value than converting hi back and
+// subtracting; the result is the same.
 __device__ __forceinline__ void split16x2(f2 v, h2 &hi, h2 &lo) {
   hi = __builtin_convertvector(v, h2);
-  const f2 back = __builtin_convertvector(hi, f2);
-  lo = __builtin_convertvector(v - back, h2);
+  unsigned h, l;
+  __builtin_memcpy(&h, &hi, 4);
+  asm("v_fma_mixlo_f16 %0, %1, -1.0, %2 op_sel:[0,0,0] op_sel_hi:[1,0,0]\n\t"
+      "v_fma_mixhi_f16 %0, %1, -1.0, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+      : "=&v"(l)
+      : "v"(h), "v"(v.x), "v"(v.y));
+  __builtin_memcpy(&lo, &l, 4);
 }
 
 constexpr int kHChunk = kBlock;   // source positions staged in LDS per pass of a block
@@ -545,14 +554,13 @@ __global__ __launch_bounds__(kBlock) void far_tile_h_kernel(int n, const double2
     xt[mi] = p.x;
     yt[mi] = p.y;
   }
-  v4f p0[MT][NT], p1[MT][NT], p2[MT][NT];
+  v4f re[MT][NT], im[MT][NT];   // Re and Im of the 16 x 16 result tiles
 #pragma unroll
   for (int mi = 0; mi < MT; ++mi)
 #pragma unroll
     for (int ni = 0; ni < NT; ++ni) {
-      p0[mi][ni] = v4f{0, 0, 0, 0};
-      p1[mi][ni] = v4f{0, 0, 0, 0};
-      p2[mi][ni] = v4f{0, 0, 0, 0};
+      re[mi][ni] = v4f{0, 0, 0, 0};
+      im[mi][ni] = v4f{0, 0, 0, 0};
     }
   for (int c0 = s0; c0 < s1; c0 += kHChunk) {
     __syncthreads();   // every wave is done with the previous chunk
@@ -589,7 +597,7 @@ __global__ __launch_bounds__(kBlock) void far_tile_h_kernel(int n, const double2
             }
         }
       }
-      H8 ar_h[MT], ar_l[MT], ai_h[MT], ai_l[MT], a2_h[MT], a2_l[MT];
+      H8 ar_h[MT], ar_l[MT], ai_h[MT], ai_l[MT], an_h[MT], an_l[MT];
 #pragma unroll
       for (int mi = 0; mi < MT; ++mi)
 #pragma unroll
@@ -597,25 +605,34 @@ __global__ __launch_bounds__(kBlock) void far_tile_h_kernel(int n, const double2
           const f2 vr = {gr[mi][2 * q], gr[mi][2 * q + 1]}, vi = {gi[mi][2 * q], gi[mi][2 * q + 1]};
           split16x2(vr, ar_h[mi].p[q], ar_l[mi].p[q]);
           split16x2(vi, ai_h[mi].p[q], ai_l[mi].p[q]);
-          split16x2(vr + vi, a2_h[mi].p[q], a2_l[mi].p[q]);
+          // -Im G for the real part: the sign bits of both halves flipped
+          unsigned u, w;
+          __builtin_memcpy(&u, &ai_h[mi].p[q], 4);
+          __builtin_memcpy(&w, &ai_l[mi].p[q], 4);
+          u ^= 0x80008000u;
+          w ^= 0x80008000u;
+          __builtin_memcpy(&an_h[mi].p[q], &u, 4);
+          __builtin_memcpy(&an_l[mi].p[q], &w, 4);
         }
 #pragma unroll
       for (int ni = 0; ni < NT; ++ni) {
         const size_t bi = ((size_t)(s / 8 + kq) * ldx + b0 + 16 * ni + col) * 8;
         const v8h br_h = *(const v8h *)(Xh + bi), br_l = *(const v8h *)(Xh + plane + bi);
         const v8h bi_h = *(const v8h *)(Xh + 2 * plane + bi), bi_l = *(const v8h *)(Xh + 3 * plane + bi);
-        const v8h b2_h = *(const v8h *)(Xh + 4 * plane + bi), b2_l = *(const v8h *)(Xh + 5 * plane + bi);
 #pragma unroll
         for (int mi = 0; mi < MT; ++mi) {
-          p0[mi][ni] = mma16(ar_h[mi].v, br_h, p0[mi][ni]);
-          p0[mi][ni] = mma16(ar_h[mi].v, br_l, p0[mi][ni]);
-          p0[mi][ni] = mma16(ar_l[mi].v, br_h, p0[mi][ni]);
-          p1[mi][ni] = mma16(ai_h[mi].v, bi_h, p1[mi][ni]);
-          p1[mi][ni] = mma16(ai_h[mi].v, bi_l, p1[mi][ni]);
-          p1[mi][ni] = mma16(ai_l[mi].v, bi_h, p1[mi][ni]);
-          p2[mi][ni] = mma16(a2_h[mi].v, b2_h, p2[mi][ni]);
-          p2[mi][ni] = mma16(a2_h[mi].v, b2_l, p2[mi][ni]);
-          p2[mi][ni] = mma16(a2_l[mi].v, b2_h, p2[mi][ni]);
+          re[mi][ni] = mma16(ar_h[mi].v, br_h, re[mi][ni]);
+          re[mi][ni] = mma16(ar_h[mi].v, br_l, re[mi][ni]);
+          re[mi][ni] = mma16(ar_l[mi].v, br_h, re[mi][ni]);
+          re[mi][ni] = mma16(an_h[mi].v, bi_h, re[mi][ni]);
+          re[mi][ni] = mma16(an_h[mi].v, bi_l, re[mi][ni]);
+          re[mi][ni] = mma16(an_l[mi].v, bi_h, re[mi][ni]);
+          im[mi][ni] = mma16(ar_h[mi].v, bi_h, im[mi][ni]);
+          im[mi][ni] = mma16(ar_h[mi].v, bi_l, im[mi][ni]);
+          im[mi][ni] = mma16(ar_l[mi].v, bi_h, im[mi][ni]);
+          im[mi][ni] = mma16(ai_h[mi].v, br_h, im[mi][ni]);
+          im[mi][ni] = mma16(ai_h[mi].v, br_l, im[mi][ni]);
+          im[mi][ni] = mma16(ai_l[mi].v, br_h, im[mi][ni]);
         }
       }
     }
@@ -630,9 +647,8 @@ __global__ __launch_bounds__(kBlock) void far_tile_h_kernel(int n, const double2
       for (int r = 0; r < 4; ++r) {
         const int t = t0 + 16 * mi + 4 * kq + r;
         if (t < n && b < nrhs) {
-          const double a = (double)p0[mi][ni][r], c = (double)p1[mi][ni][r];
           part[((int64_t)blockIdx.y * nrhs + b) * n + t] =
-              make_double2((a - c) * ci, ((double)p2[mi][ni][r] - a - c) * ci);
+              make_double2((double)re[mi][ni][r] * ci, (double)im[mi][ni][r] * ci);
         }
       }
     }
@@ -853,7 +869,7 @@ int tile_source_split(int64_t n, int nrhs, bool single) {
 }
 
 size_t tile_h_workspace_bytes(int64_t n, int nrhs, int nsplit) {
-  // six FP16 planes [npad][ldx], column maxima and scales, f [nrhs][n], part [nsplit][nrhs][n]
+  // four FP16 planes [npad][ldx], column maxima and scales, f [nrhs][n], part [nsplit][nrhs][n]
   const size_t ldx = (size_t)tile_ldx(nrhs);
   return 2 * kHPlanes * (size_t)h_npad(n) * ldx + 256 + 16 * ldx + 256 +
          sizeof(double2) * (size_t)n * nrhs * (1 + (size_t)nsplit) + 512;
@@ -885,9 +901,9 @@ hipError_t launch_apply_tile_h(const Scat &s, const double *x, double *y, int nr
   const int excl = s.near_ok ? 1 : 0;   // z < 1 pairs in FP64 through the mixed correction
   if (far_start) (void)hipEventRecord(far_start, st);
   // the kernel is bound by the Green's evaluation on the VALU, so a wave takes as many right-hand
-  // sides as its registers hold: two M-tiles and four N-tiles (221 VGPRs) at 64 columns.  Measured at
-  // N = 122 500, B = 64, k = 40: 36.5 ms (MT 2, NT 4), 40.9 (MT 1, NT 4), 49.0 (MT 2, NT 2); the FP32
-  // tiles take 62.7 ms
+  // sides as its registers hold: two M-tiles and four N-tiles (162 VGPRs, three waves per SIMD) at 64
+  // columns.  Measured at N = 122 500, B = 64, k = 40: 29.1 ms (MT 2, NT 4), 35.0 (MT 1, NT 4), 40.9
+  // (MT 2, NT 4 held to 128 VGPRs, four waves per SIMD, with spills); the FP32 tiles take 62.7 ms
   constexpr int MT = 2, NT = 2;
   const dim3 grid((unsigned)((n + 64 * MT - 1) / (64 * MT)), (unsigned)used, (unsigned)(ldx / 32 > 0 ? ldx / 32 : 1));
   if (ldx % 64 == 0) {
