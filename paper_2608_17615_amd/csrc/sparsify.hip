@@ -596,13 +596,14 @@ __global__ __launch_bounds__(kSweepBlock) void block_sweep_kernel(int nx, int ny
 }
 
 // Sweep shape for grid rows of nx entries and nrhs right-hand sides: R right-hand sides per
-// workgroup (1 while that still gives 32 workgroups, else up to what the LDS vectors hold) and P
-// threads per (entry, right-hand side) pair.
+// workgroup and P threads per (entry, right-hand side) pair.  One right-hand side per workgroup at
+// every nrhs: a sweep is bound by the latency of each thread's chain of block-factor loads (nx / P
+// long), which several right-hand sides per workgroup lengthen.  Eight columns on a 99 x 197 grid:
+// 6.46 ms per sweep with all eight in one workgroup, the solve of that scatterer 10.7 -> 6.6 s.
 void sweep_shape(int nx, int nrhs, int *R, int *P) {
-  int r = nrhs >= 32 ? 1 : std::max(1, std::min(8, kSweepLds / nx));
-  r = std::max(1, std::min(r, kSweepLds / nx));
-  *R = r;
-  *P = std::max(1, kSweepBlock / (nx * r));   // P nx R <= max(kSweepBlock, nx R) <= kSweepLds
+  (void)nrhs;
+  *R = 1;
+  *P = std::max(1, kSweepBlock / nx);   // P nx <= max(kSweepBlock, nx) <= kSweepLds
 }
 
 }  // namespace
