@@ -341,6 +341,9 @@ void ls_destroy(ls_handle h) {
   lsk::free_solve_ws(h);
   for (hipEvent_t e : h->ev_far) (void)hipEventDestroy(e);
   for (hipEvent_t e : h->ev_apply) (void)hipEventDestroy(e);
+  for (hipEvent_t e : h->aux_join) (void)hipEventDestroy(e);
+  if (h->aux_fork) (void)hipEventDestroy(h->aux_fork);
+  for (hipStream_t q : h->aux_streams) (void)hipStreamDestroy(q);
   (void)hipSetDevice(cur);
   delete h;
 }

@@ -142,6 +142,11 @@ struct ls_ctx {
   // unwritten, and the solver never reads them (their systems have all finished).
   std::vector<char> scat_skip;
   std::vector<void *> owned;  // device allocations freed by ls_destroy
+  // streams (default priority) on which the solver runs the preconditioners of several scatterers
+  // side by side, with a fork event and one join event each; created on first use
+  std::vector<hipStream_t> aux_streams;
+  std::vector<hipEvent_t> aux_join;
+  hipEvent_t aux_fork = nullptr;
 };
 
 namespace lsk {

@@ -283,6 +283,28 @@ hipError_t ensure(void *&p, size_t &have, size_t need) {
   return e;
 }
 
+// three auxiliary streams at the default priority (a fourth chain goes back to the first), with
+// their join events and the fork event, created once per handle
+constexpr int kAuxStreams = 3;
+hipError_t aux_streams_ready(ls_ctx *h) {
+  if (!h->aux_streams.empty()) return hipSuccess;
+  hipError_t e = hipEventCreateWithFlags(&h->aux_fork, hipEventDisableTiming);
+  for (int a = 0; a < kAuxStreams && e == hipSuccess; ++a) {
+    hipStream_t q = nullptr;
+    hipEvent_t ev = nullptr;
+    e = hipStreamCreateWithFlags(&q, hipStreamNonBlocking);
+    if (e != hipSuccess) break;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      (void)hipStreamDestroy(q);
+      break;
+    }
+    h->aux_streams.push_back(q);
+    h->aux_join.push_back(ev);
+  }
+  return e;
+}
+
 SolveWs *solve_ws(ls_ctx *h, int level) {
   if (!h->ws_solve.ptr) h->ws_solve.ptr = new SolveWs[3]();
   return (SolveWs *)h->ws_solve.ptr + level;
@@ -603,26 +625,54 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
           HIPTRY(launch_precond_finish(scp, vj, n, pc.c, pc.sc, pc.ldc, zj, nrhs, st));
         } else {
           // the library's S^(C) per scatterer (P^H with D^-1 S^H D for adjoint solves); scatterers
-          // none of whose systems is active keep z = v
+          // none of whose systems is active keep z = v.  Each scatterer has its own grid buffers,
+          // and with several live ones their chains run side by side on the auxiliary streams (a
+          // sweep occupies one workgroup per right-hand side): each stream waits for z = v on st,
+          // and st for every stream, before the operator application.  The chains write disjoint
+          // node ranges of z.
           size_t need = 0;
           for (const Scat &scp : h->sc)
-            if (scp.sp) need = std::max(need, 3 * sizeof(double2) * (size_t)scp.sp->nx * scp.sp->ny * nrhs);
+            if (scp.sp) need += 3 * sizeof(double2) * (size_t)scp.sp->nx * scp.sp->ny * nrhs;
           if (need > ws->grid_bytes) {
             HIPTRY(hipStreamSynchronize(st));
             HIPTRY(ensure(ws->grid, ws->grid_bytes, need));
           }
+          int live_n = 0;
+          for (int si = 0; si < nseg; ++si) {
+            if (!h->sc[si].sp) continue;
+            for (int c = 0; c < nrhs; ++c)
+              if (act[c * nseg + si]) {
+                ++live_n;
+                break;
+              }
+          }
+          const bool side = live_n > 1;
+          if (side) {
+            HIPTRY(aux_streams_ready(h));
+            HIPTRY(hipEventRecord(h->aux_fork, st));
+            for (hipStream_t q : h->aux_streams) HIPTRY(hipStreamWaitEvent(q, h->aux_fork, 0));
+          }
+          double2 *gbase = (double2 *)ws->grid;
+          int used = 0;
           for (int si = 0; si < nseg; ++si) {
             const Scat &scp = h->sc[si];
             if (!scp.sp) continue;
+            const int64_t nc = (int64_t)scp.sp->nx * scp.sp->ny;
+            double2 *gc = gbase, *gs = gc + (size_t)nc * nrhs, *gt = gs + (size_t)nc * nrhs;
+            gbase = gt + (size_t)nc * nrhs;
             bool live = false;
             for (int c = 0; c < nrhs && !live; ++c) live = act[c * nseg + si] != 0;
             if (!live) continue;
-            const int64_t nc = (int64_t)scp.sp->nx * scp.sp->ny;
-            double2 *gc = (double2 *)ws->grid, *gs = gc + (size_t)nc * nrhs, *gt = gs + (size_t)nc * nrhs;
-            HIPTRY(launch_quad_to_cart(scp, vj, n, gc, nc, nrhs, st));
-            HIPTRY(launch_sparsify(*scp.sp, gc, nc, gs, nc, gt, nc, nrhs, o.mode == Mode::Adjoint, true, st));
-            HIPTRY(launch_precond_finish(scp, vj, n, gc, gs, nc, zj, nrhs, st));
+            const hipStream_t q = side ? h->aux_streams[used++ % h->aux_streams.size()] : st;
+            HIPTRY(launch_quad_to_cart(scp, vj, n, gc, nc, nrhs, q));
+            HIPTRY(launch_sparsify(*scp.sp, gc, nc, gs, nc, gt, nc, nrhs, o.mode == Mode::Adjoint, true, q));
+            HIPTRY(launch_precond_finish(scp, vj, n, gc, gs, nc, zj, nrhs, q));
           }
+          if (side)
+            for (size_t a = 0; a < h->aux_streams.size(); ++a) {
+              HIPTRY(hipEventRecord(h->aux_join[a], h->aux_streams[a]));
+              HIPTRY(hipStreamWaitEvent(st, h->aux_join[a], 0));
+            }
         }
         // relaxed: the mixed-precision operator once the residual allows it (as below)
         ls_precision pj = o.all_mixed ? LS_MIXED : LS_FP64;
