@@ -107,6 +107,77 @@ __global__ __launch_bounds__(kBlock) void prologue_tile_kernel(int64_t n, int nr
 
 // One wavefront's work: targets [t0, t0 + 16 MT), right-hand sides [b0, b0 + 16 NT), sources
 // [s0, s1) of one split; writes that split's FP64 partial sums part[(split * nrhs + b) * n + t].
+// RI (at most 8 right-hand sides, NT = 1): the 16 columns of the N-tile carry Re X of the eight
+// right-hand sides in columns 0-7 and Im X in columns 8-15, so two real MFMAs per step, one with
+// Re G and one with Im G, give all four real products of the complex tile without padding columns
+// (Gauss's form needs three MFMAs on 16 columns, half of them zero).  Column b and b + 8 of the
+// results are then combined across lanes l and l ^ 8.
+template <class T, int MT, int NT, bool CONJ, bool RI>
+__device__ __forceinline__ void tile_body_ri(int n, const double2 *__restrict__ pos,
+                                             const typename Tile<T>::cplx_t *__restrict__ X, int ldx, int nrhs,
+                                             double k2, int s0, int s1, int t0, int b0, int split,
+                                             double2 *__restrict__ part, const PhaseLds &sct, bool excl) {
+  static_assert(NT == 1 && RI, "the split-column form has one N-tile");
+  typedef Tile<T> TL;
+  typedef typename TL::acc_t acc_t;
+  const int lane = threadIdx.x & 63;
+  const int kk = lane >> 4, col = lane & 15;
+  const int bcol = col & 7;
+  const bool im_col = col >= 8;
+  int tm[MT];
+  double xt[MT], yt[MT];
+#pragma unroll
+  for (int mi = 0; mi < MT; ++mi) {
+    tm[mi] = t0 + 16 * mi + col;
+    const double2 p = pos[tm[mi] < n ? tm[mi] : n - 1];
+    xt[mi] = p.x;
+    yt[mi] = p.y;
+  }
+  // d0 = Re G X_col, d1 = Im G X_col with X_col = Re X (columns 0-7) or Im X (columns 8-15)
+  acc_t d0[MT], d1[MT];
+#pragma unroll
+  for (int mi = 0; mi < MT; ++mi) {
+    d0[mi] = acc_t{0, 0, 0, 0};
+    d1[mi] = acc_t{0, 0, 0, 0};
+  }
+  for (int s = s0; s < s1; s += 4) {
+    const int src = s + kk;
+    const bool ok = src < s1;
+    const int sc = ok ? src : s0;
+    const double2 p = pos[sc];
+    T gr[MT], gi[MT];
+#pragma unroll
+    for (int mi = 0; mi < MT; ++mi) {
+      const double dx = xt[mi] - p.x, dy = yt[mi] - p.y;
+      const double A = k2 * std::fma(dx, dx, dy * dy);
+      TL::green(A, gr[mi], gi[mi], sct, excl);
+      const bool zero = !ok || src == tm[mi];
+      gr[mi] = zero ? (T)0 : gr[mi];
+      gi[mi] = zero ? (T)0 : gi[mi];
+      if (CONJ) gi[mi] = -gi[mi];
+    }
+    const typename TL::cplx_t xb = X[(int64_t)sc * ldx + b0 + bcol];
+    const T xv = !ok ? (T)0 : (im_col ? xb.y : xb.x);
+#pragma unroll
+    for (int mi = 0; mi < MT; ++mi) {
+      d0[mi] = TL::mma(gr[mi], xv, d0[mi]);
+      d1[mi] = TL::mma(gi[mi], xv, d1[mi]);
+    }
+  }
+#pragma unroll
+  for (int mi = 0; mi < MT; ++mi)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      // lane col < 8 holds Re G Re X and Im G Re X of column col, its partner col + 8 the products
+      // with Im X: Re Y = Re G Re X - Im G Im X, Im Y = Re G Im X + Im G Re X
+      const double a = (double)d0[mi][r], c = (double)d1[mi][r];
+      const double pa = __shfl_xor(a, 8), pc = __shfl_xor(c, 8);
+      const int t = t0 + 16 * mi + TL::row(lane, r);
+      const int b = b0 + bcol;
+      if (!im_col && t < n && b < nrhs) part[((int64_t)split * nrhs + b) * n + t] = make_double2(a - pc, pa + c);
+    }
+}
+
 template <class T, int MT, int NT, bool CONJ>
 __device__ __forceinline__ void tile_body(int n, const double2 *__restrict__ pos,
                                           const typename Tile<T>::cplx_t *__restrict__ X, int ldx, int nrhs,
@@ -186,7 +257,7 @@ __device__ __forceinline__ void tile_body(int n, const double2 *__restrict__ pos
 }
 
 // grid: (ceil(n / (4 * 16 * MT)), source splits, ldx / (16 * NT))
-template <class T, int MT, int NT, bool CONJ>
+template <class T, int MT, int NT, bool CONJ, bool RI = false>
 __global__ __launch_bounds__(kBlock) void far_tile_kernel(int n, const double2 *__restrict__ pos,
                                                           const typename Tile<T>::cplx_t *__restrict__ X, int ldx,
                                                           int nrhs, double k2, int split_len,
@@ -197,16 +268,21 @@ __global__ __launch_bounds__(kBlock) void far_tile_kernel(int n, const double2 *
   if constexpr (kFP64<T>) sct = load_sincos(sct_lds, m_sincos);
   const int wave = threadIdx.x >> 6;
   const int s0 = blockIdx.y * split_len;
-  tile_body<T, MT, NT, CONJ>(n, pos, X, ldx, nrhs, k2, s0, min(n, s0 + split_len),
-                             (blockIdx.x * 4 + wave) * 16 * MT, blockIdx.z * 16 * NT, blockIdx.y, part, sct,
-                             excl != 0);
+  if constexpr (RI)
+    tile_body_ri<T, MT, NT, CONJ, RI>(n, pos, X, ldx, nrhs, k2, s0, min(n, s0 + split_len),
+                                      (blockIdx.x * 4 + wave) * 16 * MT, blockIdx.z * 16 * NT, blockIdx.y, part, sct,
+                                      excl != 0);
+  else
+    tile_body<T, MT, NT, CONJ>(n, pos, X, ldx, nrhs, k2, s0, min(n, s0 + split_len),
+                               (blockIdx.x * 4 + wave) * 16 * MT, blockIdx.z * 16 * NT, blockIdx.y, part, sct,
+                               excl != 0);
 }
 
 // Uneven batch of scatterers in one launch: each workgroup repeatedly takes the next work item
 // (scatterer, block of 64 MT targets, source split, RHS group) from a global counter until the
 // list, ordered longest first, is exhausted.  Every item writes its own partials, so the result
 // does not depend on which workgroup took it.
-template <class T, int MT, int NT, bool CONJ>
+template <class T, int MT, int NT, bool CONJ, bool RI = false>
 __global__ __launch_bounds__(kBlock) void far_tile_persistent(const BatchDesc *__restrict__ desc,
                                                               const WorkItem *__restrict__ items, int n_items,
                                                               int *__restrict__ counter, int ldx, int nrhs) {
@@ -224,13 +300,18 @@ __global__ __launch_bounds__(kBlock) void far_tile_persistent(const BatchDesc *_
     const WorkItem wi = items[it];
     const BatchDesc d = desc[wi.s];
     const int s0 = wi.split * d.split_len;
-    tile_body<T, MT, NT, CONJ>(d.n, d.pos, (const typename Tile<T>::cplx_t *)d.X, ldx, nrhs, d.k2, s0,
-                               min(d.n, s0 + d.split_len), (wi.tblock * 4 + wave) * 16 * MT, wi.bgroup * 16 * NT,
-                               wi.split, d.part, sct, d.excl != 0);
+    if constexpr (RI)
+      tile_body_ri<T, MT, NT, CONJ, RI>(d.n, d.pos, (const typename Tile<T>::cplx_t *)d.X, ldx, nrhs, d.k2, s0,
+                                        min(d.n, s0 + d.split_len), (wi.tblock * 4 + wave) * 16 * MT,
+                                        wi.bgroup * 16 * NT, wi.split, d.part, sct, d.excl != 0);
+    else
+      tile_body<T, MT, NT, CONJ>(d.n, d.pos, (const typename Tile<T>::cplx_t *)d.X, ldx, nrhs, d.k2, s0,
+                                 min(d.n, s0 + d.split_len), (wi.tblock * 4 + wave) * 16 * MT, wi.bgroup * 16 * NT,
+                                 wi.split, d.part, sct, d.excl != 0);
   }
 }
 
-template <class T, int MT, int NT>
+template <class T, int MT, int NT, bool RI = false>
 void launch_tile(const Scat &s, const void *X, int ldx, int nrhs, int split_len, int nsplit, double2 *part,
                  bool conj, hipStream_t st) {
   dim3 grid((unsigned)((s.n + 64 * MT - 1) / (64 * MT)), (unsigned)nsplit, (unsigned)(ldx / (16 * NT)));
@@ -238,11 +319,11 @@ void launch_tile(const Scat &s, const void *X, int ldx, int nrhs, int split_len,
   // the FP32 tiles leave the pairs with z < 1 to the FP64 near part of the mixed correction
   const int excl = (!kFP64<T> && s.near_ok) ? 1 : 0;
   if (conj)
-    far_tile_kernel<T, MT, NT, true><<<grid, kBlock, 0, st>>>((int)s.n, s.pos, (const C *)X, ldx, nrhs, s.k * s.k,
-                                                             split_len, part, excl);
+    far_tile_kernel<T, MT, NT, true, RI><<<grid, kBlock, 0, st>>>((int)s.n, s.pos, (const C *)X, ldx, nrhs,
+                                                                 s.k * s.k, split_len, part, excl);
   else
-    far_tile_kernel<T, MT, NT, false><<<grid, kBlock, 0, st>>>((int)s.n, s.pos, (const C *)X, ldx, nrhs, s.k * s.k,
-                                                              split_len, part, excl);
+    far_tile_kernel<T, MT, NT, false, RI><<<grid, kBlock, 0, st>>>((int)s.n, s.pos, (const C *)X, ldx, nrhs,
+                                                                  s.k * s.k, split_len, part, excl);
 }
 
 // The pairs with z < 1 of a mixed-precision application, in FP64 (the mixed tiles leave them out):
@@ -315,7 +396,9 @@ template <class T, int MT>
 void launch_tile_nt(const Scat &s, const void *X, int ldx, int nrhs, int split_len, int nsplit, double2 *part,
                     bool conj, hipStream_t st) {
   const int groups = ldx / 16;
-  if (groups % 4 == 0)
+  if (nrhs <= 8)
+    launch_tile<T, MT, 1, true>(s, X, ldx, nrhs, split_len, nsplit, part, conj, st);
+  else if (groups % 4 == 0)
     launch_tile<T, MT, 4>(s, X, ldx, nrhs, split_len, nsplit, part, conj, st);
   else if (groups % 2 == 0)
     launch_tile<T, MT, 2>(s, X, ldx, nrhs, split_len, nsplit, part, conj, st);
@@ -325,7 +408,7 @@ void launch_tile_nt(const Scat &s, const void *X, int ldx, int nrhs, int split_l
 
 __global__ void zero_counter_kernel(int *c) { *c = 0; }
 
-template <class T, int MT, int NT>
+template <class T, int MT, int NT, bool RI = false>
 void launch_persistent(const BatchDesc *desc, const WorkItem *items, int n_items, int *counter, int ldx, int nrhs,
                        bool conj, hipStream_t st) {
   // one full round of resident workgroups; each keeps taking items until none are left
@@ -339,16 +422,18 @@ void launch_persistent(const BatchDesc *desc, const WorkItem *items, int n_items
   const int grid = std::max(1, std::min(n_items, cus * std::max(per_cu, 1)));
   zero_counter_kernel<<<1, 1, 0, st>>>(counter);
   if (conj)
-    far_tile_persistent<T, MT, NT, true><<<grid, kBlock, 0, st>>>(desc, items, n_items, counter, ldx, nrhs);
+    far_tile_persistent<T, MT, NT, true, RI><<<grid, kBlock, 0, st>>>(desc, items, n_items, counter, ldx, nrhs);
   else
-    far_tile_persistent<T, MT, NT, false><<<grid, kBlock, 0, st>>>(desc, items, n_items, counter, ldx, nrhs);
+    far_tile_persistent<T, MT, NT, false, RI><<<grid, kBlock, 0, st>>>(desc, items, n_items, counter, ldx, nrhs);
 }
 
 template <class T, int MT>
 void launch_persistent_nt(const BatchDesc *desc, const WorkItem *items, int n_items, int *counter, int ldx, int nrhs,
                           bool conj, hipStream_t st) {
   const int groups = ldx / 16;
-  if (groups % 4 == 0)
+  if (nrhs <= 8)
+    launch_persistent<T, MT, 1, true>(desc, items, n_items, counter, ldx, nrhs, conj, st);
+  else if (groups % 4 == 0)
     launch_persistent<T, MT, 4>(desc, items, n_items, counter, ldx, nrhs, conj, st);
   else if (groups % 2 == 0)
     launch_persistent<T, MT, 2>(desc, items, n_items, counter, ldx, nrhs, conj, st);
