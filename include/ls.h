@@ -178,8 +178,14 @@ typedef struct {
    *   mixed_scheme = 1: refinement passes; every Arnoldi application uses the mixed operator,
    *                    each pass is a GMRES cycle from the FP64 residual that stops once its
    *                    estimate has fallen by the factor inner_tol (default 1e-5) or below
-   *                    0.3 tol, and passes repeat until the FP64 residual meets tol (one FP64
-   *                    application per pass).  inner_maxit is ignored.
+   *                    0.3 tol, and passes repeat until the residual meets tol (one FP64
+   *                    application per pass).  A pass whose FP64 starting residual r is small
+   *                    (1e-5 ||r|| <= tol ||b|| / 2) closes on r - L_mixed dx, dx its correction
+   *                    of x, instead of a new FP64 residual: that differs from b - L x by the mixed
+   *                    far sum's error on dx, bounded by 1e-5 (||L_mixed dx|| + ||dx||) (50 times
+   *                    the mixed operators' measured error), and a column counts as converged
+   *                    only if its updated residual plus that bound meets tol.  inner_maxit is
+   *                    ignored.
    * With several scatterers in the handle, every (column, scatterer) pair is an independent
    * system with its own Krylov space and convergence test; iters reports the most steps any
    * scatterer of the column took, relres the residual over the whole column. */
@@ -187,7 +193,9 @@ typedef struct {
 
 typedef struct {
   int32_t *iters;       /* [nrhs] host, may be NULL: Arnoldi steps per column */
-  double *relres;       /* [nrhs] host, may be NULL: final true relative residual (FP64 apply) */
+  double *relres;       /* [nrhs] host, may be NULL: final true relative residual (FP64 apply; for
+                         * refinement passes that closed on the residual update, the updated
+                         * residual, within the bound given above of the FP64 one) */
   int64_t n_apply_fp64; /* FP64 operator applications (per column count summed) */
   int64_t n_apply_mixed;
   double seconds;

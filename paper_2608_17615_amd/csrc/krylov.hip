@@ -452,7 +452,19 @@ struct CoreOpts {
                                    // at the start of a cycle stays FP64)
   double pass_reduce = 0.0;        // > 0: a cycle stops once its residual estimate is below
                                    // max(0.3 tol, pass_reduce x the largest starting residual)
+  bool close_update = false;       // a refinement cycle that starts from a small FP64 residual
+                                   // closes on r - L_mixed dx instead of a new FP64 residual
 };
+
+// The closing check of a refinement cycle by the residual update r_new = r - L_mixed dx, with r
+// the cycle's FP64 starting residual and dx the cycle's correction of x.  It differs from the FP64
+// residual b - L (x + dx) by (L - L_mixed) dx, i.e. by the mixed far sum's error on dx, at most
+// kCloseEps (||L_mixed dx|| + ||dx||) (the far sum K = L - I is bounded by those two): 50 times the
+// 2-norm error of the mixed operators measured on the workloads (split FP16 1.8e-7, FP32 tiles
+// 2.9e-7).  A system is closed only if its estimate plus that bound meets tol, and the check runs
+// only when it can succeed (kCloseEps ||r|| <= tol ||b|| / 2), so the first pass from x = 0 never
+// spends a mixed application on it.
+constexpr double kCloseEps = 1e-5;
 
 struct CoreResult {
   std::vector<int> iters;   // per system
@@ -461,6 +473,9 @@ struct CoreResult {
   // residual and right-hand-side norms of that check (x has not changed since)
   bool start_done = false;
   std::vector<double> rn0, bn0;
+  // the call closed every system by the residual update (CoreOpts::close_update); rn0 and bn0 then
+  // hold the updated residuals' norms and those of b
+  bool closed = false;
   int64_t n_fp64 = 0, n_mixed = 0;
   int64_t n_reorth = 0;     // system-steps that took a second Gram-Schmidt pass
 };
@@ -483,9 +498,10 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
   HIPTRY(G.init(cyc + 1));
   const int nseg = G.nseg, nsys = G.nsys;
   const size_t vb = sizeof(double2) * (size_t)n * nrhs;
-  HIPTRY(ensure(ws->vecs, ws->vec_bytes, 2 * vb));
+  HIPTRY(ensure(ws->vecs, ws->vec_bytes, (o.close_update ? 3 : 2) * vb));
   double2 *r = (double2 *)ws->vecs;
   double2 *t = r + (size_t)n * nrhs;
+  double2 *d = o.close_update ? t + (size_t)n * nrhs : nullptr;
   // the basis grows chunk by chunk as the iteration needs it (a solve that converges early never
   // holds maxit vectors); new chunks enter the device pointer table as they arrive
   HIPTRY(ensure_chunks(ws->V, 1, n, nrhs));
@@ -824,6 +840,13 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
     const int mmax = std::max(1, *std::max_element(mc.begin(), mc.end()));
     HIPTRY(hipMemcpyAsync(G.hbuf, yv.data(), sizeof(double2) * nsys * m, hipMemcpyHostToDevice, st));
     HIPTRY(G.set_active(part_in));
+    // the residual update can close this cycle when its starting residual is small enough
+    bool closing = o.close_update && o.x0_given;
+    for (int q = 0; q < nsys && closing; ++q)
+      if (part_in[q] && kCloseEps * rnorm[q] > 0.5 * o.tol * bnorm[q]) closing = false;
+    // dx = V y (or Z y) into t, then x += dx (or straight into x)
+    double2 *upd = closing ? t : x;
+    if (closing) HIPTRY(hipMemsetAsync(t, 0, vb, st));
     std::vector<double2 *> ztbl;
     if (o.flexible) {
       ztbl.resize(mmax);
@@ -831,12 +854,44 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
       HIPTRY(hipMemcpyAsync(G.ptrs + G.max_vec + 4, ztbl.data(), sizeof(double2 *) * mmax, hipMemcpyHostToDevice,
                             st));
       update_kernel<<<gt, kBlock, 0, st>>>(mmax, nseg, G.tiles, G.active, G.ptrs + G.max_vec + 4, n, G.hbuf, m, 1.0,
-                                           x, n);
+                                           upd, n);
     } else {
-      update_kernel<<<gt, kBlock, 0, st>>>(mmax, nseg, G.tiles, G.active, G.ptrs, n, G.hbuf, m, 1.0, x, n);
+      update_kernel<<<gt, kBlock, 0, st>>>(mmax, nseg, G.tiles, G.active, G.ptrs, n, G.hbuf, m, 1.0, upd, n);
     }
     HIPTRY(hipGetLastError());
     HIPTRY(hipStreamSynchronize(st));   // yv and ztbl go out of scope
+    if (closing) {
+      axpy_kernel<<<gv, kBlock, 0, st>>>(n, x, n, 1.0, t, n, x, n);
+      HIPTRY(hipGetLastError());
+      set_skip(part_in);
+      ls_status s3 = apply_op(h, (const double *)t, (double *)d, nrhs, n, o.mode, LS_MIXED, st);
+      if (s3 != LS_OK) return s3;
+      ++res.n_mixed;
+      axpy_kernel<<<gv, kBlock, 0, st>>>(n, r, n, -1.0, d, n, r, n);   // r - L_mixed dx
+      HIPTRY(hipGetLastError());
+      std::vector<double> rn(nsys), dn(nsys), ln(nsys);
+      HIPTRY(G.set_active(part_in));
+      HIPTRY(norms_of(r, rn));
+      HIPTRY(norms_of(t, dn));
+      HIPTRY(norms_of(d, ln));
+      bool all_closed = true;
+      for (int q = 0; q < nsys; ++q) {
+        if (!part_in[q]) continue;
+        const double bq = bnorm[q] > 0 ? bnorm[q] : 1.0;
+        const double e = rn[q] / bq, bound = kCloseEps * (ln[q] + dn[q]) / bq;
+        if (!std::isfinite(e)) return setup_fail(h, LS_ERR_NONFINITE, "non-finite residual");
+        all_closed = all_closed && e + bound <= o.tol;
+      }
+      if (all_closed) {
+        for (int q = 0; q < nsys; ++q)
+          if (part_in[q]) rnorm[q] = rn[q];
+        res.closed = true;
+        res.rn0 = rnorm;
+        res.bn0 = bnorm;
+        break;
+      }
+      // some system is not closed: the next pass starts from the FP64 residual of the updated x
+    }
     bool all_done = true;
     for (int q = 0; q < nsys; ++q) all_done = all_done && res.done[q];
     if (all_done || cyc >= maxit) break;
@@ -893,15 +948,16 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
     co.matvec = LS_MIXED;
     co.flexible = pc != nullptr;
     co.pass_reduce = o.inner_tol > 0 ? o.inner_tol : 1e-5;
+    co.close_update = true;
   }
   CoreResult res;
   ls_status status = gmres_core(h, ws, wi, bb, xs, nrhs, co, res, st);
   if (status < 0) return status;
   const int nsys = (int)res.iters.size();
   // the last GMRES call's closing residual check, when it found every system done
-  bool have_final = res.start_done;
+  bool have_final = res.start_done || res.closed;
   std::vector<double> rn_final = res.rn0, bn_final = res.bn0;
-  for (int pass = 0; pass < 30 && passes; ++pass) {
+  for (int pass = 0; pass < 30 && passes && !res.closed; ++pass) {
     int used = 0;
     for (int q = 0; q < nsys; ++q) used = std::max(used, res.iters[q]);
     if (used >= o.maxit) break;
@@ -920,10 +976,10 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
     res.n_fp64 += rr.n_fp64;
     res.n_mixed += rr.n_mixed;
     res.n_reorth += rr.n_reorth;
-    have_final = rr.start_done;
+    have_final = rr.start_done || rr.closed;
     rn_final = rr.rn0;
     bn_final = rr.bn0;
-    if (more == 0) break;   // every system met tol on its FP64 residual
+    if (more == 0 || rr.closed) break;   // every system met tol on its FP64 (or updated) residual
   }
   for (int pass = 0; pass < 3 && relax > 0 && !passes; ++pass) {
     // refinement from the FP64 residual for systems the relaxed iteration left above tol

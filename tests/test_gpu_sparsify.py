@@ -82,6 +82,35 @@ def test_preconditioned_solve_reaches_lu_and_cuts_steps():
           f"vs LU {ep:.2e}", flush=True)
     assert ip["converged"] and max(ip["relres"]) <= 1e-8 and ep <= 1e-6
     assert ip["n_apply_mixed"] > 4 * ip["n_apply_fp64"]
+    # the last pass closes on r - L_mixed dx (its FP64 starting residual being small): the returned
+    # x's FP64 residual meets tol and equals the reported one up to the mixed operator's error on dx
+    rt = np.linalg.norm((bt - op.apply(up)).cpu().numpy(), axis=1) / np.linalg.norm(b, axis=1)
+    print(f"passes: FP64 residual of the returned x {rt.tolist()}", flush=True)
+    assert rt.max() <= 1e-8
+    assert np.abs(rt - ip["relres"]).max() <= 1e-9
+    assert ip["n_apply_fp64"] <= 2 * len(b)
+
+
+def test_passes_close_on_the_residual_update_at_full_size():
+    """The benchmark's solve (unit disk, k = 40, N = 122 500, 64 waves, the library's preconditioner,
+    split-FP16 refinement passes): one FP64 application (the second pass's starting residual), the
+    closing check by the residual update, and every returned column's FP64 residual below 1e-8 and
+    within a tenth of the tolerance of the reported one (measured 4.9e-11: the split-FP16 far sum's
+    error on the last pass's correction)."""
+    p = P.config3()
+    op = _op(p)
+    g = P.cartesian_grid(p, 0.3)
+    op.sparsify_setup(*g, P.grid_contrast(p, g))
+    b = torch.tensor(p.incident(), device="cuda")
+    x, info = op.solve_precond(b, None, tol=1e-8, maxit=200, precision="mixed", scheme="passes")
+    rt = (torch.linalg.norm(b - op.apply(x), dim=1) / torch.linalg.norm(b, dim=1)).cpu().numpy()
+    print(f"N={p.n_nodes}, 64 waves: steps {int(max(info['iters']))}, applications {info['n_apply_fp64']}+"
+          f"{info['n_apply_mixed']}, reported max {max(info['relres']):.3e}, FP64 max {rt.max():.3e}, "
+          f"largest difference {np.abs(rt - info['relres']).max():.1e}", flush=True)
+    assert info["converged"]
+    assert rt.max() <= 1e-8
+    assert np.abs(rt - info["relres"]).max() <= 1e-9
+    assert info["n_apply_fp64"] == 64
 
 
 def test_several_scatterers_each_with_its_own_preconditioner():
