@@ -253,6 +253,9 @@ __global__ __launch_bounds__(kBlock) void epilogue_kernel(
   const int b = blockIdx.y;
   if (i >= n) return;
   double ar = 0.0, ai = 0.0;
+  // unrolled so that eight partial loads are in flight before the first add (the sum keeps its
+  // order); one load per iteration waited for each round trip in turn
+#pragma unroll 8
   for (int sp = 0; sp < nsplit; ++sp) {
     const double2 p = part[((int64_t)sp * nrhs + b) * n + i];
     ar += p.x;
@@ -264,6 +267,7 @@ __global__ __launch_bounds__(kBlock) void epilogue_kernel(
   ai *= gs;
   const double2 *fb = f + (int64_t)b * n;
   double cr = 0.0, cim = 0.0;
+#pragma unroll 4
   for (int64_t q = rp[i]; q < rp[i + 1]; ++q) {
     const double2 c = cv[q];
     const double2 v = fb[ci[q]];
@@ -360,6 +364,7 @@ __global__ __launch_bounds__(kBlock) void field_epilogue_kernel(int64_t nt, int 
   const int b = blockIdx.y;
   if (t >= nt) return;
   double ar = 0.0, ai = 0.0;
+#pragma unroll 8
   for (int sp = 0; sp < nsplit; ++sp) {
     const double2 p = part[((int64_t)sp * nrhs + b) * nt + t];
     ar += p.x;
@@ -368,6 +373,7 @@ __global__ __launch_bounds__(kBlock) void field_epilogue_kernel(int64_t nt, int 
   ar *= G_SCALE;
   ai *= G_SCALE;
   const double2 *fb = f + (int64_t)b * n;
+#pragma unroll 4
   for (int64_t q = rp[t]; q < rp[t + 1]; ++q) {
     const double2 c = cv[q];
     const double2 v = fb[ci[q]];
