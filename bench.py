@@ -263,8 +263,8 @@ def run_plain(args, prob, label):
     fpp = flops_per_pair(frac, 1)
     # the single right-hand-side sum evaluates each unordered pair once (blocks of 256 on the
     # diagonal in both orders) and does two complex multiply-adds per evaluation: executed flops
-    # per launch, against which the roofline is taken; the survey's count per ordered pair is the
-    # effective rate
+    # per launch, against which the roofline is taken; the ordered-pair count (every ordered pair
+    # at the plain sum's flops) gives the effective rate
     blk = 256
     nb = -(-n // blk)
     evals = n * (n - 1) // 2 + nb * blk * (blk - 1) // 2
