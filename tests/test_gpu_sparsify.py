@@ -113,29 +113,37 @@ def test_passes_close_on_the_residual_update_at_full_size():
     assert info["n_apply_fp64"] == 64
 
 
-def test_several_scatterers_each_with_its_own_preconditioner():
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_several_scatterers_each_with_its_own_preconditioner(adjoint):
+    """Four preconditioned scatterers and one without in one handle: their preconditioners run
+    side by side on the auxiliary streams (four chains over three streams), and every block of the
+    solution equals that scatterer's own solve, forward and adjoint."""
     a = P.disk_problem(4, 9.0, 2.0, directions=[0.0, 0.7])
     b = P.graded_two_material(2, 8.0, directions=[0.0, 0.7])
+    d = P.disk_problem(3, 7.0, 2.5, directions=[0.0, 0.7])
+    e2 = P.disk_problem(4, 5.0, 1.5, directions=[0.0, 0.7])
     c = P.disk_problem(3, 6.0, 1.5, directions=[0.0, 0.7])   # left without a preconditioner
-    probs = [a, b, c]
+    probs = [a, b, d, e2, c]
+    npre = 4
     big = lsg.Operator([lsg.Scatterer.from_mesh(p.mesh, p.m, p.k) for p in probs])
-    for s, p in enumerate(probs[:2]):
+    for s, p in enumerate(probs[:npre]):
         g = P.cartesian_grid(p, 0.8)
         big.sparsify_setup(*g, P.grid_contrast(p, g), s=s)
     rhs = torch.tensor(np.concatenate([p.incident() for p in probs], axis=1), device="cuda")
-    u, info = big.solve_precond(rhs, tol=1e-12, maxit=400)
+    u, info = big.solve_precond(rhs, tol=1e-12, maxit=400, adjoint=adjoint)
     assert info["converged"]
     off = 0
     for s, p in enumerate(probs):
         one = _op(p)
-        if s < 2:
+        bs = torch.tensor(p.incident(), device="cuda")
+        if s < npre:
             g = P.cartesian_grid(p, 0.8)
             one.sparsify_setup(*g, P.grid_contrast(p, g))
-            us, _ = one.solve_precond(torch.tensor(p.incident(), device="cuda"), tol=1e-12, maxit=400)
+            us, _ = one.solve_precond(bs, tol=1e-12, maxit=400, adjoint=adjoint)
         else:
-            us, _ = one.solve(torch.tensor(p.incident(), device="cuda"), tol=1e-12, maxit=400)
+            us, _ = one.solve(bs, tol=1e-12, maxit=400, adjoint=adjoint)
         e = relmax(u[:, off:off + p.n_nodes].cpu().numpy(), us.cpu().numpy())
-        print(f"scatterer {s}: N={p.n_nodes}, vs its own solve {e:.2e}", flush=True)
+        print(f"adjoint={adjoint} scatterer {s}: N={p.n_nodes}, vs its own solve {e:.2e}", flush=True)
         assert e <= 1e-10
         off += p.n_nodes
 
