@@ -323,7 +323,11 @@ typedef ls_status (*ls_grid_op)(const double *c, double *sc, int32_t nrhs, int64
  *     scatterer that has one (ls_sparsify_setup), each (column, scatterer) system preconditioned
  *     by its own scatterer's P; scatterers without one are not preconditioned.  Adjoint solves
  *     (o->adjoint) take P^H = I + T_C^Q (D^-1 S^H D - I) T_Q^C (D of eq. D_def), the
- *     preconditioner of L^H that corresponds to P.  The grid workspaces are the library's.
+ *     preconditioner of L^H that corresponds to P.  The grid workspaces are the library's, one
+ *     per scatterer.  With two or more scatterers still iterating, their preconditioner steps run
+ *     side by side on three streams the handle creates on first use (default priority, on the
+ *     current device, destroyed by ls_destroy); each waits on stream for the step's input and
+ *     stream waits for all of them, so the call stays ordered on stream.
  * With o->prec = LS_MIXED the operator applications switch to the mixed precision once the
  * residual allows it, as in relaxed GMRES (o->inner_tol is the granted accuracy, default 1e-4),
  * followed by FP64 refinement; o->inner_maxit is ignored.  Everything else is as for
