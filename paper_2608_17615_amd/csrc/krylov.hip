@@ -457,13 +457,13 @@ struct CoreOpts {
 };
 
 // The closing check of a refinement cycle by the residual update r_new = r - L_mixed dx, with r
-// the cycle's FP64 starting residual and dx the cycle's correction of x.  It differs from the FP64
-// residual b - L (x + dx) by (L - L_mixed) dx, i.e. by the mixed far sum's error on dx, at most
-// kCloseEps (||L_mixed dx|| + ||dx||) (the far sum K = L - I is bounded by those two): 50 times the
-// 2-norm error of the mixed operators measured on the workloads (split FP16 1.8e-7, FP32 tiles
-// 2.9e-7).  A system is closed only if its estimate plus that bound meets tol, and the check runs
-// only when it can succeed (kCloseEps ||r|| <= tol ||b|| / 2), so the first pass from x = 0 never
-// spends a mixed application on it.
+// the cycle's FP64 starting residual and dx the cycle's correction of x; r_new is formed from the
+// Arnoldi basis (no operator application).  It differs from the FP64 residual b - L (x + dx) by
+// (L - L_mixed) dx, i.e. by the mixed far sum's error on dx, at most kCloseEps (||L_mixed dx|| +
+// ||dx||) (the far sum K = L - I is bounded by those two): 50 times the 2-norm error of the mixed
+// operators measured on the workloads (split FP16 1.8e-7, FP32 tiles 2.9e-7).  A system is closed
+// only if its updated residual plus that bound meets tol, and the check runs only when it can
+// succeed (kCloseEps ||r|| <= tol ||b|| / 2), so it is not tried on the first pass from x = 0.
 constexpr double kCloseEps = 1e-5;
 
 struct CoreResult {
@@ -863,22 +863,40 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
     if (closing) {
       axpy_kernel<<<gv, kBlock, 0, st>>>(n, x, n, 1.0, t, n, x, n);
       HIPTRY(hipGetLastError());
-      set_skip(part_in);
-      ls_status s3 = apply_op(h, (const double *)t, (double *)d, nrhs, n, o.mode, LS_MIXED, st);
-      if (s3 != LS_OK) return s3;
-      ++res.n_mixed;
-      axpy_kernel<<<gv, kBlock, 0, st>>>(n, r, n, -1.0, d, n, r, n);   // r - L_mixed dx
+      // r - L_mixed dx without another application: the Arnoldi relation L_mixed Z = V H (H the
+      // (m + 1) x m Hessenberg matrix) gives r - L_mixed Z y = V (beta e_0 - H y) = V Q^H (g_m e_m),
+      // Q the product of the cycle's Givens rotations and g_m the last entry of the rotated right-hand
+      // side (|g_m| is the residual estimate).  Its coefficients u: from w = g_m, for i = m - 1 .. 0,
+      // u_{i+1} = c_i w and w <- -s_i w; u_0 = w.
+      std::vector<double2> uv((size_t)nsys * (m + 1), make_double2(0, 0));
+      for (int q = 0; q < nsys; ++q) {
+        if (!part_in[q]) continue;
+        const int mm = mc[q];
+        const cplx *csc = &cs[(size_t)q * m], *snc = &sn[(size_t)q * m];
+        cplx w = g[(size_t)q * (m + 1) + mm];
+        double2 *u = &uv[(size_t)q * (m + 1)];
+        for (int i = mm - 1; i >= 0; --i) {
+          const cplx ui = csc[i] * w;
+          u[i + 1] = make_double2(ui.real(), ui.imag());
+          w = -snc[i] * w;
+        }
+        u[0] = make_double2(w.real(), w.imag());
+      }
+      HIPTRY(hipMemcpyAsync(G.hbuf, uv.data(), sizeof(double2) * uv.size(), hipMemcpyHostToDevice, st));
+      HIPTRY(hipMemsetAsync(d, 0, vb, st));
+      update_kernel<<<gt, kBlock, 0, st>>>(mmax + 1, nseg, G.tiles, G.active, G.ptrs, n, G.hbuf, m + 1, 1.0, d, n);
       HIPTRY(hipGetLastError());
-      std::vector<double> rn(nsys), dn(nsys), ln(nsys);
+      HIPTRY(hipStreamSynchronize(st));   // uv goes out of scope
+      std::vector<double> rn(nsys), dn(nsys);
       HIPTRY(G.set_active(part_in));
-      HIPTRY(norms_of(r, rn));
+      HIPTRY(norms_of(d, rn));
       HIPTRY(norms_of(t, dn));
-      HIPTRY(norms_of(d, ln));
       bool all_closed = true;
       for (int q = 0; q < nsys; ++q) {
         if (!part_in[q]) continue;
         const double bq = bnorm[q] > 0 ? bnorm[q] : 1.0;
-        const double e = rn[q] / bq, bound = kCloseEps * (ln[q] + dn[q]) / bq;
+        // ||L_mixed dx|| = ||r - r_new|| <= ||r|| + ||r_new||
+        const double e = rn[q] / bq, bound = kCloseEps * (rnorm[q] + rn[q] + dn[q]) / bq;
         if (!std::isfinite(e)) return setup_fail(h, LS_ERR_NONFINITE, "non-finite residual");
         all_closed = all_closed && e + bound <= o.tol;
       }
