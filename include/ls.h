@@ -182,11 +182,11 @@ typedef struct {
    *                    application per pass).  A pass whose FP64 starting residual r is small
    *                    (1e-5 ||r|| <= tol ||b|| / 2) closes on r - L_mixed dx, dx its correction
    *                    of x, formed from the Arnoldi basis (V Q^H g_m e_m, no operator
-   *                    application), instead of a new FP64 residual: that differs from b - L x by the mixed
-   *                    far sum's error on dx, bounded by 1e-5 (||r|| + ||r - L_mixed dx|| + ||dx||) (50 times
-   *                    the mixed operators' measured error), and a column counts as converged
-   *                    only if its updated residual plus that bound meets tol.  inner_maxit is
-   *                    ignored.
+   *                    application), instead of a new FP64 residual.  That differs from b - L x
+   *                    by the mixed far sum's error on dx, bounded by
+   *                    1e-5 (||r|| + ||r - L_mixed dx|| + ||dx||) (50 times the mixed operators'
+   *                    measured error), and a column counts as converged only if its updated
+   *                    residual plus that bound meets tol.  inner_maxit is ignored.
    * With several scatterers in the handle, every (column, scatterer) pair is an independent
    * system with its own Krylov space and convergence test; iters reports the most steps any
    * scatterer of the column took, relres the residual over the whole column. */
