@@ -454,6 +454,9 @@ struct CoreOpts {
                                    // max(0.3 tol, pass_reduce x the largest starting residual)
   bool close_update = false;       // a refinement cycle that starts from a small FP64 residual
                                    // closes on r - L_mixed dx instead of a new FP64 residual
+  bool close_relaxed = false;      // a relaxed flexible cycle (z_j = P v_j kept) closes on its
+                                   // basis residual when the mixed steps' bound allows it
+  double close_tol = 0.0;          // the caller's tolerance for these closing checks
 };
 
 // The closing check of a refinement cycle by the residual update r_new = r - L_mixed dx, with r
@@ -464,6 +467,11 @@ struct CoreOpts {
 // operators measured on the workloads (split FP16 1.8e-7, FP32 tiles 2.9e-7).  A system is closed
 // only if its updated residual plus that bound meets tol, and the check runs only when it can
 // succeed (kCloseEps ||r|| <= tol ||b|| / 2), so it is not tried on the first pass from x = 0.
+// A relaxed cycle (FP64 applications first, mixed ones once the residual allows) has
+// r - sum_j y_j L_j z_j = V Q^H g_m e_m with L_j the operator of step j, so its basis residual
+// differs from the FP64 one by sum over the mixed steps of y_j (L_mixed - L) z_j, at most
+// kCloseEps sum_j |y_j| (||h_j|| + ||z_j||) (||L_mixed z_j|| = ||h_j||, the unrotated Hessenberg
+// column, V being orthonormal).
 constexpr double kCloseEps = 1e-5;
 
 struct CoreResult {
@@ -498,10 +506,11 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
   HIPTRY(G.init(cyc + 1));
   const int nseg = G.nseg, nsys = G.nsys;
   const size_t vb = sizeof(double2) * (size_t)n * nrhs;
-  HIPTRY(ensure(ws->vecs, ws->vec_bytes, (o.close_update ? 3 : 2) * vb));
+  const bool any_close = o.close_update || o.close_relaxed;
+  HIPTRY(ensure(ws->vecs, ws->vec_bytes, (any_close ? 3 : 2) * vb));
   double2 *r = (double2 *)ws->vecs;
   double2 *t = r + (size_t)n * nrhs;
-  double2 *d = o.close_update ? t + (size_t)n * nrhs : nullptr;
+  double2 *d = any_close ? t + (size_t)n * nrhs : nullptr;   // the closing check's residual
   // the basis grows chunk by chunk as the iteration needs it (a solve that converges early never
   // holds maxit vectors); new chunks enter the device pointer table as they arrive
   HIPTRY(ensure_chunks(ws->V, 1, n, nrhs));
@@ -620,6 +629,8 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
     sn.assign((size_t)nsys * m, cplx(0));
     g.assign((size_t)nsys * (m + 1), cplx(0));
     std::vector<int> mc(nsys, 0);
+    std::vector<char> step_mixed(m, 0);   // step j applied the mixed operator (relaxed closing)
+    std::vector<double> hcol(o.close_relaxed ? (size_t)nsys * m : 0, 0.0);   // ||h_j|| before rotation
     const std::vector<int> part_in(act);   // systems that take part in this cycle
     for (int q = 0; q < nsys; ++q) g[(size_t)q * (m + 1)] = rnorm[q];
     int j = 0;
@@ -702,6 +713,7 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
         ls_status s2 = apply_op(h, (const double *)zj, (double *)w, nrhs, n, o.mode, pj, st);
         if (s2 != LS_OK) return s2;
         if (pj == LS_FP64) ++res.n_fp64; else ++res.n_mixed;
+        step_mixed[j] = pj == LS_MIXED ? 1 : 0;
       } else if (o.flexible) {
         // z_j ~ L^{-1} v_j by an inner GMRES with the mixed-precision operator (active systems
         // only), then w = L z_j
@@ -781,6 +793,11 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
         }
         Hat(j + 1, j) = betah[q];
         if (!std::isfinite(betah[q])) return setup_fail(h, LS_ERR_BREAKDOWN, "non-finite Arnoldi vector");
+        if (o.close_relaxed) {
+          double s2 = betah[q] * betah[q];
+          for (int i = 0; i < nv; ++i) s2 += std::norm(Hat(i, j));
+          hcol[(size_t)q * m + j] = std::sqrt(s2);
+        }
         cplx *csc = &cs[(size_t)q * m], *snc = &sn[(size_t)q * m], *gc = &g[(size_t)q * (m + 1)];
         for (int i = 0; i < j; ++i) {
           const cplx tq = csc[i] * Hat(i, j) + snc[i] * Hat(i + 1, j);
@@ -840,13 +857,15 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
     const int mmax = std::max(1, *std::max_element(mc.begin(), mc.end()));
     HIPTRY(hipMemcpyAsync(G.hbuf, yv.data(), sizeof(double2) * nsys * m, hipMemcpyHostToDevice, st));
     HIPTRY(G.set_active(part_in));
-    // the residual update can close this cycle when its starting residual is small enough
-    bool closing = o.close_update && o.x0_given;
-    for (int q = 0; q < nsys && closing; ++q)
-      if (part_in[q] && kCloseEps * rnorm[q] > 0.5 * o.tol * bnorm[q]) closing = false;
+    // the residual update can close a refinement cycle when its starting residual is small enough,
+    // and a relaxed cycle when its mixed steps' bound allows it
+    bool closing_pass = o.close_update && o.x0_given;
+    for (int q = 0; q < nsys && closing_pass; ++q)
+      if (part_in[q] && kCloseEps * rnorm[q] > 0.5 * o.close_tol * bnorm[q]) closing_pass = false;
+    const bool closing = closing_pass || o.close_relaxed;
     // dx = V y (or Z y) into t, then x += dx (or straight into x)
-    double2 *upd = closing ? t : x;
-    if (closing) HIPTRY(hipMemsetAsync(t, 0, vb, st));
+    double2 *upd = closing_pass ? t : x;
+    if (closing_pass) HIPTRY(hipMemsetAsync(t, 0, vb, st));
     std::vector<double2 *> ztbl;
     if (o.flexible) {
       ztbl.resize(mmax);
@@ -861,8 +880,10 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
     HIPTRY(hipGetLastError());
     HIPTRY(hipStreamSynchronize(st));   // yv and ztbl go out of scope
     if (closing) {
-      axpy_kernel<<<gv, kBlock, 0, st>>>(n, x, n, 1.0, t, n, x, n);
-      HIPTRY(hipGetLastError());
+      if (closing_pass) {
+        axpy_kernel<<<gv, kBlock, 0, st>>>(n, x, n, 1.0, t, n, x, n);
+        HIPTRY(hipGetLastError());
+      }
       // r - L_mixed dx without another application: the Arnoldi relation L_mixed Z = V H (H the
       // (m + 1) x m Hessenberg matrix) gives r - L_mixed Z y = V (beta e_0 - H y) = V Q^H (g_m e_m),
       // Q the product of the cycle's Givens rotations and g_m the last entry of the rotated right-hand
@@ -887,18 +908,34 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
       update_kernel<<<gt, kBlock, 0, st>>>(mmax + 1, nseg, G.tiles, G.active, G.ptrs, n, G.hbuf, m + 1, 1.0, d, n);
       HIPTRY(hipGetLastError());
       HIPTRY(hipStreamSynchronize(st));   // uv goes out of scope
-      std::vector<double> rn(nsys), dn(nsys);
+      std::vector<double> rn(nsys), extra(nsys, 0.0);
       HIPTRY(G.set_active(part_in));
       HIPTRY(norms_of(d, rn));
-      HIPTRY(norms_of(t, dn));
+      if (closing_pass) {
+        // ||L_mixed dx|| = ||r - r_new|| <= ||r|| + ||r_new||
+        std::vector<double> dn(nsys);
+        HIPTRY(norms_of(t, dn));
+        for (int q = 0; q < nsys; ++q) extra[q] = rnorm[q] + rn[q] + dn[q];
+      } else {
+        // sum over the mixed steps of |y_j| (||h_j|| + ||z_j||)
+        std::vector<double> zn(nsys);
+        for (int jj = 0; jj < mmax; ++jj) {
+          if (!step_mixed[jj]) continue;
+          HIPTRY(norms_of(ws->Z.vec(jj, n, nrhs), zn));
+          for (int q = 0; q < nsys; ++q)
+            if (part_in[q] && jj < mc[q]) {
+              const double2 yq = yv[(size_t)q * m + jj];
+              extra[q] += std::hypot(yq.x, yq.y) * (hcol[(size_t)q * m + jj] + zn[q]);
+            }
+        }
+      }
       bool all_closed = true;
       for (int q = 0; q < nsys; ++q) {
         if (!part_in[q]) continue;
         const double bq = bnorm[q] > 0 ? bnorm[q] : 1.0;
-        // ||L_mixed dx|| = ||r - r_new|| <= ||r|| + ||r_new||
-        const double e = rn[q] / bq, bound = kCloseEps * (rnorm[q] + rn[q] + dn[q]) / bq;
+        const double e = rn[q] / bq, bound = kCloseEps * extra[q] / bq;
         if (!std::isfinite(e)) return setup_fail(h, LS_ERR_NONFINITE, "non-finite residual");
-        all_closed = all_closed && e + bound <= o.tol;
+        all_closed = all_closed && e + bound <= o.close_tol;
       }
       if (all_closed) {
         for (int q = 0; q < nsys; ++q)
@@ -955,6 +992,9 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
   // perturbed by the mixed applications, still meets tol without a (Krylov-space-losing) restart
   CoreOpts co{relax > 0 ? 0.3 * o.tol : o.tol, o.maxit, o.restart, mode, LS_FP64, flexible,
               o.inner_tol > 0 ? o.inner_tol : 1e-12, o.inner_maxit, o.x0_given != 0, relax, progress, pc};
+  co.close_tol = o.tol;
+  // a preconditioned relaxed solve keeps its z_j, so it can close on its basis residual
+  co.close_relaxed = relax > 0 && pc != nullptr;
   // LS_MIXED with mixed_scheme = 1: refinement passes, each a GMRES cycle from the FP64 residual
   // whose applications are all mixed-precision, stopped once its estimate has fallen by inner_tol
   // (default 1e-5) or below 0.3 tol; the passes repeat until the FP64 residual meets tol
@@ -967,6 +1007,7 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
     co.flexible = pc != nullptr;
     co.pass_reduce = o.inner_tol > 0 ? o.inner_tol : 1e-5;
     co.close_update = true;
+    co.close_relaxed = false;
   }
   CoreResult res;
   ls_status status = gmres_core(h, ws, wi, bb, xs, nrhs, co, res, st);
@@ -999,7 +1040,7 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
     bn_final = rr.bn0;
     if (more == 0 || rr.closed) break;   // every system met tol on its FP64 (or updated) residual
   }
-  for (int pass = 0; pass < 3 && relax > 0 && !passes; ++pass) {
+  for (int pass = 0; pass < 3 && relax > 0 && !passes && !res.closed; ++pass) {
     // refinement from the FP64 residual for systems the relaxed iteration left above tol
     int used = 0;
     for (int q = 0; q < nsys; ++q) used = std::max(used, res.iters[q]);

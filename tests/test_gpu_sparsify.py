@@ -75,6 +75,11 @@ def test_preconditioned_solve_reaches_lu_and_cuts_steps():
     um, im = op.solve_precond(bt, tol=1e-8, maxit=300, precision="mixed", inner_tol=1e-6)
     print(f"mixed: relres {im['relres'].tolist()}, applications {im['n_apply_fp64']}+{im['n_apply_mixed']}", flush=True)
     assert im["converged"] and max(im["relres"]) <= 1e-8
+    # the relaxed cycle closes on its basis residual (bounded by the mixed steps): the returned x's
+    # FP64 residual meets tol and equals the reported one
+    rtm = np.linalg.norm((bt - op.apply(um)).cpu().numpy(), axis=1) / np.linalg.norm(b, axis=1)
+    print(f"mixed: FP64 residual of the returned x {rtm.tolist()}", flush=True)
+    assert rtm.max() <= 1e-8 and np.abs(rtm - im["relres"]).max() <= 1e-9
     # mixed-precision refinement passes: FP32 tiles in every Arnoldi step, one FP64 residual per pass
     up, ip = op.solve_precond(bt, tol=1e-8, maxit=300, precision="mixed", scheme="passes")
     ep = relmax(up.cpu().numpy(), u_ref)
