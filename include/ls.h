@@ -332,10 +332,10 @@ typedef ls_status (*ls_grid_op)(const double *c, double *sc, int32_t nrhs, int64
  * With o->prec = LS_MIXED the operator applications switch to the mixed precision once the
  * residual allows it, as in relaxed GMRES (o->inner_tol is the granted accuracy, default 1e-4),
  * followed by FP64 refinement; o->inner_maxit is ignored.  The relaxed cycle closes on its
- * Arnoldi-basis residual when that is within tol including the bound 1e-5 sum_j |y_j|
- * (||h_j|| + ||z_j||) over its mixed steps (y the cycle's coefficients, h_j the Hessenberg column,
- * z_j = P v_j), the difference such steps can make to the FP64 residual; otherwise it takes the
- * FP64 residual.  Everything else is as for ls_solve_gmres. */
+ * Arnoldi-basis residual when that is within tol including the bound
+ * 1e-5 (||L_mixed dm|| + ||dm||), dm = sum over its mixed steps of y_j z_j (y the cycle's
+ * coefficients, z_j = P v_j), the most such steps can change the FP64 residual; otherwise it takes
+ * the FP64 residual.  Everything else is as for ls_solve_gmres. */
 ls_status ls_solve_gmres_precond(ls_handle h, const double *b, double *x, int32_t nrhs, int64_t ld,
                                  const ls_solve_opts *o, int32_t s, ls_grid_op S, void *user, double *c, double *sc,
                                  int64_t ldc, ls_solve_info *info, hipStream_t stream);

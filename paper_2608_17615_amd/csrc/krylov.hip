@@ -469,9 +469,9 @@ struct CoreOpts {
 // succeed (kCloseEps ||r|| <= tol ||b|| / 2), so it is not tried on the first pass from x = 0.
 // A relaxed cycle (FP64 applications first, mixed ones once the residual allows) has
 // r - sum_j y_j L_j z_j = V Q^H g_m e_m with L_j the operator of step j, so its basis residual
-// differs from the FP64 one by sum over the mixed steps of y_j (L_mixed - L) z_j, at most
-// kCloseEps sum_j |y_j| (||h_j|| + ||z_j||) (||L_mixed z_j|| = ||h_j||, the unrotated Hessenberg
-// column, V being orthonormal).
+// differs from the FP64 one by (L_mixed - L) dm, dm = sum over the mixed steps of y_j z_j, at most
+// kCloseEps (||L_mixed dm|| + ||dm||) with L_mixed dm = V sum_{j mixed} y_j h_j (h_j the unrotated
+// Hessenberg column).
 constexpr double kCloseEps = 1e-5;
 
 struct CoreResult {
@@ -630,7 +630,6 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
     g.assign((size_t)nsys * (m + 1), cplx(0));
     std::vector<int> mc(nsys, 0);
     std::vector<char> step_mixed(m, 0);   // step j applied the mixed operator (relaxed closing)
-    std::vector<double> hcol(o.close_relaxed ? (size_t)nsys * m : 0, 0.0);   // ||h_j|| before rotation
     const std::vector<int> part_in(act);   // systems that take part in this cycle
     for (int q = 0; q < nsys; ++q) g[(size_t)q * (m + 1)] = rnorm[q];
     int j = 0;
@@ -793,11 +792,6 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
         }
         Hat(j + 1, j) = betah[q];
         if (!std::isfinite(betah[q])) return setup_fail(h, LS_ERR_BREAKDOWN, "non-finite Arnoldi vector");
-        if (o.close_relaxed) {
-          double s2 = betah[q] * betah[q];
-          for (int i = 0; i < nv; ++i) s2 += std::norm(Hat(i, j));
-          hcol[(size_t)q * m + j] = std::sqrt(s2);
-        }
         cplx *csc = &cs[(size_t)q * m], *snc = &sn[(size_t)q * m], *gc = &g[(size_t)q * (m + 1)];
         for (int i = 0; i < j; ++i) {
           const cplx tq = csc[i] * Hat(i, j) + snc[i] * Hat(i + 1, j);
@@ -917,16 +911,51 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
         HIPTRY(norms_of(t, dn));
         for (int q = 0; q < nsys; ++q) extra[q] = rnorm[q] + rn[q] + dn[q];
       } else {
-        // sum over the mixed steps of |y_j| (||h_j|| + ||z_j||)
-        std::vector<double> zn(nsys);
-        for (int jj = 0; jj < mmax; ++jj) {
-          if (!step_mixed[jj]) continue;
-          HIPTRY(norms_of(ws->Z.vec(jj, n, nrhs), zn));
-          for (int q = 0; q < nsys; ++q)
-            if (part_in[q] && jj < mc[q]) {
-              const double2 yq = yv[(size_t)q * m + jj];
-              extra[q] += std::hypot(yq.x, yq.y) * (hcol[(size_t)q * m + jj] + zn[q]);
+        // the mixed steps' part of the correction, dm = sum_{j mixed} y_j z_j, and L_mixed dm =
+        // V sum_{j mixed} y_j h_j, h_j the unrotated Hessenberg column (rebuilt from the stored,
+        // rotated one by the inverse rotations G_j^H .. G_0^H): (L - L_mixed) dm, the difference
+        // between the basis residual and the FP64 one, is at most kCloseEps (||L_mixed dm|| + ||dm||)
+        std::vector<double2> cv((size_t)nsys * (m + 1), make_double2(0, 0));
+        std::vector<double2> ym((size_t)nsys * m, make_double2(0, 0));
+        bool any_mixed = false;
+        for (int q = 0; q < nsys; ++q) {
+          if (!part_in[q]) continue;
+          const int mm = mc[q];
+          const cplx *Hc = H[q].data();
+          const cplx *csc = &cs[(size_t)q * m], *snc = &sn[(size_t)q * m];
+          std::vector<cplx> col(mm + 1), acc(mm + 1, cplx(0));
+          for (int jj = 0; jj < mm; ++jj) {
+            if (!step_mixed[jj]) continue;
+            any_mixed = true;
+            std::fill(col.begin(), col.end(), cplx(0));
+            for (int i = 0; i <= jj; ++i) col[i] = Hc[(size_t)jj * (jj + 3) / 2 + i];
+            for (int i = jj; i >= 0; --i) {
+              const cplx a = col[i], b = col[i + 1];
+              col[i] = std::conj(csc[i]) * a - snc[i] * b;
+              col[i + 1] = std::conj(snc[i]) * a + csc[i] * b;
             }
+            const double2 y2 = yv[(size_t)q * m + jj];
+            const cplx yj(y2.x, y2.y);
+            for (int i = 0; i <= jj + 1; ++i) acc[i] += yj * col[i];
+            ym[(size_t)q * m + jj] = y2;
+          }
+          for (int i = 0; i <= mm; ++i) cv[(size_t)q * (m + 1) + i] = make_double2(acc[i].real(), acc[i].imag());
+        }
+        if (any_mixed) {
+          HIPTRY(hipMemcpyAsync(G.hbuf, cv.data(), sizeof(double2) * cv.size(), hipMemcpyHostToDevice, st));
+          HIPTRY(hipMemcpyAsync(G.ybuf, ym.data(), sizeof(double2) * ym.size(), hipMemcpyHostToDevice, st));
+          HIPTRY(hipMemsetAsync(d, 0, vb, st));
+          HIPTRY(hipMemsetAsync(t, 0, vb, st));
+          update_kernel<<<gt, kBlock, 0, st>>>(mmax + 1, nseg, G.tiles, G.active, G.ptrs, n, G.hbuf, m + 1, 1.0, d,
+                                               n);
+          update_kernel<<<gt, kBlock, 0, st>>>(mmax, nseg, G.tiles, G.active, G.ptrs + G.max_vec + 4, n, G.ybuf, m,
+                                               1.0, t, n);
+          HIPTRY(hipGetLastError());
+          HIPTRY(hipStreamSynchronize(st));   // cv and ym go out of scope
+          std::vector<double> ln(nsys), dn(nsys);
+          HIPTRY(norms_of(d, ln));
+          HIPTRY(norms_of(t, dn));
+          for (int q = 0; q < nsys; ++q) extra[q] = ln[q] + dn[q];
         }
       }
       bool all_closed = true;
