@@ -5,8 +5,9 @@ Default workload (c3): the unit disk with n = 2, k = 40, O-grid mesh with 35 cel
 the central square (N = 122 500 nodes), 64 plane waves at evenly spaced angles as one right-hand
 side block.  Form pcm: flexible GMRES (no restart within a pass, x0 = 0), right-preconditioned by
 the paper's P = I + T_C^Q (S - I) T_Q^C with the library's sparsifying S^(C) on a grid of
-k h = 0.3 (273 x 273 nodes), in mixed-precision refinement passes: every Arnoldi application uses the FP32
-matrix-core Green's tiles (FP64 correction, Arnoldi and residuals), and each pass starts from the
+k h = 0.3, raised to 1.5 mean node spacings (k h = 0.304, 270 x 270 nodes), in mixed-precision
+refinement passes: every Arnoldi application uses the split-FP16 matrix-core Green's tiles (FP64
+for the pairs with k r < 1, the correction, Arnoldi and residuals), and each pass starts from the
 FP64 residual, until that meets the tolerance.  One step =
 one solve of all 64 waves to a relative residual of 1e-8 in every column; every operator
 application is the far-field Green's sum over all N(N-1) node pairs plus the sparse correction.
@@ -26,7 +27,8 @@ Other workloads (--workload, one JSON line each):
       points of a Cartesian grid over the enclosing square.
 Forms: p64 = FP64 VALU kernel, one right-hand side at a time (columns beyond --cols are
 extrapolated from the timed ones, and the line says so); b64 = all right-hand sides together on
-FP64 matrix-core tiles; bm = all together, FP32 matrix-core tiles inside FP64 GMRES (relaxed);
+FP64 matrix-core tiles; bm = all together, mixed-precision matrix-core tiles inside FP64 GMRES
+(relaxed; split-FP16 tiles for a single scatterer's 64-column groups, FP32 tiles otherwise);
 pc / pcm = b64 / bm with the library's sparsifying preconditioner.
 
 Reported: Green interactions per second over the timed work (value), the time to a 1e-8
@@ -362,7 +364,7 @@ def setup_precond(op, probs, kh):
 
     from workloads import problems as P
     t0 = time.perf_counter()
-    nodes, lu_res, sv, skipped = 0, 0.0, [], []
+    nodes, lu_res, sv, skipped, grids, khs = 0, 0.0, [], [], [], []
     for s, p in enumerate(probs):
         if p.m_at is None:
             raise SystemExit("the preconditioned forms need the contrast off the nodes")
@@ -371,13 +373,17 @@ def setup_precond(op, probs, kh):
             continue
         # at least MIN_CELL node spacings per grid cell, so that T_Q^C sees nodes in most cells
         spacing = float(np.sqrt(p.mesh.w.sum() / p.n_nodes))
-        g = P.cartesian_grid(p, max(kh, MIN_CELL * spacing * p.k))
+        kh_s = max(kh, MIN_CELL * spacing * p.k)
+        g = P.cartesian_grid(p, kh_s)
         info = op.sparsify_setup(*g, P.grid_contrast(p, g), s=s)
         nodes += g[3] * g[4]
+        grids.append([g[3], g[4]])
+        khs.append(round(kh_s, 4))
         lu_res = max(lu_res, info["lu_residual"])
         sv.append(info["sv_ratio"])
     torch.cuda.synchronize()
     out = {"S": "sparsifying (C^(C))^-1 A, first-order V^(C), block LU by grid rows (library)", "k_h": kh,
+           "k_h_used": khs, "grids": grids,
            "grid_nodes": nodes, "build_s": time.perf_counter() - t0, "lu_residual_max": lu_res,
            "stencil_sv_ratio_min": min(sv), "unpreconditioned_scatterers": skipped,
            "max_resolution": MAX_RESOLUTION, "min_cell_node_spacings": MIN_CELL}

@@ -182,9 +182,10 @@ def _apply9(E, z, nx, ny):
 
 
 def test_full_size_grid_sweeps_invert_c_and_adjoint_identity():
-    """The grid of the unit disk at k = 40 and k h = 0.3 (273 x 273 nodes) with 64 vectors, the
-    launch the benchmark's preconditioned solve makes: C^(C) (S c) = A c through the stencils the
-    library builds (a property of the block LU at any size), and <S c, d> = <c, S^H d>."""
+    """The grid of a unit disk at k = 40 and k h = 0.3 (271 x 271 nodes; the benchmark's is
+    270 x 270) with 64 vectors, the launch the benchmark's preconditioned solve makes:
+    C^(C) (S c) = A c through the stencils the library builds (a property of the block LU at any
+    size), and <S c, d> = <c, S^H d>."""
     p = P.disk_problem(4, 40.0, 2.0)
     op = _op(p)
     g = P.cartesian_grid(p, 0.3)
