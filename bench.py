@@ -37,7 +37,7 @@ HIP events the library records around each launch on the caller's stream), and t
 own throughput on a bounded sample of the same far sum on the host cores.
 
 Usage: python bench.py [--workload c3] [--form pcm] [--steps K] [--warmup W] [--gpus 1]
-                       [--no-cpu-baseline] [--no-compare]
+                       [--no-cpu-baseline] [--no-compare] [--check-orth]
 """
 import argparse
 import json
@@ -280,7 +280,8 @@ def run_plain(args, prob, label):
            "flops_per_pair": fpp, "z_range_fractions": frac,
            "hankel_evaluations_per_ordered_pair": evals / pairs,
            "executed_flops_per_launch": executed,
-           "effective_tflops_ordered_pair_count": fpp * pairs / t.far_avg_s / 1e12}
+           "effective_tflops_ordered_pair_count": fpp * pairs / t.far_avg_s / 1e12,
+           **orth_check(op, b, "p64", args)}
     roof = {"bound": "alu", "achieved": executed / t.far_avg_s / 1e12, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": executed / t.far_avg_s / 1e12 / PEAK_FP64_TFLOPS,
             "traffic": far_traffic() if args.workload == "c2" else None}
@@ -421,6 +422,29 @@ def tiles_roofline(prof, nrhs, meshes_k):
     return kind, roof, kern, ms
 
 
+def orth_check(op, b, form, args):
+    """--check-orth (untimed): column 0 solved again by the timed form with the loss of
+    orthogonality of its Krylov basis measured, max |<v_i, v_j> - delta_ij| over the normalized
+    basis vectors (each scatterer's own basis)."""
+    import numpy as np
+    if not args.check_orth:
+        return {}
+    kw = dict(tol=args.tol, maxit=args.maxit, restart=args.restart, check_orth=True)
+    if form in ("pc", "pcm"):
+        _, info = op.solve_precond(b[:1], None, precision="mixed" if form == "pcm" else "fp64",
+                                   inner_tol=args.relax, scheme=args.scheme, **kw)
+    elif form in ("b64", "bm"):
+        _, info = op.solve(b[:1], precision="mixed" if form == "bm" else "fp64",
+                           inner_maxit=args.inner if form == "bm" else 0,
+                           inner_tol=args.relax if form == "bm" else 0.0,
+                           scheme=args.scheme if form == "bm" else "relaxed", **kw)
+    else:
+        _, info = op.solve(b[:1], **kw)
+    it = int(np.max(info["iters"]))
+    log(f"  orthogonality check (column 0): {it} steps, loss {info['orth_loss']:.2e}")
+    return {"orth_loss": float(info["orth_loss"]), "orth_check_steps": it}
+
+
 def reference_column(op, b, args, precond):
     """Untimed reference: one column solved alone (the FP64 VALU kernel, one right-hand side at a
     time), with or without the library's preconditioner; returns (seconds, iterations, GI/s)."""
@@ -530,7 +554,7 @@ def run_batched(args, probs, label, B):
            "applies_fp64": a64, "applies_mixed": amx, "final_fp64_relres_max": float(relres.max()),
            "setup_s": setup_s, "dominant_kernel": kern, "z_range_fractions": frac,
            "autotune": tune, "error_vs_fp64_column0": check, "preconditioner": pre, "compare": compare,
-           "per_scatterer": per_scat}
+           "per_scatterer": per_scat, **orth_check(op, b, form, args)}
     return line(value, step_s * 1e3, steps, warm, dtype, cfg, roof, None), x
 
 
@@ -669,6 +693,9 @@ def main():
     ap.add_argument("--no-compare", dest="compare", action="store_false",
                     help="c3: skip the untimed one-column P64 reference solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--check-orth", action="store_true",
+                    help="after the timed steps, solve column 0 again with the Krylov basis's loss of "
+                         "orthogonality measured (orth_loss in the line's config)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); a multi-GPU layout (target rows, or "

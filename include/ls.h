@@ -164,7 +164,9 @@ typedef struct {
   double inner_tol;    /* LS_MIXED: inner tolerance (flexible), granted operator accuracy (relaxed) or
                         * residual reduction per pass (mixed_scheme 1) */
   int32_t mixed_scheme;/* LS_MIXED: 0 = relaxed or flexible as below, 1 = refinement passes */
-  int32_t pad_;
+  int32_t check_orth;  /* nonzero: measure the Arnoldi basis's loss of orthogonality (one more pass of
+                        * inner products per step over the basis, about the cost of the
+                        * Gram-Schmidt pass itself), reported in ls_solve_info.orth_loss */
   /* LS_MIXED solves keep the Krylov basis, orthogonalisation and residuals in FP64.
    *   inner_maxit > 0: flexible GMRES; each outer direction is preconditioned by up to
    *                    inner_maxit steps of GMRES with the mixed operator (to inner_tol,
@@ -201,6 +203,9 @@ typedef struct {
   int64_t n_apply_mixed;
   double seconds;
   int64_t n_reorth;     /* Arnoldi steps (summed over systems) that needed a second Gram-Schmidt pass */
+  double orth_loss;     /* with check_orth: the largest |<v_i, v_j> - delta_ij| over the normalized
+                         * basis vectors of the outer iteration (each system's own basis, every
+                         * cycle), measured as each v_j is formed; 0 otherwise */
 } ls_solve_info;
 
 /* Solve L x = b (or L^H x = b) by GMRES without restart, x0 = 0 unless x0_given, each column

@@ -69,12 +69,13 @@ class _SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("adjoint", ctypes.c_int32), ("x0_given", ctypes.c_int32),
                 ("inner_maxit", ctypes.c_int32), ("inner_tol", ctypes.c_double),
-                ("mixed_scheme", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("mixed_scheme", ctypes.c_int32), ("check_orth", ctypes.c_int32)]
 
 
 class _SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_void_p), ("relres", ctypes.c_void_p), ("n_apply_fp64", ctypes.c_int64),
-                ("n_apply_mixed", ctypes.c_int64), ("seconds", ctypes.c_double), ("n_reorth", ctypes.c_int64)]
+                ("n_apply_mixed", ctypes.c_int64), ("seconds", ctypes.c_double), ("n_reorth", ctypes.c_int64),
+                ("orth_loss", ctypes.c_double)]
 
 
 def lib():
@@ -285,10 +286,11 @@ class Operator:
         return self.apply(x, precision, adjoint=True, out=out)
 
     def solve(self, b, tol=1e-8, maxit=1000, precision="fp64", adjoint=False, x0=None, inner_tol=0.0,
-              inner_maxit=0, restart=0, scheme="relaxed"):
+              inner_maxit=0, restart=0, scheme="relaxed", check_orth=False):
         """Solve L x = b (or L^H x = b) by GMRES (restart = 0: none); returns (x, info dict).
         precision="mixed": scheme "relaxed" (or flexible with inner_maxit > 0) or "passes"
-        (mixed-precision refinement passes), see ls_solve_opts."""
+        (mixed-precision refinement passes), see ls_solve_opts.  check_orth: also measure the
+        Krylov basis's loss of orthogonality (info["orth_loss"])."""
         import torch
         b2 = self._cols(b)
         if x0 is not None:
@@ -299,13 +301,14 @@ class Operator:
         iters = np.zeros(B, dtype=np.int32)
         relres = np.zeros(B, dtype=np.float64)
         o = _SolveOpts(float(tol), int(maxit), int(restart), _PREC[precision], int(bool(adjoint)), int(x0 is not None),
-                       int(inner_maxit), float(inner_tol), _SCHEME[scheme], 0)
-        info = _SolveInfo(iters.ctypes.data, relres.ctypes.data, 0, 0, 0.0, 0)
+                       int(inner_maxit), float(inner_tol), _SCHEME[scheme], int(bool(check_orth)))
+        info = _SolveInfo(iters.ctypes.data, relres.ctypes.data, 0, 0, 0.0, 0, 0.0)
         st = _check(lib().ls_solve_gmres(self._h, b2.data_ptr(), x.data_ptr(), B, self.n, ctypes.byref(o),
                                          ctypes.byref(info), _stream()), self._h)
         return x.reshape(b.shape), {"converged": st == LS_OK, "iters": iters, "relres": relres,
                                     "n_apply_fp64": info.n_apply_fp64, "n_apply_mixed": info.n_apply_mixed,
-                                    "seconds": info.seconds, "n_reorth": info.n_reorth}
+                                    "seconds": info.seconds, "n_reorth": info.n_reorth,
+                                    "orth_loss": info.orth_loss}
 
     def grad_contrast(self, u, lam, a):
         import torch
@@ -447,11 +450,12 @@ class Operator:
         return out
 
     def solve_precond(self, b, S=None, s=0, tol=1e-8, maxit=1000, restart=0, adjoint=False, precision="fp64",
-                      inner_tol=0.0, scheme="relaxed"):
+                      inner_tol=0.0, scheme="relaxed", check_orth=False):
         """GMRES preconditioned on the right by P = I + T_C^Q (S - I) T_Q^C.  S=None: the library's
         sparsifying S^(C) on every scatterer that has one (sparsify_setup; s is ignored).  Otherwise S
         is a callable on (B, nx ny) CUDA tensors for scatterer s (set_grid first).  precision="mixed"
-        relaxes the operator applications to the FP32 tiles late in the iteration.  Returns (x, info)."""
+        relaxes the operator applications to the mixed-precision tiles late in the iteration (or runs
+        refinement passes, scheme="passes").  check_orth as in solve.  Returns (x, info)."""
         import torch
         b2 = self._cols(b)
         B = b2.shape[0]
@@ -460,14 +464,15 @@ class Operator:
             iters = np.zeros(B, dtype=np.int32)
             relres = np.zeros(B, dtype=np.float64)
             o = _SolveOpts(float(tol), int(maxit), int(restart), _PREC[precision], int(bool(adjoint)), 0, 0,
-                           float(inner_tol), _SCHEME[scheme], 0)
-            info = _SolveInfo(iters.ctypes.data, relres.ctypes.data, 0, 0, 0.0, 0)
+                           float(inner_tol), _SCHEME[scheme], int(bool(check_orth)))
+            info = _SolveInfo(iters.ctypes.data, relres.ctypes.data, 0, 0, 0.0, 0, 0.0)
             st = _check(lib().ls_solve_gmres_precond(self._h, b2.data_ptr(), x.data_ptr(), B, self.n, ctypes.byref(o),
                                                      -1, _GridOp(), None, None, None, 0, ctypes.byref(info),
                                                      _stream()), self._h)
             return x.reshape(b.shape), {"converged": st == LS_OK, "iters": iters, "relres": relres,
                                         "n_apply_fp64": info.n_apply_fp64, "n_apply_mixed": info.n_apply_mixed,
-                                        "seconds": info.seconds, "n_reorth": info.n_reorth}
+                                        "seconds": info.seconds, "n_reorth": info.n_reorth,
+                                        "orth_loss": info.orth_loss}
         nc = self._grid_n(s)
         c = torch.empty((B, nc), dtype=torch.complex128, device=b2.device)
         sc = torch.empty_like(c)
@@ -489,8 +494,8 @@ class Operator:
         iters = np.zeros(B, dtype=np.int32)
         relres = np.zeros(B, dtype=np.float64)
         o = _SolveOpts(float(tol), int(maxit), int(restart), _PREC[precision], int(bool(adjoint)), 0, 0,
-                       float(inner_tol), _SCHEME[scheme], 0)
-        info = _SolveInfo(iters.ctypes.data, relres.ctypes.data, 0, 0, 0.0, 0)
+                       float(inner_tol), _SCHEME[scheme], int(bool(check_orth)))
+        info = _SolveInfo(iters.ctypes.data, relres.ctypes.data, 0, 0, 0.0, 0, 0.0)
         st = lib().ls_solve_gmres_precond(self._h, b2.data_ptr(), x.data_ptr(), B, self.n, ctypes.byref(o), s, fn,
                                           None, c.data_ptr(), sc.data_ptr(), nc, ctypes.byref(info), _stream())
         if failed:
@@ -498,7 +503,7 @@ class Operator:
         _check(st, self._h)
         return x.reshape(b.shape), {"converged": st == LS_OK, "iters": iters, "relres": relres,
                                     "n_apply_fp64": info.n_apply_fp64, "n_apply_mixed": info.n_apply_mixed,
-                                    "seconds": info.seconds}
+                                    "seconds": info.seconds, "n_reorth": info.n_reorth, "orth_loss": info.orth_loss}
 
     def farfield_adjoint(self, res, thetas, s=0):
         """(a, rhs) with a = A^H res and rhs = conj(m) a on scatterer s (zero elsewhere)."""

@@ -457,6 +457,7 @@ struct CoreOpts {
   bool close_relaxed = false;      // a relaxed flexible cycle (z_j = P v_j kept) closes on its
                                    // basis residual when the mixed steps' bound allows it
   double close_tol = 0.0;          // the caller's tolerance for these closing checks
+  bool check_orth = false;         // measure each new basis vector's loss of orthogonality
 };
 
 // The closing check of a refinement cycle by the residual update r_new = r - L_mixed dx, with r
@@ -486,6 +487,7 @@ struct CoreResult {
   bool closed = false;
   int64_t n_fp64 = 0, n_mixed = 0;
   int64_t n_reorth = 0;     // system-steps that took a second Gram-Schmidt pass
+  double orth_loss = 0.0;   // CoreOpts::check_orth: max |<v_i, v_j> - delta_ij| of the outer basis
 };
 
 // GMRES on contiguous (ld = n) device vectors b, x of nrhs columns, one independent system per
@@ -572,6 +574,7 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
   std::vector<double2> hh((size_t)nsys * (cyc + 2) * 2);
   std::vector<int> rflag(nsys, 0);
   std::vector<double> betah(nsys), rnorm(nsys);
+  std::vector<double2> oc;   // check_orth: the new basis vector's inner products, per system
   const dim3 gv(blocks_of(n), nrhs);
   const dim3 gt = G.tile_grid();
   while (total_it < maxit) {
@@ -776,8 +779,23 @@ ls_status gmres_core(ls_ctx *h, SolveWs *ws, SolveWs *ws_inner, const double2 *b
                             hipMemcpyDeviceToHost, st));
       HIPTRY(hipMemcpyAsync(betah.data(), G.beta, sizeof(double) * nsys, hipMemcpyDeviceToHost, st));
       HIPTRY(hipMemcpyAsync(rflag.data(), G.reorth, sizeof(int) * nsys, hipMemcpyDeviceToHost, st));
+      if (o.check_orth) {
+        // <v_i, v_{j+1}> for i <= j and ||v_{j+1}||^2 of the normalized new vector: one more pass of
+        // inner products (into h2, whose copy to the host is already enqueued before it)
+        oc.resize((size_t)nsys * (nv + 1));
+        HIPTRY(G.dots(nv + 1, w, h2, nv + 1));
+        HIPTRY(hipMemcpyAsync(oc.data(), h2, sizeof(double2) * oc.size(), hipMemcpyDeviceToHost, st));
+      }
       HIPTRY(hipStreamSynchronize(st));
       for (int q = 0; q < nsys; ++q) res.n_reorth += rflag[q];
+      if (o.check_orth)
+        for (int q = 0; q < nsys; ++q) {
+          if (!act[q] || !(betah[q] > 0.0)) continue;   // no new vector for this system
+          const double2 *c = &oc[(size_t)q * (nv + 1)];
+          double l = std::hypot(c[nv].x - 1.0, c[nv].y);
+          for (int i = 0; i < nv; ++i) l = std::max(l, std::hypot(c[i].x, c[i].y));
+          res.orth_loss = std::max(res.orth_loss, l);
+        }
       bool any = false, changed = false;
       double worst = 0.0;
       for (int q = 0; q < nsys; ++q) {
@@ -1022,6 +1040,7 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
   CoreOpts co{relax > 0 ? 0.3 * o.tol : o.tol, o.maxit, o.restart, mode, LS_FP64, flexible,
               o.inner_tol > 0 ? o.inner_tol : 1e-12, o.inner_maxit, o.x0_given != 0, relax, progress, pc};
   co.close_tol = o.tol;
+  co.check_orth = o.check_orth != 0;
   // a preconditioned relaxed solve keeps its z_j, so it can close on its basis residual
   co.close_relaxed = relax > 0 && pc != nullptr;
   // LS_MIXED with mixed_scheme = 1: refinement passes, each a GMRES cycle from the FP64 residual
@@ -1064,6 +1083,7 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
     res.n_fp64 += rr.n_fp64;
     res.n_mixed += rr.n_mixed;
     res.n_reorth += rr.n_reorth;
+    res.orth_loss = std::max(res.orth_loss, rr.orth_loss);
     have_final = rr.start_done || rr.closed;
     rn_final = rr.rn0;
     bn_final = rr.bn0;
@@ -1090,6 +1110,7 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
     res.n_fp64 += rr.n_fp64;
     res.n_mixed += rr.n_mixed;
     res.n_reorth += rr.n_reorth;
+    res.orth_loss = std::max(res.orth_loss, rr.orth_loss);
     have_final = rr.start_done;
     rn_final = rr.rn0;
     bn_final = rr.bn0;
@@ -1151,6 +1172,7 @@ ls_status solve_gmres(ls_ctx *h, const double *b_in, double *x_out, int nrhs, in
     info->n_apply_mixed = res.n_mixed * nrhs;
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     info->n_reorth = res.n_reorth;
+    info->orth_loss = res.orth_loss;
   }
   return status;
 #undef HIPTRY

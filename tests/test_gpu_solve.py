@@ -36,6 +36,26 @@ def test_gmres_matches_dense_lu(name, tol, rbound, ebound):
     assert e <= ebound
 
 
+def test_orthogonality_check_is_transparent_and_bounded():
+    """check_orth measures max |<v_i, v_j> - delta_ij| over the Krylov basis without touching the
+    iteration: solution and step counts equal those of the unchecked solve bit for bit; the tol
+    1e-12 solve, whose first steps are the tol 1e-6 solve's, reports at least that solve's loss;
+    and while the residual is far above the rounding level the basis stays orthogonal (GMRES's
+    basis loses orthogonality roughly as eps times the condition number over the relative
+    residual, i.e. only as the residual nears the rounding level)."""
+    p, c, op = _golden_op("twomat1040")
+    b = torch.tensor(c["b"], device="cuda")
+    x0, i0 = op.solve(b, tol=1e-12, maxit=800)
+    x1, i1 = op.solve(b, tol=1e-12, maxit=800, check_orth=True)
+    _, i2 = op.solve(b, tol=1e-6, maxit=800, check_orth=True)
+    print(f"steps {i1['iters'].tolist()} / {i2['iters'].tolist()}: loss {i1['orth_loss']:.2e} at 1e-12, "
+          f"{i2['orth_loss']:.2e} at 1e-6", flush=True)
+    assert i0["orth_loss"] == 0.0
+    assert torch.equal(x0, x1) and np.array_equal(i0["iters"], i1["iters"])
+    assert 0.0 < i2["orth_loss"] <= i1["orth_loss"]
+    assert i2["orth_loss"] <= 1e-7
+
+
 def test_restart_and_initial_guess():
     p, c, op = _golden_op("disk2500")
     b = torch.tensor(c["b"], device="cuda")

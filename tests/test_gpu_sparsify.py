@@ -62,6 +62,15 @@ def test_preconditioned_solve_reaches_lu_and_cuts_steps():
           f"preconditioned 1e-13 solve vs LU {e:.2e}", flush=True)
     assert info["converged"] and e <= 1e-10
     assert max(pre8["iters"]) * 3 <= min(plain["iters"])
+    # the orthogonality check leaves the flexible iteration as it is.  The basis loses
+    # orthogonality as the residual nears the rounding level (the 1e-13 solve), not at the
+    # workloads' 1e-8, whose steps are the first steps of the 1e-13 solve
+    uo, io = op.solve_precond(bt, tol=1e-13, maxit=300, check_orth=True)
+    _, io8 = op.solve_precond(bt, tol=1e-8, maxit=300, check_orth=True)
+    print(f"preconditioned basis: loss of orthogonality {io8['orth_loss']:.2e} at 1e-8, "
+          f"{io['orth_loss']:.2e} at 1e-13", flush=True)
+    assert torch.equal(u, uo) and info["orth_loss"] == 0.0
+    assert 0.0 < io8["orth_loss"] <= io["orth_loss"] and io8["orth_loss"] <= 1e-5
     # the adjoint system with P^H = I + T_C^Q (D^-1 S^H D - I) T_Q^C
     ua, ia = op.solve_precond(bt, tol=1e-13, maxit=300, adjoint=True)
     ea = relmax(ua.cpu().numpy(), krylov.lu_solve(oop.dense().conj().T, b))
