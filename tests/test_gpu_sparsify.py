@@ -110,7 +110,8 @@ def test_passes_close_on_the_residual_update_at_full_size():
     split-FP16 refinement passes): one FP64 application (the second pass's starting residual), the
     closing check by the residual update, and every returned column's FP64 residual below 1e-8 and
     within a tenth of the tolerance of the reported one (measured 4.9e-11: the split-FP16 far sum's
-    error on the last pass's correction)."""
+    error on the last pass's correction).  Then column 0 to 1e-12 in FP64 and in mixed passes: the
+    two solutions agree to 1e-8."""
     p = P.config3()
     op = _op(p)
     g = P.cartesian_grid(p, 0.3)
@@ -125,6 +126,16 @@ def test_passes_close_on_the_residual_update_at_full_size():
     assert rt.max() <= 1e-8
     assert np.abs(rt - info["relres"]).max() <= 1e-9
     assert info["n_apply_fp64"] == 64
+    # column 0 solved to 1e-12 by the FP64 preconditioned solve and by mixed refinement passes
+    # (FP32 tiles for one column): the mixed tiles limit the solution only through the tolerance
+    x64, i64 = op.solve_precond(b[:1], None, tol=1e-12, maxit=200)
+    xm, im = op.solve_precond(b[:1], None, tol=1e-12, maxit=200, precision="mixed", scheme="passes")
+    d = relmax(xm.cpu().numpy(), x64.cpu().numpy())
+    print(f"column 0 to 1e-12: FP64 {int(i64['iters'][0])} steps, mixed passes {int(im['iters'][0])} steps "
+          f"({im['n_apply_fp64']}+{im['n_apply_mixed']} applications), solutions differ by {d:.2e}", flush=True)
+    assert i64["converged"] and im["converged"] and max(im["relres"]) <= 1e-12
+    assert im["n_apply_mixed"] > 2 * im["n_apply_fp64"]
+    assert d <= 1e-8
 
 
 @pytest.mark.parametrize("adjoint", [False, True])
