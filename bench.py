@@ -79,18 +79,18 @@ PEAK_FP32_MFMA_TFLOPS = 157.3
 # 58 500), from two rocprofv3 counter passes (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors that
 # make a 1 GiB copy read 1 GiB and write 1 GiB; profiles/far_fp64_sym_two_material_N58500_counters.md),
 # valid for the kernel sources with this digest only: after any change to them the field is null.
-FAR_TRAFFIC_BYTES = 71_467_000 + 214_344_000
+FAR_TRAFFIC_BYTES = 73_242_000 + 214_344_000
 FAR_TRAFFIC_SOURCES = ("apply.hip", "hankel.h", "hankel_tables.h")
-FAR_TRAFFIC_DIGEST = "4222d59bc846cd48"
+FAR_TRAFFIC_DIGEST = "b8817d7cdd27a686"
 
 
 # The same for the split-FP16 tile kernel at the default workload (unit disk, N = 122 500, 64
 # plane waves): FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 per launch, averaged over the 17 launches of one
 # solve (profiles/far_tile_h_disk_N122500_B64_counters.md); most of it is the 34 source splits'
-# partial sums (34 x 64 x 122 500 x 16 B written, read back by the epilogue).
-H16_TRAFFIC_BYTES = 1_926_313_000 + 4_435_587_000
+# FP32 partial sums (34 x 64 x 122 500 x 8 B written, read back by the epilogue).
+H16_TRAFFIC_BYTES = 1_339_250_000 + 2_191_376_000
 H16_TRAFFIC_SOURCES = ("mfma.hip", "hankel.h", "hankel_tables.h")
-H16_TRAFFIC_DIGEST = "ff1e9b84cfb2f9b6"
+H16_TRAFFIC_DIGEST = "8ea75eff935bb254"
 
 
 def _digest(files):

@@ -539,7 +539,7 @@ ApplyPlan apply_plan(const ls_ctx *h, int nrhs, ls_precision p) {
       const int nsplit = plan_splits(h, pl, sc, nrhs);
       // the mixed tiles' partial sums have one more split for the FP64 near launch
       const int near = (pl.single && sc.near_ok) ? 1 : 0;
-      pl.need = std::max(pl.need, pl.h16     ? lsk::tile_h_workspace_bytes(sc.n, nrhs, nsplit + near)
+      pl.need = std::max(pl.need, pl.h16     ? lsk::tile_h_workspace_bytes(sc.n, nrhs, nsplit)
                                   : pl.tiles ? lsk::tile_workspace_bytes(sc.n, nrhs, nsplit + near)
                                              : lsk::apply_workspace_bytes(sc.n, nrhs, nsplit));
     }

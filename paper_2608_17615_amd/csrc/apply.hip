@@ -243,9 +243,12 @@ __global__ __launch_bounds__(kBlock) void far_fp64_sym_kernel(int n, int nb, con
   }
 }
 
-template <Mode M>
+// H: the partials are the split-FP16 tiles' FP32 sums (parth, [split][rhs][n]) times the column
+// scale colinv[b], then the near launch's FP64 partial (part, [rhs][n], when given)
+template <Mode M, bool H>
 __global__ __launch_bounds__(kBlock) void epilogue_kernel(
-    int64_t n, int nrhs, int nsplit, const double2 *__restrict__ part, const double2 *__restrict__ f,
+    int64_t n, int nrhs, int nsplit, const double2 *__restrict__ part, const float2 *__restrict__ parth,
+    const double *__restrict__ colinv, const double2 *__restrict__ f,
     const int64_t *__restrict__ rp, const int32_t *__restrict__ ci, const double2 *__restrict__ cv,
     const double *__restrict__ w, const double2 *__restrict__ m, const int32_t *__restrict__ perm,
     const double2 *__restrict__ x, double2 *__restrict__ y, int64_t ld, int64_t off, double k2) {
@@ -255,11 +258,29 @@ __global__ __launch_bounds__(kBlock) void epilogue_kernel(
   double ar = 0.0, ai = 0.0;
   // unrolled so that eight partial loads are in flight before the first add (the sum keeps its
   // order); one load per iteration waited for each round trip in turn
+  if constexpr (H) {
+    // each partial scaled, then added, without contraction into a fused multiply-add: the same
+    // values as scaling in the tile kernel and summing FP64 partials
+#pragma clang fp contract(off)
+    const double cb = colinv[b];
 #pragma unroll 8
-  for (int sp = 0; sp < nsplit; ++sp) {
-    const double2 p = part[((int64_t)sp * nrhs + b) * n + i];
-    ar += p.x;
-    ai += p.y;
+    for (int sp = 0; sp < nsplit; ++sp) {
+      const float2 p = parth[((int64_t)sp * nrhs + b) * n + i];
+      ar += (double)p.x * cb;
+      ai += (double)p.y * cb;
+    }
+    if (part) {
+      const double2 p = part[(int64_t)b * n + i];
+      ar += p.x;
+      ai += p.y;
+    }
+  } else {
+#pragma unroll 8
+    for (int sp = 0; sp < nsplit; ++sp) {
+      const double2 p = part[((int64_t)sp * nrhs + b) * n + i];
+      ar += p.x;
+      ai += p.y;
+    }
   }
   // the far kernels sum G/K (hankel.h); K and, for the adjoint, the weight are applied here
   const double gs = M != Mode::Forward ? w[i] * G_SCALE : G_SCALE;
@@ -472,14 +493,36 @@ hipError_t launch_epilogue(const Scat &s, const double2 *part, int nsplit, const
   const int32_t *ci = s.ci, *ciH = s.ciH;
   const double2 *cv = s.cv, *cvH = s.cvH;
   if (mode == Mode::Forward)
-    epilogue_kernel<Mode::Forward><<<ge, kBlock, 0, st>>>(n, nrhs, nsplit, part, f, rp, ci, cv, s.w, s.m, s.perm,
-                                                         xc, yc, ld, s.off, k2);
+    epilogue_kernel<Mode::Forward, false><<<ge, kBlock, 0, st>>>(n, nrhs, nsplit, part, nullptr, nullptr, f, rp, ci,
+                                                                cv, s.w, s.m, s.perm, xc, yc, ld, s.off, k2);
   else if (mode == Mode::Adjoint)
-    epilogue_kernel<Mode::Adjoint><<<ge, kBlock, 0, st>>>(n, nrhs, nsplit, part, f, rpH, ciH, cvH, s.w, s.m,
-                                                         s.perm, xc, yc, ld, s.off, k2);
+    epilogue_kernel<Mode::Adjoint, false><<<ge, kBlock, 0, st>>>(n, nrhs, nsplit, part, nullptr, nullptr, f, rpH, ciH,
+                                                                cvH, s.w, s.m, s.perm, xc, yc, ld, s.off, k2);
   else
-    epilogue_kernel<Mode::AdjointPotential><<<ge, kBlock, 0, st>>>(n, nrhs, nsplit, part, f, rpH, ciH, cvH, s.w,
-                                                                  s.m, s.perm, xc, yc, ld, s.off, k2);
+    epilogue_kernel<Mode::AdjointPotential, false><<<ge, kBlock, 0, st>>>(n, nrhs, nsplit, part, nullptr, nullptr, f,
+                                                                         rpH, ciH, cvH, s.w, s.m, s.perm, xc, yc, ld,
+                                                                         s.off, k2);
+  return hipGetLastError();
+}
+
+hipError_t launch_epilogue_h(const Scat &s, const float2 *parth, int nsplit, const double *colinv,
+                             const double2 *near, const double2 *f, const double *x, double *y, int nrhs, int64_t ld,
+                             Mode mode, hipStream_t st) {
+  const int64_t n = s.n;
+  const double2 *xc = (const double2 *)x;
+  double2 *yc = (double2 *)y;
+  dim3 ge((unsigned)((n + kBlock - 1) / kBlock), (unsigned)nrhs);
+  const double k2 = s.k * s.k;
+  if (mode == Mode::Forward)
+    epilogue_kernel<Mode::Forward, true><<<ge, kBlock, 0, st>>>(n, nrhs, nsplit, near, parth, colinv, f, s.rp, s.ci,
+                                                               s.cv, s.w, s.m, s.perm, xc, yc, ld, s.off, k2);
+  else if (mode == Mode::Adjoint)
+    epilogue_kernel<Mode::Adjoint, true><<<ge, kBlock, 0, st>>>(n, nrhs, nsplit, near, parth, colinv, f, s.rpH,
+                                                               s.ciH, s.cvH, s.w, s.m, s.perm, xc, yc, ld, s.off, k2);
+  else
+    epilogue_kernel<Mode::AdjointPotential, true><<<ge, kBlock, 0, st>>>(n, nrhs, nsplit, near, parth, colinv, f,
+                                                                        s.rpH, s.ciH, s.cvH, s.w, s.m, s.perm, xc, yc,
+                                                                        ld, s.off, k2);
   return hipGetLastError();
 }
 

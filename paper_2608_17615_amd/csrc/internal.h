@@ -175,6 +175,12 @@ size_t apply_workspace_bytes(int64_t n, int nrhs, int source_split);
 int fp64_sym_splits(int64_t n);
 hipError_t launch_epilogue(const Scat &s, const double2 *part, int nsplit, const double2 *f, const double *x,
                            double *y, int nrhs, int64_t ld, Mode mode, hipStream_t st);
+// the same for the split-FP16 tiles, whose nsplit partial sums are FP32 ([split][rhs][n] float2,
+// each column scaled by colinv[b] here, in FP64); near (may be null) is the FP64 near launch's
+// partial [rhs][n], added after them
+hipError_t launch_epilogue_h(const Scat &s, const float2 *parth, int nsplit, const double *colinv,
+                             const double2 *near, const double2 *f, const double *x, double *y, int nrhs, int64_t ld,
+                             Mode mode, hipStream_t st);
 // mfma.hip: batched right-hand sides on the matrix cores (single = FP32 tiles)
 int tile_ldx(int nrhs);
 int tile_mt(int nrhs, bool single);

@@ -619,9 +619,8 @@ constexpr int kHChunk = kBlock;   // source positions staged in LDS per pass of 
 template <int MT, int NT, bool CONJ>
 __global__ __launch_bounds__(kBlock) void far_tile_h_kernel(int n, const double2 *__restrict__ pos,
                                                             const _Float16 *__restrict__ Xh, int ldx, int nrhs,
-                                                            double k2, int split_len,
-                                                            const double *__restrict__ colinv,
-                                                            double2 *__restrict__ part, int excl) {
+                                                            double k2, int split_len, float2 *__restrict__ part,
+                                                            int excl) {
   __shared__ double2 spos[kHChunk];
   const int lane = threadIdx.x & 63;
   const int kq = lane >> 4, col = lane & 15;
@@ -722,19 +721,16 @@ __global__ __launch_bounds__(kBlock) void far_tile_h_kernel(int n, const double2
       }
     }
   }
+  // the FP32 sums as they are: the epilogue applies the column scale in FP64
 #pragma unroll
   for (int mi = 0; mi < MT; ++mi)
 #pragma unroll
     for (int ni = 0; ni < NT; ++ni) {
       const int b = b0 + 16 * ni + col;
-      const double ci = b < nrhs ? colinv[b] : 0.0;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int t = t0 + 16 * mi + 4 * kq + r;
-        if (t < n && b < nrhs) {
-          part[((int64_t)blockIdx.y * nrhs + b) * n + t] =
-              make_double2((double)re[mi][ni][r] * ci, (double)im[mi][ni][r] * ci);
-        }
+        if (t < n && b < nrhs) part[((int64_t)blockIdx.y * nrhs + b) * n + t] = make_float2(re[mi][ni][r], im[mi][ni][r]);
       }
     }
 }
@@ -954,10 +950,11 @@ int tile_source_split(int64_t n, int nrhs, bool single) {
 }
 
 size_t tile_h_workspace_bytes(int64_t n, int nrhs, int nsplit) {
-  // four FP16 planes [npad][ldx], column maxima and scales, f [nrhs][n], part [nsplit][nrhs][n]
+  // four FP16 planes [npad][ldx], column maxima and scales, f [nrhs][n], the FP32 partial sums
+  // [nsplit][nrhs][n] and the near launch's FP64 partial [nrhs][n]
   const size_t ldx = (size_t)tile_ldx(nrhs);
-  return 2 * kHPlanes * (size_t)h_npad(n) * ldx + 256 + 16 * ldx + 256 +
-         sizeof(double2) * (size_t)n * nrhs * (1 + (size_t)nsplit) + 512;
+  return 2 * kHPlanes * (size_t)h_npad(n) * ldx + 256 + 16 * ldx + 256 + sizeof(double2) * (size_t)n * nrhs +
+         sizeof(float2) * (size_t)n * nrhs * (size_t)nsplit + 256 + sizeof(double2) * (size_t)n * nrhs + 512;
 }
 
 hipError_t launch_apply_tile_h(const Scat &s, const double *x, double *y, int nrhs, int64_t ld, Mode mode, int nsplit,
@@ -972,7 +969,8 @@ hipError_t launch_apply_tile_h(const Scat &s, const double *x, double *y, int nr
   double *colinv = (double *)(p + 8 * (size_t)ldx);
   p = al(p + 16 * (size_t)ldx);
   double2 *f = (double2 *)p;
-  double2 *part = f + n * nrhs;
+  // the tiles' FP32 partial sums [split][rhs][n], then the near launch's FP64 partial [rhs][n]
+  float2 *part = (float2 *)(f + n * nrhs);
   const double2 *xc = (const double2 *)x;
   const int fwd = mode == Mode::Forward ? 1 : 0;
   zero_u32_kernel<<<(nrhs + 255) / 256, 256, 0, st>>>(cmax, nrhs);
@@ -995,32 +993,33 @@ hipError_t launch_apply_tile_h(const Scat &s, const double *x, double *y, int nr
     const dim3 g4((unsigned)((n + 64 * MT - 1) / (64 * MT)), (unsigned)used, (unsigned)(ldx / 64));
     if (fwd)
       far_tile_h_kernel<MT, 4, false><<<g4, kBlock, 0, st>>>((int)n, s.pos, Xh, ldx, nrhs, s.k * s.k, split_len,
-                                                              colinv, part, excl);
+                                                              part, excl);
     else
       far_tile_h_kernel<MT, 4, true><<<g4, kBlock, 0, st>>>((int)n, s.pos, Xh, ldx, nrhs, s.k * s.k, split_len,
-                                                             colinv, part, excl);
+                                                             part, excl);
   } else if (ldx % 32 != 0) {
     // an odd number of 16-column groups: one N-tile per wave
     const dim3 g1((unsigned)((n + 64 * MT - 1) / (64 * MT)), (unsigned)used, (unsigned)(ldx / 16));
     if (fwd)
       far_tile_h_kernel<MT, 1, false><<<g1, kBlock, 0, st>>>((int)n, s.pos, Xh, ldx, nrhs, s.k * s.k, split_len,
-                                                              colinv, part, excl);
+                                                              part, excl);
     else
       far_tile_h_kernel<MT, 1, true><<<g1, kBlock, 0, st>>>((int)n, s.pos, Xh, ldx, nrhs, s.k * s.k, split_len,
-                                                             colinv, part, excl);
+                                                             part, excl);
   } else if (fwd) {
     far_tile_h_kernel<MT, NT, false><<<grid, kBlock, 0, st>>>((int)n, s.pos, Xh, ldx, nrhs, s.k * s.k, split_len,
-                                                               colinv, part, excl);
+                                                               part, excl);
   } else {
     far_tile_h_kernel<MT, NT, true><<<grid, kBlock, 0, st>>>((int)n, s.pos, Xh, ldx, nrhs, s.k * s.k, split_len,
-                                                              colinv, part, excl);
+                                                              part, excl);
   }
   if (far_stop) (void)hipEventRecord(far_stop, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = launch_near(s, f, nrhs, !fwd, part + (size_t)used * nrhs * n, st);
+  double2 *near = (double2 *)al((char *)(part + (size_t)used * nrhs * n));
+  e = launch_near(s, f, nrhs, !fwd, near, st);
   if (e != hipSuccess) return e;
-  return launch_epilogue(s, part, used + (s.near_ok ? 1 : 0), f, x, y, nrhs, ld, mode, st);
+  return launch_epilogue_h(s, part, used, colinv, s.near_ok ? near : nullptr, f, x, y, nrhs, ld, mode, st);
 }
 
 hipError_t launch_apply_tile(const Scat &s, const double *x, double *y, int nrhs, int64_t ld, Mode mode, bool single,
