@@ -936,7 +936,8 @@ int tile_source_split(int64_t n, int nrhs, bool single) {
   int64_t cap = ((int64_t)1 << 30) / ((int64_t)16 * n * nrhs);   // FP64 partials <= 1 GiB
   if (single) {
     // The FP32 accumulation error grows with the number of sources one split sums, so aim at
-    // about 2 048 per split, with up to 4 GiB of partials.  At N = 122 500, B = 64 going from 9 to
+    // about 2 048 per split, with up to 4 GiB of partials counted at 16 B per value (the FP32 tiles'
+    // FP64 partials; the split-FP16 tiles store 8 B, half that).  At N = 122 500, B = 64 going from 9 to
     // 32 splits took the operator's relative error from 1.9e-6 to 6.7e-7 (2-norm; 5.9e-6 to 2.1e-6
     // entrywise) at the same launch time; 64 splits gave 4.1e-7.
     s = std::max<int64_t>(s, (n + 2047) / 2048);
