@@ -145,19 +145,25 @@ __device__ __forceinline__ void tile_body_ri(int n, const double2 *__restrict__ 
     const bool ok = src < s1;
     const int sc = ok ? src : s0;
     const double2 p = pos[sc];
+    // only a step that meets the wave's targets (the diagonal pair, G undefined there) or runs past
+    // the split's last source has pairs to zero (the same for the whole wave); a zero G also
+    // cancels the clamped source's density, so X needs no mask
+    const bool edge = (s < t0 + 16 * MT && t0 < s + 4) || s + 4 > s1;
     T gr[MT], gi[MT];
 #pragma unroll
     for (int mi = 0; mi < MT; ++mi) {
       const double dx = xt[mi] - p.x, dy = yt[mi] - p.y;
       const double A = k2 * std::fma(dx, dx, dy * dy);
       TL::green(A, gr[mi], gi[mi], sct, excl);
-      const bool zero = !ok || src == tm[mi];
-      gr[mi] = zero ? (T)0 : gr[mi];
-      gi[mi] = zero ? (T)0 : gi[mi];
+      if (edge) {
+        const bool zero = !ok || src == tm[mi];
+        gr[mi] = zero ? (T)0 : gr[mi];
+        gi[mi] = zero ? (T)0 : gi[mi];
+      }
       if (CONJ) gi[mi] = -gi[mi];
     }
     const typename TL::cplx_t xb = X[(int64_t)sc * ldx + b0 + bcol];
-    const T xv = !ok ? (T)0 : (im_col ? xb.y : xb.x);
+    const T xv = im_col ? xb.y : xb.x;
 #pragma unroll
     for (int mi = 0; mi < MT; ++mi) {
       d0[mi] = TL::mma(gr[mi], xv, d0[mi]);
@@ -212,15 +218,21 @@ __device__ __forceinline__ void tile_body(int n, const double2 *__restrict__ pos
     const bool ok = src < s1;
     const int sc = ok ? src : s0;
     const double2 p = pos[sc];
+    // only a step that meets the wave's targets (the diagonal pair, G undefined there) or runs past
+    // the split's last source has pairs to zero (the same for the whole wave); a zero G also
+    // cancels the clamped source's density, so X needs no mask
+    const bool edge = (s < t0 + 16 * MT && t0 < s + 4) || s + 4 > s1;
     T gr[MT], gi[MT], g2[MT];
 #pragma unroll
     for (int mi = 0; mi < MT; ++mi) {
       const double dx = xt[mi] - p.x, dy = yt[mi] - p.y;
       const double A = k2 * std::fma(dx, dx, dy * dy);
       TL::green(A, gr[mi], gi[mi], sct, excl);
-      const bool zero = !ok || src == tm[mi];
-      gr[mi] = zero ? (T)0 : gr[mi];
-      gi[mi] = zero ? (T)0 : gi[mi];
+      if (edge) {
+        const bool zero = !ok || src == tm[mi];
+        gr[mi] = zero ? (T)0 : gr[mi];
+        gi[mi] = zero ? (T)0 : gi[mi];
+      }
       if (CONJ) gi[mi] = -gi[mi];
       g2[mi] = gr[mi] + gi[mi];
     }
@@ -229,7 +241,6 @@ __device__ __forceinline__ void tile_body(int n, const double2 *__restrict__ pos
 #pragma unroll
     for (int ni = 0; ni < NT; ++ni) {
       xb[ni] = X[(int64_t)sc * ldx + b0 + 16 * ni + col];
-      if (!ok) xb[ni] = TL::make(0.0, 0.0);
       x2[ni] = xb[ni].x + xb[ni].y;
     }
 #pragma unroll
